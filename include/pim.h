@@ -1,0 +1,210 @@
+/*
+ * pim.h -- C ABI of the MI355X PIMI sweep library (libpim.so).
+ *
+ * The library runs the fully parallel, synchronous p-bit update with inertia
+ * (PIMI, Eq. (4) and Box 1 of Zhu et al., "A fully parallel densely connected
+ * probabilistic Ising machine with inertia for real-time applications") on
+ * dense integer Ising instances, many trials and instances per launch, on one
+ * AMD Instinct MI355X (gfx950).
+ *
+ * Problem statement (Sec. II, Eq. (1)): minimise
+ *     H(s) = -sum_{i<j} J_ij s_i s_j - sum_i h_i s_i,   s_i in {-1, +1},
+ * for a symmetric J with zero diagonal.  A *trial* starts from an initial
+ * configuration and applies T update steps, producing one candidate; the
+ * host keeps the lowest-energy candidate (Box 1; Suppl. "PIMI FPGA
+ * implementation for Max-cut and SK-1", "Output handling and solution
+ * selection").
+ *
+ * Update rule evaluated for every spin i of every trial at step t:
+ *     I_i(t)   = sum_j J_ij s_j(t) + h_i                          (Eq. (2))
+ *     s_i(t+1) = sign[ LUT_L( (beta(t) * c) * I_i(t) ) + xi * s_i(t)
+ *                      + eta(t) * Z[u_i(t)] ]                      (Eq. (4))
+ * where
+ *   - c is the coupling normalisation (2/sqrt(N) for Max-Cut, 1/sqrt(N) for
+ *     SK-1: Suppl. "Max-Cut instance generation" / "SK-1 instance
+ *     generation", Preprocessing), applied to the accumulated integer field
+ *     (Suppl. "Quantization scheme");
+ *   - LUT_L is the L-level tanh table (Suppl. "Quantization scheme",
+ *     Algorithm "LUT-based tanh approximation"): breakpoints b_k = (2k-L)/L,
+ *     levels (2k-(L-1))/(L-1), saturating outside [-1, 1], x = 1 -> top level;
+ *   - u_i(t) is a B-bit uniform integer (B = 8) from Philox4x32-10 with key
+ *     (seed low 32 bits, seed high 32 bits) and counter
+ *     (i / 16, start_step + t, trial, rng_stream); value i % 16 is byte i % 16
+ *     of the 128-bit output read little-endian;
+ *   - Z is a non-decreasing table of 2^B noise quantiles (Gaussian N(0,1) for
+ *     PIMI; uniform U(-1,1) for the conventional PIM of Eq. (3));
+ *   - every real operation is IEEE binary64 in the order written; an argument
+ *     of sign that is exactly zero keeps s_i(t).
+ * The library compiles these binary64 decisions, per step, into integer
+ * thresholds on the exact integer field and the noise index, so every kernel
+ * reproduces them bit for bit.  The conventional fully parallel PIM (Box 1,
+ * middle) is the same rule with xi = 0 and uniform noise.
+ *
+ * Initial spins: caller-supplied, or s_i(0) = (u >= 128) ? +1 : -1 with u from
+ * the same generator and counter (i / 16, 0, trial, (1 << 24) | rng_stream).
+ *
+ * Conventions common to every entry point
+ *   - Every function returns a pim_status; a non-OK status leaves a
+ *     thread-local message readable through pim_last_error().  No C++
+ *     exception crosses this boundary.
+ *   - "host" pointers are ordinary CPU memory owned by the caller; the
+ *     library copies what it needs before returning (or, for asynchronous
+ *     calls, before the call returns to the caller).
+ *   - Device memory is obtained only through the allocator registered with
+ *     pim_set_allocator (hipMalloc/hipFree when none is registered) and is
+ *     owned by the handle that allocated it.
+ *   - `stream` arguments are hipStream_t values owned by the caller (NULL =
+ *     the default stream).  pim_run is asynchronous on its stream; pim_best,
+ *     pim_trials and pim_energy synchronise the stream they use.
+ *   - Handles are not thread-safe; distinct handles may be used from
+ *     distinct threads.
+ */
+#ifndef PIM_H
+#define PIM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PIM_ABI_VERSION 1
+
+/* Largest N accepted by pim_create (int8 couplings staged on chip). */
+#define PIM_MAX_N 256
+
+typedef enum {
+  PIM_OK = 0,
+  PIM_ERR_INVALID = 1,     /* argument fails validation (message says which)   */
+  PIM_ERR_UNSUPPORTED = 2, /* valid request this build does not implement       */
+  PIM_ERR_NOMEM = 3,       /* the allocator returned NULL                       */
+  PIM_ERR_DEVICE = 4,      /* a HIP call failed; sticky on the batch            */
+  PIM_ERR_STATE = 5,       /* call out of order (e.g. results before a run)     */
+  PIM_ERR_CANCELLED = 6    /* the run was cancelled; results are partial        */
+} pim_status;
+
+typedef enum {
+  PIM_NOISE_GAUSS = 0,   /* Z = standard normal quantiles, Eq. (4)   */
+  PIM_NOISE_UNIFORM = 1  /* Z = U(-1, 1) cell midpoints, Eq. (3)     */
+} pim_noise;
+
+typedef enum {
+  PIM_KERNEL_MFMA_I8 = 0,   /* persistent batched sweep, int8 MFMA contraction       */
+  PIM_KERNEL_PLAIN_F32 = 1  /* one instance per launch, plain FP32 dot products      */
+} pim_kernel;
+
+/* Per-instance constants of the update rule. */
+typedef struct {
+  int32_t n;                 /* number of spins N, 1 <= N <= PIM_MAX_N            */
+  double j_scale;            /* c > 0, finite                                      */
+  double xi;                 /* inertia xi >= 0, finite                             */
+  int32_t levels;            /* L, 2 <= L <= 16                                     */
+  int32_t noise;             /* pim_noise                                           */
+  int32_t noise_bits;        /* B; must be 8                                        */
+  const double* noise_table; /* host, 2^B finite non-decreasing values, or NULL for
+                                the built-in table of `noise` (copied at create)   */
+  uint32_t rng_stream;       /* counter word 3 id, < 2^24 (request/instance id)    */
+} pim_params;
+
+/* Per-run annealing schedule (Sec. II: beta(t) up, eta(t) down; xi constant). */
+typedef struct {
+  int32_t steps;             /* T >= 1 update steps                                 */
+  const double* beta;        /* host [T], beta(t) >= 0 finite (copied)              */
+  const double* eta;         /* host [T], eta(t) >= 0 finite (copied)               */
+  int32_t start_step;        /* counter step of the first update (resume), >= 0,
+                                start_step + T < 2^31                               */
+  int32_t kernel;            /* pim_kernel                                          */
+  int32_t use_target;        /* nonzero: record first step with E <= target        */
+  const int64_t* target;     /* host [instance count] integer energies, or NULL     */
+} pim_schedule;
+
+typedef struct pim_instance pim_instance; /* device copy of one (J, h, params)       */
+typedef struct pim_batch pim_batch;       /* instances x trials + per-trial results  */
+
+/* Device allocator hooks: alloc returns NULL on failure. */
+typedef void* (*pim_alloc_fn)(size_t bytes, void* stream, void* user);
+typedef void (*pim_free_fn)(void* ptr, void* stream, void* user);
+
+/* Registers the device allocator used by every later allocation (process
+ * wide).  Both NULL restores hipMalloc/hipFree.  Memory allocated through one
+ * allocator is freed through the same one. */
+pim_status pim_set_allocator(pim_alloc_fn alloc, pim_free_fn free_fn, void* user);
+
+/* Creates an instance from a host int8 coupling matrix J (row-major N x N,
+ * symmetric, zero diagonal) and host int32 biases h (length N, NULL = zeros).
+ * Rejects |sum_j |J_ij|| + |h_i| > 32766 (the integer field must fit the
+ * int16 thresholds).  Copies J and h to the device on `stream`; *out owns the
+ * copies.  Eq. (1)-(2). */
+pim_status pim_create(const int8_t* J, const int32_t* h, const pim_params* params,
+                      void* stream, pim_instance** out);
+
+/* Groups `count` instances of equal N with `trials` trials each.  init_spins:
+ * host int8 [count][trials][N] of +-1, or NULL for generator-drawn initial
+ * spins.  The batch keeps pointers to the instances, which must outlive it.
+ * Trial a of instance k is trial id a in the generator counter. */
+pim_status pim_batch_create(pim_instance* const* insts, int32_t count, int32_t trials,
+                            const int8_t* init_spins, void* stream, pim_batch** out);
+
+/* Runs T steps of Eq. (4) on every trial of every instance of the batch,
+ * asynchronously on `stream`.  Compiles the schedule on the host, uploads the
+ * tables and launches the sweep (PIM_KERNEL_MFMA_I8: one launch for the whole
+ * batch; PIM_KERNEL_PLAIN_F32: one launch per instance).  Tracks, over the
+ * energies E(t) of s(t) for t = 0..T (counter steps start_step..start_step+T):
+ * the lowest energy and its earliest step, the state there, and the first step
+ * with E <= target.  Resuming: pass the previous final spins as init_spins of a
+ * new batch and start_step = previous start_step + T. */
+pim_status pim_run(pim_batch* batch, const pim_schedule* sched, uint64_t seed, void* stream);
+
+/* Requests cancellation of the batch's current run: host-callable at any time
+ * from any thread; the kernel stops within 256 steps.  Results of a cancelled
+ * run are partial and the result getters return PIM_ERR_CANCELLED. */
+pim_status pim_cancel(pim_batch* batch);
+
+/* Energies (Eq. (1)) of `count` host configurations spins[count][N] (+-1), in
+ * binary64 on the device; out: host double[count].  Synchronises `stream`. */
+pim_status pim_energy(const pim_instance* inst, const int8_t* spins, int32_t count,
+                      double* out, void* stream);
+
+/* Best candidate of instance `inst` after a run: re-evaluates every trial's
+ * best state in binary64 on the device (once per run), takes the lowest
+ * energy (ties: lowest trial id) and returns its state (host int8[N]), energy,
+ * trial id and the step at which it occurred.  Any output may be NULL.
+ * Synchronises the batch's stream. */
+pim_status pim_best(pim_batch* batch, int32_t inst, int8_t* spins_out, double* e_out,
+                    int32_t* trial_out, int32_t* step_out);
+
+/* Per-trial results of instance `inst` (host arrays of length `trials`, or
+ * trials*N for spins; any may be NULL): best energy, its step, first step at
+ * or below target (-1 = never), final energy E(T), best and final states.
+ * Synchronises. */
+pim_status pim_trials(pim_batch* batch, int32_t inst, double* best_e, int32_t* best_step,
+                      int32_t* first_hit, double* final_e, int8_t* best_spins,
+                      int8_t* final_spins);
+
+/* Duration in milliseconds of the sweep kernel(s) of the last pim_run,
+ * measured with HIP events on the run's stream.  Synchronises. */
+pim_status pim_kernel_time(pim_batch* batch, float* ms);
+
+/* Host-only: the integer thresholds the library compiles for one step t of a
+ * schedule (no device work).  theta: int32[L-1], the smallest integer field
+ * I with LUT bin index >= j (j = 1..L-1), clamped to [-32768, 32767];
+ * u_min: int32[2*L], for LUT bin k and current spin s (index 2k + (s < 0)),
+ * the smallest noise index u giving s(t+1) = +1 (2^B = never). */
+pim_status pim_compile_step(const pim_params* params, double beta, double eta,
+                            int32_t* theta, int32_t* u_min);
+
+void pim_batch_destroy(pim_batch* batch);
+void pim_destroy(pim_instance* inst);
+
+/* Text of the last non-OK status on this thread ("" if none). */
+const char* pim_last_error(void);
+
+/* PIM_ABI_VERSION of the loaded library. */
+int32_t pim_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PIM_H */

@@ -1,0 +1,342 @@
+"""Python binding of libpim.so, the MI355X PIMI sweep library.
+
+Argument marshalling only: every step of the sweep runs in the library's HIP
+kernels.  PyTorch supplies the device allocator (its caching allocator) and
+the stream (its current stream); nothing here computes the method.
+
+    import paper_2604_17109_amd as pim
+    inst = pim.Instance(J, h, j_scale=1/np.sqrt(n), xi=0.5, levels=4)
+    batch = pim.Batch([inst], trials=1024)
+    batch.run(beta, eta, seed=1)
+    spins, energy, trial, step = batch.best(0)
+
+The library refuses to fall back to anything else: if libpim.so is missing
+the import raises.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpim.so")
+
+PIM_OK, PIM_ERR_INVALID, PIM_ERR_UNSUPPORTED, PIM_ERR_NOMEM = 0, 1, 2, 3
+PIM_ERR_DEVICE, PIM_ERR_STATE, PIM_ERR_CANCELLED = 4, 5, 6
+NOISE_GAUSS, NOISE_UNIFORM = 0, 1
+KERNEL_MFMA_I8, KERNEL_PLAIN_F32 = 0, 1
+_KERNELS = {"mfma": KERNEL_MFMA_I8, "mfma_i8": KERNEL_MFMA_I8, "plain": KERNEL_PLAIN_F32,
+            "plain_f32": KERNEL_PLAIN_F32}
+_NOISES = {"gauss": NOISE_GAUSS, "uniform": NOISE_UNIFORM}
+
+# every symbol declared in include/pim.h
+EXPORTED = (
+    "pim_set_allocator", "pim_create", "pim_batch_create", "pim_run", "pim_cancel",
+    "pim_energy", "pim_best", "pim_trials", "pim_kernel_time", "pim_compile_step",
+    "pim_batch_destroy", "pim_destroy", "pim_last_error", "pim_abi_version",
+)
+
+
+class PimError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"[pim status {status}] {message}")
+        self.status = status
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int32),
+        ("j_scale", ctypes.c_double),
+        ("xi", ctypes.c_double),
+        ("levels", ctypes.c_int32),
+        ("noise", ctypes.c_int32),
+        ("noise_bits", ctypes.c_int32),
+        ("noise_table", ctypes.POINTER(ctypes.c_double)),
+        ("rng_stream", ctypes.c_uint32),
+    ]
+
+
+class Schedule(ctypes.Structure):
+    _fields_ = [
+        ("steps", ctypes.c_int32),
+        ("beta", ctypes.POINTER(ctypes.c_double)),
+        ("eta", ctypes.POINTER(ctypes.c_double)),
+        ("start_step", ctypes.c_int32),
+        ("kernel", ctypes.c_int32),
+        ("use_target", ctypes.c_int32),
+        ("target", ctypes.POINTER(ctypes.c_int64)),
+    ]
+
+
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2604_17109_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I32, F64, VP = ctypes.POINTER, ctypes.c_int32, ctypes.c_double, ctypes.c_void_p
+    sig = {
+        "pim_set_allocator": (I32, [_ALLOC_FN, _FREE_FN, VP]),
+        "pim_create": (I32, [P(ctypes.c_int8), P(ctypes.c_int32), P(Params), VP, P(VP)]),
+        "pim_batch_create": (I32, [P(VP), I32, I32, P(ctypes.c_int8), VP, P(VP)]),
+        "pim_run": (I32, [VP, P(Schedule), ctypes.c_uint64, VP]),
+        "pim_cancel": (I32, [VP]),
+        "pim_energy": (I32, [VP, P(ctypes.c_int8), I32, P(F64), VP]),
+        "pim_best": (I32, [VP, I32, P(ctypes.c_int8), P(F64), P(I32), P(I32)]),
+        "pim_trials": (I32, [VP, I32, P(F64), P(I32), P(I32), P(F64), P(ctypes.c_int8), P(ctypes.c_int8)]),
+        "pim_kernel_time": (I32, [VP, P(ctypes.c_float)]),
+        "pim_compile_step": (I32, [P(Params), F64, F64, P(I32), P(I32)]),
+        "pim_batch_destroy": (None, [VP]),
+        "pim_destroy": (None, [VP]),
+        "pim_last_error": (ctypes.c_char_p, []),
+        "pim_abi_version": (I32, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+def _check(status):
+    if status != PIM_OK:
+        raise PimError(status, lib.pim_last_error().decode(errors="replace"))
+
+
+def _ptr(a, ctype):
+    return a.ctypes.data_as(ctypes.POINTER(ctype)) if a is not None else None
+
+
+# ---------------------------------------------------------------------------
+# torch plumbing: caching allocator and current stream
+# ---------------------------------------------------------------------------
+_torch_hooks = None
+
+
+def use_torch_allocator():
+    """Route every device allocation of the library through torch's caching
+    allocator (idempotent)."""
+    global _torch_hooks
+    if _torch_hooks is not None:
+        return
+    import torch
+
+    def _alloc(nbytes, stream, user):
+        try:
+            return int(torch.cuda.caching_allocator_alloc(int(nbytes), stream=int(stream or 0)))
+        except Exception:  # noqa: BLE001 - reported to the library as NULL (PIM_ERR_NOMEM)
+            return None
+
+    def _free(ptr, stream, user):
+        if ptr:
+            torch.cuda.caching_allocator_delete(int(ptr))
+
+    hooks = (_ALLOC_FN(_alloc), _FREE_FN(_free))
+    _check(lib.pim_set_allocator(hooks[0], hooks[1], None))
+    _torch_hooks = hooks
+
+
+def current_stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _device_ready():
+    import torch
+    if not torch.cuda.is_available():
+        raise PimError(PIM_ERR_DEVICE, "no GPU visible to torch")
+    use_torch_allocator()
+
+
+# ---------------------------------------------------------------------------
+def make_params(n, j_scale, xi, levels=4, noise="gauss", noise_table=None, rng_stream=0,
+                noise_bits=8):
+    p = Params()
+    p.n = int(n)
+    p.j_scale = float(j_scale)
+    p.xi = float(xi)
+    p.levels = int(levels)
+    p.noise = _NOISES[noise] if isinstance(noise, str) else int(noise)
+    p.noise_bits = int(noise_bits)
+    keep = None
+    if noise_table is not None:
+        keep = np.ascontiguousarray(noise_table, dtype=np.float64)
+        p.noise_table = _ptr(keep, ctypes.c_double)
+    p.rng_stream = int(rng_stream)
+    return p, keep
+
+
+def validate(J, h=None, *, j_scale, xi, levels=4, noise="gauss", noise_table=None, noise_bits=8):
+    """Runs pim_create's argument validation only (no device work): returns
+    None when the arguments are valid, else raises PimError.  Valid input is
+    detected by the library reaching its first device allocation, which this
+    call forbids through a refusing allocator."""
+    J = np.ascontiguousarray(J, dtype=np.int8)
+    hh = None if h is None else np.ascontiguousarray(h, dtype=np.int32)
+    p, keep = make_params(J.shape[0] if J.ndim == 2 else 0, j_scale, xi, levels, noise, noise_table,
+                          noise_bits=noise_bits)
+    handle = ctypes.c_void_p()
+    refuse = (_ALLOC_FN(lambda nb, st, u: None), _FREE_FN(lambda ptr, st, u: None))
+    prev = _torch_hooks
+    _check(lib.pim_set_allocator(refuse[0], refuse[1], None))
+    try:
+        st = lib.pim_create(_ptr(J, ctypes.c_int8), _ptr(hh, ctypes.c_int32), ctypes.byref(p), None,
+                            ctypes.byref(handle))
+    finally:
+        if prev is not None:
+            _check(lib.pim_set_allocator(prev[0], prev[1], None))
+        else:
+            _check(lib.pim_set_allocator(_ALLOC_FN(0), _FREE_FN(0), None))
+    del keep
+    if st == PIM_ERR_NOMEM:
+        return None  # validation passed; the refusing allocator stopped it
+    _check(st)
+    lib.pim_destroy(handle)
+    return None
+
+
+def compile_step(n, j_scale, xi, beta, eta, levels=4, noise="gauss", noise_table=None):
+    """Host-only: integer thresholds (theta[L-1], umin[2L]) compiled for one step."""
+    p, keep = make_params(n, j_scale, xi, levels, noise, noise_table)
+    theta = np.zeros(levels - 1, dtype=np.int32)
+    umin = np.zeros(2 * levels, dtype=np.int32)
+    _check(lib.pim_compile_step(ctypes.byref(p), float(beta), float(eta), _ptr(theta, ctypes.c_int32),
+                                _ptr(umin, ctypes.c_int32)))
+    del keep
+    return theta, umin
+
+
+class Instance:
+    """One integer Ising instance (J int8 symmetric, zero diagonal; h int32)
+    with its update-rule constants, copied to the device."""
+
+    def __init__(self, J, h=None, *, j_scale, xi, levels=4, noise="gauss", noise_table=None,
+                 rng_stream=0, stream=None):
+        J = np.ascontiguousarray(J, dtype=np.int8)
+        if J.ndim != 2 or J.shape[0] != J.shape[1]:
+            raise ValueError("J must be square")
+        self.n = J.shape[0]
+        hh = None if h is None else np.ascontiguousarray(h, dtype=np.int32)
+        p, keep = make_params(self.n, j_scale, xi, levels, noise, noise_table, rng_stream)
+        self._handle = ctypes.c_void_p()
+        _device_ready()
+        st = stream if stream is not None else current_stream()
+        _check(lib.pim_create(_ptr(J, ctypes.c_int8), _ptr(hh, ctypes.c_int32), ctypes.byref(p), st,
+                              ctypes.byref(self._handle)))
+        del keep
+
+    @property
+    def handle(self):
+        return self._handle
+
+    def energy(self, spins, stream=None):
+        """Binary64 energies (Eq. (1)) of configurations spins[count, n]."""
+        s = np.ascontiguousarray(np.atleast_2d(spins), dtype=np.int8)
+        out = np.zeros(s.shape[0], dtype=np.float64)
+        _check(lib.pim_energy(self._handle, _ptr(s, ctypes.c_int8), s.shape[0], _ptr(out, ctypes.c_double),
+                              stream if stream is not None else current_stream()))
+        return out
+
+    def close(self):
+        if self._handle:
+            lib.pim_destroy(self._handle)
+            self._handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001
+            pass
+
+
+class Batch:
+    """Instances of one N x `trials` trials, with per-trial result buffers."""
+
+    def __init__(self, instances, trials, init_spins=None, stream=None):
+        _device_ready()
+        self.instances = list(instances)  # keep the instances alive
+        self.count = len(self.instances)
+        self.trials = int(trials)
+        self.n = self.instances[0].n
+        arr = (ctypes.c_void_p * self.count)(*[i.handle.value for i in self.instances])
+        init = None
+        if init_spins is not None:
+            init = np.ascontiguousarray(init_spins, dtype=np.int8).reshape(self.count, self.trials, self.n)
+        self._handle = ctypes.c_void_p()
+        self.stream = stream if stream is not None else current_stream()
+        _check(lib.pim_batch_create(arr, self.count, self.trials, _ptr(init, ctypes.c_int8), self.stream,
+                                    ctypes.byref(self._handle)))
+
+    def run(self, beta, eta, seed, start_step=0, kernel="mfma", target=None, stream=None):
+        beta = np.ascontiguousarray(beta, dtype=np.float64)
+        eta = np.ascontiguousarray(eta, dtype=np.float64)
+        if beta.shape != eta.shape or beta.ndim != 1:
+            raise ValueError("beta and eta must be 1-D arrays of equal length")
+        sc = Schedule()
+        sc.steps = beta.size
+        sc.beta = _ptr(beta, ctypes.c_double)
+        sc.eta = _ptr(eta, ctypes.c_double)
+        sc.start_step = int(start_step)
+        sc.kernel = _KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
+        tgt = None
+        if target is not None:
+            tgt = np.ascontiguousarray(np.broadcast_to(np.asarray(target, dtype=np.int64), (self.count,)))
+            sc.use_target = 1
+            sc.target = _ptr(tgt, ctypes.c_int64)
+        if stream is not None:
+            self.stream = stream
+        _check(lib.pim_run(self._handle, ctypes.byref(sc), ctypes.c_uint64(int(seed) & (2**64 - 1)),
+                           self.stream))
+        self._keep = (beta, eta, tgt)
+        return self
+
+    def cancel(self):
+        _check(lib.pim_cancel(self._handle))
+
+    def best(self, k):
+        """(spins int8[n], energy, trial, step) of the lowest-energy candidate."""
+        spins = np.zeros(self.n, dtype=np.int8)
+        e = ctypes.c_double()
+        tr = ctypes.c_int32()
+        st = ctypes.c_int32()
+        _check(lib.pim_best(self._handle, int(k), _ptr(spins, ctypes.c_int8), ctypes.byref(e),
+                            ctypes.byref(tr), ctypes.byref(st)))
+        return spins, e.value, tr.value, st.value
+
+    def trials_of(self, k, spins=True):
+        R, n = self.trials, self.n
+        out = {
+            "e_best": np.zeros(R, np.float64), "t_best": np.zeros(R, np.int32),
+            "first_hit": np.zeros(R, np.int32), "e_final": np.zeros(R, np.float64),
+        }
+        bs = np.zeros((R, n), np.int8) if spins else None
+        fs = np.zeros((R, n), np.int8) if spins else None
+        _check(lib.pim_trials(self._handle, int(k), _ptr(out["e_best"], ctypes.c_double),
+                              _ptr(out["t_best"], ctypes.c_int32), _ptr(out["first_hit"], ctypes.c_int32),
+                              _ptr(out["e_final"], ctypes.c_double), _ptr(bs, ctypes.c_int8),
+                              _ptr(fs, ctypes.c_int8)))
+        if spins:
+            out["best_state"] = bs
+            out["final"] = fs
+        return out
+
+    def kernel_ms(self):
+        ms = ctypes.c_float()
+        _check(lib.pim_kernel_time(self._handle, ctypes.byref(ms)))
+        return ms.value
+
+    def close(self):
+        if self._handle:
+            lib.pim_batch_destroy(self._handle)
+            self._handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001
+            pass

@@ -1,0 +1,143 @@
+// Internal declarations shared by the host library and the kernel launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "pim.h"
+
+namespace pim {
+
+// ---- errors / allocation (pim_api.cpp) ------------------------------------
+pim_status fail(pim_status st, const char* fmt, ...);
+void* dev_alloc(size_t bytes, hipStream_t s);
+void dev_free(void* p, hipStream_t s);
+
+// ---- update-rule constants of one instance --------------------------------
+constexpr int kNoiseBits = 8;              // B
+constexpr int kNoiseVals = 1 << kNoiseBits;
+constexpr int kTabEntries = kNoiseVals * 2;  // theta-by-noise table over (u, s)
+constexpr int kFieldLimit = 32766;           // |I| bound that keeps thresholds in int16
+constexpr int kMaxLevels = 16;
+
+struct Rule {
+  int n = 0;
+  double c = 0, xi = 0;
+  int levels = 0;
+  int noise = 0;
+  std::vector<double> ztab;  // 2^B non-decreasing
+  uint32_t stream = 0;
+  bool same_table_class(const Rule& o) const {
+    return c == o.c && xi == o.xi && levels == o.levels && ztab == o.ztab;
+  }
+};
+
+// ---- schedule compiler (schedule.cpp) -------------------------------------
+// theta[j-1], j = 1..L-1: smallest integer I with fl(fl(beta*c) * I) >= b_j,
+// clamped to [-32768, 32767].  umin[2k + (s<0)]: smallest u in [0, 2^B) with
+// s(t+1) = +1 for LUT bin k and current spin s; 2^B if none.
+void compile_step(const Rule& r, double beta, double eta, int32_t* theta, int32_t* umin);
+// Field threshold per (u, s): s(t+1) = +1  <=>  I >= tab[kNoiseVals + (u ^ s)],
+// s = +-1 as a two's-complement int (u ^ 1 for s = +1, ~u for s = -1).
+void theta_by_noise(const int32_t* theta, const int32_t* umin, int levels, int16_t* tab);
+// Built-in quantile table of a noise law; false if unknown.
+bool builtin_noise_table(int noise, std::vector<double>& out);
+
+// ---- device argument blocks ----------------------------------------------
+struct SweepArgs {
+  const int8_t* jfrag;       // [count][NT*NT][64][16] MFMA A fragments
+  const int32_t* h;          // [count][npad] or nullptr
+  const int16_t* thtab;      // [classes][T][kTabEntries]
+  const int32_t* inst_class; // [count]
+  const uint32_t* inst_stream;  // [count]
+  const int32_t* target;     // [count] or nullptr
+  const int8_t* init;        // [count][R][npad] or nullptr
+  int8_t* final_s;           // [count][R][npad]
+  int8_t* best_s;            // [count][R][npad]
+  int32_t* e_best;           // [count][R]
+  int32_t* t_best;
+  int32_t* first_hit;
+  int32_t* e_final;
+  int32_t* steps_done;
+  const volatile int32_t* cancel;
+  int32_t n, npad, R, T, start_step;
+  uint32_t k0, k1;
+};
+
+struct PlainArgs {
+  const float* jf32;         // [n][n] of one instance
+  const int32_t* h;          // [n] or nullptr
+  const int32_t* steptab;    // [T][(L-1) + 2L] theta then umin
+  const int8_t* init;        // [R][npad] or nullptr
+  int8_t* final_s;           // [R][npad]
+  int8_t* best_s;
+  int32_t* e_best;
+  int32_t* t_best;
+  int32_t* first_hit;
+  int32_t* e_final;
+  int32_t* steps_done;
+  const volatile int32_t* cancel;
+  int32_t n, npad, R, T, start_step, levels, use_target, target;
+  uint32_t stream, k0, k1;
+};
+
+struct EnergyArgs {
+  const float* jf32;   // [n][n]
+  const int32_t* h;    // [n] or nullptr
+  const int8_t* spins; // [count][stride]
+  double* out;         // [count]
+  int32_t n, stride, count;
+};
+
+hipError_t launch_sweep_mfma(const SweepArgs& a, int count, int nt, bool has_h, hipStream_t s);
+hipError_t launch_sweep_plain(const PlainArgs& a, hipStream_t s);
+hipError_t launch_energy_f64(const EnergyArgs& a, hipStream_t s);
+
+// Host packing of J into the MFMA fragment order (sweep_mfma.hip).
+void pack_mfma_fragments(const int8_t* J, int n, int nt, int8_t* out);
+
+}  // namespace pim
+
+// ---- handles ------------------------------------------------------------
+struct pim_instance {
+  pim::Rule rule;
+  int npad = 0, nt = 0;
+  bool has_h = false;
+  int8_t* d_jfrag = nullptr;
+  float* d_jf32 = nullptr;
+  int32_t* d_h = nullptr;
+};
+
+struct pim_batch {
+  std::vector<pim_instance*> insts;
+  int count = 0, R = 0, n = 0, npad = 0, nt = 0;
+  bool has_h = false;
+  hipStream_t stream = nullptr;
+  // device buffers
+  int8_t* d_jfrag = nullptr;      // concatenated fragments of all instances
+  int32_t* d_h = nullptr;
+  int8_t* d_init = nullptr;
+  int8_t* d_final = nullptr;
+  int8_t* d_best = nullptr;
+  int32_t* d_stats = nullptr;     // 5 x [count][R]: e_best, t_best, first_hit, e_final, steps_done
+  int32_t* d_class = nullptr;
+  uint32_t* d_stream_ids = nullptr;
+  int32_t* d_target = nullptr;
+  double* d_rerank = nullptr;     // [count][R]
+  int16_t* d_thtab = nullptr;
+  size_t thtab_bytes = 0;
+  int32_t* d_steptab = nullptr;
+  size_t steptab_bytes = 0;
+  int32_t* h_cancel = nullptr;    // pinned, host-mapped
+  int32_t* d_cancel = nullptr;    // device view of h_cancel
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  // host-side class bookkeeping
+  std::vector<int> inst_class;
+  std::vector<int> class_rep;     // representative instance of each class
+  // run state
+  bool ran = false, reranked = false, sticky_error = false;
+  int last_T = 0, last_start = 0;
+  std::vector<double> h_rerank;
+};

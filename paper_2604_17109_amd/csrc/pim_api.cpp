@@ -1,0 +1,674 @@
+// C ABI of the PIMI sweep library: validation, handles, allocation, schedule
+// upload, launches and result readout.  Every entry point catches everything
+// and reports a pim_status; no exception crosses the ABI.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace pim {
+namespace {
+
+thread_local std::string g_last_error;
+
+struct AllocHooks {
+  pim_alloc_fn alloc = nullptr;
+  pim_free_fn free_fn = nullptr;
+  void* user = nullptr;
+};
+AllocHooks g_alloc;
+
+}  // namespace
+
+pim_status fail(pim_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return st;
+}
+
+void* dev_alloc(size_t bytes, hipStream_t s) {
+  if (bytes == 0) bytes = 16;
+  if (g_alloc.alloc) return g_alloc.alloc(bytes, (void*)s, g_alloc.user);
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+  return p;
+}
+
+void dev_free(void* p, hipStream_t s) {
+  if (!p) return;
+  if (g_alloc.free_fn) {
+    g_alloc.free_fn(p, (void*)s, g_alloc.user);
+    return;
+  }
+  (void)hipFree(p);
+}
+
+}  // namespace pim
+
+using namespace pim;
+
+namespace {
+
+#define HIP_TRY(expr)                                                              \
+  do {                                                                             \
+    hipError_t _e = (expr);                                                        \
+    if (_e != hipSuccess)                                                          \
+      return fail(PIM_ERR_DEVICE, "%s failed: %s", #expr, hipGetErrorString(_e)); \
+  } while (0)
+
+template <typename T>
+pim_status alloc_dev(T** p, size_t count, hipStream_t s) {
+  *p = (T*)dev_alloc(count * sizeof(T), s);
+  if (!*p) return fail(PIM_ERR_NOMEM, "device allocation of %zu bytes failed", count * sizeof(T));
+  return PIM_OK;
+}
+
+bool finite_nonneg(double v) { return std::isfinite(v) && v >= 0.0; }
+
+pim_status validate_params(const pim_params* p, Rule& r) {
+  if (!p) return fail(PIM_ERR_INVALID, "params is NULL");
+  if (p->n < 1 || p->n > PIM_MAX_N) return fail(PIM_ERR_INVALID, "n = %d outside [1, %d]", p->n, PIM_MAX_N);
+  if (!std::isfinite(p->j_scale) || !(p->j_scale > 0.0))
+    return fail(PIM_ERR_INVALID, "j_scale must be finite and > 0");
+  if (!finite_nonneg(p->xi)) return fail(PIM_ERR_INVALID, "xi must be finite and >= 0");
+  if (p->levels < 2 || p->levels > kMaxLevels)
+    return fail(PIM_ERR_INVALID, "levels = %d outside [2, %d]", p->levels, kMaxLevels);
+  if (p->noise != PIM_NOISE_GAUSS && p->noise != PIM_NOISE_UNIFORM)
+    return fail(PIM_ERR_INVALID, "unknown noise law %d", p->noise);
+  if (p->noise_bits != kNoiseBits)
+    return fail(PIM_ERR_UNSUPPORTED, "noise_bits = %d (only %d is implemented)", p->noise_bits, kNoiseBits);
+  if (p->rng_stream >= (1u << 24)) return fail(PIM_ERR_INVALID, "rng_stream must be < 2^24");
+  r.n = p->n;
+  r.c = p->j_scale;
+  r.xi = p->xi;
+  r.levels = p->levels;
+  r.noise = p->noise;
+  r.stream = p->rng_stream;
+  if (p->noise_table) {
+    r.ztab.assign(p->noise_table, p->noise_table + kNoiseVals);
+    for (int u = 0; u < kNoiseVals; ++u) {
+      if (!std::isfinite(r.ztab[u])) return fail(PIM_ERR_INVALID, "noise_table[%d] is not finite", u);
+      if (u && r.ztab[u] < r.ztab[u - 1]) return fail(PIM_ERR_INVALID, "noise_table is not non-decreasing at %d", u);
+    }
+  } else if (!builtin_noise_table(p->noise, r.ztab)) {
+    return fail(PIM_ERR_INVALID, "no built-in table for noise law %d", p->noise);
+  }
+  return PIM_OK;
+}
+
+pim_status validate_couplings(const int8_t* J, const int32_t* h, int n) {
+  if (!J) return fail(PIM_ERR_INVALID, "J is NULL");
+  for (int i = 0; i < n; ++i) {
+    if (J[(size_t)i * n + i] != 0) return fail(PIM_ERR_INVALID, "J[%d][%d] != 0 (diagonal must be zero)", i, i);
+    int64_t bound = h ? std::llabs((long long)h[i]) : 0;
+    for (int j = 0; j < n; ++j) {
+      const int8_t v = J[(size_t)i * n + j];
+      if (v != J[(size_t)j * n + i]) return fail(PIM_ERR_INVALID, "J is not symmetric at (%d, %d)", i, j);
+      if (v == -128) return fail(PIM_ERR_INVALID, "J[%d][%d] = -128 (use [-127, 127])", i, j);
+      bound += std::abs((int)v);
+    }
+    if (bound > kFieldLimit)
+      return fail(PIM_ERR_INVALID, "row %d: sum_j |J_ij| + |h_i| = %lld exceeds %d", i, (long long)bound, kFieldLimit);
+  }
+  return PIM_OK;
+}
+
+pim_status check_spins(const int8_t* s, size_t count) {
+  for (size_t i = 0; i < count; ++i)
+    if (s[i] != 1 && s[i] != -1) return fail(PIM_ERR_INVALID, "spin value %d at %zu is not +-1", (int)s[i], i);
+  return PIM_OK;
+}
+
+void free_batch_buffers(pim_batch* b) {
+  hipStream_t s = b->stream;
+  dev_free(b->d_jfrag, s);
+  dev_free(b->d_h, s);
+  dev_free(b->d_init, s);
+  dev_free(b->d_final, s);
+  dev_free(b->d_best, s);
+  dev_free(b->d_stats, s);
+  dev_free(b->d_class, s);
+  dev_free(b->d_stream_ids, s);
+  dev_free(b->d_target, s);
+  dev_free(b->d_rerank, s);
+  dev_free(b->d_thtab, s);
+  dev_free(b->d_steptab, s);
+  if (b->h_cancel) (void)hipHostFree(b->h_cancel);
+  if (b->ev0) (void)hipEventDestroy(b->ev0);
+  if (b->ev1) (void)hipEventDestroy(b->ev1);
+}
+
+int32_t* stat_ptr(pim_batch* b, int which) { return b->d_stats + (size_t)which * b->count * b->R; }
+
+// Re-evaluates every trial's best state in binary64 (once per run).
+pim_status ensure_rerank(pim_batch* b) {
+  if (b->reranked) return PIM_OK;
+  for (int k = 0; k < b->count; ++k) {
+    EnergyArgs ea{};
+    ea.jf32 = b->insts[k]->d_jf32;
+    ea.h = b->insts[k]->has_h ? b->insts[k]->d_h : nullptr;
+    ea.spins = b->d_best + (size_t)k * b->R * b->npad;
+    ea.out = b->d_rerank + (size_t)k * b->R;
+    ea.n = b->n;
+    ea.stride = b->npad;
+    ea.count = b->R;
+    HIP_TRY(launch_energy_f64(ea, b->stream));
+  }
+  b->h_rerank.resize((size_t)b->count * b->R);
+  HIP_TRY(hipMemcpyAsync(b->h_rerank.data(), b->d_rerank, b->h_rerank.size() * sizeof(double),
+                         hipMemcpyDeviceToHost, b->stream));
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  b->reranked = true;
+  return PIM_OK;
+}
+
+pim_status check_batch_ready(pim_batch* b, int32_t inst) {
+  if (!b) return fail(PIM_ERR_INVALID, "batch is NULL");
+  if (b->sticky_error) return fail(PIM_ERR_DEVICE, "batch is in an error state after a failed device call");
+  if (!b->ran) return fail(PIM_ERR_STATE, "no run has been issued on this batch");
+  if (inst < 0 || inst >= b->count) return fail(PIM_ERR_INVALID, "instance index %d outside [0, %d)", inst, b->count);
+  return PIM_OK;
+}
+
+// steps_done < T on any trial of the instance means the run was cancelled.
+pim_status cancelled_status(pim_batch* b, int32_t inst) {
+  std::vector<int32_t> done(b->R);
+  HIP_TRY(hipMemcpyAsync(done.data(), stat_ptr(b, 4) + (size_t)inst * b->R, b->R * sizeof(int32_t),
+                         hipMemcpyDeviceToHost, b->stream));
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  for (int a = 0; a < b->R; ++a)
+    if (done[a] < b->last_T) return fail(PIM_ERR_CANCELLED, "run was cancelled after %d of %d steps", done[a], b->last_T);
+  return PIM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t pim_abi_version(void) { return PIM_ABI_VERSION; }
+
+const char* pim_last_error(void) { return g_last_error.c_str(); }
+
+pim_status pim_set_allocator(pim_alloc_fn alloc, pim_free_fn free_fn, void* user) {
+  if ((alloc == nullptr) != (free_fn == nullptr))
+    return fail(PIM_ERR_INVALID, "alloc and free must both be set or both be NULL");
+  g_alloc.alloc = alloc;
+  g_alloc.free_fn = free_fn;
+  g_alloc.user = user;
+  return PIM_OK;
+}
+
+pim_status pim_compile_step(const pim_params* params, double beta, double eta, int32_t* theta,
+                            int32_t* u_min) {
+  try {
+    Rule r;
+    pim_status st = validate_params(params, r);
+    if (st != PIM_OK) return st;
+    if (!finite_nonneg(beta) || !finite_nonneg(eta)) return fail(PIM_ERR_INVALID, "beta and eta must be finite and >= 0");
+    if (!theta || !u_min) return fail(PIM_ERR_INVALID, "output pointer is NULL");
+    compile_step(r, beta, eta, theta, u_min);
+    return PIM_OK;
+  } catch (...) {
+    return fail(PIM_ERR_INVALID, "internal error in pim_compile_step");
+  }
+}
+
+pim_status pim_create(const int8_t* J, const int32_t* h, const pim_params* params, void* stream,
+                      pim_instance** out) {
+  try {
+    if (!out) return fail(PIM_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    Rule r;
+    pim_status st = validate_params(params, r);
+    if (st != PIM_OK) return st;
+    st = validate_couplings(J, h, r.n);
+    if (st != PIM_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    auto* inst = new pim_instance();
+    inst->rule = std::move(r);
+    const int n = inst->rule.n;
+    inst->nt = (n + 31) / 32;
+    inst->npad = inst->nt * 32;
+    inst->has_h = false;
+    if (h)
+      for (int i = 0; i < n; ++i) inst->has_h |= (h[i] != 0);
+    std::vector<int8_t> frag((size_t)inst->nt * inst->nt * 1024);
+    pack_mfma_fragments(J, n, inst->nt, frag.data());
+    std::vector<float> jf((size_t)n * n);
+    for (size_t i = 0; i < jf.size(); ++i) jf[i] = (float)J[i];
+    std::vector<int32_t> hp(inst->npad, 0);
+    if (h) std::copy(h, h + n, hp.begin());
+    st = alloc_dev(&inst->d_jfrag, frag.size(), s);
+    if (st == PIM_OK) st = alloc_dev(&inst->d_jf32, jf.size(), s);
+    if (st == PIM_OK) st = alloc_dev(&inst->d_h, hp.size(), s);
+    if (st != PIM_OK) {
+      pim_destroy(inst);
+      return st;
+    }
+    hipError_t e = hipMemcpyAsync(inst->d_jfrag, frag.data(), frag.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(inst->d_jf32, jf.data(), jf.size() * 4, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(inst->d_h, hp.data(), hp.size() * 4, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);  // host staging buffers go out of scope
+    if (e != hipSuccess) {
+      pim_destroy(inst);
+      return fail(PIM_ERR_DEVICE, "copying the instance to the device failed: %s", hipGetErrorString(e));
+    }
+    *out = inst;
+    return PIM_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(PIM_ERR_NOMEM, "host allocation failed");
+  } catch (...) {
+    return fail(PIM_ERR_INVALID, "internal error in pim_create");
+  }
+}
+
+void pim_destroy(pim_instance* inst) {
+  if (!inst) return;
+  dev_free(inst->d_jfrag, nullptr);
+  dev_free(inst->d_jf32, nullptr);
+  dev_free(inst->d_h, nullptr);
+  delete inst;
+}
+
+pim_status pim_batch_create(pim_instance* const* insts, int32_t count, int32_t trials,
+                            const int8_t* init_spins, void* stream, pim_batch** out) {
+  try {
+    if (!out) return fail(PIM_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!insts || count < 1) return fail(PIM_ERR_INVALID, "need at least one instance");
+    if (trials < 1 || trials > (1 << 24)) return fail(PIM_ERR_INVALID, "trials = %d outside [1, 2^24]", trials);
+    if (count > 65535) return fail(PIM_ERR_INVALID, "count = %d exceeds 65535", count);
+    for (int k = 0; k < count; ++k) {
+      if (!insts[k]) return fail(PIM_ERR_INVALID, "instance %d is NULL", k);
+      if (insts[k]->rule.n != insts[0]->rule.n)
+        return fail(PIM_ERR_UNSUPPORTED, "instances of different N in one batch (%d vs %d)", insts[k]->rule.n,
+                    insts[0]->rule.n);
+    }
+    const int n = insts[0]->rule.n;
+    if (init_spins) {
+      pim_status st = check_spins(init_spins, (size_t)count * trials * n);
+      if (st != PIM_OK) return st;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    auto* b = new pim_batch();
+    b->insts.assign(insts, insts + count);
+    b->count = count;
+    b->R = trials;
+    b->n = n;
+    b->nt = insts[0]->nt;
+    b->npad = insts[0]->npad;
+    b->stream = s;
+    for (int k = 0; k < count; ++k) b->has_h |= insts[k]->has_h;
+    // table classes: instances whose compiled tables coincide share one
+    b->inst_class.resize(count);
+    for (int k = 0; k < count; ++k) {
+      int cls = -1;
+      for (size_t c = 0; c < b->class_rep.size(); ++c)
+        if (insts[b->class_rep[c]]->rule.same_table_class(insts[k]->rule)) { cls = (int)c; break; }
+      if (cls < 0) {
+        cls = (int)b->class_rep.size();
+        b->class_rep.push_back(k);
+      }
+      b->inst_class[k] = cls;
+    }
+    const size_t frag = (size_t)b->nt * b->nt * 1024;
+    const size_t cells = (size_t)count * trials;
+    pim_status st = alloc_dev(&b->d_jfrag, frag * count, s);
+    if (st == PIM_OK) st = alloc_dev(&b->d_h, (size_t)count * b->npad, s);
+    if (st == PIM_OK) st = alloc_dev(&b->d_final, cells * b->npad, s);
+    if (st == PIM_OK) st = alloc_dev(&b->d_best, cells * b->npad, s);
+    if (st == PIM_OK) st = alloc_dev(&b->d_stats, cells * 5, s);
+    if (st == PIM_OK) st = alloc_dev(&b->d_class, (size_t)count, s);
+    if (st == PIM_OK) st = alloc_dev(&b->d_stream_ids, (size_t)count, s);
+    if (st == PIM_OK) st = alloc_dev(&b->d_target, (size_t)count, s);
+    if (st == PIM_OK) st = alloc_dev(&b->d_rerank, cells, s);
+    if (st == PIM_OK && init_spins) st = alloc_dev(&b->d_init, cells * b->npad, s);
+    if (st != PIM_OK) {
+      free_batch_buffers(b);
+      delete b;
+      return st;
+    }
+    hipError_t e = hipHostMalloc((void**)&b->h_cancel, sizeof(int32_t), hipHostMallocMapped | hipHostMallocCoherent);
+    if (e == hipSuccess) {
+      *b->h_cancel = 0;
+      e = hipHostGetDevicePointer((void**)&b->d_cancel, b->h_cancel, 0);
+    }
+    if (e == hipSuccess) e = hipEventCreate(&b->ev0);
+    if (e == hipSuccess) e = hipEventCreate(&b->ev1);
+    std::vector<uint32_t> sid(count);
+    for (int k = 0; k < count; ++k) sid[k] = insts[k]->rule.stream;
+    for (int k = 0; k < count && e == hipSuccess; ++k) {
+      e = hipMemcpyAsync(b->d_jfrag + frag * k, insts[k]->d_jfrag, frag, hipMemcpyDeviceToDevice, s);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(b->d_h + (size_t)k * b->npad, insts[k]->d_h, b->npad * 4, hipMemcpyDeviceToDevice, s);
+    }
+    if (e == hipSuccess) e = hipMemcpyAsync(b->d_class, b->inst_class.data(), count * 4, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(b->d_stream_ids, sid.data(), count * 4, hipMemcpyHostToDevice, s);
+    std::vector<int8_t> init_pad;
+    if (e == hipSuccess && init_spins) {
+      init_pad.assign(cells * b->npad, (int8_t)1);
+      for (size_t c = 0; c < cells; ++c) std::memcpy(&init_pad[c * b->npad], init_spins + c * n, n);
+      e = hipMemcpyAsync(b->d_init, init_pad.data(), init_pad.size(), hipMemcpyHostToDevice, s);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+      free_batch_buffers(b);
+      delete b;
+      return fail(PIM_ERR_DEVICE, "batch setup failed: %s", hipGetErrorString(e));
+    }
+    *out = b;
+    return PIM_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(PIM_ERR_NOMEM, "host allocation failed");
+  } catch (...) {
+    return fail(PIM_ERR_INVALID, "internal error in pim_batch_create");
+  }
+}
+
+void pim_batch_destroy(pim_batch* b) {
+  if (!b) return;
+  if (b->stream || true) (void)hipStreamSynchronize(b->stream);
+  free_batch_buffers(b);
+  delete b;
+}
+
+pim_status pim_cancel(pim_batch* b) {
+  if (!b || !b->h_cancel) return fail(PIM_ERR_INVALID, "batch is NULL");
+  __atomic_store_n(b->h_cancel, 1, __ATOMIC_SEQ_CST);
+  return PIM_OK;
+}
+
+pim_status pim_run(pim_batch* b, const pim_schedule* sc, uint64_t seed, void* stream) {
+  try {
+    if (!b) return fail(PIM_ERR_INVALID, "batch is NULL");
+    if (b->sticky_error) return fail(PIM_ERR_DEVICE, "batch is in an error state after a failed device call");
+    if (!sc) return fail(PIM_ERR_INVALID, "schedule is NULL");
+    if (sc->steps < 1) return fail(PIM_ERR_INVALID, "steps must be >= 1");
+    if (!sc->beta || !sc->eta) return fail(PIM_ERR_INVALID, "beta and eta must be non-NULL");
+    if (sc->start_step < 0 || (int64_t)sc->start_step + sc->steps >= (int64_t)1 << 31)
+      return fail(PIM_ERR_INVALID, "start_step + steps must lie in [0, 2^31)");
+    if (sc->kernel != PIM_KERNEL_MFMA_I8 && sc->kernel != PIM_KERNEL_PLAIN_F32)
+      return fail(PIM_ERR_INVALID, "unknown kernel %d", sc->kernel);
+    if (sc->use_target && !sc->target) return fail(PIM_ERR_INVALID, "use_target set without target energies");
+    const int T = sc->steps;
+    for (int t = 0; t < T; ++t)
+      if (!finite_nonneg(sc->beta[t]) || !finite_nonneg(sc->eta[t]))
+        return fail(PIM_ERR_INVALID, "beta[%d] / eta[%d] must be finite and >= 0", t, t);
+    std::vector<int32_t> tgt(b->count, INT32_MIN);
+    if (sc->use_target)
+      for (int k = 0; k < b->count; ++k)
+        tgt[k] = (int32_t)std::max<int64_t>(std::min<int64_t>(sc->target[k], INT32_MAX), INT32_MIN + 1);
+    hipStream_t s = stream ? (hipStream_t)stream : b->stream;
+    b->stream = s;
+    const int L = b->insts[0]->rule.levels;
+    const int ncls = (int)b->class_rep.size();
+    // ---- compile ----
+    std::vector<int32_t> theta(kMaxLevels), umin(2 * kMaxLevels);
+    std::vector<int16_t> thtab;
+    std::vector<int32_t> steptab;
+    const bool mfma = sc->kernel == PIM_KERNEL_MFMA_I8;
+    if (mfma) {
+      thtab.resize((size_t)ncls * T * kTabEntries);
+      for (int c = 0; c < ncls; ++c) {
+        const Rule& r = b->insts[b->class_rep[c]]->rule;
+        for (int t = 0; t < T; ++t) {
+          compile_step(r, sc->beta[t], sc->eta[t], theta.data(), umin.data());
+          theta_by_noise(theta.data(), umin.data(), r.levels, &thtab[((size_t)c * T + t) * kTabEntries]);
+        }
+      }
+    } else {
+      for (int k = 0; k < b->count; ++k)
+        if (b->insts[k]->rule.levels != L)
+          return fail(PIM_ERR_UNSUPPORTED, "the plain kernel needs one LUT size per batch");
+      const int w = (L - 1) + 2 * L;
+      steptab.resize((size_t)ncls * T * w);
+      for (int c = 0; c < ncls; ++c) {
+        const Rule& r = b->insts[b->class_rep[c]]->rule;
+        for (int t = 0; t < T; ++t) {
+          int32_t* row = &steptab[((size_t)c * T + t) * w];
+          compile_step(r, sc->beta[t], sc->eta[t], row, row + (L - 1));
+        }
+      }
+    }
+    // ---- upload ----
+    if (mfma && thtab.size() * 2 > b->thtab_bytes) {
+      dev_free(b->d_thtab, s);
+      b->d_thtab = nullptr;
+      b->thtab_bytes = 0;
+      pim_status st = alloc_dev(&b->d_thtab, thtab.size(), s);
+      if (st != PIM_OK) return st;
+      b->thtab_bytes = thtab.size() * 2;
+    }
+    if (!mfma && steptab.size() * 4 > b->steptab_bytes) {
+      dev_free(b->d_steptab, s);
+      b->d_steptab = nullptr;
+      b->steptab_bytes = 0;
+      pim_status st = alloc_dev(&b->d_steptab, steptab.size(), s);
+      if (st != PIM_OK) return st;
+      b->steptab_bytes = steptab.size() * 4;
+    }
+    auto device_fail = [&](hipError_t e, const char* what) {
+      b->sticky_error = true;
+      return fail(PIM_ERR_DEVICE, "%s failed: %s", what, hipGetErrorString(e));
+    };
+    hipError_t e = hipSuccess;
+    if (mfma) e = hipMemcpyAsync(b->d_thtab, thtab.data(), thtab.size() * 2, hipMemcpyHostToDevice, s);
+    else e = hipMemcpyAsync(b->d_steptab, steptab.data(), steptab.size() * 4, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(b->d_target, tgt.data(), b->count * 4, hipMemcpyHostToDevice, s);
+    // the host tables must stay alive until the copies are done
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return device_fail(e, "schedule upload");
+    __atomic_store_n(b->h_cancel, 0, __ATOMIC_SEQ_CST);
+    // ---- launch ----
+    e = hipEventRecord(b->ev0, s);
+    if (e != hipSuccess) return device_fail(e, "hipEventRecord");
+    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    if (mfma) {
+      SweepArgs a{};
+      a.jfrag = b->d_jfrag;
+      a.h = b->has_h ? b->d_h : nullptr;
+      a.thtab = b->d_thtab;
+      a.inst_class = b->d_class;
+      a.inst_stream = b->d_stream_ids;
+      a.target = sc->use_target ? b->d_target : nullptr;
+      a.init = b->d_init;
+      a.final_s = b->d_final;
+      a.best_s = b->d_best;
+      a.e_best = stat_ptr(b, 0);
+      a.t_best = stat_ptr(b, 1);
+      a.first_hit = stat_ptr(b, 2);
+      a.e_final = stat_ptr(b, 3);
+      a.steps_done = stat_ptr(b, 4);
+      a.cancel = b->d_cancel;
+      a.n = b->n;
+      a.npad = b->npad;
+      a.R = b->R;
+      a.T = T;
+      a.start_step = sc->start_step;
+      a.k0 = k0;
+      a.k1 = k1;
+      e = launch_sweep_mfma(a, b->count, b->nt, b->has_h, s);
+      if (e != hipSuccess) return device_fail(e, "sweep launch");
+    } else {
+      const int w = (L - 1) + 2 * L;
+      for (int k = 0; k < b->count && e == hipSuccess; ++k) {
+        const size_t cell0 = (size_t)k * b->R;
+        PlainArgs a{};
+        a.jf32 = b->insts[k]->d_jf32;
+        a.h = b->insts[k]->has_h ? b->insts[k]->d_h : nullptr;
+        a.steptab = b->d_steptab + (size_t)b->inst_class[k] * T * w;
+        a.init = b->d_init ? b->d_init + cell0 * b->npad : nullptr;
+        a.final_s = b->d_final + cell0 * b->npad;
+        a.best_s = b->d_best + cell0 * b->npad;
+        a.e_best = stat_ptr(b, 0) + cell0;
+        a.t_best = stat_ptr(b, 1) + cell0;
+        a.first_hit = stat_ptr(b, 2) + cell0;
+        a.e_final = stat_ptr(b, 3) + cell0;
+        a.steps_done = stat_ptr(b, 4) + cell0;
+        a.cancel = b->d_cancel;
+        a.n = b->n;
+        a.npad = b->npad;
+        a.R = b->R;
+        a.T = T;
+        a.start_step = sc->start_step;
+        a.levels = L;
+        a.use_target = sc->use_target ? 1 : 0;
+        a.target = tgt[k];
+        a.stream = b->insts[k]->rule.stream;
+        a.k0 = k0;
+        a.k1 = k1;
+        e = launch_sweep_plain(a, s);
+      }
+      if (e != hipSuccess) return device_fail(e, "plain sweep launch");
+    }
+    e = hipEventRecord(b->ev1, s);
+    if (e != hipSuccess) return device_fail(e, "hipEventRecord");
+    b->ran = true;
+    b->reranked = false;
+    b->last_T = T;
+    b->last_start = sc->start_step;
+    return PIM_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(PIM_ERR_NOMEM, "host allocation failed");
+  } catch (...) {
+    return fail(PIM_ERR_INVALID, "internal error in pim_run");
+  }
+}
+
+pim_status pim_kernel_time(pim_batch* b, float* ms) {
+  if (!b || !ms) return fail(PIM_ERR_INVALID, "NULL argument");
+  if (!b->ran) return fail(PIM_ERR_STATE, "no run has been issued on this batch");
+  HIP_TRY(hipEventSynchronize(b->ev1));
+  HIP_TRY(hipEventElapsedTime(ms, b->ev0, b->ev1));
+  return PIM_OK;
+}
+
+pim_status pim_energy(const pim_instance* inst, const int8_t* spins, int32_t count, double* out, void* stream) {
+  try {
+    if (!inst || !spins || !out) return fail(PIM_ERR_INVALID, "NULL argument");
+    if (count < 1) return fail(PIM_ERR_INVALID, "count must be >= 1");
+    const int n = inst->rule.n;
+    pim_status st = check_spins(spins, (size_t)count * n);
+    if (st != PIM_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    int8_t* d_s = nullptr;
+    double* d_o = nullptr;
+    st = alloc_dev(&d_s, (size_t)count * n, s);
+    if (st == PIM_OK) st = alloc_dev(&d_o, (size_t)count, s);
+    if (st != PIM_OK) {
+      dev_free(d_s, s);
+      return st;
+    }
+    EnergyArgs ea{};
+    ea.jf32 = inst->d_jf32;
+    ea.h = inst->has_h ? inst->d_h : nullptr;
+    ea.spins = d_s;
+    ea.out = d_o;
+    ea.n = n;
+    ea.stride = n;
+    ea.count = count;
+    hipError_t e = hipMemcpyAsync(d_s, spins, (size_t)count * n, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = launch_energy_f64(ea, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(out, d_o, (size_t)count * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    dev_free(d_s, s);
+    dev_free(d_o, s);
+    if (e != hipSuccess) return fail(PIM_ERR_DEVICE, "pim_energy failed: %s", hipGetErrorString(e));
+    return PIM_OK;
+  } catch (...) {
+    return fail(PIM_ERR_INVALID, "internal error in pim_energy");
+  }
+}
+
+pim_status pim_best(pim_batch* b, int32_t inst, int8_t* spins_out, double* e_out, int32_t* trial_out,
+                    int32_t* step_out) {
+  try {
+    pim_status st = check_batch_ready(b, inst);
+    if (st != PIM_OK) return st;
+    st = ensure_rerank(b);
+    if (st != PIM_OK) {
+      b->sticky_error = true;
+      return st;
+    }
+    const double* e = &b->h_rerank[(size_t)inst * b->R];
+    int best = 0;
+    for (int a = 1; a < b->R; ++a)
+      if (e[a] < e[best]) best = a;  // ties keep the lowest trial id
+    const size_t cell = (size_t)inst * b->R + best;
+    int32_t tb = 0, eb = 0;
+    HIP_TRY(hipMemcpyAsync(&tb, stat_ptr(b, 1) + cell, 4, hipMemcpyDeviceToHost, b->stream));
+    HIP_TRY(hipMemcpyAsync(&eb, stat_ptr(b, 0) + cell, 4, hipMemcpyDeviceToHost, b->stream));
+    std::vector<int8_t> sp(b->npad);
+    HIP_TRY(hipMemcpyAsync(sp.data(), b->d_best + cell * b->npad, b->npad, hipMemcpyDeviceToHost, b->stream));
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    if ((double)eb != e[best])
+      return fail(PIM_ERR_DEVICE, "tracked energy %d disagrees with the binary64 re-evaluation %.17g", eb, e[best]);
+    if (spins_out) std::memcpy(spins_out, sp.data(), b->n);
+    if (e_out) *e_out = e[best];
+    if (trial_out) *trial_out = best;
+    if (step_out) *step_out = tb;
+    return cancelled_status(b, inst);
+  } catch (...) {
+    return fail(PIM_ERR_INVALID, "internal error in pim_best");
+  }
+}
+
+pim_status pim_trials(pim_batch* b, int32_t inst, double* best_e, int32_t* best_step, int32_t* first_hit,
+                      double* final_e, int8_t* best_spins, int8_t* final_spins) {
+  try {
+    pim_status st = check_batch_ready(b, inst);
+    if (st != PIM_OK) return st;
+    const int R = b->R;
+    const size_t cell0 = (size_t)inst * R;
+    std::vector<int32_t> tmp(R);
+    auto fetch = [&](int which, std::vector<int32_t>& dst) -> pim_status {
+      HIP_TRY(hipMemcpyAsync(dst.data(), stat_ptr(b, which) + cell0, R * 4, hipMemcpyDeviceToHost, b->stream));
+      HIP_TRY(hipStreamSynchronize(b->stream));
+      return PIM_OK;
+    };
+    if (best_e) {
+      if ((st = fetch(0, tmp)) != PIM_OK) return st;
+      for (int a = 0; a < R; ++a) best_e[a] = tmp[a];
+    }
+    if (best_step) {
+      if ((st = fetch(1, tmp)) != PIM_OK) return st;
+      std::copy(tmp.begin(), tmp.end(), best_step);
+    }
+    if (first_hit) {
+      if ((st = fetch(2, tmp)) != PIM_OK) return st;
+      std::copy(tmp.begin(), tmp.end(), first_hit);
+    }
+    if (final_e) {
+      if ((st = fetch(3, tmp)) != PIM_OK) return st;
+      for (int a = 0; a < R; ++a) final_e[a] = tmp[a];
+    }
+    if (best_spins || final_spins) {
+      std::vector<int8_t> sp((size_t)R * b->npad);
+      for (int which = 0; which < 2; ++which) {
+        int8_t* dst = which ? final_spins : best_spins;
+        if (!dst) continue;
+        const int8_t* src = (which ? b->d_final : b->d_best) + cell0 * b->npad;
+        HIP_TRY(hipMemcpyAsync(sp.data(), src, sp.size(), hipMemcpyDeviceToHost, b->stream));
+        HIP_TRY(hipStreamSynchronize(b->stream));
+        for (int a = 0; a < R; ++a) std::memcpy(dst + (size_t)a * b->n, &sp[(size_t)a * b->npad], b->n);
+      }
+    }
+    return cancelled_status(b, inst);
+  } catch (...) {
+    return fail(PIM_ERR_INVALID, "internal error in pim_trials");
+  }
+}
+
+}  // extern "C"

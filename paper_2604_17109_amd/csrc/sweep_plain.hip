@@ -1,0 +1,153 @@
+// Plain FP32 PIMI sweep: one instance per launch, no matrix cores.
+//
+// Workgroup = 32 trials x (N/16 spin blocks); thread (b, a) owns spins
+// 16b..16b+15 of trial a.  Each step it forms the 16 local fields (Eq. (2))
+// with ordinary FP32 multiply-adds over J rows read from global memory and the
+// current spins kept in LDS, then applies the same integer-threshold form of
+// Eq. (4) as the MFMA kernel: k = #{j : I >= theta_j}, s' = +1 iff
+// u >= umin[2k + (s<0)].  FP32 sums of integers below 2^24 are exact, so both
+// kernels produce identical trajectories.
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cstdint>
+
+#include "internal.hpp"
+#include "philox.hpp"
+
+namespace pim {
+namespace {
+
+constexpr int kTrials = 32;
+constexpr int kBlocks = PIM_MAX_N / 16;  // spin blocks of 16
+constexpr int kThreads = kTrials * kBlocks;
+
+__global__ __launch_bounds__(kThreads) void sweep_plain_kernel(PlainArgs a) {
+  __shared__ float sS[PIM_MAX_N][kTrials];
+  __shared__ int32_t sE[kTrials];
+  const int b = threadIdx.x / kTrials;
+  const int al = threadIdx.x % kTrials;
+  const int trial = blockIdx.x * kTrials + al;
+  const bool live = trial < a.R;
+  const int nb = (a.n + 15) / 16;
+  const bool owner = b < nb;
+  const size_t cell = (size_t)trial;
+  const int L = a.levels;
+  const int w = (L - 1) + 2 * L;
+
+  // s(0)
+  if (owner) {
+    if (a.init) {
+      for (int q = 0; q < 16; ++q) {
+        const int i = 16 * b + q;
+        // clamped address: no load outside the trial's row even if speculated
+        const float v = (float)a.init[(live ? cell : 0) * a.npad + min(i, a.n - 1)];
+        sS[i][al] = (live && i < a.n) ? v : 1.0f;
+      }
+    } else {
+      const Ctr4 x = philox4x32_10(Ctr4{(uint32_t)b, 0u, (uint32_t)trial, (kDomainInit << 24) | a.stream}, a.k0, a.k1);
+      const uint32_t xw[4] = {x.x, x.y, x.z, x.w};
+      for (int q = 0; q < 16; ++q) {
+        const uint32_t u = (xw[q >> 2] >> (8 * (q & 3))) & 0xFFu;
+        sS[16 * b + q][al] = u >= 128u ? 1.0f : -1.0f;
+      }
+    }
+  }
+  if (threadIdx.x < kTrials) sE[threadIdx.x] = 0;
+  __syncthreads();
+
+  int32_t e_best = INT_MAX, t_best = -1, first_hit = -1, e_cur = 0;
+  int done = a.T;
+  for (int t = 0;; ++t) {
+    const int tg = a.start_step + t;
+    float I[16];
+    float s_old[16];
+    if (owner) {
+#pragma unroll
+      for (int q = 0; q < 16; ++q) I[q] = 0.0f;
+      for (int j = 0; j < a.n; ++j) {
+        const float sj = sS[j][al];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+          const int i = 16 * b + q;
+          const float jij = a.jf32[(size_t)min(i, a.n - 1) * a.n + j];
+          I[q] = fmaf((i < a.n) ? jij : 0.0f, sj, I[q]);
+        }
+      }
+      int32_t ep = 0;
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int i = 16 * b + q;
+        s_old[q] = sS[i][al];
+        const int hv = (a.h && i < a.n) ? a.h[min(i, a.n - 1)] : 0;
+        I[q] += (float)hv;
+        if (i < a.n) ep += (int32_t)s_old[q] * ((int32_t)I[q] + hv);
+      }
+      atomicAdd(&sE[al], ep);
+    }
+    __syncthreads();
+    const int32_t E = -(sE[al] / 2);
+    if (E < e_best) {
+      e_best = E;
+      t_best = tg;
+      if (owner && live)
+        for (int q = 0; q < 16; ++q) {
+          const int i = 16 * b + q;
+          if (i < a.npad) a.best_s[cell * a.npad + i] = (int8_t)s_old[q];
+        }
+    }
+    if (a.use_target && first_hit < 0 && E <= a.target) first_hit = tg;
+    e_cur = E;
+    if (t == a.T) break;
+    if ((t & 255) == 0 && __atomic_load_n(a.cancel, __ATOMIC_RELAXED) != 0) {
+      done = t;
+      break;
+    }
+    float s_new[16];
+    if (owner) {
+      const int32_t* row = a.steptab + (size_t)t * w;
+      const Ctr4 x = philox4x32_10(Ctr4{(uint32_t)b, (uint32_t)tg, (uint32_t)trial, (kDomainNoise << 24) | a.stream},
+                                   a.k0, a.k1);
+      const uint32_t xw[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        int k = 0;
+        for (int j = 0; j < L - 1; ++j) k += (I[q] >= (float)row[j]) ? 1 : 0;
+        const int sneg = s_old[q] < 0.0f ? 1 : 0;
+        const int umin = row[(L - 1) + 2 * k + sneg];
+        const int u = (int)((xw[q >> 2] >> (8 * (q & 3))) & 0xFFu);
+        s_new[q] = (u >= umin) ? 1.0f : -1.0f;
+      }
+    }
+    __syncthreads();  // every thread has read the old spins and E
+    if (owner)
+#pragma unroll
+      for (int q = 0; q < 16; ++q) sS[16 * b + q][al] = s_new[q];
+    if (threadIdx.x < kTrials) sE[threadIdx.x] = 0;
+    __syncthreads();
+  }
+
+  if (owner && live)
+    for (int q = 0; q < 16; ++q) {
+      const int i = 16 * b + q;
+      if (i < a.npad) a.final_s[cell * a.npad + i] = (int8_t)sS[i][al];
+    }
+  if (b == 0 && live) {
+    a.e_best[cell] = e_best;
+    a.t_best[cell] = t_best;
+    a.first_hit[cell] = first_hit;
+    a.e_final[cell] = e_cur;
+    a.steps_done[cell] = done;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_sweep_plain(const PlainArgs& a, hipStream_t s) {
+  if (a.n > PIM_MAX_N) return hipErrorInvalidValue;
+  const dim3 grid((a.R + kTrials - 1) / kTrials);
+  hipLaunchKernelGGL(sweep_plain_kernel, grid, dim3(kThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace pim

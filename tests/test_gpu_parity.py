@@ -1,0 +1,197 @@
+"""GPU parity: the HIP kernels against the CPU oracle, element by element.
+
+Integer instances must reproduce the oracle bit for bit: final spins, best
+energy, its step, the state there, first hit, final energy.  Every case prints
+its name before touching the GPU.
+"""
+import numpy as np
+import pytest
+
+import workloads as w
+from oracle import pimi
+
+pytestmark = pytest.mark.gpu
+
+KERNELS = ["mfma", "plain"]
+
+
+def _say(msg):
+    print(f"\n[gpu-case] {msg}", flush=True)
+
+
+def _oracle(J, h, c, xi, L, ztab, beta, eta, seed, stream, trials, init=None, start=0, target=None):
+    prob = pimi.Problem(J, h, c=c, xi=xi, levels=L, ztab=ztab)
+    return pimi.run_parallel(prob, beta, eta, seed, stream, np.asarray(trials), init=init,
+                             start_step=start, target=target)
+
+
+def _compare(batch, k, ref, trials, n):
+    got = batch.trials_of(k)
+    idx = np.asarray(trials)
+    np.testing.assert_array_equal(got["final"][idx], ref["final"].T.astype(np.int8))
+    np.testing.assert_array_equal(got["e_best"][idx], ref["e_best"].astype(np.float64))
+    np.testing.assert_array_equal(got["t_best"][idx], ref["t_best"])
+    np.testing.assert_array_equal(got["best_state"][idx], ref["best_state"].T.astype(np.int8))
+    np.testing.assert_array_equal(got["first_hit"][idx], ref["first_hit"])
+    return got
+
+
+def _run_case(pim, kind, n, trials, steps, kernel, seed=7, count=1, xi=0.5, noise="gauss",
+              hmax=0, jmax=1, init=False, c=None, stream_base=3, beta1=3.0):
+    insts, probs = [], []
+    ztab = w.gauss_table(8) if noise == "gauss" else w.uniform_table(8)
+    for k in range(count):
+        if kind == "sk":
+            J, h = w.sk1(n, seed=seed, index=k)
+        elif kind == "maxcut":
+            J, h = w.maxcut(n, seed=seed, index=k)
+        else:
+            J, h = w.random_int8(n, seed=seed, index=k, jmax=jmax, hmax=hmax)
+        cc = c if c is not None else 1.0 / np.sqrt(n)
+        insts.append(pim.Instance(J, h, j_scale=cc, xi=xi, levels=4, noise_table=ztab,
+                                  rng_stream=stream_base + k))
+        probs.append((J, h, cc))
+    init_spins = None
+    if init:
+        init_spins = np.random.default_rng(seed).choice([-1, 1], size=(count, trials, n)).astype(np.int8)
+    beta = w.linear_beta(steps, 0.1, beta1)
+    eta = w.eta_sqrt_beta_over_5(beta)
+    batch = pim.Batch(insts, trials, init_spins=init_spins)
+    targets = []
+    for (J, h, cc) in probs:
+        targets.append(int(pimi.energy(J, h, np.ones(n, dtype=np.int64))) - 1)
+    batch.run(beta, eta, seed=seed, kernel=kernel, target=targets)
+    for k, (J, h, cc) in enumerate(probs):
+        ref = _oracle(J, h, cc, xi, 4, ztab, beta, eta, seed, stream_base + k, np.arange(trials),
+                      init=None if init_spins is None else init_spins[k].T.astype(np.int64),
+                      target=targets[k])
+        _compare(batch, k, ref, np.arange(trials), n)
+    return batch
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_sk20_config_parity(gpu_lib, kernel):
+    """SK-1 N=20, 64 trials x 1000 steps, beta linear 0.1 -> 3.0 (first
+    workload), four instances of the sixteen."""
+    _say(f"sk20 64x1000 kernel={kernel}")
+    _run_case(gpu_lib, "sk", 20, 64, 1000, kernel, seed=1, count=4)
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+@pytest.mark.parametrize("n,trials", [(1, 8), (31, 40), (32, 64), (33, 33), (200, 70), (256, 32)])
+def test_sizes_and_ragged_tails(gpu_lib, kernel, n, trials):
+    _say(f"sizes n={n} trials={trials} kernel={kernel}")
+    _run_case(gpu_lib, "maxcut" if n > 2 else "sk", n, trials, 120, kernel, seed=n, count=2)
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_general_int8_with_fields(gpu_lib, kernel):
+    _say(f"int8 couplings with h kernel={kernel}")
+    _run_case(gpu_lib, "int8", 45, 48, 200, kernel, seed=5, count=2, jmax=100, hmax=900, c=0.004, xi=0.3)
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_conventional_parallel_uniform_noise(gpu_lib, kernel):
+    _say(f"conventional parallel (xi=0, uniform) kernel={kernel}")
+    _run_case(gpu_lib, "sk", 60, 32, 150, kernel, seed=9, xi=0.0, noise="uniform")
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_caller_initial_spins(gpu_lib, kernel):
+    _say(f"caller initial spins kernel={kernel}")
+    _run_case(gpu_lib, "maxcut", 70, 36, 100, kernel, seed=11, count=2, init=True, xi=0.7)
+
+
+def test_resume_equals_uninterrupted(gpu_lib):
+    _say("resume 2 x 150 == 300")
+    pim = gpu_lib
+    n, R = 90, 64
+    J, h = w.sk1(n, seed=4)
+    ztab = w.gauss_table(8)
+    mk = lambda: pim.Instance(J, h, j_scale=1 / np.sqrt(n), xi=0.5, noise_table=ztab, rng_stream=2)
+    beta = w.linear_beta(300)
+    eta = w.eta_sqrt_beta_over_5(beta)
+    i0 = mk()
+    full = pim.Batch([i0], R).run(beta, eta, seed=3).trials_of(0)
+    a = pim.Batch([i0], R).run(beta[:150], eta[:150], seed=3).trials_of(0)
+    b = pim.Batch([i0], R, init_spins=a["final"][None]).run(beta[150:], eta[150:], seed=3,
+                                                             start_step=150).trials_of(0)
+    np.testing.assert_array_equal(b["final"], full["final"])
+    np.testing.assert_array_equal(np.minimum(a["e_best"], b["e_best"]), full["e_best"])
+
+
+def test_energy_f64_matches_eq1(gpu_lib):
+    _say("pim_energy binary64")
+    pim = gpu_lib
+    for n in (5, 64, 200, 256):
+        J, h = w.random_int8(n, seed=n, jmax=60 if n < 100 else 1, hmax=50)
+        inst = pim.Instance(J, h, j_scale=0.01, xi=0.5)
+        S = np.random.default_rng(n).choice([-1, 1], size=(37, n)).astype(np.int8)
+        got = inst.energy(S)
+        want = pimi.energy(J, h, S.T.astype(np.int64)).astype(np.float64)
+        np.testing.assert_array_equal(got, want)
+
+
+def test_best_is_lowest_trial_argmin(gpu_lib):
+    _say("pim_best argmin")
+    pim = gpu_lib
+    n, R = 24, 96
+    J, h = w.sk1(n, seed=12)
+    inst = pim.Instance(J, h, j_scale=1 / np.sqrt(n), xi=0.5, noise_table=w.gauss_table(8))
+    batch = pim.Batch([inst], R)
+    beta = w.linear_beta(400)
+    batch.run(beta, w.eta_sqrt_beta_over_5(beta), seed=5)
+    tr = batch.trials_of(0)
+    spins, e, trial, step = batch.best(0)
+    assert e == tr["e_best"].min()
+    assert trial == int(np.flatnonzero(tr["e_best"] == e)[0])
+    assert step == tr["t_best"][trial]
+    np.testing.assert_array_equal(spins, tr["best_state"][trial])
+    assert pimi.energy(J, h, spins.astype(np.int64)) == e
+
+
+def test_cancel_reports_partial_results(gpu_lib):
+    _say("cancel")
+    pim = gpu_lib
+    n, R = 64, 64
+    J, h = w.sk1(n, seed=2)
+    inst = pim.Instance(J, h, j_scale=1 / np.sqrt(n), xi=0.5)
+    batch = pim.Batch([inst], R)
+    T = 200000
+    beta = np.full(T, 1.0)
+    batch.run(beta, np.full(T, 0.4), seed=1)
+    batch.cancel()
+    with pytest.raises(pim.PimError) as ei:
+        batch.trials_of(0)
+    assert ei.value.status == pim.PIM_ERR_CANCELLED
+    # a new run on the same batch clears the request and completes
+    batch.run(beta[:50], np.full(50, 0.4), seed=1)
+    batch.trials_of(0)
+
+
+def test_full_size_maxcut200_sampled_trials(gpu_lib):
+    """Max-Cut N=200, 1024 trials x 10^4 steps (second workload) in the launch
+    configuration the benchmark uses; the oracle recomputes three sampled
+    trials in full, and every trial's best state must have the energy the
+    kernel tracked."""
+    _say("maxcut200 1024x10000 mfma, sampled oracle trials")
+    pim = gpu_lib
+    n, R, T = 200, 1024, 10000
+    J, h = w.maxcut(n, seed=1, index=0)
+    ztab = w.gauss_table(8)
+    c = 2.0 / np.sqrt(n)
+    inst = pim.Instance(J, h, j_scale=c, xi=0.7, noise_table=ztab, rng_stream=0)
+    beta = w.linear_beta(T)
+    eta = w.eta_sqrt_beta_over_5(beta)
+    batch = pim.Batch([inst], R)
+    batch.run(beta, eta, seed=1, kernel="mfma")
+    got = batch.trials_of(0)
+    sample = np.array([0, 517, 1023])
+    ref = _oracle(J, h, c, 0.7, 4, ztab, beta, eta, 1, 0, sample)
+    np.testing.assert_array_equal(got["final"][sample], ref["final"].T.astype(np.int8))
+    np.testing.assert_array_equal(got["e_best"][sample], ref["e_best"])
+    np.testing.assert_array_equal(got["t_best"][sample], ref["t_best"])
+    e_states = pimi.energy(J, h, got["best_state"].T.astype(np.int64))
+    np.testing.assert_array_equal(e_states, got["e_best"])
+    e_final = pimi.energy(J, h, got["final"].T.astype(np.int64))
+    np.testing.assert_array_equal(e_final, got["e_final"])
