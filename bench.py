@@ -1,0 +1,157 @@
+"""Benchmark: batched PIMI sweep on SK-1 N=200 on one MI355X.
+
+One step = the whole hot path over one batch: host schedule compile and
+upload, the persistent int8-MFMA sweep of every trial of every instance,
+the binary64 re-rank of every trial's best state, and the per-instance argmin
+readout.  The instances are staged in device memory before the timed region.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Prints one JSON line.  Workload defaults: 128 SK-1 instances of N = 200
+(J = +-1, h = 0), 1024 trials each, 10^4 synchronous steps, beta linear
+0.1 -> 3.0, eta = sqrt(beta / 5), xi = 0.5, c = 1/sqrt(N), 4-level LUT, 8-bit
+Gaussian noise.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+INT8_MFMA_PEAK = 5.0e15            # dense int8 MFMA, ops/s (MI355X)
+VALU_PEAK = 256 * 4 * 16 * 2.4e9   # 32-bit VALU lane-ops/s: CUs x SIMDs x lanes x clock
+HBM_PEAK = 8.0e12
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--instances", type=int, default=128)
+    ap.add_argument("--trials", type=int, default=1024)
+    ap.add_argument("--sweeps", type=int, default=10000, help="update steps T per trial")
+    ap.add_argument("--n", type=int, default=200)
+    ap.add_argument("--kernel", default="mfma", choices=["mfma", "plain"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-trials", type=int, default=128)
+    ap.add_argument("--cpu-steps", type=int, default=2000)
+    return ap.parse_args()
+
+
+def cpu_baseline(n, trials, steps, xi, c):
+    """The oracle as it stands, on one SK-1 instance: `trials` trials for the
+    first `steps` steps of the same schedule (per-step cost is constant)."""
+    import workloads as w
+    from oracle import pimi
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:  # noqa: BLE001
+        threads = os.cpu_count() or 1
+    J, h = w.sk1(n, seed=1, index=0)
+    beta = w.linear_beta(10000)[:steps]
+    eta = w.eta_sqrt_beta_over_5(beta)
+    prob = pimi.Problem(J, h, c=c, xi=xi, levels=4, ztab=w.gauss_table(8))
+    t0 = time.perf_counter()
+    pimi.run_parallel(prob, beta, eta, 1, 0, np.arange(trials))
+    dt = time.perf_counter() - t0
+    return {"value": trials * steps * n / dt, "unit": "spin-updates/s", "cores": int(threads),
+            "kind": "oracle",
+            "sample": f"SK-1 N={n} instance 0, {trials} trials x first {steps} of the 10^4 steps "
+                      f"({dt:.1f} s, NumPy binary64 on the host)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the sweep shards by "
+              "instance and trial with no exchange, see DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2604_17109_amd as pim
+    import workloads as w
+
+    torch.cuda.set_device(0)
+    n, R, T, I = args.n, args.trials, args.sweeps, args.instances
+    xi, c = 0.5, 1.0 / math.sqrt(n)
+    ztab = w.gauss_table(8)
+    insts = [pim.Instance(*w.sk1(n, seed=1, index=k), j_scale=c, xi=xi, levels=4, noise_table=ztab,
+                          rng_stream=k) for k in range(I)]
+    batch = pim.Batch(insts, R)
+    beta = w.linear_beta(T, 0.1, 3.0)
+    eta = w.eta_sqrt_beta_over_5(beta)
+
+    def step(seed, target=None):
+        batch.run(beta, eta, seed=seed, kernel=args.kernel, target=target)
+        return [batch.best(k)[1] for k in range(I)]
+
+    # warmup: also fixes the reference energy per instance (best found)
+    ref = None
+    for wi in range(max(1, args.warmup)):
+        e = step(seed=1000 + wi)
+        ref = e if ref is None else [min(a, b) for a, b in zip(ref, e)]
+    target = [int(math.floor(0.999 * r)) for r in ref]  # relaxed success threshold, H < 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    kms = []
+    for si in range(args.steps):
+        step(seed=1, target=target)
+        kms.append(batch.kernel_ms())
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_per_step = 1000.0 * dt / args.steps
+    updates = float(I) * R * T * n
+    value = updates / (dt / args.steps)
+    kernel_ms = float(np.mean(kms))
+
+    # success statistics of the last timed run -> TTS99
+    hits = [batch.trials_of(k, spins=False)["first_hit"] for k in range(I)]
+    p_bar = float(np.mean([(fh >= 0).mean() for fh in hits]))
+    n99 = (1 if p_bar >= 1 else (math.inf if p_bar <= 0 else math.ceil(math.log(0.01) / math.log(1 - p_bar))))
+    tau = (kernel_ms / 1000.0) / (I * R * T)  # seconds per trial-step on the full batch
+    tts99 = n99 * T * tau if n99 != math.inf else None
+
+    # roofline of the sweep kernel (algorithmic counts per launch)
+    contractions = float(I) * R * (T + 1)
+    mfma_ops = 2.0 * n * n * contractions
+    alu_per_update = 6.75  # Philox share 60/16 + threshold read/compare 2 + energy 1
+    alu_ops = alu_per_update * updates
+    kernel_s = kernel_ms / 1000.0
+    line = {
+        "metric": "spin-updates/s (batched SK-1 N=200)",
+        "value": value,
+        "unit": "spin-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "i8",
+        "data": "synthetic",
+        "config": {"workload": f"SK-1 N={n}, {I} instances x {R} trials x {T} steps, kernel {args.kernel}",
+                   "instances": I, "trials": R, "steps_per_trial": T, "n": n, "parallelism": "single GPU"},
+        "kernel_ms": kernel_ms,
+        "tts99": {"p_bar": p_bar, "n99": n99 if n99 != math.inf else None, "tts99_s": tts99,
+                  "criterion": "E <= floor(0.999 * best energy of the warmup run)", "steps": T},
+        "roofline": {"bound": "alu", "achieved": alu_ops / kernel_s, "peak": VALU_PEAK, "unit": "lane-op/s",
+                     "frac": alu_ops / kernel_s / VALU_PEAK, "traffic": None,
+                     "algorithmic_per_update": alu_per_update},
+        "roofline_mfma": {"bound": "mfma", "achieved": mfma_ops / kernel_s / 1e12, "peak": INT8_MFMA_PEAK / 1e12,
+                          "unit": "TOP/s", "frac": mfma_ops / kernel_s / INT8_MFMA_PEAK},
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(n, args.cpu_trials, args.cpu_steps, xi, c)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()
