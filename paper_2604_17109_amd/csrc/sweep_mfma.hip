@@ -45,8 +45,39 @@ __device__ __forceinline__ int spins_from_bits(uint32_t w) {
   return (int)(0xFFFFFFFFu - 0xFEu * ((w >> 7) & 0x01010101u));
 }
 
-template <int NT, bool HAS_H>
-__global__ __launch_bounds__(64 * kWaves, (NT <= 4 ? 2 : 1)) void sweep_mfma_kernel(SweepArgs a) {
+// One Philox block of noise: counter (block, step, trial, stream) in the NOISE
+// domain; its 16 bytes are the noise indices of 16 consecutive spins.
+__device__ __forceinline__ Ctr4 noise_block(uint32_t block, int tg, uint32_t trial, uint32_t stream,
+                                            uint32_t k0, uint32_t k1) {
+  return philox4x32_10(Ctr4{block, (uint32_t)tg, trial, (kDomainNoise << 24) | stream}, k0, k1);
+}
+
+// Ordering fence for the instruction selector: the value passes through an
+// empty volatile asm, so arithmetic that depends on it cannot be hoisted above
+// this point (scheduling barriers only bind the later machine scheduler).
+// Emits no instruction.
+#define PIM_FENCE(v) asm volatile("" : "+v"(v))
+
+// I for row tile mt of the wave's CB x 32 trials: NT chained int8 MFMAs per
+// column block over the K tiles; each A fragment is read from LDS once and
+// used by every column block.
+template <int NT, int CB>
+__device__ __forceinline__ void mfma_row_tile(const v4i* sJl, int mt, const v4i (&B)[CB][NT], v16i (&acc)[CB]) {
+#pragma unroll
+  for (int c = 0; c < CB; ++c) acc[c] = v16i{};
+#pragma unroll
+  for (int kt = 0; kt < NT; ++kt) {
+    const v4i A = sJl[(mt * NT + kt) * 64];
+#pragma unroll
+    for (int c = 0; c < CB; ++c) acc[c] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A, B[c][kt], acc[c], 0, 0, 0);
+  }
+}
+
+// Each wave owns CB blocks of 32 trials.  Two independent blocks give the
+// in-order issue of one wave per SIMD enough independent work to keep the
+// vector ALU busy while MFMA chains and LDS lookups are in flight.
+template <int NT, int CB, bool HAS_H>
+__global__ __launch_bounds__(64 * kWaves, 2) void sweep_mfma_kernel(SweepArgs a) {
   extern __shared__ __align__(16) unsigned char lds[];
   constexpr int kFragBytes = NT * NT * 1024;
   constexpr int kNpad = NT * 32;
@@ -67,17 +98,23 @@ __global__ __launch_bounds__(64 * kWaves, (NT <= 4 ? 2 : 1)) void sweep_mfma_ker
     }
   }
   const v4i* sJ = reinterpret_cast<const v4i*>(lds);
-  // volatile: re-read h each step instead of pinning NT*16 registers for it
+  // volatile: re-read h each tile instead of pinning NT*16 registers for it
   const volatile int32_t* sH = reinterpret_cast<const volatile int32_t*>(lds + kFragBytes);
   int16_t* sTab = reinterpret_cast<int16_t*>(lds + kFragBytes + kHBytes + wave * 2 * kTabBytes);
   uint4* sTab4 = reinterpret_cast<uint4*>(sTab);
   __syncthreads();  // the only workgroup barrier
 
-  const int wblock = blockIdx.x * kWaves + wave;
-  if (wblock * 32 >= a.R) return;
-  const int trial = wblock * 32 + col;
-  const bool live = trial < a.R;
-  const size_t cell = (size_t)inst * a.R + trial;
+  const int tbase = (blockIdx.x * kWaves + wave) * 32 * CB;
+  if (tbase >= a.R) return;
+  int trial[CB];
+  bool live[CB];
+  size_t cell[CB];
+#pragma unroll
+  for (int c = 0; c < CB; ++c) {
+    trial[c] = tbase + 32 * c + col;
+    live[c] = trial[c] < a.R;
+    cell[c] = (size_t)inst * a.R + trial[c];
+  }
   const uint32_t stream = a.inst_stream[inst];
   const int cls = a.inst_class[inst];
   const uint4* gTab4 = reinterpret_cast<const uint4*>(a.thtab + (size_t)cls * a.T * kTabEntries);
@@ -85,115 +122,169 @@ __global__ __launch_bounds__(64 * kWaves, (NT <= 4 ? 2 : 1)) void sweep_mfma_ker
   const uint32_t k0 = a.k0, k1 = a.k1;
 
   // ---- s(0) ----
-  v4i B[NT];
+  v4i B[CB][NT];
 #pragma unroll
-  for (int mt = 0; mt < NT; ++mt) {
-    if (a.init) {
-      if (live) B[mt] = *reinterpret_cast<const v4i*>(a.init + cell * kNpad + 32 * mt + 16 * half);
-      else B[mt] = v4i{0x01010101, 0x01010101, 0x01010101, 0x01010101};
-    } else {
-      const Ctr4 x = philox4x32_10(Ctr4{(uint32_t)(2 * mt + half), 0u, (uint32_t)trial,
-                                        (kDomainInit << 24) | stream}, k0, k1);
-      B[mt] = v4i{spins_from_bits(x.x), spins_from_bits(x.y), spins_from_bits(x.z), spins_from_bits(x.w)};
+  for (int c = 0; c < CB; ++c)
+#pragma unroll
+    for (int mt = 0; mt < NT; ++mt) {
+      if (a.init) {
+        if (live[c]) B[c][mt] = *reinterpret_cast<const v4i*>(a.init + cell[c] * kNpad + 32 * mt + 16 * half);
+        else B[c][mt] = v4i{0x01010101, 0x01010101, 0x01010101, 0x01010101};
+      } else {
+        const Ctr4 x = philox4x32_10(Ctr4{(uint32_t)(2 * mt + half), 0u, (uint32_t)trial[c],
+                                          (kDomainInit << 24) | stream}, k0, k1);
+        B[c][mt] = v4i{spins_from_bits(x.x), spins_from_bits(x.y), spins_from_bits(x.z), spins_from_bits(x.w)};
+      }
     }
-  }
 
-  int32_t e_best = INT_MAX, t_best = -1, first_hit = -1, e_cur = 0;
+  int32_t e_best[CB], t_best[CB], first_hit[CB], e_cur[CB];
+  // noise block of the next row tile, carried across steps (tile 0 of step 0
+  // is drawn here so the step loop has no branch after its MFMA chains)
+  Ctr4 x_next[CB];
+#pragma unroll
+  for (int c = 0; c < CB; ++c) {
+    e_best[c] = INT_MAX;
+    t_best[c] = -1;
+    first_hit[c] = -1;
+    e_cur[c] = 0;
+    x_next[c] = noise_block((uint32_t)half, a.start_step, (uint32_t)trial[c], stream, k0, k1);
+  }
   int done = a.T;
   sTab4[lane] = gTab4[lane];  // table of step 0 into buffer 0
 
   for (int t = 0;; ++t) {
     const int tg = a.start_step + t;
-    // ---- Eq. (2): I = J s (+ h), one MFMA chain per row tile ----
-    v16i acc[NT];
-#pragma unroll
-    for (int mt = 0; mt < NT; ++mt) acc[mt] = v16i{};
-#pragma unroll
-    for (int kt = 0; kt < NT; ++kt) {
-#pragma unroll
-      for (int mt = 0; mt < NT; ++mt)
-        acc[mt] = __builtin_amdgcn_mfma_i32_32x32x32_i8(sJ[(mt * NT + kt) * 64 + lane], B[kt], acc[mt], 0, 0, 0);
-      // keep at most one K tile of A fragments in flight (register pressure)
-      __builtin_amdgcn_sched_barrier(0);
-    }
-    if (HAS_H) {
-#pragma unroll
-      for (int mt = 0; mt < NT; ++mt)
-#pragma unroll
-        for (int r = 0; r < 16; ++r) acc[mt][r] += sH[32 * mt + 16 * half + r];
-    }
-    // One pass over the 16*NT fields of the lane: the energy of s(t) (Eq. (1),
-    // E = -1/2 sum_i s_i (I_i + h_i)) and, unless t = T, the update to s(t+1)
-    // (Eq. (4)) into Bn.  B keeps s(t) until the best-state bookkeeping is done.
-    int32_t ep = 0;
-    v4i Bn[NT];
+    // Eq. (2) and Eq. (4), one row tile at a time and software-pipelined: the
+    // MFMA chains of tile mt+1 (I = J' s over all K tiles) are issued before
+    // the VALU work of tile mt, so the matrix core runs while the lanes decide
+    // the previous tile's spins.  Per tile: energy of s(t) (Eq. (1),
+    // E = -1/2 sum_i s_i (I_i + h_i)) and the update to s(t+1) into Bn; B
+    // keeps s(t) until the best-state bookkeeping is done.  At t = T only the
+    // energy is used (the update there reads a stale, in-bounds table and is
+    // discarded).
+    int32_t ep[CB];
+    v4i Bn[CB][NT];
     const bool last = (t == a.T);
-    uint4 nxt = uint4{0, 0, 0, 0};
     const bool has_next = t + 1 < a.T;
-    if (has_next) nxt = gTab4[(size_t)(t + 1) * 64 + lane];
-    if (last) {
+    // next step's table (clamped index: a branch-free, always in-bounds load)
+    const uint4 nxt = gTab4[(size_t)min(t + 1, a.T - 1) * 64 + lane];
+    // centre of this step's table: entry idx in [-256, 256) holds the field
+    // threshold for (u, s) with idx = u ^ s (s = +1 -> u ^ 1, s = -1 -> ~u)
+    const int16_t* tab = sTab + (t & 1) * kTabEntries + kNoiseVals;
+    uint32_t ctr_trial[CB];
+    uint32_t ctr_half = (uint32_t)half;
+    PIM_FENCE(ctr_half);
 #pragma unroll
-      for (int mt = 0; mt < NT; ++mt)
+    for (int c = 0; c < CB; ++c) {
+      ep[c] = 0;
+      ctr_trial[c] = (uint32_t)trial[c];
+      PIM_FENCE(ctr_trial[c]);
+    }
+    const v4i* sJl0 = sJ + lane;
+    v16i acc_next[CB];
+    mfma_row_tile<NT, CB>(sJl0, 0, B, acc_next);
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const int s = (int)(int8_t)((uint32_t)B[mt][r >> 2] >> (8 * (r & 3)));
-          int v = acc[mt][r];
-          if (HAS_H) v += sH[32 * mt + 16 * half + r];
-          ep += __mul24(s, v);
-        }
-    } else {
-      // centre of this step's table: entry idx in [-256, 256) holds the field
-      // threshold for (u, s) with idx = u ^ s (s = +1 -> u ^ 1, s = -1 -> ~u)
-      const int16_t* tab = sTab + (t & 1) * kTabEntries + kNoiseVals;
+    for (int mt = 0; mt < NT; ++mt) {
+      v16i acc[CB];
+      uint32_t xw[CB][4], bw[CB][4];
 #pragma unroll
-      for (int mt = 0; mt < NT; ++mt) {
-        const Ctr4 x = philox4x32_10(Ctr4{(uint32_t)(2 * mt + half), (uint32_t)tg, (uint32_t)trial,
-                                          (kDomainNoise << 24) | stream}, k0, k1);
-        const uint32_t xw[4] = {x.x, x.y, x.z, x.w};
+      for (int c = 0; c < CB; ++c) {
+        acc[c] = acc_next[c];
+        xw[c][0] = x_next[c].x; xw[c][1] = x_next[c].y; xw[c][2] = x_next[c].z; xw[c][3] = x_next[c].w;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          const uint32_t sw = (uint32_t)B[mt][q];
+          bw[c][q] = (uint32_t)B[c][mt][q];
+          PIM_FENCE(xw[c][q]);
+          PIM_FENCE(bw[c][q]);
+        }
+      }
+      const v4i* sJl = sJl0;
+      PIM_FENCE(sJl);
+      // (1) LDS: the field thresholds of this tile, indexed by u ^ s
+      int th[CB][16];
+#pragma unroll
+      for (int c = 0; c < CB; ++c)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int sv = (int)(int8_t)(bw[c][r >> 2] >> (8 * (r & 3)));
+          const int idx = (int)((xw[c][r >> 2] >> (8 * (r & 3))) & 0xFFu) ^ sv;
+          th[c][r] = tab[idx];
+        }
+      // (2) independent work that covers the LDS latency: the next tile's MFMA
+      //     chains and noise blocks (or the first blocks of the next step)
+      if (mt + 1 < NT) mfma_row_tile<NT, CB>(sJl, mt + 1, B, acc_next);
+#pragma unroll
+      for (int c = 0; c < CB; ++c) {
+        if (mt + 1 < NT) x_next[c] = noise_block(2u * (mt + 1) + ctr_half, tg, ctr_trial[c], stream, k0, k1);
+        else x_next[c] = noise_block(ctr_half, tg + 1, ctr_trial[c], stream, k0, k1);
+      }
+      // (3) energy of s(t) and the decisions of this tile
+#pragma unroll
+      for (int c = 0; c < CB; ++c)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
           int d[4];
 #pragma unroll
           for (int b = 0; b < 4; ++b) {
-            const int s = (int)(int8_t)(sw >> (8 * b));
-            const int I = acc[mt][4 * q + b];
-            int v = I;
-            if (HAS_H) v += sH[32 * mt + 16 * half + 4 * q + b];
-            ep += __mul24(s, v);  // |v| < 2^23: one full-rate 24-bit multiply-add
-            const int idx = (int)((xw[q] >> (8 * b)) & 0xFFu) ^ s;
-            d[b] = I - (int)tab[idx];  // >= 0  <=>  s(t+1) = +1
+            const int r = 4 * q + b;
+            const int sv = (int)(int8_t)(bw[c][q] >> (8 * b));
+            int I = acc[c][r];
+            int v;
+            if (HAS_H) {
+              const int hv = sH[32 * mt + 16 * half + r];
+              I += hv;
+              v = I + hv;
+            } else {
+              v = I;
+            }
+            ep[c] += __mul24(sv, v);  // |v| < 2^23: one full-rate 24-bit multiply-add
+            d[b] = I - th[c][r];      // >= 0  <=>  s(t+1) = +1
           }
           // sign bytes of d (0xFF where negative) via byte-permute sign
           // replication, then | 0x01 gives the int8 spins +1 / -1
           const uint32_t p01 = __builtin_amdgcn_perm((uint32_t)d[1], (uint32_t)d[0], 0x0C0C0B09u);
           const uint32_t p23 = __builtin_amdgcn_perm((uint32_t)d[3], (uint32_t)d[2], 0x0B090C0Cu);
-          Bn[mt][q] = (int)(p01 | p23 | 0x01010101u);
+          Bn[c][mt][q] = (int)(p01 | p23 | 0x01010101u);
         }
-        // one row tile's lookups in flight at a time (register pressure)
-        __builtin_amdgcn_sched_barrier(0);
-      }
-    }
-    ep += __shfl_xor(ep, 32);
-    const int32_t E = -(ep / 2);
-    if (E < e_best) {
-      e_best = E;
-      t_best = tg;
-      if (live) {
+      // fence the tile's results as well, so its decisions cannot be sunk
+      // past the next tiles' MFMA chains (which would keep every tile's
+      // accumulator live at once)
 #pragma unroll
-        for (int mt = 0; mt < NT; ++mt)
-          *reinterpret_cast<v4i*>(a.best_s + cell * kNpad + 32 * mt + 16 * half) = B[mt];
+      for (int c = 0; c < CB; ++c) {
+        PIM_FENCE(ep[c]);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) PIM_FENCE(Bn[c][mt][q]);
       }
+      __builtin_amdgcn_sched_barrier(0);
     }
-    if (first_hit < 0 && E <= target) first_hit = tg;
-    e_cur = E;
+#pragma unroll
+    for (int c = 0; c < CB; ++c) {
+      const int32_t epc = ep[c] + __shfl_xor(ep[c], 32);
+      const int32_t E = -(epc / 2);
+      if (E < e_best[c]) {
+        e_best[c] = E;
+        t_best[c] = tg;
+        if (live[c]) {
+          // address formed here (opaque base, immediate tile offsets) rather
+          // than hoisted per tile out of the step loop
+          int8_t* dst = a.best_s + cell[c] * kNpad + 16 * half;
+          PIM_FENCE(dst);
+#pragma unroll
+          for (int mt = 0; mt < NT; ++mt) *reinterpret_cast<v4i*>(dst + 32 * mt) = B[c][mt];
+        }
+      }
+      if (first_hit[c] < 0 && E <= target) first_hit[c] = tg;
+      e_cur[c] = E;
+    }
     if (last) break;
     if ((t & 255) == 0 && __atomic_load_n(a.cancel, __ATOMIC_RELAXED) != 0) {
       done = t;  // s(t) stays the final state
       break;
     }
 #pragma unroll
-    for (int mt = 0; mt < NT; ++mt) B[mt] = Bn[mt];
+    for (int c = 0; c < CB; ++c)
+#pragma unroll
+      for (int mt = 0; mt < NT; ++mt) B[c][mt] = Bn[c][mt];
     if (has_next) {
       sTab4[((t + 1) & 1) * 64 + lane] = nxt;
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -202,28 +293,33 @@ __global__ __launch_bounds__(64 * kWaves, (NT <= 4 ? 2 : 1)) void sweep_mfma_ker
     }
   }
 
-  if (live) {
+#pragma unroll
+  for (int c = 0; c < CB; ++c) {
+    if (!live[c]) continue;
 #pragma unroll
     for (int mt = 0; mt < NT; ++mt)
-      *reinterpret_cast<v4i*>(a.final_s + cell * kNpad + 32 * mt + 16 * half) = B[mt];
+      *reinterpret_cast<v4i*>(a.final_s + cell[c] * kNpad + 32 * mt + 16 * half) = B[c][mt];
     if (half == 0) {
-      a.e_best[cell] = e_best;
-      a.t_best[cell] = t_best;
-      a.first_hit[cell] = first_hit;
-      a.e_final[cell] = e_cur;
-      a.steps_done[cell] = done;
+      a.e_best[cell[c]] = e_best[c];
+      a.t_best[cell[c]] = t_best[c];
+      a.first_hit[cell[c]] = first_hit[c];
+      a.e_final[cell[c]] = e_cur[c];
+      a.steps_done[cell[c]] = done;
     }
   }
 }
 
+constexpr int kBlocksPerWave = 1;  // CB: 32-trial column blocks per wave
+
 template <int NT, bool HAS_H>
 hipError_t launch_nt(const SweepArgs& a, int count, hipStream_t s) {
   const size_t lds = (size_t)NT * NT * 1024 + (HAS_H ? NT * 32 * 4 : 0) + (size_t)kWaves * 2 * kTabBytes;
-  auto kern = sweep_mfma_kernel<NT, HAS_H>;
+  auto kern = sweep_mfma_kernel<NT, kBlocksPerWave, HAS_H>;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  const dim3 grid((a.R + 32 * kWaves - 1) / (32 * kWaves), count);
+  const int per_wg = 32 * kBlocksPerWave * kWaves;
+  const dim3 grid((a.R + per_wg - 1) / per_wg, count);
   hipLaunchKernelGGL(kern, grid, dim3(64 * kWaves), lds, s, a);
   return hipGetLastError();
 }
