@@ -194,6 +194,11 @@ pim_status pim_kernel_time(pim_batch* batch, float* ms);
 pim_status pim_compile_step(const pim_params* params, double beta, double eta,
                             int32_t* theta, int32_t* u_min);
 
+/* Host-only: the 512-entry table the MFMA kernel uses for one step:
+ * s(t+1) = +1 iff I >= table[256 + (u ^ s)] with s = +-1 as a two's-complement
+ * int (index 256 + (u ^ 1) for s = +1, 255 - u for s = -1).  table: int16[512]. */
+pim_status pim_compile_table(const pim_params* params, double beta, double eta, int16_t* table);
+
 void pim_batch_destroy(pim_batch* batch);
 void pim_destroy(pim_instance* inst);
 

@@ -32,7 +32,7 @@ _NOISES = {"gauss": NOISE_GAUSS, "uniform": NOISE_UNIFORM}
 # every symbol declared in include/pim.h
 EXPORTED = (
     "pim_set_allocator", "pim_create", "pim_batch_create", "pim_run", "pim_cancel",
-    "pim_energy", "pim_best", "pim_trials", "pim_kernel_time", "pim_compile_step",
+    "pim_energy", "pim_best", "pim_trials", "pim_kernel_time", "pim_compile_step", "pim_compile_table",
     "pim_batch_destroy", "pim_destroy", "pim_last_error", "pim_abi_version",
 )
 
@@ -74,7 +74,7 @@ _FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_voi
 
 def _load():
     if not os.path.exists(LIB_PATH):
-        raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_2604_17109_amd.build`")
+        raise ImportError(f"{LIB_PATH} is not built; run `python paper_2604_17109_amd/build.py`")
     lib = ctypes.CDLL(LIB_PATH)
     P, I32, F64, VP = ctypes.POINTER, ctypes.c_int32, ctypes.c_double, ctypes.c_void_p
     sig = {
@@ -88,6 +88,7 @@ def _load():
         "pim_trials": (I32, [VP, I32, P(F64), P(I32), P(I32), P(F64), P(ctypes.c_int8), P(ctypes.c_int8)]),
         "pim_kernel_time": (I32, [VP, P(ctypes.c_float)]),
         "pim_compile_step": (I32, [P(Params), F64, F64, P(I32), P(I32)]),
+        "pim_compile_table": (I32, [P(Params), F64, F64, P(ctypes.c_int16)]),
         "pim_batch_destroy": (None, [VP]),
         "pim_destroy": (None, [VP]),
         "pim_last_error": (ctypes.c_char_p, []),
@@ -209,6 +210,15 @@ def compile_step(n, j_scale, xi, beta, eta, levels=4, noise="gauss", noise_table
                                 _ptr(umin, ctypes.c_int32)))
     del keep
     return theta, umin
+
+
+def compile_table(n, j_scale, xi, beta, eta, levels=4, noise="gauss", noise_table=None):
+    """Host-only: the 512-entry (u, s) field-threshold table of one step."""
+    p, keep = make_params(n, j_scale, xi, levels, noise, noise_table)
+    tab = np.zeros(512, dtype=np.int16)
+    _check(lib.pim_compile_table(ctypes.byref(p), float(beta), float(eta), _ptr(tab, ctypes.c_int16)))
+    del keep
+    return tab
 
 
 class Instance:

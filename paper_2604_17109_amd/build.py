@@ -1,7 +1,7 @@
 """Builds libpim.so (the HIP kernels and the C-ABI host library) in-tree for
 gfx950 with hipcc.
 
-    python -m paper_2604_17109_amd.build      (from the repository root)
+    python paper_2604_17109_amd/build.py      (from the repository root)
 """
 import concurrent.futures
 import os

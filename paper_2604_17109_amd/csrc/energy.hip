@@ -1,7 +1,15 @@
-// Binary64 re-evaluation of Eq. (1) for candidate configurations: one
-// workgroup per configuration, E = -1/2 sum_i s_i (sum_j J_ij s_j + 2 h_i).
+// Binary64 evaluation of Eq. (1) for candidate configurations, and the
+// per-instance selection of the lowest-energy trial (the paper's host keeps
+// the lowest-energy configuration of all returned states).
+//
+// One wave per configuration.  Lanes own columns j (coalesced reads of each
+// coupling row), loop over rows i with s_i broadcast, and accumulate
+// s_i J_ij s_j in binary64; one wave reduction per configuration:
+//   E = -1/2 (sum_ij s_i J_ij s_j + 2 sum_i h_i s_i).
 #include <hip/hip_runtime.h>
 
+#include <cfloat>
+#include <climits>
 #include <cstdint>
 
 #include "internal.hpp"
@@ -9,26 +17,80 @@
 namespace pim {
 namespace {
 
-constexpr int kThreads = 256;
+constexpr int kWavesPerBlock = 4;
 
-__global__ __launch_bounds__(kThreads) void energy_f64_kernel(EnergyArgs a) {
-  __shared__ double part[kThreads / 64];
-  const int8_t* s = a.spins + (size_t)blockIdx.x * a.stride;
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+__device__ double config_energy(const float* J, const int32_t* h, const int8_t* s, int n, int lane) {
   double acc = 0.0;
-  for (int i = threadIdx.x; i < a.n; i += kThreads) {
-    double row = 0.0;
-    const float* Ji = a.jf32 + (size_t)i * a.n;
-    for (int j = 0; j < a.n; ++j) row += (double)Ji[j] * (double)s[j];
-    const double hv = a.h ? (double)a.h[i] : 0.0;
-    acc += (double)s[i] * (row + 2.0 * hv);
+  for (int i = 0; i < n; ++i) {
+    const double si = (double)s[i];
+    const float* Ji = J + (size_t)i * n;
+    for (int j = lane; j < n; j += 64) acc += si * (double)Ji[j] * (double)s[j];
   }
-  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off);
-  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
+  if (h)
+    for (int j = lane; j < n; j += 64) acc += 2.0 * (double)h[j] * (double)s[j];
+  return -0.5 * wave_sum(acc);
+}
+
+__global__ __launch_bounds__(64 * kWavesPerBlock) void energy_f64_kernel(EnergyArgs a) {
+  const int lane = threadIdx.x & 63;
+  const int cfg = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+  if (cfg >= a.count) return;
+  const double e = config_energy(a.jf32, a.h, a.spins + (size_t)cfg * a.stride, a.n, lane);
+  if (lane == 0) a.out[cfg] = e;
+}
+
+__global__ __launch_bounds__(64 * kWavesPerBlock) void rerank_kernel(RerankArgs a) {
+  const int lane = threadIdx.x & 63;
+  const int inst = blockIdx.y;
+  const int trial = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
+  if (trial >= a.R) return;
+  const size_t cell = (size_t)inst * a.R + trial;
+  const double e = config_energy(a.jf32[inst], a.h ? a.h[inst] : nullptr, a.best_s + cell * a.npad, a.n, lane);
+  if (lane == 0) a.energy[cell] = e;
+}
+
+// One block per instance: lowest binary64 energy, ties to the lowest trial;
+// gathers that trial's state, step and tracked integer energy.
+__global__ __launch_bounds__(256) void select_best_kernel(RerankArgs a) {
+  __shared__ double se[256];
+  __shared__ int st[256];
+  const int inst = blockIdx.x;
+  double best = DBL_MAX;
+  int arg = INT_MAX;
+  for (int r = threadIdx.x; r < a.R; r += 256) {
+    const double e = a.energy[(size_t)inst * a.R + r];
+    if (e < best || (e == best && r < arg)) {
+      best = e;
+      arg = r;
+    }
+  }
+  se[threadIdx.x] = best;
+  st[threadIdx.x] = arg;
   __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      const double e2 = se[threadIdx.x + w];
+      const int a2 = st[threadIdx.x + w];
+      if (e2 < se[threadIdx.x] || (e2 == se[threadIdx.x] && a2 < st[threadIdx.x])) {
+        se[threadIdx.x] = e2;
+        st[threadIdx.x] = a2;
+      }
+    }
+    __syncthreads();
+  }
+  const int bt = st[0];
+  const size_t cell = (size_t)inst * a.R + bt;
+  for (int i = threadIdx.x; i < a.npad; i += 256) a.out_spins[(size_t)inst * a.npad + i] = a.best_s[cell * a.npad + i];
   if (threadIdx.x == 0) {
-    double tot = 0.0;
-    for (int k = 0; k < kThreads / 64; ++k) tot += part[k];
-    a.out[blockIdx.x] = -0.5 * tot;
+    a.out_energy[inst] = se[0];
+    a.out_trial[inst] = bt;
+    a.out_step[inst] = a.t_best[cell];
+    a.out_tracked[inst] = a.e_best[cell];
   }
 }
 
@@ -36,7 +98,17 @@ __global__ __launch_bounds__(kThreads) void energy_f64_kernel(EnergyArgs a) {
 
 hipError_t launch_energy_f64(const EnergyArgs& a, hipStream_t s) {
   if (a.count < 1) return hipSuccess;
-  hipLaunchKernelGGL(energy_f64_kernel, dim3(a.count), dim3(kThreads), 0, s, a);
+  const dim3 grid((a.count + kWavesPerBlock - 1) / kWavesPerBlock);
+  hipLaunchKernelGGL(energy_f64_kernel, grid, dim3(64 * kWavesPerBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_rerank_select(const RerankArgs& a, hipStream_t s) {
+  const dim3 grid((a.R + kWavesPerBlock - 1) / kWavesPerBlock, a.count);
+  hipLaunchKernelGGL(rerank_kernel, grid, dim3(64 * kWavesPerBlock), 0, s, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(select_best_kernel, dim3(a.count), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

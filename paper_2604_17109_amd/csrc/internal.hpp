@@ -91,6 +91,22 @@ struct EnergyArgs {
   int32_t n, stride, count;
 };
 
+struct RerankArgs {
+  const float* const* jf32;    // [count] device pointers to each instance's J (n x n)
+  const int32_t* const* h;     // [count] device pointers to h, or nullptr (no fields)
+  const int8_t* best_s;        // [count][R][npad]
+  const int32_t* t_best;       // [count][R]
+  const int32_t* e_best;       // [count][R]
+  double* energy;              // [count][R] binary64 re-evaluation
+  int8_t* out_spins;           // [count][npad]
+  double* out_energy;          // [count]
+  int32_t* out_trial;          // [count]
+  int32_t* out_step;           // [count]
+  int32_t* out_tracked;        // [count]
+  int32_t n, npad, R, count;
+};
+
+hipError_t launch_rerank_select(const RerankArgs& a, hipStream_t s);
 hipError_t launch_sweep_mfma(const SweepArgs& a, int count, int nt, bool has_h, hipStream_t s);
 hipError_t launch_sweep_plain(const PlainArgs& a, hipStream_t s);
 hipError_t launch_energy_f64(const EnergyArgs& a, hipStream_t s);
@@ -126,8 +142,19 @@ struct pim_batch {
   uint32_t* d_stream_ids = nullptr;
   int32_t* d_target = nullptr;
   double* d_rerank = nullptr;     // [count][R]
+  // per-instance selection (device, then one readback): ptr tables + outputs
+  const float** d_jptrs = nullptr;
+  const int32_t** d_hptrs = nullptr;
+  int8_t* d_sel_spins = nullptr;  // [count][npad]
+  double* d_sel_e = nullptr;      // [count]
+  int32_t* d_sel_i = nullptr;     // [count][3]: trial, step, tracked energy
+  std::vector<int8_t> h_sel_spins;
+  std::vector<double> h_sel_e;
+  std::vector<int32_t> h_sel_i;
   int16_t* d_thtab = nullptr;
   size_t thtab_bytes = 0;
+  int16_t* h_thtab = nullptr;     // pinned staging of the step tables
+  size_t h_thtab_bytes = 0;
   int32_t* d_steptab = nullptr;
   size_t steptab_bytes = 0;
   int32_t* h_cancel = nullptr;    // pinned, host-mapped
@@ -139,5 +166,5 @@ struct pim_batch {
   // run state
   bool ran = false, reranked = false, sticky_error = false;
   int last_T = 0, last_start = 0;
-  std::vector<double> h_rerank;
+  int cancelled_checked = -1;     // -1 unknown, 0 complete, 1 cancelled
 };

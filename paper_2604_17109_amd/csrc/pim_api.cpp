@@ -10,6 +10,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "internal.hpp"
@@ -125,6 +126,24 @@ pim_status validate_couplings(const int8_t* J, const int32_t* h, int n) {
   return PIM_OK;
 }
 
+// Runs fn(lo, hi) over [0, n) on up to hardware_concurrency threads.
+template <typename F>
+void parallel_for(int n, F&& fn) {
+  const int hw = (int)std::max(1u, std::thread::hardware_concurrency());
+  const int nt = std::min(hw, std::max(1, n / 256));
+  if (nt <= 1) {
+    fn(0, n);
+    return;
+  }
+  std::vector<std::thread> pool;
+  const int chunk = (n + nt - 1) / nt;
+  for (int k = 0; k < nt; ++k) {
+    const int lo = k * chunk, hi = std::min(n, lo + chunk);
+    if (lo < hi) pool.emplace_back([&fn, lo, hi] { fn(lo, hi); });
+  }
+  for (auto& th : pool) th.join();
+}
+
 pim_status check_spins(const int8_t* s, size_t count) {
   for (size_t i = 0; i < count; ++i)
     if (s[i] != 1 && s[i] != -1) return fail(PIM_ERR_INVALID, "spin value %d at %zu is not +-1", (int)s[i], i);
@@ -145,30 +164,49 @@ void free_batch_buffers(pim_batch* b) {
   dev_free(b->d_rerank, s);
   dev_free(b->d_thtab, s);
   dev_free(b->d_steptab, s);
+  dev_free((void*)b->d_jptrs, s);
+  dev_free((void*)b->d_hptrs, s);
+  dev_free(b->d_sel_spins, s);
+  dev_free(b->d_sel_e, s);
+  dev_free(b->d_sel_i, s);
   if (b->h_cancel) (void)hipHostFree(b->h_cancel);
+  if (b->h_thtab) (void)hipHostFree(b->h_thtab);
   if (b->ev0) (void)hipEventDestroy(b->ev0);
   if (b->ev1) (void)hipEventDestroy(b->ev1);
 }
 
 int32_t* stat_ptr(pim_batch* b, int which) { return b->d_stats + (size_t)which * b->count * b->R; }
 
-// Re-evaluates every trial's best state in binary64 (once per run).
-pim_status ensure_rerank(pim_batch* b) {
+// Re-evaluates every trial's best state in binary64 and selects each
+// instance's lowest-energy trial on the device, then reads the selection back
+// in one go (once per run).
+pim_status ensure_selection(pim_batch* b) {
   if (b->reranked) return PIM_OK;
-  for (int k = 0; k < b->count; ++k) {
-    EnergyArgs ea{};
-    ea.jf32 = b->insts[k]->d_jf32;
-    ea.h = b->insts[k]->has_h ? b->insts[k]->d_h : nullptr;
-    ea.spins = b->d_best + (size_t)k * b->R * b->npad;
-    ea.out = b->d_rerank + (size_t)k * b->R;
-    ea.n = b->n;
-    ea.stride = b->npad;
-    ea.count = b->R;
-    HIP_TRY(launch_energy_f64(ea, b->stream));
-  }
-  b->h_rerank.resize((size_t)b->count * b->R);
-  HIP_TRY(hipMemcpyAsync(b->h_rerank.data(), b->d_rerank, b->h_rerank.size() * sizeof(double),
-                         hipMemcpyDeviceToHost, b->stream));
+  RerankArgs ra{};
+  ra.jf32 = b->d_jptrs;
+  ra.h = b->has_h ? b->d_hptrs : nullptr;
+  ra.best_s = b->d_best;
+  ra.t_best = stat_ptr(b, 1);
+  ra.e_best = stat_ptr(b, 0);
+  ra.energy = b->d_rerank;
+  ra.out_spins = b->d_sel_spins;
+  ra.out_energy = b->d_sel_e;
+  ra.out_trial = b->d_sel_i;
+  ra.out_step = b->d_sel_i + b->count;
+  ra.out_tracked = b->d_sel_i + 2 * b->count;
+  ra.n = b->n;
+  ra.npad = b->npad;
+  ra.R = b->R;
+  ra.count = b->count;
+  HIP_TRY(launch_rerank_select(ra, b->stream));
+  b->h_sel_spins.resize((size_t)b->count * b->npad);
+  b->h_sel_e.resize(b->count);
+  b->h_sel_i.resize((size_t)3 * b->count);
+  HIP_TRY(hipMemcpyAsync(b->h_sel_spins.data(), b->d_sel_spins, b->h_sel_spins.size(), hipMemcpyDeviceToHost,
+                         b->stream));
+  HIP_TRY(hipMemcpyAsync(b->h_sel_e.data(), b->d_sel_e, b->count * sizeof(double), hipMemcpyDeviceToHost, b->stream));
+  HIP_TRY(hipMemcpyAsync(b->h_sel_i.data(), b->d_sel_i, 3 * b->count * sizeof(int32_t), hipMemcpyDeviceToHost,
+                         b->stream));
   HIP_TRY(hipStreamSynchronize(b->stream));
   b->reranked = true;
   return PIM_OK;
@@ -179,6 +217,17 @@ pim_status check_batch_ready(pim_batch* b, int32_t inst) {
   if (b->sticky_error) return fail(PIM_ERR_DEVICE, "batch is in an error state after a failed device call");
   if (!b->ran) return fail(PIM_ERR_STATE, "no run has been issued on this batch");
   if (inst < 0 || inst >= b->count) return fail(PIM_ERR_INVALID, "instance index %d outside [0, %d)", inst, b->count);
+  return PIM_OK;
+}
+
+// steps_done < T on any trial of the batch means the run was cancelled.
+pim_status cancelled_any(pim_batch* b) {
+  std::vector<int32_t> done((size_t)b->count * b->R);
+  HIP_TRY(hipMemcpyAsync(done.data(), stat_ptr(b, 4), done.size() * sizeof(int32_t), hipMemcpyDeviceToHost,
+                         b->stream));
+  HIP_TRY(hipStreamSynchronize(b->stream));
+  for (size_t c = 0; c < done.size(); ++c)
+    if (done[c] < b->last_T) return fail(PIM_ERR_CANCELLED, "run was cancelled after %d of %d steps", done[c], b->last_T);
   return PIM_OK;
 }
 
@@ -222,6 +271,22 @@ pim_status pim_compile_step(const pim_params* params, double beta, double eta, i
     return PIM_OK;
   } catch (...) {
     return fail(PIM_ERR_INVALID, "internal error in pim_compile_step");
+  }
+}
+
+pim_status pim_compile_table(const pim_params* params, double beta, double eta, int16_t* table) {
+  try {
+    Rule r;
+    pim_status st = validate_params(params, r);
+    if (st != PIM_OK) return st;
+    if (!finite_nonneg(beta) || !finite_nonneg(eta)) return fail(PIM_ERR_INVALID, "beta and eta must be finite and >= 0");
+    if (!table) return fail(PIM_ERR_INVALID, "output pointer is NULL");
+    int32_t th[kMaxLevels], um[2 * kMaxLevels];
+    compile_step(r, beta, eta, th, um);
+    theta_by_noise(th, um, r.levels, table);
+    return PIM_OK;
+  } catch (...) {
+    return fail(PIM_ERR_INVALID, "internal error in pim_compile_table");
   }
 }
 
@@ -335,6 +400,11 @@ pim_status pim_batch_create(pim_instance* const* insts, int32_t count, int32_t t
     if (st == PIM_OK) st = alloc_dev(&b->d_target, (size_t)count, s);
     if (st == PIM_OK) st = alloc_dev(&b->d_rerank, cells, s);
     if (st == PIM_OK && init_spins) st = alloc_dev(&b->d_init, cells * b->npad, s);
+    if (st == PIM_OK) st = alloc_dev(&b->d_jptrs, (size_t)count, s);
+    if (st == PIM_OK) st = alloc_dev(&b->d_hptrs, (size_t)count, s);
+    if (st == PIM_OK) st = alloc_dev(&b->d_sel_spins, (size_t)count * b->npad, s);
+    if (st == PIM_OK) st = alloc_dev(&b->d_sel_e, (size_t)count, s);
+    if (st == PIM_OK) st = alloc_dev(&b->d_sel_i, (size_t)3 * count, s);
     if (st != PIM_OK) {
       free_batch_buffers(b);
       delete b;
@@ -348,7 +418,13 @@ pim_status pim_batch_create(pim_instance* const* insts, int32_t count, int32_t t
     if (e == hipSuccess) e = hipEventCreate(&b->ev0);
     if (e == hipSuccess) e = hipEventCreate(&b->ev1);
     std::vector<uint32_t> sid(count);
-    for (int k = 0; k < count; ++k) sid[k] = insts[k]->rule.stream;
+    std::vector<const float*> jp(count);
+    std::vector<const int32_t*> hp(count);
+    for (int k = 0; k < count; ++k) {
+      sid[k] = insts[k]->rule.stream;
+      jp[k] = insts[k]->d_jf32;
+      hp[k] = insts[k]->d_h;
+    }
     for (int k = 0; k < count && e == hipSuccess; ++k) {
       e = hipMemcpyAsync(b->d_jfrag + frag * k, insts[k]->d_jfrag, frag, hipMemcpyDeviceToDevice, s);
       if (e == hipSuccess)
@@ -356,6 +432,10 @@ pim_status pim_batch_create(pim_instance* const* insts, int32_t count, int32_t t
     }
     if (e == hipSuccess) e = hipMemcpyAsync(b->d_class, b->inst_class.data(), count * 4, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(b->d_stream_ids, sid.data(), count * 4, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync((void*)b->d_jptrs, jp.data(), count * sizeof(void*), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync((void*)b->d_hptrs, hp.data(), count * sizeof(void*), hipMemcpyHostToDevice, s);
     std::vector<int8_t> init_pad;
     if (e == hipSuccess && init_spins) {
       init_pad.assign(cells * b->npad, (int8_t)1);
@@ -415,19 +495,28 @@ pim_status pim_run(pim_batch* b, const pim_schedule* sc, uint64_t seed, void* st
     const int L = b->insts[0]->rule.levels;
     const int ncls = (int)b->class_rep.size();
     // ---- compile ----
-    std::vector<int32_t> theta(kMaxLevels), umin(2 * kMaxLevels);
-    std::vector<int16_t> thtab;
     std::vector<int32_t> steptab;
     const bool mfma = sc->kernel == PIM_KERNEL_MFMA_I8;
     if (mfma) {
-      thtab.resize((size_t)ncls * T * kTabEntries);
-      for (int c = 0; c < ncls; ++c) {
-        const Rule& r = b->insts[b->class_rep[c]]->rule;
-        for (int t = 0; t < T; ++t) {
-          compile_step(r, sc->beta[t], sc->eta[t], theta.data(), umin.data());
-          theta_by_noise(theta.data(), umin.data(), r.levels, &thtab[((size_t)c * T + t) * kTabEntries]);
-        }
+      const size_t need = (size_t)ncls * T * kTabEntries;
+      if (need * 2 > b->h_thtab_bytes) {
+        if (b->h_thtab) (void)hipHostFree(b->h_thtab);
+        b->h_thtab = nullptr;
+        b->h_thtab_bytes = 0;
+        if (hipHostMalloc((void**)&b->h_thtab, need * 2, hipHostMallocDefault) != hipSuccess)
+          return fail(PIM_ERR_NOMEM, "pinned staging allocation of %zu bytes failed", need * 2);
+        b->h_thtab_bytes = need * 2;
       }
+      int16_t* out = b->h_thtab;
+      parallel_for(T * ncls, [&](int lo, int hi) {
+        int32_t th[kMaxLevels], um[2 * kMaxLevels];
+        for (int i = lo; i < hi; ++i) {
+          const int c = i / T, t = i % T;
+          const Rule& r = b->insts[b->class_rep[c]]->rule;
+          compile_step(r, sc->beta[t], sc->eta[t], th, um);
+          theta_by_noise(th, um, r.levels, out + ((size_t)c * T + t) * kTabEntries);
+        }
+      });
     } else {
       for (int k = 0; k < b->count; ++k)
         if (b->insts[k]->rule.levels != L)
@@ -443,13 +532,14 @@ pim_status pim_run(pim_batch* b, const pim_schedule* sc, uint64_t seed, void* st
       }
     }
     // ---- upload ----
-    if (mfma && thtab.size() * 2 > b->thtab_bytes) {
+    const size_t thtab_need = mfma ? (size_t)ncls * T * kTabEntries : 0;
+    if (mfma && thtab_need * 2 > b->thtab_bytes) {
       dev_free(b->d_thtab, s);
       b->d_thtab = nullptr;
       b->thtab_bytes = 0;
-      pim_status st = alloc_dev(&b->d_thtab, thtab.size(), s);
+      pim_status st = alloc_dev(&b->d_thtab, thtab_need, s);
       if (st != PIM_OK) return st;
-      b->thtab_bytes = thtab.size() * 2;
+      b->thtab_bytes = thtab_need * 2;
     }
     if (!mfma && steptab.size() * 4 > b->steptab_bytes) {
       dev_free(b->d_steptab, s);
@@ -464,7 +554,7 @@ pim_status pim_run(pim_batch* b, const pim_schedule* sc, uint64_t seed, void* st
       return fail(PIM_ERR_DEVICE, "%s failed: %s", what, hipGetErrorString(e));
     };
     hipError_t e = hipSuccess;
-    if (mfma) e = hipMemcpyAsync(b->d_thtab, thtab.data(), thtab.size() * 2, hipMemcpyHostToDevice, s);
+    if (mfma) e = hipMemcpyAsync(b->d_thtab, b->h_thtab, (size_t)ncls * T * kTabEntries * 2, hipMemcpyHostToDevice, s);
     else e = hipMemcpyAsync(b->d_steptab, steptab.data(), steptab.size() * 4, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(b->d_target, tgt.data(), b->count * 4, hipMemcpyHostToDevice, s);
     // the host tables must stay alive until the copies are done
@@ -537,6 +627,7 @@ pim_status pim_run(pim_batch* b, const pim_schedule* sc, uint64_t seed, void* st
     if (e != hipSuccess) return device_fail(e, "hipEventRecord");
     b->ran = true;
     b->reranked = false;
+    b->cancelled_checked = -1;
     b->last_T = T;
     b->last_start = sc->start_step;
     return PIM_OK;
@@ -597,29 +688,28 @@ pim_status pim_best(pim_batch* b, int32_t inst, int8_t* spins_out, double* e_out
   try {
     pim_status st = check_batch_ready(b, inst);
     if (st != PIM_OK) return st;
-    st = ensure_rerank(b);
+    st = ensure_selection(b);
     if (st != PIM_OK) {
       b->sticky_error = true;
       return st;
     }
-    const double* e = &b->h_rerank[(size_t)inst * b->R];
-    int best = 0;
-    for (int a = 1; a < b->R; ++a)
-      if (e[a] < e[best]) best = a;  // ties keep the lowest trial id
-    const size_t cell = (size_t)inst * b->R + best;
-    int32_t tb = 0, eb = 0;
-    HIP_TRY(hipMemcpyAsync(&tb, stat_ptr(b, 1) + cell, 4, hipMemcpyDeviceToHost, b->stream));
-    HIP_TRY(hipMemcpyAsync(&eb, stat_ptr(b, 0) + cell, 4, hipMemcpyDeviceToHost, b->stream));
-    std::vector<int8_t> sp(b->npad);
-    HIP_TRY(hipMemcpyAsync(sp.data(), b->d_best + cell * b->npad, b->npad, hipMemcpyDeviceToHost, b->stream));
-    HIP_TRY(hipStreamSynchronize(b->stream));
-    if ((double)eb != e[best])
-      return fail(PIM_ERR_DEVICE, "tracked energy %d disagrees with the binary64 re-evaluation %.17g", eb, e[best]);
-    if (spins_out) std::memcpy(spins_out, sp.data(), b->n);
-    if (e_out) *e_out = e[best];
-    if (trial_out) *trial_out = best;
-    if (step_out) *step_out = tb;
-    return cancelled_status(b, inst);
+    const double e = b->h_sel_e[inst];
+    const int32_t trial = b->h_sel_i[inst];
+    const int32_t step = b->h_sel_i[b->count + inst];
+    const int32_t tracked = b->h_sel_i[2 * b->count + inst];
+    if ((double)tracked != e)
+      return fail(PIM_ERR_DEVICE, "tracked energy %d disagrees with the binary64 re-evaluation %.17g", tracked, e);
+    if (spins_out) std::memcpy(spins_out, &b->h_sel_spins[(size_t)inst * b->npad], b->n);
+    if (e_out) *e_out = e;
+    if (trial_out) *trial_out = trial;
+    if (step_out) *step_out = step;
+    if (b->cancelled_checked < 0) {
+      st = cancelled_any(b);
+      b->cancelled_checked = (st == PIM_OK) ? 0 : 1;
+    }
+    if (b->cancelled_checked == 1)
+      return fail(PIM_ERR_CANCELLED, "run was cancelled; results are partial");
+    return PIM_OK;
   } catch (...) {
     return fail(PIM_ERR_INVALID, "internal error in pim_best");
   }

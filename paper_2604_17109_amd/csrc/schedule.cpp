@@ -75,18 +75,23 @@ void compile_step(const Rule& r, double beta, double eta, int32_t* theta, int32_
 
 void theta_by_noise(const int32_t* theta, const int32_t* umin, int levels, int16_t* tab) {
   // s' = +1 <=> bin(I) >= kmin(u, s), with kmin = #{k : u < umin[k][s]}
-  // (umin is non-increasing in k), and bin(I) >= m <=> I >= theta_m.
-  for (int u = 0; u < kNoiseVals; ++u) {
-    for (int sneg = 0; sneg < 2; ++sneg) {
-      int kmin = 0;
-      for (int k = 0; k < levels; ++k) kmin += (u < umin[2 * k + sneg]) ? 1 : 0;
+  // (umin is non-increasing in k), and bin(I) >= m <=> I >= theta_m.  So kmin
+  // is constant on the u-ranges [umin[k][s], umin[k-1][s]): fill them.
+  for (int sneg = 0; sneg < 2; ++sneg) {
+    for (int m = 0; m <= levels; ++m) {
+      // u-range with kmin == m: u >= umin[m][s] (or 0 when m == L) and
+      // u < umin[m-1][s] (or 2^B when m == 0)
+      const int lo = (m == levels) ? 0 : umin[2 * m + sneg];
+      const int hi = (m == 0) ? kNoiseVals : umin[2 * (m - 1) + sneg];
       int32_t th;
-      if (kmin == 0) th = kThetaLo;
-      else if (kmin >= levels) th = kThetaHi;
-      else th = theta[kmin - 1];
-      // index relative to the centre kNoiseVals: u ^ s with s = +-1 as int
-      const int idx = sneg ? ~u : (u ^ 1);
-      tab[kNoiseVals + idx] = (int16_t)th;
+      if (m == 0) th = kThetaLo;
+      else if (m >= levels) th = kThetaHi;
+      else th = theta[m - 1];
+      for (int u = lo; u < hi; ++u) {
+        // index relative to the centre kNoiseVals: u ^ s with s = +-1 as int
+        const int idx = sneg ? ~u : (u ^ 1);
+        tab[kNoiseVals + idx] = (int16_t)th;
+      }
     }
   }
 }

@@ -68,6 +68,23 @@ def test_compiled_thresholds_reproduce_direct_rule(pim, case):
     assert np.array_equal(got, want)
 
 
+@pytest.mark.parametrize("case", CASES)
+def test_kernel_table_reproduces_direct_rule(pim, case):
+    """The 512-entry table the MFMA kernel reads: s(t+1) = +1 iff
+    I >= table[256 + (u ^ s)], against the oracle's direct binary64 rule."""
+    n, c, xi, L, noise, beta, eta = case
+    ztab = w.gauss_table(8) if noise == "gauss" else w.uniform_table(8)
+    tab = pim.compile_table(n, c, xi, beta, eta, levels=L, noise_table=ztab).astype(np.int64)
+    I = np.arange(-600, 601)[:, None, None]
+    s = np.array([-1, 1])[None, :, None]
+    u = np.arange(256)[None, None, :]
+    I, s, u = np.broadcast_arrays(I, s, u)
+    got = np.where(I >= tab[256 + (u ^ s)], 1, -1)
+    act = pimi.tanh_lut((beta * c) * I.astype(np.float64), L)
+    want = pimi.spin_decision(act, s, xi, eta, ztab[u])
+    assert np.array_equal(got, want)
+
+
 def test_threshold_clamp_range(pim):
     # tiny g: thresholds lie far outside any admissible field and clamp
     theta, _ = pim.compile_step(10, 1e-9, 0.5, 1.0, 0.5, levels=4, noise_table=w.gauss_table(8))
