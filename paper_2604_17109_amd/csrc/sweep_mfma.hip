@@ -20,8 +20,8 @@
 // of s_i(t)) of integer field thresholds; s_i(t+1) = +1 iff I_i >= tab[u ^ s]
 // (index u ^ 1 for s = +1 and ~u for s = -1, both relative to the table's
 // centre, so the two halves are disjoint).
-// Each wave double-buffers that 1 KB table in LDS and streams the next step's
-// copy from global memory while it works on the current one.
+// Each wave keeps that 1 KB table in LDS and streams the next step's copy from
+// global memory into registers while it works on the current one.
 #include <hip/hip_runtime.h>
 
 #include <climits>
@@ -77,7 +77,7 @@ __device__ __forceinline__ void mfma_row_tile(const v4i* sJl, int mt, const v4i 
 // in-order issue of one wave per SIMD enough independent work to keep the
 // vector ALU busy while MFMA chains and LDS lookups are in flight.
 template <int NT, int CB, bool HAS_H>
-__global__ __launch_bounds__(64 * kWaves, 2) void sweep_mfma_kernel(SweepArgs a) {
+__global__ __launch_bounds__(64 * kWaves, 3) void sweep_mfma_kernel(SweepArgs a) {
   extern __shared__ __align__(16) unsigned char lds[];
   constexpr int kFragBytes = NT * NT * 1024;
   constexpr int kNpad = NT * 32;
@@ -98,9 +98,8 @@ __global__ __launch_bounds__(64 * kWaves, 2) void sweep_mfma_kernel(SweepArgs a)
     }
   }
   const v4i* sJ = reinterpret_cast<const v4i*>(lds);
-  // volatile: re-read h each tile instead of pinning NT*16 registers for it
-  const volatile int32_t* sH = reinterpret_cast<const volatile int32_t*>(lds + kFragBytes);
-  int16_t* sTab = reinterpret_cast<int16_t*>(lds + kFragBytes + kHBytes + wave * 2 * kTabBytes);
+  const int32_t* sH = reinterpret_cast<const int32_t*>(lds + kFragBytes);
+  int16_t* sTab = reinterpret_cast<int16_t*>(lds + kFragBytes + kHBytes + wave * kTabBytes);
   uint4* sTab4 = reinterpret_cast<uint4*>(sTab);
   __syncthreads();  // the only workgroup barrier
 
@@ -170,7 +169,7 @@ __global__ __launch_bounds__(64 * kWaves, 2) void sweep_mfma_kernel(SweepArgs a)
     const uint4 nxt = gTab4[(size_t)min(t + 1, a.T - 1) * 64 + lane];
     // centre of this step's table: entry idx in [-256, 256) holds the field
     // threshold for (u, s) with idx = u ^ s (s = +1 -> u ^ 1, s = -1 -> ~u)
-    const int16_t* tab = sTab + (t & 1) * kTabEntries + kNoiseVals;
+    const int16_t* tab = sTab + kNoiseVals;
     uint32_t ctr_trial[CB];
     uint32_t ctr_half = (uint32_t)half;
     PIM_FENCE(ctr_half);
@@ -198,8 +197,15 @@ __global__ __launch_bounds__(64 * kWaves, 2) void sweep_mfma_kernel(SweepArgs a)
           PIM_FENCE(bw[c][q]);
         }
       }
-      const v4i* sJl = sJl0;
-      PIM_FENCE(sJl);
+      // fence an integer lane offset, not the pointer: a pointer through the
+      // asm would lose its LDS address space and turn the reads into flat loads
+      int lane_off = lane;
+      PIM_FENCE(lane_off);
+      // h of this tile re-read from LDS each step (fenced offset: not hoisted
+      // into NT*16 loop-carried registers)
+      int hoff = 32 * mt + 16 * half;
+      if (HAS_H) PIM_FENCE(hoff);
+      const v4i* sJl = sJ + lane_off;
       // (1) LDS: the field thresholds of this tile, indexed by u ^ s
       int th[CB][16];
 #pragma unroll
@@ -231,7 +237,7 @@ __global__ __launch_bounds__(64 * kWaves, 2) void sweep_mfma_kernel(SweepArgs a)
             int I = acc[c][r];
             int v;
             if (HAS_H) {
-              const int hv = sH[32 * mt + 16 * half + r];
+              const int hv = sH[hoff + r];
               I += hv;
               v = I + hv;
             } else {
@@ -267,8 +273,9 @@ __global__ __launch_bounds__(64 * kWaves, 2) void sweep_mfma_kernel(SweepArgs a)
         if (live[c]) {
           // address formed here (opaque base, immediate tile offsets) rather
           // than hoisted per tile out of the step loop
-          int8_t* dst = a.best_s + cell[c] * kNpad + 16 * half;
-          PIM_FENCE(dst);
+          size_t off = cell[c] * kNpad + 16 * half;
+          PIM_FENCE(off);
+          int8_t* dst = a.best_s + off;
 #pragma unroll
           for (int mt = 0; mt < NT; ++mt) *reinterpret_cast<v4i*>(dst + 32 * mt) = B[c][mt];
         }
@@ -286,7 +293,8 @@ __global__ __launch_bounds__(64 * kWaves, 2) void sweep_mfma_kernel(SweepArgs a)
 #pragma unroll
       for (int mt = 0; mt < NT; ++mt) B[c][mt] = Bn[c][mt];
     if (has_next) {
-      sTab4[((t + 1) & 1) * 64 + lane] = nxt;
+      // every lookup of this step precedes this write in the wave's LDS order
+      sTab4[lane] = nxt;
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -313,7 +321,7 @@ constexpr int kBlocksPerWave = 1;  // CB: 32-trial column blocks per wave
 
 template <int NT, bool HAS_H>
 hipError_t launch_nt(const SweepArgs& a, int count, hipStream_t s) {
-  const size_t lds = (size_t)NT * NT * 1024 + (HAS_H ? NT * 32 * 4 : 0) + (size_t)kWaves * 2 * kTabBytes;
+  const size_t lds = (size_t)NT * NT * 1024 + (HAS_H ? NT * 32 * 4 : 0) + (size_t)kWaves * kTabBytes;
   auto kern = sweep_mfma_kernel<NT, kBlocksPerWave, HAS_H>;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
