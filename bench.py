@@ -40,9 +40,39 @@ def parse():
     ap.add_argument("--n", type=int, default=200)
     ap.add_argument("--kernel", default="mfma", choices=["mfma", "plain"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-trials", type=int, default=128)
+    ap.add_argument("--cpu-trials", type=int, default=512)
     ap.add_argument("--cpu-steps", type=int, default=2000)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only run a device-to-device copy of BYTES bytes (x3), for calibrating the "
+                         "FETCH_SIZE / WRITE_SIZE counters against a known byte count")
     return ap.parse_args()
+
+
+def copy_probe(nbytes):
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": nbytes, "launches": 3}), flush=True)
+
+
+def measured_traffic():
+    """HBM bytes per launch of the sweep kernel from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary, or None when the kernel sources changed
+    since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "sweep_mfma_sk200_traffic.txt")
+    if not os.path.exists(path):
+        return None
+    kv = dict(l.strip().split("=", 1) for l in open(path) if "=" in l and not l.startswith(" "))
+    csrc = os.path.join(ROOT, "paper_2604_17109_amd", "csrc")
+    sha = hashlib.sha256(b"".join(open(os.path.join(csrc, f), "rb").read()
+                                  for f in ["sweep_mfma.hip", "philox.hpp", "internal.hpp"])).hexdigest()[:16]
+    if kv.get("kernel_source_sha256_16") != sha:
+        return None
+    return int(kv["hbm_bytes_per_launch"])
 
 
 def cpu_baseline(n, trials, steps, xi, c):
@@ -70,6 +100,9 @@ def cpu_baseline(n, trials, steps, xi, c):
 
 def main():
     args = parse()
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the sweep shards by "
               "instance and trial with no exchange, see DESIGN.md", file=sys.stderr)
@@ -121,7 +154,10 @@ def main():
     # roofline of the sweep kernel (algorithmic counts per launch)
     contractions = float(I) * R * (T + 1)
     mfma_ops = 2.0 * n * n * contractions
-    alu_per_update = 6.75  # Philox share 60/16 + threshold read/compare 2 + energy 1
+    # algorithmic 32-bit lane-ops per spin update: Philox4x32-10 share
+    # (10 rounds x (2 widening multiplies + 2 three-way xors) / 16 values)
+    # 2.5, threshold address + compare 2, spin pack 1, energy multiply-add 1
+    alu_per_update = 6.5
     alu_ops = alu_per_update * updates
     kernel_s = kernel_ms / 1000.0
     line = {
@@ -143,7 +179,9 @@ def main():
         "tts99": {"p_bar": p_bar, "n99": n99 if n99 != math.inf else None, "tts99_s": tts99,
                   "criterion": "E <= floor(0.999 * best energy of the warmup run)", "steps": T},
         "roofline": {"bound": "alu", "achieved": alu_ops / kernel_s, "peak": VALU_PEAK, "unit": "lane-op/s",
-                     "frac": alu_ops / kernel_s / VALU_PEAK, "traffic": None,
+                     "frac": alu_ops / kernel_s / VALU_PEAK,
+                     "traffic": measured_traffic() if (args.n, args.trials, args.instances, args.sweeps)
+                     == (200, 1024, 128, 10000) and args.kernel == "mfma" else None,
                      "algorithmic_per_update": alu_per_update},
         "roofline_mfma": {"bound": "mfma", "achieved": mfma_ops / kernel_s / 1e12, "peak": INT8_MFMA_PEAK / 1e12,
                           "unit": "TOP/s", "frac": mfma_ops / kernel_s / INT8_MFMA_PEAK},
