@@ -1,10 +1,6 @@
 // Binary64 evaluation of Eq. (1) for candidate configurations, and the
 // per-instance selection of the lowest-energy trial (the paper's host keeps
-// the lowest-energy configuration of all returned states).
-//
-// One wave per configuration.  Lanes own columns j (coalesced reads of each
-// coupling row), loop over rows i with s_i broadcast, and accumulate
-// s_i J_ij s_j in binary64; one wave reduction per configuration:
+// the lowest-energy configuration of all returned states):
 //   E = -1/2 (sum_ij s_i J_ij s_j + 2 sum_i h_i s_i).
 #include <hip/hip_runtime.h>
 
@@ -44,14 +40,53 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void energy_f64_kernel(EnergyA
   if (lane == 0) a.out[cfg] = e;
 }
 
+// Batch re-rank of every trial's best state.  One block per (instance, 16
+// trials): the instance's int8 couplings are staged in LDS once and each wave
+// evaluates four candidates.  Lane l owns columns 4l..4l+3; for every row i
+// the exact integer s_i * sum_j J_ij s_j (one v_dot4 per lane) is accumulated
+// in binary64, then the lanes are reduced in binary64.
+constexpr int kRerankTrialsPerBlock = 16;
+
 __global__ __launch_bounds__(64 * kWavesPerBlock) void rerank_kernel(RerankArgs a) {
-  const int lane = threadIdx.x & 63;
+  __shared__ __align__(16) int8_t sJ[PIM_MAX_N * PIM_MAX_N];
+  __shared__ __align__(16) int8_t sS[kWavesPerBlock][PIM_MAX_N];
   const int inst = blockIdx.y;
-  const int trial = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
-  if (trial >= a.R) return;
-  const size_t cell = (size_t)inst * a.R + trial;
-  const double e = config_energy(a.jf32[inst], a.h ? a.h[inst] : nullptr, a.best_s + cell * a.npad, a.n, lane);
-  if (lane == 0) a.energy[cell] = e;
+  const int n = a.n, npad = a.npad;
+  const int8_t* J = a.j8[inst];
+  // row stride PIM_MAX_N; columns >= n are never initialised, which is
+  // harmless: the candidate's spins there are 0, so they add 0 to every dot
+  for (int i = threadIdx.x; i < n * n; i += 64 * kWavesPerBlock) {
+    const int r = i / n, c = i - r * n;
+    sJ[r * PIM_MAX_N + c] = J[i];
+  }
+  __syncthreads();
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int32_t* hp = a.h ? a.h[inst] : nullptr;
+  for (int k = 0; k < kRerankTrialsPerBlock / kWavesPerBlock; ++k) {
+    const int trial = blockIdx.x * kRerankTrialsPerBlock + k * kWavesPerBlock + wave;
+    if (trial >= a.R) break;  // wave-uniform
+    const size_t cell = (size_t)inst * a.R + trial;
+    const int8_t* s = a.best_s + cell * npad;
+    for (int i = lane; i < PIM_MAX_N; i += 64) sS[wave][i] = (i < n) ? s[i] : (int8_t)0;
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    const int32_t s4 = reinterpret_cast<const int32_t*>(sS[wave])[lane];  // columns 4l..4l+3
+    double acc = 0.0;
+    for (int i = 0; i < n; ++i) {
+      const int32_t j4 = reinterpret_cast<const int32_t*>(sJ + i * PIM_MAX_N)[lane];
+      const int dot = __builtin_amdgcn_sdot4(j4, s4, 0, false);  // sum_j J_ij s_j over 4 columns
+      acc += (double)(sS[wave][i] * dot);
+    }
+    if (hp)
+      for (int b = 0; b < 4; ++b) {
+        const int j = 4 * lane + b;
+        if (j < n) acc += 2.0 * (double)hp[j] * (double)sS[wave][j];
+      }
+    const double e = -0.5 * wave_sum(acc);
+    if (lane == 0) a.energy[cell] = e;
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  }
 }
 
 // One block per instance: lowest binary64 energy, ties to the lowest trial;
@@ -104,7 +139,8 @@ hipError_t launch_energy_f64(const EnergyArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_rerank_select(const RerankArgs& a, hipStream_t s) {
-  const dim3 grid((a.R + kWavesPerBlock - 1) / kWavesPerBlock, a.count);
+  if (a.n > PIM_MAX_N) return hipErrorInvalidValue;
+  const dim3 grid((a.R + kRerankTrialsPerBlock - 1) / kRerankTrialsPerBlock, a.count);
   hipLaunchKernelGGL(rerank_kernel, grid, dim3(64 * kWavesPerBlock), 0, s, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

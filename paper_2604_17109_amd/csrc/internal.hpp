@@ -92,7 +92,7 @@ struct EnergyArgs {
 };
 
 struct RerankArgs {
-  const float* const* jf32;    // [count] device pointers to each instance's J (n x n)
+  const int8_t* const* j8;     // [count] device pointers to each instance's int8 J (n x n)
   const int32_t* const* h;     // [count] device pointers to h, or nullptr (no fields)
   const int8_t* best_s;        // [count][R][npad]
   const int32_t* t_best;       // [count][R]
@@ -123,6 +123,7 @@ struct pim_instance {
   bool has_h = false;
   int8_t* d_jfrag = nullptr;
   float* d_jf32 = nullptr;
+  int8_t* d_j8 = nullptr;         // row-major int8 J (re-rank)
   int32_t* d_h = nullptr;
 };
 
@@ -143,7 +144,7 @@ struct pim_batch {
   int32_t* d_target = nullptr;
   double* d_rerank = nullptr;     // [count][R]
   // per-instance selection (device, then one readback): ptr tables + outputs
-  const float** d_jptrs = nullptr;
+  const int8_t** d_jptrs = nullptr;
   const int32_t** d_hptrs = nullptr;
   int8_t* d_sel_spins = nullptr;  // [count][npad]
   double* d_sel_e = nullptr;      // [count]

@@ -183,7 +183,7 @@ int32_t* stat_ptr(pim_batch* b, int which) { return b->d_stats + (size_t)which *
 pim_status ensure_selection(pim_batch* b) {
   if (b->reranked) return PIM_OK;
   RerankArgs ra{};
-  ra.jf32 = b->d_jptrs;
+  ra.j8 = b->d_jptrs;
   ra.h = b->has_h ? b->d_hptrs : nullptr;
   ra.best_s = b->d_best;
   ra.t_best = stat_ptr(b, 1);
@@ -318,6 +318,7 @@ pim_status pim_create(const int8_t* J, const int32_t* h, const pim_params* param
     st = alloc_dev(&inst->d_jfrag, frag.size(), s);
     if (st == PIM_OK) st = alloc_dev(&inst->d_jf32, jf.size(), s);
     if (st == PIM_OK) st = alloc_dev(&inst->d_h, hp.size(), s);
+    if (st == PIM_OK) st = alloc_dev(&inst->d_j8, (size_t)n * n, s);
     if (st != PIM_OK) {
       pim_destroy(inst);
       return st;
@@ -325,6 +326,7 @@ pim_status pim_create(const int8_t* J, const int32_t* h, const pim_params* param
     hipError_t e = hipMemcpyAsync(inst->d_jfrag, frag.data(), frag.size(), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(inst->d_jf32, jf.data(), jf.size() * 4, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(inst->d_h, hp.data(), hp.size() * 4, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(inst->d_j8, J, (size_t)n * n, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);  // host staging buffers go out of scope
     if (e != hipSuccess) {
       pim_destroy(inst);
@@ -344,6 +346,7 @@ void pim_destroy(pim_instance* inst) {
   dev_free(inst->d_jfrag, nullptr);
   dev_free(inst->d_jf32, nullptr);
   dev_free(inst->d_h, nullptr);
+  dev_free(inst->d_j8, nullptr);
   delete inst;
 }
 
@@ -418,11 +421,11 @@ pim_status pim_batch_create(pim_instance* const* insts, int32_t count, int32_t t
     if (e == hipSuccess) e = hipEventCreate(&b->ev0);
     if (e == hipSuccess) e = hipEventCreate(&b->ev1);
     std::vector<uint32_t> sid(count);
-    std::vector<const float*> jp(count);
+    std::vector<const int8_t*> jp(count);
     std::vector<const int32_t*> hp(count);
     for (int k = 0; k < count; ++k) {
       sid[k] = insts[k]->rule.stream;
-      jp[k] = insts[k]->d_jf32;
+      jp[k] = insts[k]->d_j8;
       hp[k] = insts[k]->d_h;
     }
     for (int k = 0; k < count && e == hipSuccess; ++k) {
