@@ -42,6 +42,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-trials", type=int, default=512)
     ap.add_argument("--cpu-steps", type=int, default=2000)
+    ap.add_argument("--plain-instances", type=int, default=8,
+                    help="instances run through the plain FP32 per-instance kernel for the comparison "
+                         "(0 = skip); trajectories are bit-identical, so TTS99 is equal")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a device-to-device copy of BYTES bytes (x3), for calibrating the "
                          "FETCH_SIZE / WRITE_SIZE counters against a known byte count")
@@ -186,6 +189,21 @@ def main():
         "roofline_mfma": {"bound": "mfma", "achieved": mfma_ops / kernel_s / 1e12, "peak": INT8_MFMA_PEAK / 1e12,
                           "unit": "TOP/s", "frac": mfma_ops / kernel_s / INT8_MFMA_PEAK},
     }
+    if args.plain_instances > 0 and args.kernel == "mfma":
+        # the plain FP32 per-instance kernel on the first instances of the same
+        # batch (identical trajectories, so equal TTS99): one launch per instance
+        k = min(args.plain_instances, I)
+        pb = pim.Batch(insts[:k], R)
+        pb.run(beta, eta, seed=1, kernel="plain", target=target[:k])
+        pms = pb.kernel_ms()
+        mine = [batch.trials_of(q, spins=False)["e_best"] for q in range(k)]
+        theirs = [pb.trials_of(q, spins=False)["e_best"] for q in range(k)]
+        same = all(np.array_equal(a, b) for a, b in zip(mine, theirs))
+        plain_rate = float(k) * R * T * n / (pms / 1000.0)
+        line["plain_f32"] = {"instances": k, "kernel_ms": pms, "spin_updates_per_s": plain_rate,
+                             "identical_results": bool(same),
+                             "speedup_at_equal_tts99": (updates / (kernel_ms / 1000.0)) / plain_rate}
+        pb.close()
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(n, args.cpu_trials, args.cpu_steps, xi, c)
     print(json.dumps(line), flush=True)
