@@ -20,11 +20,12 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-__device__ double config_energy(const float* J, const int32_t* h, const int8_t* s, int n, int lane) {
+__device__ double config_energy(const float* J, int jstride, const int32_t* h, const int8_t* s, int n,
+                                int lane) {
   double acc = 0.0;
   for (int i = 0; i < n; ++i) {
     const double si = (double)s[i];
-    const float* Ji = J + (size_t)i * n;
+    const float* Ji = J + (size_t)i * jstride;
     for (int j = lane; j < n; j += 64) acc += si * (double)Ji[j] * (double)s[j];
   }
   if (h)
@@ -36,7 +37,7 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void energy_f64_kernel(EnergyA
   const int lane = threadIdx.x & 63;
   const int cfg = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
   if (cfg >= a.count) return;
-  const double e = config_energy(a.jf32, a.h, a.spins + (size_t)cfg * a.stride, a.n, lane);
+  const double e = config_energy(a.jf32, a.jstride, a.h, a.spins + (size_t)cfg * a.stride, a.n, lane);
   if (lane == 0) a.out[cfg] = e;
 }
 

@@ -67,7 +67,7 @@ struct SweepArgs {
 };
 
 struct PlainArgs {
-  const float* jf32;         // [n][n] of one instance
+  const float* jf32;         // [npad][jstride] of one instance, zero-padded
   const int32_t* h;          // [n] or nullptr
   const int32_t* steptab;    // [T][(L-1) + 2L] theta then umin
   const int8_t* init;        // [R][npad] or nullptr
@@ -79,16 +79,16 @@ struct PlainArgs {
   int32_t* e_final;
   int32_t* steps_done;
   const volatile int32_t* cancel;
-  int32_t n, npad, R, T, start_step, levels, use_target, target;
+  int32_t n, npad, jstride, R, T, start_step, levels, use_target, target;
   uint32_t stream, k0, k1;
 };
 
 struct EnergyArgs {
-  const float* jf32;   // [n][n]
+  const float* jf32;   // [>= n][jstride]
   const int32_t* h;    // [n] or nullptr
   const int8_t* spins; // [count][stride]
   double* out;         // [count]
-  int32_t n, stride, count;
+  int32_t n, jstride, stride, count;
 };
 
 struct RerankArgs {
@@ -120,9 +120,10 @@ void pack_mfma_fragments(const int8_t* J, int n, int nt, int8_t* out);
 struct pim_instance {
   pim::Rule rule;
   int npad = 0, nt = 0;
+  int jstride = 0;                // row stride of d_jf32: n rounded up to 4
   bool has_h = false;
   int8_t* d_jfrag = nullptr;
-  float* d_jf32 = nullptr;
+  float* d_jf32 = nullptr;        // [npad][jstride] FP32 J, zero-padded
   int8_t* d_j8 = nullptr;         // row-major int8 J (re-rank)
   int32_t* d_h = nullptr;
 };

@@ -311,8 +311,10 @@ pim_status pim_create(const int8_t* J, const int32_t* h, const pim_params* param
       for (int i = 0; i < n; ++i) inst->has_h |= (h[i] != 0);
     std::vector<int8_t> frag((size_t)inst->nt * inst->nt * 1024);
     pack_mfma_fragments(J, n, inst->nt, frag.data());
-    std::vector<float> jf((size_t)n * n);
-    for (size_t i = 0; i < jf.size(); ++i) jf[i] = (float)J[i];
+    inst->jstride = (n + 3) & ~3;
+    std::vector<float> jf((size_t)inst->npad * inst->jstride, 0.0f);
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) jf[(size_t)i * inst->jstride + j] = (float)J[(size_t)i * n + j];
     std::vector<int32_t> hp(inst->npad, 0);
     if (h) std::copy(h, h + n, hp.begin());
     st = alloc_dev(&inst->d_jfrag, frag.size(), s);
@@ -613,6 +615,7 @@ pim_status pim_run(pim_batch* b, const pim_schedule* sc, uint64_t seed, void* st
         a.cancel = b->d_cancel;
         a.n = b->n;
         a.npad = b->npad;
+        a.jstride = b->insts[k]->jstride;
         a.R = b->R;
         a.T = T;
         a.start_step = sc->start_step;
@@ -671,6 +674,7 @@ pim_status pim_energy(const pim_instance* inst, const int8_t* spins, int32_t cou
     ea.spins = d_s;
     ea.out = d_o;
     ea.n = n;
+    ea.jstride = inst->jstride;
     ea.stride = n;
     ea.count = count;
     hipError_t e = hipMemcpyAsync(d_s, spins, (size_t)count * n, hipMemcpyHostToDevice, s);

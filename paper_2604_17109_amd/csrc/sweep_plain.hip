@@ -2,11 +2,13 @@
 //
 // Workgroup = 32 trials x (N/16 spin blocks); thread (b, a) owns spins
 // 16b..16b+15 of trial a.  Each step it forms the 16 local fields (Eq. (2))
-// with ordinary FP32 multiply-adds over J rows read from global memory and the
-// current spins kept in LDS, then applies the same integer-threshold form of
-// Eq. (4) as the MFMA kernel: k = #{j : I >= theta_j}, s' = +1 iff
-// u >= umin[2k + (s<0)].  FP32 sums of integers below 2^24 are exact, so both
-// kernels produce identical trajectories.
+// with ordinary FP32 multiply-adds: J rows come from global memory as float4
+// (zero-padded to whole rows of 16 and a multiple of 4 columns) and the trial's current spins from
+// LDS as float4, one spin chunk reused across the 16 rows.  It then applies the
+// same integer-threshold form of Eq. (4) as the MFMA kernel:
+// k = #{j : I >= theta_j}, s' = +1 iff u >= umin[2k + (s<0)].  FP32 sums of
+// integers below 2^24 are exact, so both kernels produce identical
+// trajectories.
 #include <hip/hip_runtime.h>
 
 #include <climits>
@@ -21,9 +23,10 @@ namespace {
 constexpr int kTrials = 32;
 constexpr int kBlocks = PIM_MAX_N / 16;  // spin blocks of 16
 constexpr int kThreads = kTrials * kBlocks;
+constexpr int kRow = PIM_MAX_N + 8;      // LDS row stride (floats) of one trial's spins
 
 __global__ __launch_bounds__(kThreads) void sweep_plain_kernel(PlainArgs a) {
-  __shared__ float sS[PIM_MAX_N][kTrials];
+  __shared__ __align__(16) float sS[kTrials][kRow];
   __shared__ int32_t sE[kTrials];
   const int b = threadIdx.x / kTrials;
   const int al = threadIdx.x % kTrials;
@@ -42,14 +45,14 @@ __global__ __launch_bounds__(kThreads) void sweep_plain_kernel(PlainArgs a) {
         const int i = 16 * b + q;
         // clamped address: no load outside the trial's row even if speculated
         const float v = (float)a.init[(live ? cell : 0) * a.npad + min(i, a.n - 1)];
-        sS[i][al] = (live && i < a.n) ? v : 1.0f;
+        sS[al][i] = (live && i < a.n) ? v : 1.0f;
       }
     } else {
       const Ctr4 x = philox4x32_10(Ctr4{(uint32_t)b, 0u, (uint32_t)trial, (kDomainInit << 24) | a.stream}, a.k0, a.k1);
       const uint32_t xw[4] = {x.x, x.y, x.z, x.w};
       for (int q = 0; q < 16; ++q) {
         const uint32_t u = (xw[q >> 2] >> (8 * (q & 3))) & 0xFFu;
-        sS[16 * b + q][al] = u >= 128u ? 1.0f : -1.0f;
+        sS[al][16 * b + q] = u >= 128u ? 1.0f : -1.0f;
       }
     }
   }
@@ -65,20 +68,27 @@ __global__ __launch_bounds__(kThreads) void sweep_plain_kernel(PlainArgs a) {
     if (owner) {
 #pragma unroll
       for (int q = 0; q < 16; ++q) I[q] = 0.0f;
-      for (int j = 0; j < a.n; ++j) {
-        const float sj = sS[j][al];
+      const int n4 = a.jstride;
+      const float4* S4 = reinterpret_cast<const float4*>(&sS[al][0]);
+      // rows are zero-padded to a multiple of 32 and columns to jstride, so
+      // every row of the block exists and padded columns add 0
+      const float* Jb = a.jf32 + (size_t)(16 * b) * n4;
+      for (int j4 = 0; j4 < n4 / 4; ++j4) {
+        const float4 sv = S4[j4];
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
-          const int i = 16 * b + q;
-          const float jij = a.jf32[(size_t)min(i, a.n - 1) * a.n + j];
-          I[q] = fmaf((i < a.n) ? jij : 0.0f, sj, I[q]);
+          const float4 jv = *reinterpret_cast<const float4*>(Jb + (size_t)q * n4 + 4 * j4);
+          I[q] = fmaf(jv.x, sv.x, I[q]);
+          I[q] = fmaf(jv.y, sv.y, I[q]);
+          I[q] = fmaf(jv.z, sv.z, I[q]);
+          I[q] = fmaf(jv.w, sv.w, I[q]);
         }
       }
       int32_t ep = 0;
 #pragma unroll
       for (int q = 0; q < 16; ++q) {
         const int i = 16 * b + q;
-        s_old[q] = sS[i][al];
+        s_old[q] = sS[al][i];
         const int hv = (a.h && i < a.n) ? a.h[min(i, a.n - 1)] : 0;
         I[q] += (float)hv;
         if (i < a.n) ep += (int32_t)s_old[q] * ((int32_t)I[q] + hv);
@@ -122,7 +132,7 @@ __global__ __launch_bounds__(kThreads) void sweep_plain_kernel(PlainArgs a) {
     __syncthreads();  // every thread has read the old spins and E
     if (owner)
 #pragma unroll
-      for (int q = 0; q < 16; ++q) sS[16 * b + q][al] = s_new[q];
+      for (int q = 0; q < 16; ++q) sS[al][16 * b + q] = s_new[q];
     if (threadIdx.x < kTrials) sE[threadIdx.x] = 0;
     __syncthreads();
   }
@@ -130,7 +140,7 @@ __global__ __launch_bounds__(kThreads) void sweep_plain_kernel(PlainArgs a) {
   if (owner && live)
     for (int q = 0; q < 16; ++q) {
       const int i = 16 * b + q;
-      if (i < a.npad) a.final_s[cell * a.npad + i] = (int8_t)sS[i][al];
+      if (i < a.npad) a.final_s[cell * a.npad + i] = (int8_t)sS[al][i];
     }
   if (b == 0 && live) {
     a.e_best[cell] = e_best;
