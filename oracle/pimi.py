@@ -75,6 +75,23 @@ def energy_from_field(I, h, s):
     return -(twice // 2)
 
 
+def local_field_f64(J, h, s):
+    """I = J s + h of Eq. (2) for a real-valued instance, in binary64."""
+    J = np.asarray(J, dtype=np.float64)
+    s = np.asarray(s, dtype=np.float64)
+    field = J @ s
+    h = np.asarray(h, dtype=np.float64)
+    return field + (h if field.ndim == 1 else h[:, None])
+
+
+def energy_from_field_f64(I, h, s):
+    """E(s) = -1/2 sum_i s_i (I_i + h_i) in binary64 (real-valued instance)."""
+    s = np.asarray(s, dtype=np.float64)
+    h = np.asarray(h, dtype=np.float64)
+    hb = h if s.ndim == 1 else h[:, None]
+    return -0.5 * (s * (I + hb)).sum(axis=0)
+
+
 def local_field(J, h, s):
     """I = J s + h of Eq. (2), exact in int64 ([N] or [N, R])."""
     J = np.asarray(J, dtype=np.float64)
@@ -148,6 +165,7 @@ class Problem:
     normalisation; xi: inertia (0 for the conventional PIM); levels: L;
     ztab: non-decreasing float64 quantile table of length 2^bits.
     """
+    real = False
 
     def __init__(self, J, h, c, xi, levels, ztab, bits=8):
         self.J = np.asarray(J, dtype=np.int64)
@@ -166,9 +184,35 @@ class Problem:
             raise ValueError("noise table length must be 2^bits")
 
 
-def _result(n_trials, n):
+class RealProblem(Problem):
+    """A real-valued Ising instance (binary64 J and h; e.g. the MIMO detection
+    instances of Suppl. "Delta-Ising MIMO (DI-MIMO) formulation") with the same
+    update-rule constants.  Fields and energies are binary64; the update rule is
+    unchanged (the LUT argument is (beta(t) * c) * I with I in binary64)."""
+    real = True
+
+    def __init__(self, J, h, c, xi, levels, ztab, bits=8):
+        self.J = np.asarray(J, dtype=np.float64)
+        self.h = np.asarray(h, dtype=np.float64)
+        self.n = self.J.shape[0]
+        if self.J.shape != (self.n, self.n) or self.h.shape != (self.n,):
+            raise ValueError("J must be N x N and h length N")
+        if not np.array_equal(self.J, self.J.T) or np.any(np.diag(self.J) != 0):
+            raise ValueError("J must be symmetric with a zero diagonal")
+        if not (np.all(np.isfinite(self.J)) and np.all(np.isfinite(self.h))):
+            raise ValueError("J and h must be finite")
+        self.c = float(c)
+        self.xi = float(xi)
+        self.levels = int(levels)
+        self.ztab = np.asarray(ztab, dtype=np.float64)
+        self.bits = int(bits)
+        if self.ztab.shape != (1 << self.bits,):
+            raise ValueError("noise table length must be 2^bits")
+
+
+def _result(n_trials, n, real=False):
     return {
-        "e_best": np.full(n_trials, np.iinfo(np.int64).max, dtype=np.int64),
+        "e_best": np.full(n_trials, np.inf) if real else np.full(n_trials, np.iinfo(np.int64).max, dtype=np.int64),
         "t_best": np.full(n_trials, -1, dtype=np.int64),
         "best_state": np.zeros((n, n_trials), dtype=np.int64),
         "first_hit": np.full(n_trials, -1, dtype=np.int64),
@@ -220,12 +264,16 @@ def run_parallel(prob, beta, eta, seed, stream, trials, init=None, start_step=0,
     n = prob.n
     s = initial_spins(seed, stream, trials, n, prob.bits) if init is None \
         else np.asarray(init, dtype=np.int64).copy()
-    res = _result(len(trials), n)
+    res = _result(len(trials), n, prob.real)
     energies = []
     spin = np.arange(n)[:, None]
     for t in range(steps + 1):
-        I = local_field(prob.J, prob.h, s)
-        e = energy_from_field(I, prob.h, s)
+        if prob.real:
+            I = local_field_f64(prob.J, prob.h, s)
+            e = energy_from_field_f64(I, prob.h, s)
+        else:
+            I = local_field(prob.J, prob.h, s)
+            e = energy_from_field(I, prob.h, s)
         _track(res, e, s, start_step + t, target)
         if trace:
             energies.append(e)
@@ -253,10 +301,10 @@ def run_sequential(prob, beta, eta, seed, stream, trials, init=None, start_step=
     n = prob.n
     s = initial_spins(seed, stream, trials, n, prob.bits) if init is None \
         else np.asarray(init, dtype=np.int64).copy()
-    res = _result(len(trials), n)
+    res = _result(len(trials), n, prob.real)
     energies = []
     for t in range(steps + 1):
-        e = energy(prob.J, prob.h, s)
+        e = energy_f64(prob.J, prob.h, s) if prob.real else energy(prob.J, prob.h, s)
         _track(res, e, s, start_step + t, target)
         if trace:
             energies.append(e)
@@ -264,7 +312,8 @@ def run_sequential(prob, beta, eta, seed, stream, trials, init=None, start_step=
             break
         tg = start_step + t
         i = tg % n
-        I_i = prob.J[i] @ s + prob.h[i]
+        I_i = (prob.J[i].astype(np.float64) @ s.astype(np.float64) + prob.h[i]) if prob.real \
+            else prob.J[i] @ s + prob.h[i]
         a = _activation(prob, (beta[t] * prob.c) * I_i, act)
         z = _noise_values(prob, seed, stream, trials, tg, i, noise)
         s = s.copy()

@@ -7,7 +7,12 @@
   inverse-temperature shape; its constants are not printed, so they are
   arguments here);
 * the conventional PIM's constant beta with eta(t) = max(eta_scale / sqrt(t+1),
-  eta_floor) (Suppl. "Conventional PIM FPGA implementation for Max-cut and SK-1").
+  eta_floor) (Suppl. "Conventional PIM FPGA implementation for Max-cut and SK-1");
+* MIMO detection (Suppl. "PIMI FPGA implementation for MIMO detection", update
+  schedule): constant beta = 1 and eta(t) = sqrt(1 / (5 gamma(t))) with gamma
+  linear from gamma_init to gamma_final over the T steps (the two constants
+  are not printed, so they are arguments); the conventional PIM for MIMO uses
+  eta(t) = 1 / sqrt((t + 1) / 5).
 """
 import numpy as np
 
@@ -35,3 +40,17 @@ def conventional_eta(steps, eta_scale, eta_floor):
 
 def constant(steps, value):
     return np.full(steps, float(value), dtype=np.float64)
+
+
+def mimo_eta(steps, gamma_init, gamma_final):
+    if steps == 1:
+        gamma = np.array([float(gamma_init)], dtype=np.float64)
+    else:
+        t = np.arange(steps, dtype=np.float64)
+        gamma = gamma_init + ((gamma_final - gamma_init) * t) / (steps - 1)
+    return np.sqrt(1.0 / (5.0 * gamma))
+
+
+def mimo_conventional_eta(steps):
+    t = np.arange(steps, dtype=np.float64)
+    return 1.0 / np.sqrt((t + 1.0) / 5.0)
