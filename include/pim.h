@@ -69,7 +69,7 @@
 extern "C" {
 #endif
 
-#define PIM_ABI_VERSION 1
+#define PIM_ABI_VERSION 2
 
 /* Largest N accepted by pim_create (int8 couplings staged on chip). */
 #define PIM_MAX_N 256
@@ -90,9 +90,22 @@ typedef enum {
 } pim_noise;
 
 typedef enum {
-  PIM_KERNEL_MFMA_I8 = 0,   /* persistent batched sweep, int8 MFMA contraction       */
+  PIM_KERNEL_MFMA_I8 = 0,   /* persistent batched sweep on matrix cores: int8 MFMA for
+                               integer instances, FP8 / BF16 MFMA for real-valued ones */
   PIM_KERNEL_PLAIN_F32 = 1  /* one instance per launch, plain FP32 dot products      */
 } pim_kernel;
+
+/* Operand format of a real-valued instance in the batched MFMA kernel. */
+typedef enum {
+  PIM_PREC_FP8 = 1,   /* OCP e4m3; scale = max|J| / 448 rounded to binary32         */
+  PIM_PREC_BF16 = 2   /* bfloat16; scale = the power of two with max|J|/scale in [1,2) */
+} pim_prec;
+
+/* Ising mappings of a MIMO detection problem (pim_mimo_ising). */
+typedef enum {
+  PIM_MIMO_ML = 0,    /* x_m = 0; T = I (4-QAM) or [2I, I] (16-QAM)                  */
+  PIM_MIMO_DI = 1     /* x_m = sliced MMSE estimate; T = [I, I]                      */
+} pim_mimo_map;
 
 /* Per-instance constants of the update rule. */
 typedef struct {
@@ -116,7 +129,8 @@ typedef struct {
                                 start_step + T < 2^31                               */
   int32_t kernel;            /* pim_kernel                                          */
   int32_t use_target;        /* nonzero: record first step with E <= target        */
-  const int64_t* target;     /* host [instance count] integer energies, or NULL     */
+  const double* target;      /* host [instance count] energies, or NULL; integer
+                                instances compare E <= floor(target)                */
 } pim_schedule;
 
 typedef struct pim_instance pim_instance; /* device copy of one (J, h, params)       */
@@ -139,7 +153,27 @@ pim_status pim_set_allocator(pim_alloc_fn alloc, pim_free_fn free_fn, void* user
 pim_status pim_create(const int8_t* J, const int32_t* h, const pim_params* params,
                       void* stream, pim_instance** out);
 
-/* Groups `count` instances of equal N with `trials` trials each.  init_spins:
+/* Creates a real-valued instance (the MIMO detection instances of Suppl.
+ * "Delta-Ising MIMO (DI-MIMO) formulation"; the paper's FPGA keeps them in
+ * 16-bit fixed point, Suppl. "PIMI FPGA implementation for MIMO detection").
+ * J: host binary64 N x N, symmetric, zero diagonal, finite; h: host binary64
+ * [N] or NULL.  `prec` (pim_prec) selects the batched kernel's operand format:
+ * J is quantised once to scale * q, q in FP8 e4m3 or BF16 (round to nearest,
+ * ties to even, from binary64), and that kernel forms the field in binary32 as
+ *     I_i = fma(scale, sum_j q_ij s_j, fl32(h_i))   (sum on FP32-accumulating MFMA).
+ * The plain kernel uses fl32(J) and fl32(h) without quantisation.  The
+ * decisions are exactly Eq. (4)'s binary64 rule applied to that binary32
+ * field; energies used for ranking (pim_best, pim_energy) are binary64 with
+ * the original J and h.  Copies J and h; *out owns the device copies. */
+pim_status pim_create_real(const double* J, const double* h, const pim_params* params, int32_t prec,
+                           void* stream, pim_instance** out);
+
+/* Host-only: the couplings the batched kernel uses for a real instance, as
+ * binary64 values scale * q (J_out: N x N, may alias nothing), and the scale. */
+pim_status pim_quantize(const double* J, int32_t n, int32_t prec, double* J_out, double* scale_out);
+
+/* Groups `count` instances of equal N and kind (all integer, or all real with
+ * one pim_prec) with `trials` trials each.  init_spins:
  * host int8 [count][trials][N] of +-1, or NULL for generator-drawn initial
  * spins.  The batch keeps pointers to the instances, which must outlive it.
  * Trial a of instance k is trial id a in the generator counter. */
@@ -170,14 +204,16 @@ pim_status pim_energy(const pim_instance* inst, const int8_t* spins, int32_t cou
  * best state in binary64 on the device (once per run), takes the lowest
  * energy (ties: lowest trial id) and returns its state (host int8[N]), energy,
  * trial id and the step at which it occurred.  Any output may be NULL.
- * Synchronises the batch's stream. */
+ * For integer instances the tracked integer energy must equal the binary64
+ * value (PIM_ERR_DEVICE otherwise).  Synchronises the batch's stream. */
 pim_status pim_best(pim_batch* batch, int32_t inst, int8_t* spins_out, double* e_out,
                     int32_t* trial_out, int32_t* step_out);
 
 /* Per-trial results of instance `inst` (host arrays of length `trials`, or
  * trials*N for spins; any may be NULL): best energy, its step, first step at
  * or below target (-1 = never), final energy E(T), best and final states.
- * Synchronises. */
+ * Energies are the ones the kernel tracked: exact integers for integer
+ * instances, binary32 field energies for real ones.  Synchronises. */
 pim_status pim_trials(pim_batch* batch, int32_t inst, double* best_e, int32_t* best_step,
                       int32_t* first_hit, double* final_e, int8_t* best_spins,
                       int8_t* final_spins);
@@ -198,6 +234,34 @@ pim_status pim_compile_step(const pim_params* params, double beta, double eta,
  * s(t+1) = +1 iff I >= table[256 + (u ^ s)] with s = +-1 as a two's-complement
  * int (index 256 + (u ^ 1) for s = +1, 255 - u for s = -1).  table: int16[512]. */
 pim_status pim_compile_table(const pim_params* params, double beta, double eta, int16_t* table);
+
+/* Host-only: the 512-entry table of a real-valued batch's MFMA kernel for one
+ * step: s(t+1) = +1 iff I >= table[256 + (u ^ m)], m = 0 for s = +1 and -1 for
+ * s = -1 (index 256 + u, resp. 255 - u); entries are the smallest binary32
+ * field x with fl(fl(beta*c) * x) >= b_j for the bin that decides, or -inf
+ * (always +1) / +inf (never).  table: float[512]. */
+pim_status pim_compile_table_real(const pim_params* params, double beta, double eta, float* table);
+
+/* Ising instance of one uplink MIMO detection problem y = H x + n (Suppl.
+ * "MIMO problem definition", "Real-Valued equivalent", "Delta-Ising MIMO
+ * (DI-MIMO) formulation").  H: host complex [nr][nt] and y: complex [nr], both
+ * as interleaved (re, im) binary64.  qam: 4 or 16.  map: pim_mimo_map; the DI
+ * mapping's MMSE estimate uses the regulariser 1 / esn0 (Es/N0, linear).
+ * With the real-valued model (Hr, yr) and x = x_m + T s:
+ *     J = -2 zeroDiag(T^T Hr^T Hr T)   (Eq. (1) counts each pair once),
+ *     h = 2 T^T Hr^T (yr - Hr x_m),
+ * so E(s) of Eq. (1) = ||yr - Hr(x_m + T s)||^2 - const.  Outputs (host,
+ * binary64): J [n][n], h [n], x_m [2 nt] (real parts then imaginary parts);
+ * *n_out = 2 nt (ML, 4-QAM) or 4 nt.  Buffers must hold 4 nt x 4 nt, 4 nt and
+ * 2 nt values; 4 nt <= PIM_MAX_N. */
+pim_status pim_mimo_ising(const double* H, const double* y, int32_t nr, int32_t nt, int32_t qam, int32_t map,
+                          double esn0, double* J, double* h, double* xm, int32_t* n_out);
+
+/* Detected symbols of a spin vector s (host int8 [n] of +-1) under the same
+ * mapping: x = slice(x_m + T s), each real component sliced to the nearest
+ * odd-integer level (2 floor(v/2) + 1, clipped).  x: host complex [nt] as
+ * interleaved (re, im) binary64. */
+pim_status pim_mimo_decode(const double* xm, const int8_t* s, int32_t nt, int32_t qam, int32_t map, double* x);
 
 void pim_batch_destroy(pim_batch* batch);
 void pim_destroy(pim_instance* inst);

@@ -25,6 +25,11 @@ PIM_OK, PIM_ERR_INVALID, PIM_ERR_UNSUPPORTED, PIM_ERR_NOMEM = 0, 1, 2, 3
 PIM_ERR_DEVICE, PIM_ERR_STATE, PIM_ERR_CANCELLED = 4, 5, 6
 NOISE_GAUSS, NOISE_UNIFORM = 0, 1
 KERNEL_MFMA_I8, KERNEL_PLAIN_F32 = 0, 1
+PREC_FP8, PREC_BF16 = 1, 2
+MIMO_ML, MIMO_DI = 0, 1
+ABI_VERSION = 2
+_PRECS = {"fp8": PREC_FP8, "bf16": PREC_BF16}
+_MAPS = {"ml": MIMO_ML, "di": MIMO_DI}
 _KERNELS = {"mfma": KERNEL_MFMA_I8, "mfma_i8": KERNEL_MFMA_I8, "plain": KERNEL_PLAIN_F32,
             "plain_f32": KERNEL_PLAIN_F32}
 _NOISES = {"gauss": NOISE_GAUSS, "uniform": NOISE_UNIFORM}
@@ -34,6 +39,7 @@ EXPORTED = (
     "pim_set_allocator", "pim_create", "pim_batch_create", "pim_run", "pim_cancel",
     "pim_energy", "pim_best", "pim_trials", "pim_kernel_time", "pim_compile_step", "pim_compile_table",
     "pim_batch_destroy", "pim_destroy", "pim_last_error", "pim_abi_version",
+    "pim_create_real", "pim_quantize", "pim_compile_table_real", "pim_mimo_ising", "pim_mimo_decode",
 )
 
 
@@ -64,7 +70,7 @@ class Schedule(ctypes.Structure):
         ("start_step", ctypes.c_int32),
         ("kernel", ctypes.c_int32),
         ("use_target", ctypes.c_int32),
-        ("target", ctypes.POINTER(ctypes.c_int64)),
+        ("target", ctypes.POINTER(ctypes.c_double)),
     ]
 
 
@@ -93,11 +99,19 @@ def _load():
         "pim_destroy": (None, [VP]),
         "pim_last_error": (ctypes.c_char_p, []),
         "pim_abi_version": (I32, []),
+        "pim_create_real": (I32, [P(F64), P(F64), P(Params), I32, VP, P(VP)]),
+        "pim_quantize": (I32, [P(F64), I32, I32, P(F64), P(F64)]),
+        "pim_compile_table_real": (I32, [P(Params), F64, F64, P(ctypes.c_float)]),
+        "pim_mimo_ising": (I32, [P(F64), P(F64), I32, I32, I32, I32, F64, P(F64), P(F64), P(F64), P(I32)]),
+        "pim_mimo_decode": (I32, [P(F64), P(ctypes.c_int8), I32, I32, I32, P(F64)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
         fn.restype = res
         fn.argtypes = args
+    if lib.pim_abi_version() != ABI_VERSION:
+        raise ImportError(f"{LIB_PATH} implements ABI {lib.pim_abi_version()}, this binding needs {ABI_VERSION}; "
+                          "rebuild with `python paper_2604_17109_amd/build.py`")
     return lib
 
 
@@ -172,13 +186,18 @@ def make_params(n, j_scale, xi, levels=4, noise="gauss", noise_table=None, rng_s
     return p, keep
 
 
-def validate(J, h=None, *, j_scale, xi, levels=4, noise="gauss", noise_table=None, noise_bits=8):
-    """Runs pim_create's argument validation only (no device work): returns
-    None when the arguments are valid, else raises PimError.  Valid input is
-    detected by the library reaching its first device allocation, which this
-    call forbids through a refusing allocator."""
-    J = np.ascontiguousarray(J, dtype=np.int8)
-    hh = None if h is None else np.ascontiguousarray(h, dtype=np.int32)
+def validate(J, h=None, *, j_scale, xi, levels=4, noise="gauss", noise_table=None, noise_bits=8, prec=None):
+    """Runs pim_create's (``prec`` None) or pim_create_real's argument
+    validation only (no device work): returns None when the arguments are
+    valid, else raises PimError.  Valid input is detected by the library
+    reaching its first device allocation, which this call forbids through a
+    refusing allocator."""
+    real = prec is not None
+    J = np.ascontiguousarray(J, dtype=np.float64 if real else np.int8)
+    if h is None:
+        hh = None
+    else:
+        hh = np.ascontiguousarray(h, dtype=np.float64 if real else np.int32)
     p, keep = make_params(J.shape[0] if J.ndim == 2 else 0, j_scale, xi, levels, noise, noise_table,
                           noise_bits=noise_bits)
     handle = ctypes.c_void_p()
@@ -186,8 +205,13 @@ def validate(J, h=None, *, j_scale, xi, levels=4, noise="gauss", noise_table=Non
     prev = _torch_hooks
     _check(lib.pim_set_allocator(refuse[0], refuse[1], None))
     try:
-        st = lib.pim_create(_ptr(J, ctypes.c_int8), _ptr(hh, ctypes.c_int32), ctypes.byref(p), None,
-                            ctypes.byref(handle))
+        if real:
+            st = lib.pim_create_real(_ptr(J, ctypes.c_double), _ptr(hh, ctypes.c_double), ctypes.byref(p),
+                                     _PRECS.get(prec, -1) if isinstance(prec, str) else int(prec), None,
+                                     ctypes.byref(handle))
+        else:
+            st = lib.pim_create(_ptr(J, ctypes.c_int8), _ptr(hh, ctypes.c_int32), ctypes.byref(p), None,
+                                ctypes.byref(handle))
     finally:
         if prev is not None:
             _check(lib.pim_set_allocator(prev[0], prev[1], None))
@@ -221,23 +245,87 @@ def compile_table(n, j_scale, xi, beta, eta, levels=4, noise="gauss", noise_tabl
     return tab
 
 
+def compile_table_real(n, j_scale, xi, beta, eta, levels=4, noise="gauss", noise_table=None):
+    """Host-only: the 512-entry (u, s) binary32 field-threshold table of one
+    step for real-valued instances."""
+    p, keep = make_params(n, j_scale, xi, levels, noise, noise_table)
+    tab = np.zeros(512, dtype=np.float32)
+    _check(lib.pim_compile_table_real(ctypes.byref(p), float(beta), float(eta), _ptr(tab, ctypes.c_float)))
+    del keep
+    return tab
+
+
+def quantize(J, prec):
+    """Host-only: (couplings scale * q as float64, scale) that the batched kernel
+    uses for a real-valued J in precision "fp8" or "bf16"."""
+    J = np.ascontiguousarray(J, dtype=np.float64)
+    out = np.zeros_like(J)
+    scale = ctypes.c_double()
+    _check(lib.pim_quantize(_ptr(J, ctypes.c_double), J.shape[0], _PRECS[prec], _ptr(out, ctypes.c_double),
+                            ctypes.byref(scale)))
+    return out, scale.value
+
+
+def _complex_interleaved(z):
+    z = np.asarray(z, dtype=np.complex128)
+    return np.ascontiguousarray(np.stack([z.real, z.imag], axis=-1))
+
+
+def mimo_ising(H, y, qam, mapping="di", esn0=1.0):
+    """Ising instance of one MIMO detection problem y = H x + n (complex H
+    [nr, nt], y [nr]): returns (J [n, n], h [n], x_m [2 nt]), all float64."""
+    Hc = _complex_interleaved(H)
+    yc = _complex_interleaved(y)
+    nr, nt = Hc.shape[0], Hc.shape[1]
+    J = np.zeros((4 * nt, 4 * nt), np.float64)
+    h = np.zeros(4 * nt, np.float64)
+    xm = np.zeros(2 * nt, np.float64)
+    n = ctypes.c_int32()
+    _check(lib.pim_mimo_ising(_ptr(Hc, ctypes.c_double), _ptr(yc, ctypes.c_double), nr, nt, int(qam),
+                              _MAPS[mapping], float(esn0), _ptr(J, ctypes.c_double), _ptr(h, ctypes.c_double),
+                              _ptr(xm, ctypes.c_double), ctypes.byref(n)))
+    k = n.value
+    # the library writes J as a dense k x k block at the start of the buffer
+    return np.ascontiguousarray(J.reshape(-1)[: k * k].reshape(k, k)), h[:k].copy(), xm
+
+
+def mimo_decode(xm, spins, qam, mapping="di"):
+    """Detected complex symbols [nt] of a spin vector under the same mapping."""
+    xm = np.ascontiguousarray(xm, dtype=np.float64)
+    s = np.ascontiguousarray(spins, dtype=np.int8)
+    nt = xm.size // 2
+    x = np.zeros((nt, 2), np.float64)
+    _check(lib.pim_mimo_decode(_ptr(xm, ctypes.c_double), _ptr(s, ctypes.c_int8), nt, int(qam), _MAPS[mapping],
+                               _ptr(x, ctypes.c_double)))
+    return x[:, 0] + 1j * x[:, 1]
+
+
 class Instance:
-    """One integer Ising instance (J int8 symmetric, zero diagonal; h int32)
-    with its update-rule constants, copied to the device."""
+    """One Ising instance with its update-rule constants, copied to the device.
+
+    Integer instance (default): J int8 symmetric with zero diagonal, h int32.
+    Real-valued instance (``prec`` = "fp8" or "bf16"): J, h float64; the batched
+    kernel uses J quantised to ``prec`` with a per-instance scale."""
 
     def __init__(self, J, h=None, *, j_scale, xi, levels=4, noise="gauss", noise_table=None,
-                 rng_stream=0, stream=None):
-        J = np.ascontiguousarray(J, dtype=np.int8)
+                 rng_stream=0, prec=None, stream=None):
+        self.real = prec is not None
+        J = np.ascontiguousarray(J, dtype=np.float64 if self.real else np.int8)
         if J.ndim != 2 or J.shape[0] != J.shape[1]:
             raise ValueError("J must be square")
         self.n = J.shape[0]
-        hh = None if h is None else np.ascontiguousarray(h, dtype=np.int32)
         p, keep = make_params(self.n, j_scale, xi, levels, noise, noise_table, rng_stream)
         self._handle = ctypes.c_void_p()
         _device_ready()
         st = stream if stream is not None else current_stream()
-        _check(lib.pim_create(_ptr(J, ctypes.c_int8), _ptr(hh, ctypes.c_int32), ctypes.byref(p), st,
-                              ctypes.byref(self._handle)))
+        if self.real:
+            hh = None if h is None else np.ascontiguousarray(h, dtype=np.float64)
+            _check(lib.pim_create_real(_ptr(J, ctypes.c_double), _ptr(hh, ctypes.c_double), ctypes.byref(p),
+                                       _PRECS[prec], st, ctypes.byref(self._handle)))
+        else:
+            hh = None if h is None else np.ascontiguousarray(h, dtype=np.int32)
+            _check(lib.pim_create(_ptr(J, ctypes.c_int8), _ptr(hh, ctypes.c_int32), ctypes.byref(p), st,
+                                  ctypes.byref(self._handle)))
         del keep
 
     @property
@@ -295,9 +383,9 @@ class Batch:
         sc.kernel = _KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
         tgt = None
         if target is not None:
-            tgt = np.ascontiguousarray(np.broadcast_to(np.asarray(target, dtype=np.int64), (self.count,)))
+            tgt = np.ascontiguousarray(np.broadcast_to(np.asarray(target, dtype=np.float64), (self.count,)))
             sc.use_target = 1
-            sc.target = _ptr(tgt, ctypes.c_int64)
+            sc.target = _ptr(tgt, ctypes.c_double)
         if stream is not None:
             self.stream = stream
         _check(lib.pim_run(self._handle, ctypes.byref(sc), ctypes.c_uint64(int(seed) & (2**64 - 1)),

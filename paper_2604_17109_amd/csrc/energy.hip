@@ -1,4 +1,5 @@
-// Binary64 evaluation of Eq. (1) for candidate configurations, and the
+// Binary64 evaluation of Eq. (1) for candidate configurations (integer
+// couplings staged as int8 or FP32, real ones as binary64), and the
 // per-instance selection of the lowest-energy trial (the paper's host keeps
 // the lowest-energy configuration of all returned states):
 //   E = -1/2 (sum_ij s_i J_ij s_j + 2 sum_i h_i s_i).
@@ -33,12 +34,45 @@ __device__ double config_energy(const float* J, int jstride, const int32_t* h, c
   return -0.5 * wave_sum(acc);
 }
 
+// Real-valued couplings: binary64 J (row-major n x n) and h.
+__device__ double config_energy_real(const double* J, const double* h, const int8_t* s, int n, int lane) {
+  double acc = 0.0;
+  for (int i = 0; i < n; ++i) {
+    const double* Ji = J + (size_t)i * n;
+    double row = 0.0;
+    for (int j = lane; j < n; j += 64) row += Ji[j] * (double)s[j];
+    acc += (double)s[i] * row;
+  }
+  if (h)
+    for (int j = lane; j < n; j += 64) acc += 2.0 * h[j] * (double)s[j];
+  return -0.5 * wave_sum(acc);
+}
+
 __global__ __launch_bounds__(64 * kWavesPerBlock) void energy_f64_kernel(EnergyArgs a) {
   const int lane = threadIdx.x & 63;
   const int cfg = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6);
   if (cfg >= a.count) return;
-  const double e = config_energy(a.jf32, a.jstride, a.h, a.spins + (size_t)cfg * a.stride, a.n, lane);
+  const int8_t* s = a.spins + (size_t)cfg * a.stride;
+  const double e = a.jf64 ? config_energy_real(a.jf64, a.hf64, s, a.n, lane)
+                          : config_energy(a.jf32, a.jstride, a.h, s, a.n, lane);
   if (lane == 0) a.out[cfg] = e;
+}
+
+// Re-rank for real-valued instances: one wave per candidate, binary64 J rows
+// read from global memory (too large for LDS at N = 256), lanes over columns.
+__global__ __launch_bounds__(64 * kWavesPerBlock) void rerank_real_kernel(RerankArgs a) {
+  __shared__ __align__(16) int8_t sS[kWavesPerBlock][PIM_MAX_N];
+  const int inst = blockIdx.y;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int trial = blockIdx.x * kWavesPerBlock + wave;
+  if (trial >= a.R) return;  // wave-uniform; no block barrier follows
+  const size_t cell = (size_t)inst * a.R + trial;
+  const int8_t* s = a.best_s + cell * a.npad;
+  for (int i = lane; i < a.n; i += 64) sS[wave][i] = s[i];
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  const double e = config_energy_real(a.j64[inst], a.h64 ? a.h64[inst] : nullptr, sS[wave], a.n, lane);
+  if (lane == 0) a.energy[cell] = e;
 }
 
 // Batch re-rank of every trial's best state.  One block per (instance, 16
@@ -141,8 +175,13 @@ hipError_t launch_energy_f64(const EnergyArgs& a, hipStream_t s) {
 
 hipError_t launch_rerank_select(const RerankArgs& a, hipStream_t s) {
   if (a.n > PIM_MAX_N) return hipErrorInvalidValue;
-  const dim3 grid((a.R + kRerankTrialsPerBlock - 1) / kRerankTrialsPerBlock, a.count);
-  hipLaunchKernelGGL(rerank_kernel, grid, dim3(64 * kWavesPerBlock), 0, s, a);
+  if (a.j64) {
+    const dim3 grid((a.R + kWavesPerBlock - 1) / kWavesPerBlock, a.count);
+    hipLaunchKernelGGL(rerank_real_kernel, grid, dim3(64 * kWavesPerBlock), 0, s, a);
+  } else {
+    const dim3 grid((a.R + kRerankTrialsPerBlock - 1) / kRerankTrialsPerBlock, a.count);
+    hipLaunchKernelGGL(rerank_kernel, grid, dim3(64 * kWavesPerBlock), 0, s, a);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(select_best_kernel, dim3(a.count), dim3(256), 0, s, a);

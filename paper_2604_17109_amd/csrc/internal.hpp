@@ -23,6 +23,7 @@ constexpr int kFieldLimit = 32766;           // |I| bound that keeps thresholds 
 constexpr int kMaxLevels = 16;
 
 struct Rule {
+  bool real = false;         // real-valued couplings (binary64 J, h)
   int n = 0;
   double c = 0, xi = 0;
   int levels = 0;
@@ -30,7 +31,7 @@ struct Rule {
   std::vector<double> ztab;  // 2^B non-decreasing
   uint32_t stream = 0;
   bool same_table_class(const Rule& o) const {
-    return c == o.c && xi == o.xi && levels == o.levels && ztab == o.ztab;
+    return real == o.real && c == o.c && xi == o.xi && levels == o.levels && ztab == o.ztab;
   }
 };
 
@@ -42,6 +43,12 @@ void compile_step(const Rule& r, double beta, double eta, int32_t* theta, int32_
 // Field threshold per (u, s): s(t+1) = +1  <=>  I >= tab[kNoiseVals + (u ^ s)],
 // s = +-1 as a two's-complement int (u ^ 1 for s = +1, ~u for s = -1).
 void theta_by_noise(const int32_t* theta, const int32_t* umin, int levels, int16_t* tab);
+// Real-valued fields: theta[j-1] is the smallest float x with
+// fl(fl(beta*c) * x) >= b_j (-inf: every finite field, +inf: none); umin as above.
+void compile_step_real(const Rule& r, double beta, double eta, float* theta, int32_t* umin);
+// Float field threshold per (u, s): s(t+1) = +1  <=>  I >= tab[kNoiseVals + (u ^ m)]
+// with m = 0 for s = +1 and m = -1 for s = -1 (index u, resp. ~u).
+void theta_by_noise_real(const float* theta, const int32_t* umin, int levels, float* tab);
 // Built-in quantile table of a noise law; false if unknown.
 bool builtin_noise_table(int noise, std::vector<double>& out);
 
@@ -66,10 +73,34 @@ struct SweepArgs {
   uint32_t k0, k1;
 };
 
+// Real-valued instances: spins and states as in SweepArgs; energies binary32
+// (stored in the int32 stat arrays as their bit patterns).
+struct SweepRealArgs {
+  const uint8_t* jfrag;      // [count][frag bytes] quantised couplings in fragment order
+  const float* scale;        // [count]
+  const float* h;            // [count][npad] or nullptr
+  const float* thtab;        // [classes][T][kTabEntries]
+  const int32_t* inst_class; // [count]
+  const uint32_t* inst_stream;  // [count]
+  const float* target;       // [count] or nullptr
+  const int8_t* init;        // [count][R][npad] or nullptr
+  int8_t* final_s;           // [count][R][npad]
+  int8_t* best_s;            // [count][R][npad]
+  float* e_best;             // [count][R]
+  int32_t* t_best;
+  int32_t* first_hit;
+  float* e_final;
+  int32_t* steps_done;
+  const volatile int32_t* cancel;
+  int32_t n, npad, R, T, start_step;
+  uint32_t k0, k1;
+};
+
 struct PlainArgs {
   const float* jf32;         // [npad][jstride] of one instance, zero-padded
-  const int32_t* h;          // [n] or nullptr
-  const int32_t* steptab;    // [T][(L-1) + 2L] theta then umin
+  const int32_t* h;          // [n] or nullptr (integer instances)
+  const float* hf;           // [n] or nullptr (real instances)
+  const int32_t* steptab;    // [T][(L-1) + 2L] theta (int32, or float bits) then umin
   const int8_t* init;        // [R][npad] or nullptr
   int8_t* final_s;           // [R][npad]
   int8_t* best_s;
@@ -84,8 +115,10 @@ struct PlainArgs {
 };
 
 struct EnergyArgs {
-  const float* jf32;   // [>= n][jstride]
+  const float* jf32;   // [>= n][jstride] (integer instances)
   const int32_t* h;    // [n] or nullptr
+  const double* jf64;  // [n][n] (real instances; then jf32 / h unused)
+  const double* hf64;  // [n] or nullptr
   const int8_t* spins; // [count][stride]
   double* out;         // [count]
   int32_t n, jstride, stride, count;
@@ -94,6 +127,8 @@ struct EnergyArgs {
 struct RerankArgs {
   const int8_t* const* j8;     // [count] device pointers to each instance's int8 J (n x n)
   const int32_t* const* h;     // [count] device pointers to h, or nullptr (no fields)
+  const double* const* j64;    // real instances: [count] binary64 J (n x n); then j8 / h unused
+  const double* const* h64;    // real instances: [count] binary64 h, or nullptr
   const int8_t* best_s;        // [count][R][npad]
   const int32_t* t_best;       // [count][R]
   const int32_t* e_best;       // [count][R]
@@ -108,54 +143,77 @@ struct RerankArgs {
 
 hipError_t launch_rerank_select(const RerankArgs& a, hipStream_t s);
 hipError_t launch_sweep_mfma(const SweepArgs& a, int count, int nt, bool has_h, hipStream_t s);
-hipError_t launch_sweep_plain(const PlainArgs& a, hipStream_t s);
+hipError_t launch_sweep_plain(const PlainArgs& a, bool real, hipStream_t s);
+hipError_t launch_sweep_real(const SweepRealArgs& a, int count, int nt, int prec, bool has_h, hipStream_t s);
+size_t real_frag_bytes(int prec, int nt);
 hipError_t launch_energy_f64(const EnergyArgs& a, hipStream_t s);
 
-// Host packing of J into the MFMA fragment order (sweep_mfma.hip).
+// Host packing of J into the MFMA fragment order (sweep_mfma.hip, sweep_real.hip).
 void pack_mfma_fragments(const int8_t* J, int n, int nt, int8_t* out);
+void pack_real_fragments(const double* J, int n, int nt, int prec, float scale, uint8_t* out);
+
+// ---- quantisation (quant.cpp) ---------------------------------------------
+uint8_t fp8_e4m3_rne(double x);
+double fp8_e4m3_value(uint8_t c);
+uint16_t bf16_rne(double x);
+double bf16_value(uint16_t c);
+float real_scale(const double* J, size_t count, int prec);
+double quantized_value(double x, int prec, float scale);
 
 }  // namespace pim
 
 // ---- handles ------------------------------------------------------------
 struct pim_instance {
-  pim::Rule rule;
+  pim::Rule rule;                 // rule.real: real-valued instance
+  int prec = 0;                   // real instances: PIM_PREC_*
+  float scale = 1.0f;             // real instances: J ~ scale * q
   int npad = 0, nt = 0;
   int jstride = 0;                // row stride of d_jf32: n rounded up to 4
+  size_t frag_bytes = 0;
   bool has_h = false;
-  int8_t* d_jfrag = nullptr;
+  int8_t* d_jfrag = nullptr;      // int8, FP8 or BF16 MFMA fragments
   float* d_jf32 = nullptr;        // [npad][jstride] FP32 J, zero-padded
-  int8_t* d_j8 = nullptr;         // row-major int8 J (re-rank)
-  int32_t* d_h = nullptr;
+  int8_t* d_j8 = nullptr;         // row-major int8 J (re-rank; integer instances)
+  int32_t* d_h = nullptr;         // [npad] (integer instances)
+  float* d_hf = nullptr;          // [npad] fl32(h) (real instances)
+  double* d_j64 = nullptr;        // [n][n] binary64 J (real instances)
+  double* d_h64 = nullptr;        // [n] binary64 h (real instances)
 };
 
 struct pim_batch {
   std::vector<pim_instance*> insts;
   int count = 0, R = 0, n = 0, npad = 0, nt = 0;
+  bool real = false;
+  int prec = 0;
+  size_t frag_bytes = 0;          // per instance
   bool has_h = false;
   hipStream_t stream = nullptr;
   // device buffers
   int8_t* d_jfrag = nullptr;      // concatenated fragments of all instances
-  int32_t* d_h = nullptr;
+  int32_t* d_h = nullptr;         // [count][npad] int32 (integer) or float (real) fields
+  float* d_scale = nullptr;       // [count] (real)
   int8_t* d_init = nullptr;
   int8_t* d_final = nullptr;
   int8_t* d_best = nullptr;
   int32_t* d_stats = nullptr;     // 5 x [count][R]: e_best, t_best, first_hit, e_final, steps_done
   int32_t* d_class = nullptr;
   uint32_t* d_stream_ids = nullptr;
-  int32_t* d_target = nullptr;
+  int32_t* d_target = nullptr;    // int32 (integer) or float (real) targets
   double* d_rerank = nullptr;     // [count][R]
   // per-instance selection (device, then one readback): ptr tables + outputs
   const int8_t** d_jptrs = nullptr;
   const int32_t** d_hptrs = nullptr;
+  const double** d_j64ptrs = nullptr;
+  const double** d_h64ptrs = nullptr;
   int8_t* d_sel_spins = nullptr;  // [count][npad]
   double* d_sel_e = nullptr;      // [count]
   int32_t* d_sel_i = nullptr;     // [count][3]: trial, step, tracked energy
   std::vector<int8_t> h_sel_spins;
   std::vector<double> h_sel_e;
   std::vector<int32_t> h_sel_i;
-  int16_t* d_thtab = nullptr;
+  void* d_thtab = nullptr;        // int16 (integer) or float (real) step tables
   size_t thtab_bytes = 0;
-  int16_t* h_thtab = nullptr;     // pinned staging of the step tables
+  void* h_thtab = nullptr;        // pinned staging of the step tables
   size_t h_thtab_bytes = 0;
   int32_t* d_steptab = nullptr;
   size_t steptab_bytes = 0;

@@ -166,6 +166,9 @@ void free_batch_buffers(pim_batch* b) {
   dev_free(b->d_steptab, s);
   dev_free((void*)b->d_jptrs, s);
   dev_free((void*)b->d_hptrs, s);
+  dev_free((void*)b->d_j64ptrs, s);
+  dev_free((void*)b->d_h64ptrs, s);
+  dev_free(b->d_scale, s);
   dev_free(b->d_sel_spins, s);
   dev_free(b->d_sel_e, s);
   dev_free(b->d_sel_i, s);
@@ -185,6 +188,8 @@ pim_status ensure_selection(pim_batch* b) {
   RerankArgs ra{};
   ra.j8 = b->d_jptrs;
   ra.h = b->has_h ? b->d_hptrs : nullptr;
+  ra.j64 = b->real ? b->d_j64ptrs : nullptr;
+  ra.h64 = (b->real && b->has_h) ? b->d_h64ptrs : nullptr;
   ra.best_s = b->d_best;
   ra.t_best = stat_ptr(b, 1);
   ra.e_best = stat_ptr(b, 0);
@@ -290,6 +295,109 @@ pim_status pim_compile_table(const pim_params* params, double beta, double eta, 
   }
 }
 
+pim_status pim_compile_table_real(const pim_params* params, double beta, double eta, float* table) {
+  try {
+    Rule r;
+    pim_status st = validate_params(params, r);
+    if (st != PIM_OK) return st;
+    if (!finite_nonneg(beta) || !finite_nonneg(eta)) return fail(PIM_ERR_INVALID, "beta and eta must be finite and >= 0");
+    if (!table) return fail(PIM_ERR_INVALID, "output pointer is NULL");
+    float th[kMaxLevels];
+    int32_t um[2 * kMaxLevels];
+    compile_step_real(r, beta, eta, th, um);
+    theta_by_noise_real(th, um, r.levels, table);
+    return PIM_OK;
+  } catch (...) {
+    return fail(PIM_ERR_INVALID, "internal error in pim_compile_table_real");
+  }
+}
+
+pim_status pim_quantize(const double* J, int32_t n, int32_t prec, double* J_out, double* scale_out) {
+  if (!J || !J_out) return fail(PIM_ERR_INVALID, "NULL argument");
+  if (n < 1 || n > PIM_MAX_N) return fail(PIM_ERR_INVALID, "n = %d outside [1, %d]", n, PIM_MAX_N);
+  if (prec != PIM_PREC_FP8 && prec != PIM_PREC_BF16) return fail(PIM_ERR_INVALID, "unknown precision %d", prec);
+  const size_t nn = (size_t)n * n;
+  for (size_t i = 0; i < nn; ++i)
+    if (!std::isfinite(J[i])) return fail(PIM_ERR_INVALID, "J is not finite");
+  const float scale = real_scale(J, nn, prec);
+  for (size_t i = 0; i < nn; ++i) J_out[i] = (double)scale * quantized_value(J[i], prec, scale);
+  if (scale_out) *scale_out = scale;
+  return PIM_OK;
+}
+
+pim_status pim_create_real(const double* J, const double* h, const pim_params* params, int32_t prec, void* stream,
+                           pim_instance** out) {
+  try {
+    if (!out) return fail(PIM_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    Rule r;
+    pim_status st = validate_params(params, r);
+    if (st != PIM_OK) return st;
+    if (prec != PIM_PREC_FP8 && prec != PIM_PREC_BF16) return fail(PIM_ERR_INVALID, "unknown precision %d", prec);
+    if (!J) return fail(PIM_ERR_INVALID, "J is NULL");
+    const int n = r.n;
+    for (int i = 0; i < n; ++i) {
+      if (J[(size_t)i * n + i] != 0.0) return fail(PIM_ERR_INVALID, "J[%d][%d] != 0 (diagonal must be zero)", i, i);
+      if (h && !std::isfinite(h[i])) return fail(PIM_ERR_INVALID, "h[%d] is not finite", i);
+      for (int j = 0; j < n; ++j) {
+        const double v = J[(size_t)i * n + j];
+        if (!std::isfinite(v)) return fail(PIM_ERR_INVALID, "J[%d][%d] is not finite", i, j);
+        if (v != J[(size_t)j * n + i]) return fail(PIM_ERR_INVALID, "J is not symmetric at (%d, %d)", i, j);
+      }
+    }
+    r.real = true;
+    hipStream_t s = (hipStream_t)stream;
+    auto* inst = new pim_instance();
+    inst->rule = std::move(r);
+    inst->prec = prec;
+    inst->nt = (n + 31) / 32;
+    inst->npad = inst->nt * 32;
+    inst->jstride = (n + 3) & ~3;
+    inst->has_h = false;
+    if (h)
+      for (int i = 0; i < n; ++i) inst->has_h |= (h[i] != 0.0);
+    inst->scale = real_scale(J, (size_t)n * n, prec);
+    inst->frag_bytes = real_frag_bytes(prec, inst->nt);
+    std::vector<uint8_t> frag(inst->frag_bytes);
+    pack_real_fragments(J, n, inst->nt, prec, inst->scale, frag.data());
+    std::vector<float> jf((size_t)inst->npad * inst->jstride, 0.0f);
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) jf[(size_t)i * inst->jstride + j] = (float)J[(size_t)i * n + j];
+    std::vector<float> hf(inst->npad, 0.0f);
+    std::vector<double> h64(n, 0.0);
+    if (h)
+      for (int i = 0; i < n; ++i) {
+        hf[i] = (float)h[i];
+        h64[i] = h[i];
+      }
+    st = alloc_dev(&inst->d_jfrag, frag.size(), s);
+    if (st == PIM_OK) st = alloc_dev(&inst->d_jf32, jf.size(), s);
+    if (st == PIM_OK) st = alloc_dev(&inst->d_hf, hf.size(), s);
+    if (st == PIM_OK) st = alloc_dev(&inst->d_j64, (size_t)n * n, s);
+    if (st == PIM_OK) st = alloc_dev(&inst->d_h64, (size_t)n, s);
+    if (st != PIM_OK) {
+      pim_destroy(inst);
+      return st;
+    }
+    hipError_t e = hipMemcpyAsync(inst->d_jfrag, frag.data(), frag.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(inst->d_jf32, jf.data(), jf.size() * 4, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(inst->d_hf, hf.data(), hf.size() * 4, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(inst->d_j64, J, (size_t)n * n * 8, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(inst->d_h64, h64.data(), (size_t)n * 8, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+      pim_destroy(inst);
+      return fail(PIM_ERR_DEVICE, "copying the instance to the device failed: %s", hipGetErrorString(e));
+    }
+    *out = inst;
+    return PIM_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(PIM_ERR_NOMEM, "host allocation failed");
+  } catch (...) {
+    return fail(PIM_ERR_INVALID, "internal error in pim_create_real");
+  }
+}
+
 pim_status pim_create(const int8_t* J, const int32_t* h, const pim_params* params, void* stream,
                       pim_instance** out) {
   try {
@@ -309,7 +417,8 @@ pim_status pim_create(const int8_t* J, const int32_t* h, const pim_params* param
     inst->has_h = false;
     if (h)
       for (int i = 0; i < n; ++i) inst->has_h |= (h[i] != 0);
-    std::vector<int8_t> frag((size_t)inst->nt * inst->nt * 1024);
+    inst->frag_bytes = (size_t)inst->nt * inst->nt * 1024;
+    std::vector<int8_t> frag(inst->frag_bytes);
     pack_mfma_fragments(J, n, inst->nt, frag.data());
     inst->jstride = (n + 3) & ~3;
     std::vector<float> jf((size_t)inst->npad * inst->jstride, 0.0f);
@@ -349,6 +458,9 @@ void pim_destroy(pim_instance* inst) {
   dev_free(inst->d_jf32, nullptr);
   dev_free(inst->d_h, nullptr);
   dev_free(inst->d_j8, nullptr);
+  dev_free(inst->d_hf, nullptr);
+  dev_free(inst->d_j64, nullptr);
+  dev_free(inst->d_h64, nullptr);
   delete inst;
 }
 
@@ -365,6 +477,8 @@ pim_status pim_batch_create(pim_instance* const* insts, int32_t count, int32_t t
       if (insts[k]->rule.n != insts[0]->rule.n)
         return fail(PIM_ERR_UNSUPPORTED, "instances of different N in one batch (%d vs %d)", insts[k]->rule.n,
                     insts[0]->rule.n);
+      if (insts[k]->rule.real != insts[0]->rule.real || insts[k]->prec != insts[0]->prec)
+        return fail(PIM_ERR_UNSUPPORTED, "integer and real instances, or two precisions, in one batch");
     }
     const int n = insts[0]->rule.n;
     if (init_spins) {
@@ -379,6 +493,9 @@ pim_status pim_batch_create(pim_instance* const* insts, int32_t count, int32_t t
     b->n = n;
     b->nt = insts[0]->nt;
     b->npad = insts[0]->npad;
+    b->real = insts[0]->rule.real;
+    b->prec = insts[0]->prec;
+    b->frag_bytes = insts[0]->frag_bytes;
     b->stream = s;
     for (int k = 0; k < count; ++k) b->has_h |= insts[k]->has_h;
     // table classes: instances whose compiled tables coincide share one
@@ -393,7 +510,7 @@ pim_status pim_batch_create(pim_instance* const* insts, int32_t count, int32_t t
       }
       b->inst_class[k] = cls;
     }
-    const size_t frag = (size_t)b->nt * b->nt * 1024;
+    const size_t frag = b->frag_bytes;
     const size_t cells = (size_t)count * trials;
     pim_status st = alloc_dev(&b->d_jfrag, frag * count, s);
     if (st == PIM_OK) st = alloc_dev(&b->d_h, (size_t)count * b->npad, s);
@@ -407,6 +524,9 @@ pim_status pim_batch_create(pim_instance* const* insts, int32_t count, int32_t t
     if (st == PIM_OK && init_spins) st = alloc_dev(&b->d_init, cells * b->npad, s);
     if (st == PIM_OK) st = alloc_dev(&b->d_jptrs, (size_t)count, s);
     if (st == PIM_OK) st = alloc_dev(&b->d_hptrs, (size_t)count, s);
+    if (st == PIM_OK) st = alloc_dev(&b->d_j64ptrs, (size_t)count, s);
+    if (st == PIM_OK) st = alloc_dev(&b->d_h64ptrs, (size_t)count, s);
+    if (st == PIM_OK) st = alloc_dev(&b->d_scale, (size_t)count, s);
     if (st == PIM_OK) st = alloc_dev(&b->d_sel_spins, (size_t)count * b->npad, s);
     if (st == PIM_OK) st = alloc_dev(&b->d_sel_e, (size_t)count, s);
     if (st == PIM_OK) st = alloc_dev(&b->d_sel_i, (size_t)3 * count, s);
@@ -425,16 +545,27 @@ pim_status pim_batch_create(pim_instance* const* insts, int32_t count, int32_t t
     std::vector<uint32_t> sid(count);
     std::vector<const int8_t*> jp(count);
     std::vector<const int32_t*> hp(count);
+    std::vector<const double*> jp64(count), hp64(count);
+    std::vector<float> scales(count);
     for (int k = 0; k < count; ++k) {
       sid[k] = insts[k]->rule.stream;
       jp[k] = insts[k]->d_j8;
       hp[k] = insts[k]->d_h;
+      jp64[k] = insts[k]->d_j64;
+      hp64[k] = insts[k]->d_h64;
+      scales[k] = insts[k]->scale;
     }
     for (int k = 0; k < count && e == hipSuccess; ++k) {
       e = hipMemcpyAsync(b->d_jfrag + frag * k, insts[k]->d_jfrag, frag, hipMemcpyDeviceToDevice, s);
+      const void* hsrc = b->real ? (const void*)insts[k]->d_hf : (const void*)insts[k]->d_h;
       if (e == hipSuccess)
-        e = hipMemcpyAsync(b->d_h + (size_t)k * b->npad, insts[k]->d_h, b->npad * 4, hipMemcpyDeviceToDevice, s);
+        e = hipMemcpyAsync(b->d_h + (size_t)k * b->npad, hsrc, b->npad * 4, hipMemcpyDeviceToDevice, s);
     }
+    if (e == hipSuccess)
+      e = hipMemcpyAsync((void*)b->d_j64ptrs, jp64.data(), count * sizeof(void*), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync((void*)b->d_h64ptrs, hp64.data(), count * sizeof(void*), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(b->d_scale, scales.data(), count * 4, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(b->d_class, b->inst_class.data(), count * 4, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(b->d_stream_ids, sid.data(), count * 4, hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
@@ -491,35 +622,54 @@ pim_status pim_run(pim_batch* b, const pim_schedule* sc, uint64_t seed, void* st
     for (int t = 0; t < T; ++t)
       if (!finite_nonneg(sc->beta[t]) || !finite_nonneg(sc->eta[t]))
         return fail(PIM_ERR_INVALID, "beta[%d] / eta[%d] must be finite and >= 0", t, t);
+    for (int k = 0; sc->use_target && k < b->count; ++k)
+      if (std::isnan(sc->target[k])) return fail(PIM_ERR_INVALID, "target[%d] is NaN", k);
+    // targets: integer batches compare E <= floor(target), real ones in binary32
     std::vector<int32_t> tgt(b->count, INT32_MIN);
+    std::vector<float> tgtf(b->count, -INFINITY);
     if (sc->use_target)
-      for (int k = 0; k < b->count; ++k)
-        tgt[k] = (int32_t)std::max<int64_t>(std::min<int64_t>(sc->target[k], INT32_MAX), INT32_MIN + 1);
+      for (int k = 0; k < b->count; ++k) {
+        const double f = std::floor(sc->target[k]);
+        tgt[k] = f >= (double)INT32_MAX ? INT32_MAX : (f <= (double)INT32_MIN + 1 ? INT32_MIN + 1 : (int32_t)f);
+        // largest binary32 value <= target, so E <= tgtf <=> E <= target for binary32 E
+        float tf = (float)sc->target[k];
+        if ((double)tf > sc->target[k]) tf = std::nextafter(tf, -INFINITY);
+        tgtf[k] = tf;
+      }
     hipStream_t s = stream ? (hipStream_t)stream : b->stream;
     b->stream = s;
     const int L = b->insts[0]->rule.levels;
     const int ncls = (int)b->class_rep.size();
+    const bool real = b->real;
     // ---- compile ----
     std::vector<int32_t> steptab;
     const bool mfma = sc->kernel == PIM_KERNEL_MFMA_I8;
+    const size_t entry = real ? 4 : 2;  // bytes per table entry
     if (mfma) {
-      const size_t need = (size_t)ncls * T * kTabEntries;
-      if (need * 2 > b->h_thtab_bytes) {
+      const size_t need = (size_t)ncls * T * kTabEntries * entry;
+      if (need > b->h_thtab_bytes) {
         if (b->h_thtab) (void)hipHostFree(b->h_thtab);
         b->h_thtab = nullptr;
         b->h_thtab_bytes = 0;
-        if (hipHostMalloc((void**)&b->h_thtab, need * 2, hipHostMallocDefault) != hipSuccess)
-          return fail(PIM_ERR_NOMEM, "pinned staging allocation of %zu bytes failed", need * 2);
-        b->h_thtab_bytes = need * 2;
+        if (hipHostMalloc(&b->h_thtab, need, hipHostMallocDefault) != hipSuccess)
+          return fail(PIM_ERR_NOMEM, "pinned staging allocation of %zu bytes failed", need);
+        b->h_thtab_bytes = need;
       }
-      int16_t* out = b->h_thtab;
+      void* out = b->h_thtab;
       parallel_for(T * ncls, [&](int lo, int hi) {
         int32_t th[kMaxLevels], um[2 * kMaxLevels];
+        float thf[kMaxLevels];
         for (int i = lo; i < hi; ++i) {
           const int c = i / T, t = i % T;
           const Rule& r = b->insts[b->class_rep[c]]->rule;
-          compile_step(r, sc->beta[t], sc->eta[t], th, um);
-          theta_by_noise(th, um, r.levels, out + ((size_t)c * T + t) * kTabEntries);
+          const size_t off = ((size_t)c * T + t) * kTabEntries;
+          if (real) {
+            compile_step_real(r, sc->beta[t], sc->eta[t], thf, um);
+            theta_by_noise_real(thf, um, r.levels, static_cast<float*>(out) + off);
+          } else {
+            compile_step(r, sc->beta[t], sc->eta[t], th, um);
+            theta_by_noise(th, um, r.levels, static_cast<int16_t*>(out) + off);
+          }
         }
       });
     } else {
@@ -532,19 +682,25 @@ pim_status pim_run(pim_batch* b, const pim_schedule* sc, uint64_t seed, void* st
         const Rule& r = b->insts[b->class_rep[c]]->rule;
         for (int t = 0; t < T; ++t) {
           int32_t* row = &steptab[((size_t)c * T + t) * w];
-          compile_step(r, sc->beta[t], sc->eta[t], row, row + (L - 1));
+          if (real) {
+            float thf[kMaxLevels];
+            compile_step_real(r, sc->beta[t], sc->eta[t], thf, row + (L - 1));
+            std::memcpy(row, thf, (L - 1) * sizeof(float));  // float bits in the int32 row
+          } else {
+            compile_step(r, sc->beta[t], sc->eta[t], row, row + (L - 1));
+          }
         }
       }
     }
     // ---- upload ----
-    const size_t thtab_need = mfma ? (size_t)ncls * T * kTabEntries : 0;
-    if (mfma && thtab_need * 2 > b->thtab_bytes) {
+    const size_t thtab_need = mfma ? (size_t)ncls * T * kTabEntries * entry : 0;
+    if (mfma && thtab_need > b->thtab_bytes) {
       dev_free(b->d_thtab, s);
       b->d_thtab = nullptr;
       b->thtab_bytes = 0;
-      pim_status st = alloc_dev(&b->d_thtab, thtab_need, s);
-      if (st != PIM_OK) return st;
-      b->thtab_bytes = thtab_need * 2;
+      b->d_thtab = dev_alloc(thtab_need, s);
+      if (!b->d_thtab) return fail(PIM_ERR_NOMEM, "device allocation of %zu bytes failed", thtab_need);
+      b->thtab_bytes = thtab_need;
     }
     if (!mfma && steptab.size() * 4 > b->steptab_bytes) {
       dev_free(b->d_steptab, s);
@@ -559,9 +715,11 @@ pim_status pim_run(pim_batch* b, const pim_schedule* sc, uint64_t seed, void* st
       return fail(PIM_ERR_DEVICE, "%s failed: %s", what, hipGetErrorString(e));
     };
     hipError_t e = hipSuccess;
-    if (mfma) e = hipMemcpyAsync(b->d_thtab, b->h_thtab, (size_t)ncls * T * kTabEntries * 2, hipMemcpyHostToDevice, s);
+    if (mfma) e = hipMemcpyAsync(b->d_thtab, b->h_thtab, thtab_need, hipMemcpyHostToDevice, s);
     else e = hipMemcpyAsync(b->d_steptab, steptab.data(), steptab.size() * 4, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(b->d_target, tgt.data(), b->count * 4, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(b->d_target, real ? (const void*)tgtf.data() : (const void*)tgt.data(), b->count * 4,
+                         hipMemcpyHostToDevice, s);
     // the host tables must stay alive until the copies are done
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return device_fail(e, "schedule upload");
@@ -570,11 +728,11 @@ pim_status pim_run(pim_batch* b, const pim_schedule* sc, uint64_t seed, void* st
     e = hipEventRecord(b->ev0, s);
     if (e != hipSuccess) return device_fail(e, "hipEventRecord");
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
-    if (mfma) {
+    if (mfma && !real) {
       SweepArgs a{};
       a.jfrag = b->d_jfrag;
       a.h = b->has_h ? b->d_h : nullptr;
-      a.thtab = b->d_thtab;
+      a.thtab = static_cast<const int16_t*>(b->d_thtab);
       a.inst_class = b->d_class;
       a.inst_stream = b->d_stream_ids;
       a.target = sc->use_target ? b->d_target : nullptr;
@@ -596,13 +754,41 @@ pim_status pim_run(pim_batch* b, const pim_schedule* sc, uint64_t seed, void* st
       a.k1 = k1;
       e = launch_sweep_mfma(a, b->count, b->nt, b->has_h, s);
       if (e != hipSuccess) return device_fail(e, "sweep launch");
+    } else if (mfma) {
+      SweepRealArgs a{};
+      a.jfrag = reinterpret_cast<const uint8_t*>(b->d_jfrag);
+      a.scale = b->d_scale;
+      a.h = b->has_h ? reinterpret_cast<const float*>(b->d_h) : nullptr;
+      a.thtab = static_cast<const float*>(b->d_thtab);
+      a.inst_class = b->d_class;
+      a.inst_stream = b->d_stream_ids;
+      a.target = sc->use_target ? reinterpret_cast<const float*>(b->d_target) : nullptr;
+      a.init = b->d_init;
+      a.final_s = b->d_final;
+      a.best_s = b->d_best;
+      a.e_best = reinterpret_cast<float*>(stat_ptr(b, 0));
+      a.t_best = stat_ptr(b, 1);
+      a.first_hit = stat_ptr(b, 2);
+      a.e_final = reinterpret_cast<float*>(stat_ptr(b, 3));
+      a.steps_done = stat_ptr(b, 4);
+      a.cancel = b->d_cancel;
+      a.n = b->n;
+      a.npad = b->npad;
+      a.R = b->R;
+      a.T = T;
+      a.start_step = sc->start_step;
+      a.k0 = k0;
+      a.k1 = k1;
+      e = launch_sweep_real(a, b->count, b->nt, b->prec, b->has_h, s);
+      if (e != hipSuccess) return device_fail(e, "sweep launch");
     } else {
       const int w = (L - 1) + 2 * L;
       for (int k = 0; k < b->count && e == hipSuccess; ++k) {
         const size_t cell0 = (size_t)k * b->R;
         PlainArgs a{};
         a.jf32 = b->insts[k]->d_jf32;
-        a.h = b->insts[k]->has_h ? b->insts[k]->d_h : nullptr;
+        a.h = (!real && b->insts[k]->has_h) ? b->insts[k]->d_h : nullptr;
+        a.hf = (real && b->insts[k]->has_h) ? b->insts[k]->d_hf : nullptr;
         a.steptab = b->d_steptab + (size_t)b->inst_class[k] * T * w;
         a.init = b->d_init ? b->d_init + cell0 * b->npad : nullptr;
         a.final_s = b->d_final + cell0 * b->npad;
@@ -621,11 +807,12 @@ pim_status pim_run(pim_batch* b, const pim_schedule* sc, uint64_t seed, void* st
         a.start_step = sc->start_step;
         a.levels = L;
         a.use_target = sc->use_target ? 1 : 0;
-        a.target = tgt[k];
+        if (real) std::memcpy(&a.target, &tgtf[k], 4);
+        else a.target = tgt[k];
         a.stream = b->insts[k]->rule.stream;
         a.k0 = k0;
         a.k1 = k1;
-        e = launch_sweep_plain(a, s);
+        e = launch_sweep_plain(a, real, s);
       }
       if (e != hipSuccess) return device_fail(e, "plain sweep launch");
     }
@@ -670,7 +857,9 @@ pim_status pim_energy(const pim_instance* inst, const int8_t* spins, int32_t cou
     }
     EnergyArgs ea{};
     ea.jf32 = inst->d_jf32;
-    ea.h = inst->has_h ? inst->d_h : nullptr;
+    ea.h = (!inst->rule.real && inst->has_h) ? inst->d_h : nullptr;
+    ea.jf64 = inst->rule.real ? inst->d_j64 : nullptr;
+    ea.hf64 = (inst->rule.real && inst->has_h) ? inst->d_h64 : nullptr;
     ea.spins = d_s;
     ea.out = d_o;
     ea.n = n;
@@ -704,7 +893,7 @@ pim_status pim_best(pim_batch* b, int32_t inst, int8_t* spins_out, double* e_out
     const int32_t trial = b->h_sel_i[inst];
     const int32_t step = b->h_sel_i[b->count + inst];
     const int32_t tracked = b->h_sel_i[2 * b->count + inst];
-    if ((double)tracked != e)
+    if (!b->real && (double)tracked != e)
       return fail(PIM_ERR_DEVICE, "tracked energy %d disagrees with the binary64 re-evaluation %.17g", tracked, e);
     if (spins_out) std::memcpy(spins_out, &b->h_sel_spins[(size_t)inst * b->npad], b->n);
     if (e_out) *e_out = e;
@@ -735,9 +924,15 @@ pim_status pim_trials(pim_batch* b, int32_t inst, double* best_e, int32_t* best_
       HIP_TRY(hipStreamSynchronize(b->stream));
       return PIM_OK;
     };
+    auto energy_of = [&](int32_t v) -> double {
+      if (!b->real) return (double)v;
+      float f;
+      std::memcpy(&f, &v, 4);
+      return (double)f;
+    };
     if (best_e) {
       if ((st = fetch(0, tmp)) != PIM_OK) return st;
-      for (int a = 0; a < R; ++a) best_e[a] = tmp[a];
+      for (int a = 0; a < R; ++a) best_e[a] = energy_of(tmp[a]);
     }
     if (best_step) {
       if ((st = fetch(1, tmp)) != PIM_OK) return st;
@@ -749,7 +944,7 @@ pim_status pim_trials(pim_batch* b, int32_t inst, double* best_e, int32_t* best_
     }
     if (final_e) {
       if ((st = fetch(3, tmp)) != PIM_OK) return st;
-      for (int a = 0; a < R; ++a) final_e[a] = tmp[a];
+      for (int a = 0; a < R; ++a) final_e[a] = energy_of(tmp[a]);
     }
     if (best_spins || final_spins) {
       std::vector<int8_t> sp((size_t)R * b->npad);

@@ -16,8 +16,10 @@
 //
 // This file is compiled with -ffp-contract=off: no fused multiply-add may
 // change a rounding.
+#include <cfloat>
 #include <cmath>
 #include <cstdint>
+#include <cstring>
 #include <vector>
 
 #include "internal.hpp"
@@ -51,10 +53,9 @@ int32_t field_threshold(double g, double b) {
 
 }  // namespace
 
-void compile_step(const Rule& r, double beta, double eta, int32_t* theta, int32_t* umin) {
+// umin[2k + (s<0)]: smallest u with s(t+1) = +1 in LUT bin k (2^B if none).
+void compile_umin(const Rule& r, double eta, int32_t* umin) {
   const int L = r.levels;
-  const double g = beta * r.c;
-  for (int j = 1; j < L; ++j) theta[j - 1] = field_threshold(g, breakpoint(j, L));
   const int nu = (int)r.ztab.size();
   for (int k = 0; k < L; ++k) {
     for (int sneg = 0; sneg < 2; ++sneg) {
@@ -69,6 +70,68 @@ void compile_step(const Rule& r, double beta, double eta, int32_t* theta, int32_
         if (up) hi = mid; else lo = mid + 1;
       }
       umin[2 * k + sneg] = lo;
+    }
+  }
+}
+
+void compile_step(const Rule& r, double beta, double eta, int32_t* theta, int32_t* umin) {
+  const int L = r.levels;
+  const double g = beta * r.c;
+  for (int j = 1; j < L; ++j) theta[j - 1] = field_threshold(g, breakpoint(j, L));
+  compile_umin(r, eta, umin);
+}
+
+namespace {
+// Total order of the floats as unsigned keys: -inf < ... < -0 < +0 < ... < +inf.
+uint32_t float_key(float f) {
+  uint32_t b;
+  std::memcpy(&b, &f, 4);
+  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+float key_float(uint32_t k) {
+  const uint32_t b = (k & 0x80000000u) ? (k & 0x7FFFFFFFu) : ~k;
+  float f;
+  std::memcpy(&f, &b, 4);
+  return f;
+}
+
+// Smallest float x with fl(g * x) >= b (x converted to binary64 exactly):
+// -inf when every finite x qualifies, +inf when none does.  fl(g * x) is
+// non-decreasing in x for g >= 0, so the predicate is monotone over the key
+// order and a bisection over the 2^32 keys finds the boundary.  -0 and +0
+// share the predicate's value, so the result is never +0.
+float field_threshold_real(double g, double b) {
+  auto ok = [&](float x) { return g * (double)x >= b; };
+  if (ok(-FLT_MAX)) return -INFINITY;
+  if (!ok(FLT_MAX)) return INFINITY;
+  uint32_t lo = float_key(-FLT_MAX), hi = float_key(FLT_MAX);  // ok(lo) false, ok(hi) true
+  while (hi - lo > 1) {
+    const uint32_t mid = lo + (hi - lo) / 2;
+    if (ok(key_float(mid))) hi = mid; else lo = mid;
+  }
+  return key_float(hi);
+}
+}  // namespace
+
+void compile_step_real(const Rule& r, double beta, double eta, float* theta, int32_t* umin) {
+  const int L = r.levels;
+  const double g = beta * r.c;
+  for (int j = 1; j < L; ++j) theta[j - 1] = field_threshold_real(g, breakpoint(j, L));
+  compile_umin(r, eta, umin);
+}
+
+void theta_by_noise_real(const float* theta, const int32_t* umin, int levels, float* tab) {
+  // as theta_by_noise, over float fields, with index u for s = +1 and ~u for
+  // s = -1 relative to the centre kNoiseVals
+  for (int sneg = 0; sneg < 2; ++sneg) {
+    for (int m = 0; m <= levels; ++m) {
+      const int lo = (m == levels) ? 0 : umin[2 * m + sneg];
+      const int hi = (m == 0) ? kNoiseVals : umin[2 * (m - 1) + sneg];
+      float th;
+      if (m == 0) th = -INFINITY;
+      else if (m >= levels) th = INFINITY;
+      else th = theta[m - 1];
+      for (int u = lo; u < hi; ++u) tab[kNoiseVals + (sneg ? ~u : u)] = th;
     }
   }
 }

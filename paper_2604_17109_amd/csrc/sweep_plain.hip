@@ -9,9 +9,15 @@
 // k = #{j : I >= theta_j}, s' = +1 iff u >= umin[2k + (s<0)].  FP32 sums of
 // integers below 2^24 are exact, so both kernels produce identical
 // trajectories.
+//
+// Real-valued instances use the same kernel with binary32 fields I = sum_j
+// fl32(J_ij) s_j + fl32(h_i), binary32 thresholds (smallest binary32 field that
+// reaches each LUT breakpoint under the binary64 rule) and binary32 energies
+// reduced in a fixed order.
 #include <hip/hip_runtime.h>
 
 #include <climits>
+#include <cmath>
 #include <cstdint>
 
 #include "internal.hpp"
@@ -25,9 +31,11 @@ constexpr int kBlocks = PIM_MAX_N / 16;  // spin blocks of 16
 constexpr int kThreads = kTrials * kBlocks;
 constexpr int kRow = PIM_MAX_N + 8;      // LDS row stride (floats) of one trial's spins
 
+template <bool REAL>
 __global__ __launch_bounds__(kThreads) void sweep_plain_kernel(PlainArgs a) {
   __shared__ __align__(16) float sS[kTrials][kRow];
   __shared__ int32_t sE[kTrials];
+  __shared__ float sEf[kBlocks][kTrials];  // per-block partial energies (REAL)
   const int b = threadIdx.x / kTrials;
   const int al = threadIdx.x % kTrials;
   const int trial = blockIdx.x * kTrials + al;
@@ -60,6 +68,9 @@ __global__ __launch_bounds__(kThreads) void sweep_plain_kernel(PlainArgs a) {
   __syncthreads();
 
   int32_t e_best = INT_MAX, t_best = -1, first_hit = -1, e_cur = 0;
+  float ef_best = INFINITY, ef_cur = 0.0f;
+  float target_f;
+  __builtin_memcpy(&target_f, &a.target, 4);
   int done = a.T;
   for (int t = 0;; ++t) {
     const int tg = a.start_step + t;
@@ -85,20 +96,44 @@ __global__ __launch_bounds__(kThreads) void sweep_plain_kernel(PlainArgs a) {
         }
       }
       int32_t ep = 0;
+      float epf = 0.0f;
 #pragma unroll
       for (int q = 0; q < 16; ++q) {
         const int i = 16 * b + q;
         s_old[q] = sS[al][i];
-        const int hv = (a.h && i < a.n) ? a.h[min(i, a.n - 1)] : 0;
-        I[q] += (float)hv;
-        if (i < a.n) ep += (int32_t)s_old[q] * ((int32_t)I[q] + hv);
+        if (REAL) {
+          const float hv = (a.hf && i < a.n) ? a.hf[min(i, a.n - 1)] : 0.0f;
+          I[q] += hv;
+          if (i < a.n) epf += s_old[q] * (I[q] + hv);
+        } else {
+          const int hv = (a.h && i < a.n) ? a.h[min(i, a.n - 1)] : 0;
+          I[q] += (float)hv;
+          if (i < a.n) ep += (int32_t)s_old[q] * ((int32_t)I[q] + hv);
+        }
       }
-      atomicAdd(&sE[al], ep);
+      if (REAL) sEf[b][al] = epf;
+      else atomicAdd(&sE[al], ep);
+    } else if (REAL) {
+      sEf[b][al] = 0.0f;
     }
     __syncthreads();
-    const int32_t E = -(sE[al] / 2);
-    if (E < e_best) {
-      e_best = E;
+    bool improved;
+    if (REAL) {
+      float tot = 0.0f;
+      for (int k = 0; k < kBlocks; ++k) tot += sEf[k][al];  // fixed order
+      const float E = -0.5f * tot;
+      improved = E < ef_best;
+      if (improved) ef_best = E;
+      if (a.use_target && first_hit < 0 && E <= target_f) first_hit = tg;
+      ef_cur = E;
+    } else {
+      const int32_t E = -(sE[al] / 2);
+      improved = E < e_best;
+      if (improved) e_best = E;
+      if (a.use_target && first_hit < 0 && E <= a.target) first_hit = tg;
+      e_cur = E;
+    }
+    if (improved) {
       t_best = tg;
       if (owner && live)
         for (int q = 0; q < 16; ++q) {
@@ -106,8 +141,6 @@ __global__ __launch_bounds__(kThreads) void sweep_plain_kernel(PlainArgs a) {
           if (i < a.npad) a.best_s[cell * a.npad + i] = (int8_t)s_old[q];
         }
     }
-    if (a.use_target && first_hit < 0 && E <= a.target) first_hit = tg;
-    e_cur = E;
     if (t == a.T) break;
     if ((t & 255) == 0 && __atomic_load_n(a.cancel, __ATOMIC_RELAXED) != 0) {
       done = t;
@@ -122,7 +155,7 @@ __global__ __launch_bounds__(kThreads) void sweep_plain_kernel(PlainArgs a) {
 #pragma unroll
       for (int q = 0; q < 16; ++q) {
         int k = 0;
-        for (int j = 0; j < L - 1; ++j) k += (I[q] >= (float)row[j]) ? 1 : 0;
+        for (int j = 0; j < L - 1; ++j) k += (I[q] >= (REAL ? __int_as_float(row[j]) : (float)row[j])) ? 1 : 0;
         const int sneg = s_old[q] < 0.0f ? 1 : 0;
         const int umin = row[(L - 1) + 2 * k + sneg];
         const int u = (int)((xw[q >> 2] >> (8 * (q & 3))) & 0xFFu);
@@ -143,20 +176,21 @@ __global__ __launch_bounds__(kThreads) void sweep_plain_kernel(PlainArgs a) {
       if (i < a.npad) a.final_s[cell * a.npad + i] = (int8_t)sS[al][i];
     }
   if (b == 0 && live) {
-    a.e_best[cell] = e_best;
+    a.e_best[cell] = REAL ? __float_as_int(ef_best) : e_best;
     a.t_best[cell] = t_best;
     a.first_hit[cell] = first_hit;
-    a.e_final[cell] = e_cur;
+    a.e_final[cell] = REAL ? __float_as_int(ef_cur) : e_cur;
     a.steps_done[cell] = done;
   }
 }
 
 }  // namespace
 
-hipError_t launch_sweep_plain(const PlainArgs& a, hipStream_t s) {
+hipError_t launch_sweep_plain(const PlainArgs& a, bool real, hipStream_t s) {
   if (a.n > PIM_MAX_N) return hipErrorInvalidValue;
   const dim3 grid((a.R + kTrials - 1) / kTrials);
-  hipLaunchKernelGGL(sweep_plain_kernel, grid, dim3(kThreads), 0, s, a);
+  if (real) hipLaunchKernelGGL(sweep_plain_kernel<true>, grid, dim3(kThreads), 0, s, a);
+  else hipLaunchKernelGGL(sweep_plain_kernel<false>, grid, dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }
 

@@ -1,0 +1,409 @@
+// Persistent PIMI sweep for real-valued couplings on FP8 / BF16 MFMA (gfx950).
+//
+// Same organisation as the int8 sweep: one workgroup per (instance, up to four
+// 32-trial blocks), the instance's quantised couplings staged once in LDS, one
+// wave per 32 trials (the MFMA N dimension) holding its spins in registers in
+// B-operand layout for the whole run, no barrier inside the step loop.
+//
+//   I[Npad x 32] = scale * (Q[Npad x Npad] . S[Npad x 32]) + h
+//     FP8:  v_mfma_f32_32x32x64_f8f6f4 (OCP e4m3 operands, FP32 accumulation)
+//     BF16: v_mfma_f32_32x32x16_bf16
+//
+// Layout.  Output register r of lane l (column l % 32, half hh = l / 32) holds
+// row 8(r/4) + 4hh + r%4, carrying spin 32mt + 16hh + r of row tile mt, as in
+// the int8 kernel.  A-slot (hh, p) of a lane pairs with B-slot (hh, p): with
+// FP8 (K = 64, 32 slots per half) slot (hh, p) of K step kk carries spin
+// 32(2kk + p/16) + 16hh + p%16, i.e. the lane's own 16 spins of row tiles 2kk
+// and 2kk+1; with BF16 (K = 16, 8 slots) slot (hh, p) of step (kt, j) carries
+// spin 32kt + 16hh + 8j + p.  So new spins go from the accumulator to the next
+// step's B operand inside the lane, and a lane-half's 16 spins of a tile are
+// one Philox block.  Spins are +-1 encoded in the operand format (FP8 0x38 /
+// 0xB8, BF16 0x3F80 / 0xBF80).
+//
+// Decision.  The host compiles each step into 512 binary32 field thresholds
+// over (noise index u, sign of s): s(t+1) = +1 iff I >= tab[u ^ m], m = 0 for
+// s = +1 and -1 for s = -1 (relative to the table centre).  I - tab is
+// negative exactly when I < tab (also for +-inf thresholds), so its sign bit is
+// the new spin's sign.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <climits>
+#include <cmath>
+#include <cstdint>
+
+#include "internal.hpp"
+#include "philox.hpp"
+
+namespace pim {
+namespace {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v8i __attribute__((ext_vector_type(8)));
+typedef float v16f __attribute__((ext_vector_type(16)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+constexpr int kMaxWaves = 4;
+constexpr int kRealTabBytes = kTabEntries * 4;  // 2 KB per step table
+static_assert(kRealTabBytes == 64 * 32, "two 16-byte chunks per lane");
+
+#define PIM_FENCE(v) asm volatile("" : "+v"(v))
+
+// v4i words per row tile per lane: 16 spins of 1 (FP8) or 2 (BF16) bytes.
+template <int PREC> constexpr int words() { return PREC == PIM_PREC_FP8 ? 1 : 2; }
+
+constexpr size_t frag_bytes(int prec, int nt) {
+  return prec == PIM_PREC_FP8 ? (size_t)nt * ((nt + 1) / 2) * 2048 : (size_t)nt * nt * 2048;
+}
+
+__device__ __forceinline__ uint32_t perm(uint32_t hi, uint32_t lo, uint32_t sel) {
+  return __builtin_amdgcn_perm(hi, lo, sel);
+}
+
+// int8 spin bytes (+1 = 0x01, -1 = 0xFF) <-> operand encodings
+__device__ __forceinline__ uint32_t fp8_from_i8(uint32_t w) { return (w & 0x80808080u) | 0x38383838u; }
+__device__ __forceinline__ uint32_t bf16_lo_from_i8(uint32_t w) {  // bytes 0, 1 -> two bf16
+  return (perm(w, w, 0x010C000Cu) & 0x80008000u) | 0x3F803F80u;
+}
+__device__ __forceinline__ uint32_t bf16_hi_from_i8(uint32_t w) {  // bytes 2, 3
+  return (perm(w, w, 0x030C020Cu) & 0x80008000u) | 0x3F803F80u;
+}
+__device__ __forceinline__ uint32_t i8_from_fp8(uint32_t w) { return 0x01010101u + 0xFEu * ((w >> 7) & 0x01010101u); }
+__device__ __forceinline__ uint32_t i8_from_bf16(uint32_t w0, uint32_t w1) {
+  return perm(w1, w0, 0x0B0A0908u) | 0x01010101u;  // sign bits 15 and 31 of each word
+}
+__device__ __forceinline__ int spins_from_bits(uint32_t w) {
+  return (int)(0xFFFFFFFFu - 0xFEu * ((w >> 7) & 0x01010101u));
+}
+
+// 0 for a +1 spin, -1 for a -1 spin: spin r of the lane's 16 in a tile.
+template <int PREC>
+__device__ __forceinline__ int spin_mask(const uint32_t (&sw)[4 * words<PREC>()], int r) {
+  if (PREC == PIM_PREC_FP8) return __builtin_amdgcn_sbfe((int)sw[r >> 2], 8 * (r & 3) + 7, 1);
+  return __builtin_amdgcn_sbfe((int)sw[r >> 1], 16 * (r & 1) + 15, 1);
+}
+
+__device__ __forceinline__ Ctr4 noise_block(uint32_t block, int tg, uint32_t trial, uint32_t stream,
+                                            uint32_t k0, uint32_t k1) {
+  return philox4x32_10(Ctr4{block, (uint32_t)tg, trial, (kDomainNoise << 24) | stream}, k0, k1);
+}
+
+// I' = Q . S for row tile mt (before scale and h).
+template <int NT, int PREC>
+__device__ __forceinline__ void real_row_tile(const unsigned char* sJ, int lane, int mt,
+                                              const v4i (&B)[NT][words<PREC>()], v16f& acc) {
+  acc = v16f{};
+  if constexpr (PREC == PIM_PREC_FP8) {
+    constexpr int NK = (NT + 1) / 2;
+    const v8i* f = reinterpret_cast<const v8i*>(sJ) + lane;
+#pragma unroll
+    for (int kk = 0; kk < NK; ++kk) {
+      const v8i A = f[(mt * NK + kk) * 64];
+      const v4i b0 = B[2 * kk][0];
+      const v4i b1 = (2 * kk + 1 < NT) ? B[2 * kk + 1 < NT ? 2 * kk + 1 : 0][0] : v4i{0, 0, 0, 0};
+      const v8i Bv = __builtin_shufflevector(b0, b1, 0, 1, 2, 3, 4, 5, 6, 7);
+      acc = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(A, Bv, acc, 0, 0, 0, 0, 0, 0);
+    }
+  } else {
+    const v4i* f = reinterpret_cast<const v4i*>(sJ) + lane;
+#pragma unroll
+    for (int kt = 0; kt < NT; ++kt)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const v4i A = f[((mt * NT + kt) * 2 + j) * 64];
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(v8bf, A), __builtin_bit_cast(v8bf, B[kt][j]),
+                                                      acc, 0, 0, 0);
+      }
+  }
+}
+
+template <int NT, int PREC, bool HAS_H>
+__global__ __launch_bounds__(64 * kMaxWaves) void sweep_real_kernel(SweepRealArgs a) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  constexpr int KW = words<PREC>();
+  constexpr int kFragBytes = (int)frag_bytes(PREC, NT);
+  constexpr int kNpad = NT * 32;
+  constexpr int kHBytes = HAS_H ? kNpad * 4 : 0;
+  const int nw = blockDim.x >> 6;
+  const int inst = blockIdx.y;
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int col = lane & 31;
+  const int half = lane >> 5;
+
+  {  // stage the instance: quantised couplings and h
+    const uint4* src = reinterpret_cast<const uint4*>(a.jfrag + (size_t)inst * kFragBytes);
+    uint4* dst = reinterpret_cast<uint4*>(lds);
+    for (int i = threadIdx.x; i < kFragBytes / 16; i += blockDim.x) dst[i] = src[i];
+    if (HAS_H) {
+      float* sh = reinterpret_cast<float*>(lds + kFragBytes);
+      for (int i = threadIdx.x; i < kNpad; i += blockDim.x) sh[i] = a.h[(size_t)inst * kNpad + i];
+    }
+  }
+  const unsigned char* sJ = lds;
+  const float* sH = reinterpret_cast<const float*>(lds + kFragBytes);
+  float* sTab = reinterpret_cast<float*>(lds + kFragBytes + kHBytes + wave * kRealTabBytes);
+  uint4* sTab4 = reinterpret_cast<uint4*>(sTab);
+  __syncthreads();  // the only workgroup barrier
+
+  const int tbase = (blockIdx.x * nw + wave) * 32;
+  if (tbase >= a.R) return;
+  const int trial = tbase + col;
+  const bool live = trial < a.R;
+  const size_t cell = (size_t)inst * a.R + trial;
+  const uint32_t stream = a.inst_stream[inst];
+  const int cls = a.inst_class[inst];
+  const uint4* gTab4 = reinterpret_cast<const uint4*>(a.thtab + (size_t)cls * a.T * kTabEntries);
+  const float target = a.target ? a.target[inst] : -INFINITY;
+  const float scale = a.scale[inst];
+  const uint32_t k0 = a.k0, k1 = a.k1;
+
+  // ---- s(0) ----
+  v4i B[NT][KW];
+#pragma unroll
+  for (int mt = 0; mt < NT; ++mt) {
+    uint32_t w[4];
+    if (a.init) {
+      const v4i v = live ? *reinterpret_cast<const v4i*>(a.init + cell * kNpad + 32 * mt + 16 * half)
+                         : v4i{0x01010101, 0x01010101, 0x01010101, 0x01010101};
+      for (int q = 0; q < 4; ++q) w[q] = (uint32_t)v[q];
+    } else {
+      const Ctr4 x = philox4x32_10(Ctr4{(uint32_t)(2 * mt + half), 0u, (uint32_t)trial,
+                                        (kDomainInit << 24) | stream}, k0, k1);
+      w[0] = spins_from_bits(x.x);
+      w[1] = spins_from_bits(x.y);
+      w[2] = spins_from_bits(x.z);
+      w[3] = spins_from_bits(x.w);
+    }
+    if (PREC == PIM_PREC_FP8) {
+      for (int q = 0; q < 4; ++q) B[mt][0][q] = (int)fp8_from_i8(w[q]);
+    } else {
+      for (int q = 0; q < 4; ++q) {
+        B[mt][q >> 1][2 * (q & 1)] = (int)bf16_lo_from_i8(w[q]);
+        B[mt][q >> 1][2 * (q & 1) + 1] = (int)bf16_hi_from_i8(w[q]);
+      }
+    }
+  }
+
+  float e_best = INFINITY, e_cur = 0.0f;
+  int32_t t_best = -1, first_hit = -1;
+  Ctr4 x_next = noise_block((uint32_t)half, a.start_step, (uint32_t)trial, stream, k0, k1);
+  int done = a.T;
+  sTab4[lane] = gTab4[lane];
+  sTab4[64 + lane] = gTab4[64 + lane];
+
+  for (int t = 0;; ++t) {
+    const int tg = a.start_step + t;
+    float ep = 0.0f;
+    v4i Bn[NT][KW];
+    const bool last = (t == a.T);
+    const bool has_next = t + 1 < a.T;
+    const size_t nrow = (size_t)min(t + 1, a.T - 1) * 128;
+    const uint4 nxt0 = gTab4[nrow + lane];
+    const uint4 nxt1 = gTab4[nrow + 64 + lane];
+    const float* tab = sTab + kNoiseVals;
+    uint32_t ctr_trial = (uint32_t)trial;
+    uint32_t ctr_half = (uint32_t)half;
+    PIM_FENCE(ctr_trial);
+    PIM_FENCE(ctr_half);
+    v16f acc_next;
+    real_row_tile<NT, PREC>(sJ, lane, 0, B, acc_next);
+#pragma unroll
+    for (int mt = 0; mt < NT; ++mt) {
+      const v16f acc = acc_next;
+      uint32_t xw[4] = {x_next.x, x_next.y, x_next.z, x_next.w};
+      uint32_t sw[4 * KW];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) PIM_FENCE(xw[q]);
+#pragma unroll
+      for (int q = 0; q < 4 * KW; ++q) {
+        sw[q] = (uint32_t)B[mt][q >> 2][q & 3];
+        PIM_FENCE(sw[q]);
+      }
+      int lane_off = lane;
+      PIM_FENCE(lane_off);
+      int hoff = 32 * mt + 16 * half;
+      if (HAS_H) PIM_FENCE(hoff);
+      // (1) LDS: the field thresholds of this tile
+      float th[16];
+      int sm[16];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        sm[r] = spin_mask<PREC>(sw, r);
+        const int idx = (int)((xw[r >> 2] >> (8 * (r & 3))) & 0xFFu) ^ sm[r];
+        th[r] = tab[idx];
+      }
+      // (2) the next tile's MFMA chain and noise block
+      if (mt + 1 < NT) real_row_tile<NT, PREC>(sJ, lane_off, mt + 1, B, acc_next);
+      if (mt + 1 < NT) x_next = noise_block(2u * (mt + 1) + ctr_half, tg, ctr_trial, stream, k0, k1);
+      else x_next = noise_block(ctr_half, tg + 1, ctr_trial, stream, k0, k1);
+      // (3) energy of s(t) and the decisions of this tile
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        float d[4];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const int r = 4 * q + b;
+          float I, v;
+          if (HAS_H) {
+            const float hv = sH[hoff + r];
+            I = fmaf(scale, acc[r], hv);
+            v = I + hv;
+          } else {
+            I = scale * acc[r];
+            v = I;
+          }
+          ep += __uint_as_float(__float_as_uint(v) ^ ((uint32_t)sm[r] & 0x80000000u));  // s * v
+          d[b] = I - th[r];  // sign bit set <=> s(t+1) = -1
+        }
+        const uint32_t d0 = __float_as_uint(d[0]), d1 = __float_as_uint(d[1]);
+        const uint32_t d2 = __float_as_uint(d[2]), d3 = __float_as_uint(d[3]);
+        if (PREC == PIM_PREC_FP8) {
+          const uint32_t sgn = perm(d1, d0, 0x0C0C0B09u) | perm(d3, d2, 0x0B090C0Cu);
+          Bn[mt][0][q] = (int)((sgn & 0x80808080u) | 0x38383838u);
+        } else {
+          Bn[mt][q >> 1][2 * (q & 1)] = (int)((perm(d1, d0, 0x0B0C090Cu) & 0x80008000u) | 0x3F803F80u);
+          Bn[mt][q >> 1][2 * (q & 1) + 1] = (int)((perm(d3, d2, 0x0B0C090Cu) & 0x80008000u) | 0x3F803F80u);
+        }
+      }
+      PIM_FENCE(ep);
+#pragma unroll
+      for (int j = 0; j < KW; ++j)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) PIM_FENCE(Bn[mt][j][q]);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    const float E = -0.5f * (ep + __shfl_xor(ep, 32));
+    if (E < e_best) {
+      e_best = E;
+      t_best = tg;
+      if (live) {
+        size_t off = cell * kNpad + 16 * half;
+        PIM_FENCE(off);
+        int8_t* dst = a.best_s + off;
+#pragma unroll
+        for (int mt = 0; mt < NT; ++mt) {
+          v4i o;
+          if (PREC == PIM_PREC_FP8) {
+            for (int q = 0; q < 4; ++q) o[q] = (int)i8_from_fp8((uint32_t)B[mt][0][q]);
+          } else {
+            for (int q = 0; q < 4; ++q)
+              o[q] = (int)i8_from_bf16((uint32_t)B[mt][q >> 1][2 * (q & 1)], (uint32_t)B[mt][q >> 1][2 * (q & 1) + 1]);
+          }
+          *reinterpret_cast<v4i*>(dst + 32 * mt) = o;
+        }
+      }
+    }
+    if (first_hit < 0 && E <= target) first_hit = tg;
+    e_cur = E;
+    if (last) break;
+    if ((t & 255) == 0 && __atomic_load_n(a.cancel, __ATOMIC_RELAXED) != 0) {
+      done = t;
+      break;
+    }
+#pragma unroll
+    for (int mt = 0; mt < NT; ++mt)
+#pragma unroll
+      for (int j = 0; j < KW; ++j) B[mt][j] = Bn[mt][j];
+    if (has_next) {
+      sTab4[lane] = nxt0;
+      sTab4[64 + lane] = nxt1;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+  }
+
+  if (!live) return;
+#pragma unroll
+  for (int mt = 0; mt < NT; ++mt) {
+    v4i o;
+    if (PREC == PIM_PREC_FP8) {
+      for (int q = 0; q < 4; ++q) o[q] = (int)i8_from_fp8((uint32_t)B[mt][0][q]);
+    } else {
+      for (int q = 0; q < 4; ++q)
+        o[q] = (int)i8_from_bf16((uint32_t)B[mt][q >> 1][2 * (q & 1)], (uint32_t)B[mt][q >> 1][2 * (q & 1) + 1]);
+    }
+    *reinterpret_cast<v4i*>(a.final_s + cell * kNpad + 32 * mt + 16 * half) = o;
+  }
+  if (half == 0) {
+    a.e_best[cell] = e_best;
+    a.t_best[cell] = t_best;
+    a.first_hit[cell] = first_hit;
+    a.e_final[cell] = e_cur;
+    a.steps_done[cell] = done;
+  }
+}
+
+template <int NT, int PREC, bool HAS_H>
+hipError_t launch_nt(const SweepRealArgs& a, int count, hipStream_t s) {
+  const int nw = std::min(kMaxWaves, (a.R + 31) / 32);
+  const size_t lds = frag_bytes(PREC, NT) + (HAS_H ? NT * 32 * 4 : 0) + (size_t)nw * kRealTabBytes;
+  auto kern = sweep_real_kernel<NT, PREC, HAS_H>;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  const dim3 grid((a.R + 32 * nw - 1) / (32 * nw), count);
+  hipLaunchKernelGGL(kern, grid, dim3(64 * nw), lds, s, a);
+  return hipGetLastError();
+}
+
+template <int PREC, bool HAS_H>
+hipError_t launch_p(const SweepRealArgs& a, int count, int nt, hipStream_t s) {
+  switch (nt) {
+    case 1: return launch_nt<1, PREC, HAS_H>(a, count, s);
+    case 2: return launch_nt<2, PREC, HAS_H>(a, count, s);
+    case 3: return launch_nt<3, PREC, HAS_H>(a, count, s);
+    case 4: return launch_nt<4, PREC, HAS_H>(a, count, s);
+    case 5: return launch_nt<5, PREC, HAS_H>(a, count, s);
+    case 6: return launch_nt<6, PREC, HAS_H>(a, count, s);
+    case 7: return launch_nt<7, PREC, HAS_H>(a, count, s);
+    case 8: return launch_nt<8, PREC, HAS_H>(a, count, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+size_t real_frag_bytes(int prec, int nt) { return frag_bytes(prec, nt); }
+
+hipError_t launch_sweep_real(const SweepRealArgs& a, int count, int nt, int prec, bool has_h, hipStream_t s) {
+  if (a.npad != nt * 32 || a.R < 1) return hipErrorInvalidValue;
+  if (prec == PIM_PREC_FP8)
+    return has_h ? launch_p<PIM_PREC_FP8, true>(a, count, nt, s) : launch_p<PIM_PREC_FP8, false>(a, count, nt, s);
+  if (prec == PIM_PREC_BF16)
+    return has_h ? launch_p<PIM_PREC_BF16, true>(a, count, nt, s) : launch_p<PIM_PREC_BF16, false>(a, count, nt, s);
+  return hipErrorInvalidValue;
+}
+
+void pack_real_fragments(const double* J, int n, int nt, int prec, float scale, uint8_t* out) {
+  auto row_of = [](int mt, int m) { return 32 * mt + 16 * ((m >> 2) & 1) + 4 * (m >> 3) + (m & 3); };
+  if (prec == PIM_PREC_FP8) {
+    const int nk = (nt + 1) / 2;
+    for (int mt = 0; mt < nt; ++mt)
+      for (int kk = 0; kk < nk; ++kk)
+        for (int l = 0; l < 64; ++l) {
+          const int row = row_of(mt, l & 31), hh = l >> 5;
+          for (int p = 0; p < 32; ++p) {
+            const int colj = 32 * (2 * kk + p / 16) + 16 * hh + (p % 16);
+            const double v = (row < n && colj < n) ? J[(size_t)row * n + colj] / (double)scale : 0.0;
+            out[(((size_t)mt * nk + kk) * 64 + l) * 32 + p] = fp8_e4m3_rne(v);
+          }
+        }
+  } else {
+    uint16_t* o16 = reinterpret_cast<uint16_t*>(out);
+    for (int mt = 0; mt < nt; ++mt)
+      for (int kt = 0; kt < nt; ++kt)
+        for (int j = 0; j < 2; ++j)
+          for (int l = 0; l < 64; ++l) {
+            const int row = row_of(mt, l & 31), hh = l >> 5;
+            for (int p = 0; p < 8; ++p) {
+              const int colj = 32 * kt + 16 * hh + 8 * j + p;
+              const double v = (row < n && colj < n) ? J[(size_t)row * n + colj] / (double)scale : 0.0;
+              o16[((((size_t)mt * nt + kt) * 2 + j) * 64 + l) * 8 + p] = bf16_rne(v);
+            }
+          }
+  }
+}
+
+}  // namespace pim

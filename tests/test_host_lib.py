@@ -27,7 +27,7 @@ def test_library_exports_every_declared_symbol(pim):
     assert declared == set(pim.EXPORTED)
     for name in declared:
         assert hasattr(pim.lib, name)
-    assert pim.lib.pim_abi_version() == 1
+    assert pim.lib.pim_abi_version() == pim.ABI_VERSION == 2
 
 
 def _compiled_decision(theta, umin, I, s, u):
