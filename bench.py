@@ -45,6 +45,11 @@ def parse():
     ap.add_argument("--plain-instances", type=int, default=8,
                     help="instances run through the plain FP32 per-instance kernel for the comparison "
                          "(0 = skip); trajectories are bit-identical, so TTS99 is equal")
+    ap.add_argument("--no-mimo", action="store_true", help="skip the MIMO detection leg")
+    ap.add_argument("--mimo-requests", type=int, default=512,
+                    help="MIMO channels in the batched quality/throughput run")
+    ap.add_argument("--mimo-latency", type=int, default=200,
+                    help="single requests timed per kernel for the latency percentiles")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a device-to-device copy of BYTES bytes (x3), for calibrating the "
                          "FETCH_SIZE / WRITE_SIZE counters against a known byte count")
@@ -99,6 +104,103 @@ def cpu_baseline(n, trials, steps, xi, c):
             "kind": "oracle",
             "sample": f"SK-1 N={n} instance 0, {trials} trials x first {steps} of the 10^4 steps "
                       f"({dt:.1f} s, NumPy binary64 on the host)"}
+
+
+MIMO = {"nt": 16, "nr": 16, "qam": 16, "ebn0_db": 20.0, "mapping": "di", "trials": 32, "steps": 64,
+        "gamma": (0.05, 0.3), "xi": 2.0, "beta": 1.0}
+
+
+def mimo_leg(args):
+    """MIMO detection (Suppl. "PIMI FPGA implementation for MIMO detection"):
+    16x16 16-QAM at Eb/N0 = 20 dB, DI mapping (64 spins), 32 trials x 64 steps,
+    beta = 1, xi = 2, eta = sqrt(1 / (5 gamma(t))) with gamma 0.05 -> 0.3.
+
+    * latency: one request at a time (instance upload, sweep, binary64
+      re-rank, readback of the detected state), p50 / p99 over requests, for
+      the FP8 and BF16 MFMA kernels and the plain FP32 kernel; the sweep kernel's
+      own duration (HIP events) alongside;
+    * quality and throughput: all requests in one batch (one launch), symbol
+      and bit error rates against the transmitted symbols and the sliced MMSE
+      estimate the mapping starts from."""
+    import torch
+    import paper_2604_17109_amd as pim
+    import workloads as w
+    cfg = MIMO
+    T, R, qam, nt = cfg["steps"], cfg["trials"], cfg["qam"], cfg["nt"]
+    beta = w.constant(T, cfg["beta"])
+    eta = w.mimo_eta(T, *cfg["gamma"])
+    ztab = w.gauss_table(8)
+    M = args.mimo_requests
+    probs = [w.mimo.mimo_problem(nt, cfg["nr"], qam, cfg["ebn0_db"], seed=7, index=k) for k in range(M)]
+    maps = [pim.mimo_ising(p["H"], p["y"], qam, cfg["mapping"], p["esn0"]) for p in probs]
+    n = maps[0][0].shape[0]
+    out = {"workload": f"{nt}x{cfg['nr']} {qam}-QAM, Eb/N0 {cfg['ebn0_db']} dB, {cfg['mapping'].upper()} mapping, "
+                       f"N = {n} spins, {R} trials x {T} steps",
+           "requests": M}
+
+    def one_request(k, prec, kernel):
+        J, h, xm = maps[k]
+        t0 = time.perf_counter()
+        inst = pim.Instance(J, h, j_scale=1.0, xi=cfg["xi"], levels=4, noise_table=ztab, rng_stream=k, prec=prec)
+        b = pim.Batch([inst], R)
+        b.run(beta, eta, seed=11, kernel=kernel)
+        spins, e, _, _ = b.best(0)
+        dt = time.perf_counter() - t0
+        kms = b.kernel_ms()
+        b.close()
+        inst.close()
+        return dt * 1e6, kms * 1e3, pim.mimo_decode(xm, spins, qam, cfg["mapping"])
+
+    lat = {}
+    for name, prec, kernel in (("fp8_mfma", "fp8", "mfma"), ("bf16_mfma", "bf16", "mfma"),
+                               ("plain_f32", "fp8", "plain")):
+        for k in range(5):
+            one_request(k, prec, kernel)  # warm-up
+        e2e, kus = [], []
+        for k in range(min(args.mimo_latency, M)):
+            a, b_, _ = one_request(k, prec, kernel)
+            e2e.append(a)
+            kus.append(b_)
+        lat[name] = {"e2e_p50_us": float(np.percentile(e2e, 50)), "e2e_p99_us": float(np.percentile(e2e, 99)),
+                     "kernel_p50_us": float(np.percentile(kus, 50)), "kernel_p99_us": float(np.percentile(kus, 99))}
+    lat["kernel_p99_speedup_fp8_vs_plain"] = lat["plain_f32"]["kernel_p99_us"] / lat["fp8_mfma"]["kernel_p99_us"]
+    lat["e2e_p99_speedup_fp8_vs_plain"] = lat["plain_f32"]["e2e_p99_us"] / lat["fp8_mfma"]["e2e_p99_us"]
+    out["latency"] = lat
+
+    # batched: all requests in one launch
+    bits_per_sym = w.mimo.bits_per_symbol(qam)
+    quality = {}
+    for name, prec in (("fp8_mfma", "fp8"), ("bf16_mfma", "bf16")):
+        insts = [pim.Instance(J, h, j_scale=1.0, xi=cfg["xi"], levels=4, noise_table=ztab, rng_stream=k, prec=prec)
+                 for k, (J, h, xm) in enumerate(maps)]
+        b = pim.Batch(insts, R)
+        b.run(beta, eta, seed=11)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.run(beta, eta, seed=11)
+        dets = [b.best(k)[0] for k in range(M)]
+        dt = time.perf_counter() - t0
+        kms = b.kernel_ms()
+        se = be = 0
+        for k, p in enumerate(probs):
+            x = pim.mimo_decode(maps[k][2], dets[k], qam, cfg["mapping"])
+            se += int(np.count_nonzero(x != p["x"]))
+            be += int(np.count_nonzero(w.mimo.bits_from_symbols(x, qam) != p["bits"]))
+        quality[name] = {"ser": se / (M * nt), "ber": be / (M * nt * bits_per_sym),
+                         "requests_per_s": M / dt, "kernel_ms": kms,
+                         "spin_updates_per_s": M * R * T * n / (kms / 1e3)}
+        b.close()
+        for i in insts:
+            i.close()
+    se = be = 0
+    for k, p in enumerate(probs):
+        xm = maps[k][2]
+        x = xm[:nt] + 1j * xm[nt:]
+        se += int(np.count_nonzero(x != p["x"]))
+        be += int(np.count_nonzero(w.mimo.bits_from_symbols(x, qam) != p["bits"]))
+    quality["mmse"] = {"ser": se / (M * nt), "ber": be / (M * nt * bits_per_sym)}
+    out["batched"] = quality
+    return out
 
 
 def main():
@@ -204,6 +306,8 @@ def main():
                              "identical_results": bool(same),
                              "speedup_at_equal_tts99": (updates / (kernel_ms / 1000.0)) / plain_rate}
         pb.close()
+    if not args.no_mimo:
+        line["mimo"] = mimo_leg(args)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(n, args.cpu_trials, args.cpu_steps, xi, c)
     print(json.dumps(line), flush=True)
