@@ -45,6 +45,10 @@ typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
 constexpr int kMaxWaves = 4;
 constexpr int kRealTabBytes = kTabEntries * 4;  // 2 KB per step table
+// Step tables are fetched this many steps ahead (registers, 8 per step): one
+// request's wave is often alone on its SIMD, so a table load issued only one
+// step before its use would expose the full memory latency every step.
+constexpr int kAhead = 4;
 static_assert(kRealTabBytes == 64 * 32, "two 16-byte chunks per lane");
 
 #define PIM_FENCE(v) asm volatile("" : "+v"(v))
@@ -191,6 +195,14 @@ __global__ __launch_bounds__(64 * kMaxWaves) void sweep_real_kernel(SweepRealArg
   int done = a.T;
   sTab4[lane] = gTab4[lane];
   sTab4[64 + lane] = gTab4[64 + lane];
+  // ring[i] holds the table of step t + 1 + i (clamped index: in bounds)
+  uint4 ring[kAhead][2];
+#pragma unroll
+  for (int i = 0; i < kAhead; ++i) {
+    const size_t row = (size_t)min(1 + i, a.T - 1) * 128;
+    ring[i][0] = gTab4[row + lane];
+    ring[i][1] = gTab4[row + 64 + lane];
+  }
 
   for (int t = 0;; ++t) {
     const int tg = a.start_step + t;
@@ -198,9 +210,18 @@ __global__ __launch_bounds__(64 * kMaxWaves) void sweep_real_kernel(SweepRealArg
     v4i Bn[NT][KW];
     const bool last = (t == a.T);
     const bool has_next = t + 1 < a.T;
-    const size_t nrow = (size_t)min(t + 1, a.T - 1) * 128;
-    const uint4 nxt0 = gTab4[nrow + lane];
-    const uint4 nxt1 = gTab4[nrow + 64 + lane];
+    const uint4 nxt0 = ring[0][0];
+    const uint4 nxt1 = ring[0][1];
+#pragma unroll
+    for (int i = 0; i + 1 < kAhead; ++i) {
+      ring[i][0] = ring[i + 1][0];
+      ring[i][1] = ring[i + 1][1];
+    }
+    {
+      const size_t row = (size_t)min(t + 1 + kAhead, a.T - 1) * 128;
+      ring[kAhead - 1][0] = gTab4[row + lane];
+      ring[kAhead - 1][1] = gTab4[row + 64 + lane];
+    }
     const float* tab = sTab + kNoiseVals;
     uint32_t ctr_trial = (uint32_t)trial;
     uint32_t ctr_half = (uint32_t)half;
