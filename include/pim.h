@@ -92,7 +92,10 @@ typedef enum {
 typedef enum {
   PIM_KERNEL_MFMA_I8 = 0,   /* persistent batched sweep on matrix cores: int8 MFMA for
                                integer instances, FP8 / BF16 MFMA for real-valued ones */
-  PIM_KERNEL_PLAIN_F32 = 1  /* one instance per launch, plain FP32 dot products      */
+  PIM_KERNEL_PLAIN_F32 = 1, /* one instance per launch, plain FP32 dot products      */
+  PIM_KERNEL_SEQ_I8 = 2     /* conventional PIM, sequential updates (Box 1, top):
+                               step t changes only spin i = (start_step + t) mod N;
+                               integer instances only                               */
 } pim_kernel;
 
 /* Operand format of a real-valued instance in the batched MFMA kernel. */
@@ -180,7 +183,11 @@ pim_status pim_quantize(const double* J, int32_t n, int32_t prec, double* J_out,
 pim_status pim_batch_create(pim_instance* const* insts, int32_t count, int32_t trials,
                             const int8_t* init_spins, void* stream, pim_batch** out);
 
-/* Runs T steps of Eq. (4) on every trial of every instance of the batch,
+/* Runs T steps of Eq. (4) on every trial of every instance of the batch
+ * (PIM_KERNEL_SEQ_I8: T single-spin steps of the same rule, spin
+ * (start_step + t) mod N at step t, noise u = byte i % 16 of the Philox block
+ * (i / 16, start_step + t, trial, rng_stream); the conventional PIM of Eq. (3)
+ * is this rule with xi = 0 and uniform noise),
  * asynchronously on `stream`.  Compiles the schedule on the host, uploads the
  * tables and launches the sweep (PIM_KERNEL_MFMA_I8: one launch for the whole
  * batch; PIM_KERNEL_PLAIN_F32: one launch per instance).  Tracks, over the

@@ -96,6 +96,27 @@ struct SweepRealArgs {
   uint32_t k0, k1;
 };
 
+// Sequential (conventional) PIM: same fields as SweepArgs with row-major J.
+struct SeqArgs {
+  const int8_t* j8pad;       // [count][npad][npad] int8 J, zero-padded rows
+  const int32_t* h;          // [count][npad] or nullptr
+  const int16_t* thtab;      // [classes][T][kTabEntries]
+  const int32_t* inst_class;
+  const uint32_t* inst_stream;
+  const int32_t* target;
+  const int8_t* init;
+  int8_t* final_s;
+  int8_t* best_s;
+  int32_t* e_best;
+  int32_t* t_best;
+  int32_t* first_hit;
+  int32_t* e_final;
+  int32_t* steps_done;
+  const volatile int32_t* cancel;
+  int32_t n, npad, R, T, start_step;
+  uint32_t k0, k1;
+};
+
 struct PlainArgs {
   const float* jf32;         // [npad][jstride] of one instance, zero-padded
   const int32_t* h;          // [n] or nullptr (integer instances)
@@ -144,6 +165,7 @@ struct RerankArgs {
 hipError_t launch_rerank_select(const RerankArgs& a, hipStream_t s);
 hipError_t launch_sweep_mfma(const SweepArgs& a, int count, int nt, bool has_h, hipStream_t s);
 hipError_t launch_sweep_plain(const PlainArgs& a, bool real, hipStream_t s);
+hipError_t launch_sweep_seq(const SeqArgs& a, int count, int nt, bool has_h, hipStream_t s);
 hipError_t launch_sweep_real(const SweepRealArgs& a, int count, int nt, int prec, bool has_h, hipStream_t s);
 size_t real_frag_bytes(int prec, int nt);
 hipError_t launch_energy_f64(const EnergyArgs& a, hipStream_t s);
@@ -190,6 +212,7 @@ struct pim_batch {
   hipStream_t stream = nullptr;
   // device buffers
   int8_t* d_jfrag = nullptr;      // concatenated fragments of all instances
+  int8_t* d_j8pad = nullptr;      // [count][npad][npad] row-major int8 J (sequential kernel)
   int32_t* d_h = nullptr;         // [count][npad] int32 (integer) or float (real) fields
   float* d_scale = nullptr;       // [count] (real)
   int8_t* d_init = nullptr;

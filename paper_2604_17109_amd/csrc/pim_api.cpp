@@ -153,6 +153,7 @@ pim_status check_spins(const int8_t* s, size_t count) {
 void free_batch_buffers(pim_batch* b) {
   hipStream_t s = b->stream;
   dev_free(b->d_jfrag, s);
+  dev_free(b->d_j8pad, s);
   dev_free(b->d_h, s);
   dev_free(b->d_init, s);
   dev_free(b->d_final, s);
@@ -615,8 +616,10 @@ pim_status pim_run(pim_batch* b, const pim_schedule* sc, uint64_t seed, void* st
     if (!sc->beta || !sc->eta) return fail(PIM_ERR_INVALID, "beta and eta must be non-NULL");
     if (sc->start_step < 0 || (int64_t)sc->start_step + sc->steps >= (int64_t)1 << 31)
       return fail(PIM_ERR_INVALID, "start_step + steps must lie in [0, 2^31)");
-    if (sc->kernel != PIM_KERNEL_MFMA_I8 && sc->kernel != PIM_KERNEL_PLAIN_F32)
+    if (sc->kernel != PIM_KERNEL_MFMA_I8 && sc->kernel != PIM_KERNEL_PLAIN_F32 && sc->kernel != PIM_KERNEL_SEQ_I8)
       return fail(PIM_ERR_INVALID, "unknown kernel %d", sc->kernel);
+    if (sc->kernel == PIM_KERNEL_SEQ_I8 && b->real)
+      return fail(PIM_ERR_UNSUPPORTED, "the sequential kernel takes integer instances");
     if (sc->use_target && !sc->target) return fail(PIM_ERR_INVALID, "use_target set without target energies");
     const int T = sc->steps;
     for (int t = 0; t < T; ++t)
@@ -643,7 +646,8 @@ pim_status pim_run(pim_batch* b, const pim_schedule* sc, uint64_t seed, void* st
     const bool real = b->real;
     // ---- compile ----
     std::vector<int32_t> steptab;
-    const bool mfma = sc->kernel == PIM_KERNEL_MFMA_I8;
+    const bool seq = sc->kernel == PIM_KERNEL_SEQ_I8;
+    const bool mfma = sc->kernel == PIM_KERNEL_MFMA_I8 || seq;  // both read the (u, s) tables
     const size_t entry = real ? 4 : 2;  // bytes per table entry
     if (mfma) {
       const size_t need = (size_t)ncls * T * kTabEntries * entry;
@@ -715,6 +719,17 @@ pim_status pim_run(pim_batch* b, const pim_schedule* sc, uint64_t seed, void* st
       return fail(PIM_ERR_DEVICE, "%s failed: %s", what, hipGetErrorString(e));
     };
     hipError_t e = hipSuccess;
+    if (seq && !b->d_j8pad) {
+      // row-major int8 J with rows padded to npad, for the sequential kernel
+      const size_t per = (size_t)b->npad * b->npad;
+      pim_status st = alloc_dev(&b->d_j8pad, per * b->count, s);
+      if (st != PIM_OK) return st;
+      e = hipMemsetAsync(b->d_j8pad, 0, per * b->count, s);
+      for (int k = 0; k < b->count && e == hipSuccess; ++k)
+        e = hipMemcpy2DAsync(b->d_j8pad + per * k, b->npad, b->insts[k]->d_j8, b->n, b->n, b->n,
+                             hipMemcpyDeviceToDevice, s);
+      if (e != hipSuccess) return device_fail(e, "sequential coupling layout");
+    }
     if (mfma) e = hipMemcpyAsync(b->d_thtab, b->h_thtab, thtab_need, hipMemcpyHostToDevice, s);
     else e = hipMemcpyAsync(b->d_steptab, steptab.data(), steptab.size() * 4, hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
@@ -728,7 +743,33 @@ pim_status pim_run(pim_batch* b, const pim_schedule* sc, uint64_t seed, void* st
     e = hipEventRecord(b->ev0, s);
     if (e != hipSuccess) return device_fail(e, "hipEventRecord");
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
-    if (mfma && !real) {
+    if (seq) {
+      SeqArgs a{};
+      a.j8pad = b->d_j8pad;
+      a.h = b->has_h ? b->d_h : nullptr;
+      a.thtab = static_cast<const int16_t*>(b->d_thtab);
+      a.inst_class = b->d_class;
+      a.inst_stream = b->d_stream_ids;
+      a.target = sc->use_target ? b->d_target : nullptr;
+      a.init = b->d_init;
+      a.final_s = b->d_final;
+      a.best_s = b->d_best;
+      a.e_best = stat_ptr(b, 0);
+      a.t_best = stat_ptr(b, 1);
+      a.first_hit = stat_ptr(b, 2);
+      a.e_final = stat_ptr(b, 3);
+      a.steps_done = stat_ptr(b, 4);
+      a.cancel = b->d_cancel;
+      a.n = b->n;
+      a.npad = b->npad;
+      a.R = b->R;
+      a.T = T;
+      a.start_step = sc->start_step;
+      a.k0 = k0;
+      a.k1 = k1;
+      e = launch_sweep_seq(a, b->count, b->nt, b->has_h, s);
+      if (e != hipSuccess) return device_fail(e, "sequential sweep launch");
+    } else if (mfma && !real) {
       SweepArgs a{};
       a.jfrag = b->d_jfrag;
       a.h = b->has_h ? b->d_h : nullptr;

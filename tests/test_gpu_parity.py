@@ -195,3 +195,51 @@ def test_full_size_maxcut200_sampled_trials(gpu_lib):
     np.testing.assert_array_equal(e_states, got["e_best"])
     e_final = pimi.energy(J, h, got["final"].T.astype(np.int64))
     np.testing.assert_array_equal(e_final, got["e_final"])
+
+
+SEQ_CASES = [
+    # n, trials, steps, hmax, jmax, xi, noise
+    (20, 64, 2000, 0, 1, 0.0, "uniform"),
+    (1, 8, 12, 0, 1, 0.0, "uniform"),
+    (33, 70, 700, 5, 3, 0.5, "gauss"),
+    (64, 64, 640, 0, 1, 0.0, "uniform"),
+    (200, 16, 600, 0, 1, 0.0, "uniform"),
+    (256, 40, 520, 2, 1, 0.7, "gauss"),
+]
+
+
+@pytest.mark.parametrize("case", SEQ_CASES, ids=lambda c: "-".join(map(str, c)))
+def test_sequential_kernel_parity(gpu_lib, case):
+    """Conventional PIM with sequential updates (one spin per step) against
+    the oracle's sequential dynamics, bit for bit."""
+    n, trials, steps, hmax, jmax, xi, noise = case
+    _say(f"sequential n={n} trials={trials} steps={steps} h={hmax} xi={xi} {noise}")
+    pim = gpu_lib
+    ztab = w.gauss_table(8) if noise == "gauss" else w.uniform_table(8)
+    J, h = w.random_int8(n, seed=12, index=n, jmax=jmax, hmax=hmax)
+    c = 1.0 / np.sqrt(n)
+    beta = w.constant(steps, 0.8)
+    eta = w.conventional_eta(steps, 1.5, 0.05)
+    inst = pim.Instance(J, h, j_scale=c, xi=xi, noise_table=ztab, rng_stream=2)
+    batch = pim.Batch([inst], trials)
+    target = int(pimi.energy(J, h, np.ones(n, dtype=np.int64))) - 1
+    batch.run(beta, eta, seed=9, kernel="seq", target=[target], start_step=3)
+    prob = pimi.Problem(J, h, c=c, xi=xi, levels=4, ztab=ztab)
+    ref = pimi.run_sequential(prob, beta, eta, 9, 2, np.arange(trials), start_step=3, target=target)
+    _compare(batch, 0, ref, np.arange(trials), n)
+    batch.close()
+
+
+def test_sequential_resume(gpu_lib):
+    _say("sequential resume")
+    pim = gpu_lib
+    n, trials = 40, 64
+    J, h = w.sk1(n, seed=2, index=1)
+    ztab = w.uniform_table(8)
+    beta, eta = w.constant(300, 0.5), w.conventional_eta(300, 1.0, 0.1)
+    inst = pim.Instance(J, h, j_scale=1 / np.sqrt(n), xi=0.0, noise_table=ztab, rng_stream=4)
+    full = pim.Batch([inst], trials).run(beta, eta, seed=3, kernel="seq")
+    part = pim.Batch([inst], trials).run(beta[:111], eta[:111], seed=3, kernel="seq")
+    rest = pim.Batch([inst], trials, init_spins=part.trials_of(0)["final"][None]).run(
+        beta[111:], eta[111:], seed=3, kernel="seq", start_step=111)
+    np.testing.assert_array_equal(rest.trials_of(0)["final"], full.trials_of(0)["final"])
