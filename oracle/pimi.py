@@ -241,7 +241,7 @@ def _activation(prob, x, act):
 
 
 def run_parallel(prob, beta, eta, seed, stream, trials, init=None, start_step=0,
-                 target=None, trace=False, act=None, noise=None):
+                 target=None, trace=False, act=None, noise=None, record=False):
     """PIMI (Eq. (4), Box 1): every spin of every trial updated at each step.
 
     ``beta``, ``eta``: float64 arrays of length T (step t uses index t).  The
@@ -255,7 +255,8 @@ def run_parallel(prob, beta, eta, seed, stream, trials, init=None, start_step=0,
     ``act`` (default: the L-level LUT) and ``noise`` (default: Philox index into
     the quantile table; otherwise ``noise(shape, step) -> float64 array``) are
     overridable so that statistical pins can run the same loop with the exact
-    tanh and continuous noise.
+    tanh and continuous noise.  ``record`` keeps every state: res["states"] is
+    int8 [T + 1, N, R] with s(t) at index t.
     """
     beta = np.asarray(beta, dtype=np.float64)
     eta = np.asarray(eta, dtype=np.float64)
@@ -266,8 +267,11 @@ def run_parallel(prob, beta, eta, seed, stream, trials, init=None, start_step=0,
         else np.asarray(init, dtype=np.int64).copy()
     res = _result(len(trials), n, prob.real)
     energies = []
+    states = []
     spin = np.arange(n)[:, None]
     for t in range(steps + 1):
+        if record:
+            states.append(s.astype(np.int8))
         if prob.real:
             I = local_field_f64(prob.J, prob.h, s)
             e = energy_from_field_f64(I, prob.h, s)
@@ -286,6 +290,8 @@ def run_parallel(prob, beta, eta, seed, stream, trials, init=None, start_step=0,
     res["final"] = s
     if trace:
         res["trace"] = np.stack(energies, axis=0)
+    if record:
+        res["states"] = np.stack(states, axis=0)
     return res
 
 
