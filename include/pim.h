@@ -134,6 +134,10 @@ typedef struct {
   int32_t use_target;        /* nonzero: record first step with E <= target        */
   const double* target;      /* host [instance count] energies, or NULL; integer
                                 instances compare E <= floor(target)                */
+  int32_t record_states;     /* nonzero: keep every state s(t), t = 0..T, of every
+                                trial on the device (diagnostics; integer instances,
+                                PIM_KERNEL_MFMA_I8; count*trials*(T+1)*Npad bytes,
+                                Npad = N rounded up to 32)                          */
 } pim_schedule;
 
 typedef struct pim_instance pim_instance; /* device copy of one (J, h, params)       */
@@ -224,6 +228,19 @@ pim_status pim_best(pim_batch* batch, int32_t inst, int8_t* spins_out, double* e
 pim_status pim_trials(pim_batch* batch, int32_t inst, double* best_e, int32_t* best_step,
                       int32_t* first_hit, double* final_e, int8_t* best_spins,
                       int8_t* final_spins);
+
+/* Recorded trajectory of one trial (the last run had record_states set):
+ * states: host int8 [(T+1)][N], s(t) at row t (rows after a cancellation are
+ * unspecified).  Synchronises. */
+pim_status pim_states(pim_batch* batch, int32_t inst, int32_t trial, int8_t* states);
+
+/* Neighbour-triggered flip counts of instance `inst` over the recorded run
+ * (Suppl. "Quantifying coupled oscillatory dynamics via neighbor-triggered
+ * flip rates"): for t = 0..T-1, den[t] = #{(i, trial): some j with J_ij != 0
+ * flips between s(t) and s(t+1)}, num[t] = those of them where i flips too;
+ * P_NT(t) = num[t] / den[t].  Computed on the device; num, den: host [T].
+ * Synchronises. */
+pim_status pim_flip_counts(pim_batch* batch, int32_t inst, int64_t* num, int64_t* den);
 
 /* Duration in milliseconds of the sweep kernel(s) of the last pim_run,
  * measured with HIP events on the run's stream.  Synchronises. */

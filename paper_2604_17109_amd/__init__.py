@@ -40,6 +40,7 @@ EXPORTED = (
     "pim_energy", "pim_best", "pim_trials", "pim_kernel_time", "pim_compile_step", "pim_compile_table",
     "pim_batch_destroy", "pim_destroy", "pim_last_error", "pim_abi_version",
     "pim_create_real", "pim_quantize", "pim_compile_table_real", "pim_mimo_ising", "pim_mimo_decode",
+    "pim_states", "pim_flip_counts",
 )
 
 
@@ -71,6 +72,7 @@ class Schedule(ctypes.Structure):
         ("kernel", ctypes.c_int32),
         ("use_target", ctypes.c_int32),
         ("target", ctypes.POINTER(ctypes.c_double)),
+        ("record_states", ctypes.c_int32),
     ]
 
 
@@ -104,6 +106,8 @@ def _load():
         "pim_compile_table_real": (I32, [P(Params), F64, F64, P(ctypes.c_float)]),
         "pim_mimo_ising": (I32, [P(F64), P(F64), I32, I32, I32, I32, F64, P(F64), P(F64), P(F64), P(I32)]),
         "pim_mimo_decode": (I32, [P(F64), P(ctypes.c_int8), I32, I32, I32, P(F64)]),
+        "pim_states": (I32, [VP, I32, I32, P(ctypes.c_int8)]),
+        "pim_flip_counts": (I32, [VP, I32, P(ctypes.c_int64), P(ctypes.c_int64)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -370,7 +374,7 @@ class Batch:
         _check(lib.pim_batch_create(arr, self.count, self.trials, _ptr(init, ctypes.c_int8), self.stream,
                                     ctypes.byref(self._handle)))
 
-    def run(self, beta, eta, seed, start_step=0, kernel="mfma", target=None, stream=None):
+    def run(self, beta, eta, seed, start_step=0, kernel="mfma", target=None, stream=None, record=False):
         beta = np.ascontiguousarray(beta, dtype=np.float64)
         eta = np.ascontiguousarray(eta, dtype=np.float64)
         if beta.shape != eta.shape or beta.ndim != 1:
@@ -381,6 +385,8 @@ class Batch:
         sc.eta = _ptr(eta, ctypes.c_double)
         sc.start_step = int(start_step)
         sc.kernel = _KERNELS[kernel] if isinstance(kernel, str) else int(kernel)
+        sc.record_states = 1 if record else 0
+        self._steps = beta.size
         tgt = None
         if target is not None:
             tgt = np.ascontiguousarray(np.broadcast_to(np.asarray(target, dtype=np.float64), (self.count,)))
@@ -422,6 +428,19 @@ class Batch:
             out["best_state"] = bs
             out["final"] = fs
         return out
+
+    def states(self, k, trial):
+        """Recorded trajectory of one trial: int8 [T + 1, n] (run with record=True)."""
+        out = np.zeros((self._steps + 1, self.n), np.int8)
+        _check(lib.pim_states(self._handle, int(k), int(trial), _ptr(out, ctypes.c_int8)))
+        return out
+
+    def flip_counts(self, k):
+        """(num, den) of the neighbour-triggered flip rate, int64 [T] each."""
+        num = np.zeros(self._steps, np.int64)
+        den = np.zeros(self._steps, np.int64)
+        _check(lib.pim_flip_counts(self._handle, int(k), _ptr(num, ctypes.c_int64), _ptr(den, ctypes.c_int64)))
+        return num, den
 
     def kernel_ms(self):
         ms = ctypes.c_float()

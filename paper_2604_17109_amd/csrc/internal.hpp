@@ -55,6 +55,7 @@ bool builtin_noise_table(int noise, std::vector<double>& out);
 // ---- device argument blocks ----------------------------------------------
 struct SweepArgs {
   const int8_t* jfrag;       // [count][NT*NT][64][16] MFMA A fragments
+  int8_t* trace;             // [count][R][T+1][npad] every state s(t), or nullptr
   const int32_t* h;          // [count][npad] or nullptr
   const int16_t* thtab;      // [classes][T][kTabEntries]
   const int32_t* inst_class; // [count]
@@ -170,6 +171,16 @@ hipError_t launch_sweep_real(const SweepRealArgs& a, int count, int nt, int prec
 size_t real_frag_bytes(int prec, int nt);
 hipError_t launch_energy_f64(const EnergyArgs& a, hipStream_t s);
 
+// Neighbour-triggered flip counts of one instance's recorded states.
+struct FlipRateArgs {
+  const int8_t* trace;         // [R][T+1][npad] of the instance
+  const int8_t* j8;            // [n][n]
+  unsigned long long* num;     // [T]
+  unsigned long long* den;     // [T]
+  int32_t n, npad, R, T;
+};
+hipError_t launch_flip_rate(const FlipRateArgs& a, hipStream_t s);
+
 // Host packing of J into the MFMA fragment order (sweep_mfma.hip, sweep_real.hip).
 void pack_mfma_fragments(const int8_t* J, int n, int nt, int8_t* out);
 void pack_real_fragments(const double* J, int n, int nt, int prec, float scale, uint8_t* out);
@@ -213,6 +224,9 @@ struct pim_batch {
   // device buffers
   int8_t* d_jfrag = nullptr;      // concatenated fragments of all instances
   int8_t* d_j8pad = nullptr;      // [count][npad][npad] row-major int8 J (sequential kernel)
+  int8_t* d_trace = nullptr;      // [count][R][T+1][npad] recorded states (diagnostics)
+  size_t trace_bytes = 0;
+  bool recorded = false;          // the last run recorded its states
   int32_t* d_h = nullptr;         // [count][npad] int32 (integer) or float (real) fields
   float* d_scale = nullptr;       // [count] (real)
   int8_t* d_init = nullptr;

@@ -154,6 +154,7 @@ void free_batch_buffers(pim_batch* b) {
   hipStream_t s = b->stream;
   dev_free(b->d_jfrag, s);
   dev_free(b->d_j8pad, s);
+  dev_free(b->d_trace, s);
   dev_free(b->d_h, s);
   dev_free(b->d_init, s);
   dev_free(b->d_final, s);
@@ -620,6 +621,8 @@ pim_status pim_run(pim_batch* b, const pim_schedule* sc, uint64_t seed, void* st
       return fail(PIM_ERR_INVALID, "unknown kernel %d", sc->kernel);
     if (sc->kernel == PIM_KERNEL_SEQ_I8 && b->real)
       return fail(PIM_ERR_UNSUPPORTED, "the sequential kernel takes integer instances");
+    if (sc->record_states && (sc->kernel != PIM_KERNEL_MFMA_I8 || b->real))
+      return fail(PIM_ERR_UNSUPPORTED, "state recording is implemented for the int8 MFMA kernel");
     if (sc->use_target && !sc->target) return fail(PIM_ERR_INVALID, "use_target set without target energies");
     const int T = sc->steps;
     for (int t = 0; t < T; ++t)
@@ -719,6 +722,20 @@ pim_status pim_run(pim_batch* b, const pim_schedule* sc, uint64_t seed, void* st
       return fail(PIM_ERR_DEVICE, "%s failed: %s", what, hipGetErrorString(e));
     };
     hipError_t e = hipSuccess;
+    b->recorded = false;
+    if (sc->record_states) {
+      const size_t need = (size_t)b->count * b->R * ((size_t)T + 1) * b->npad;
+      if (need / ((size_t)T + 1) != (size_t)b->count * b->R * b->npad)
+        return fail(PIM_ERR_INVALID, "recorded trajectory size overflows");
+      if (need > b->trace_bytes) {
+        dev_free(b->d_trace, s);
+        b->d_trace = nullptr;
+        b->trace_bytes = 0;
+        pim_status st = alloc_dev(&b->d_trace, need, s);
+        if (st != PIM_OK) return st;
+        b->trace_bytes = need;
+      }
+    }
     if (seq && !b->d_j8pad) {
       // row-major int8 J with rows padded to npad, for the sequential kernel
       const size_t per = (size_t)b->npad * b->npad;
@@ -772,6 +789,7 @@ pim_status pim_run(pim_batch* b, const pim_schedule* sc, uint64_t seed, void* st
     } else if (mfma && !real) {
       SweepArgs a{};
       a.jfrag = b->d_jfrag;
+      a.trace = sc->record_states ? b->d_trace : nullptr;
       a.h = b->has_h ? b->d_h : nullptr;
       a.thtab = static_cast<const int16_t*>(b->d_thtab);
       a.inst_class = b->d_class;
@@ -860,6 +878,7 @@ pim_status pim_run(pim_batch* b, const pim_schedule* sc, uint64_t seed, void* st
     e = hipEventRecord(b->ev1, s);
     if (e != hipSuccess) return device_fail(e, "hipEventRecord");
     b->ran = true;
+    b->recorded = sc->record_states != 0;
     b->reranked = false;
     b->cancelled_checked = -1;
     b->last_T = T;
@@ -869,6 +888,54 @@ pim_status pim_run(pim_batch* b, const pim_schedule* sc, uint64_t seed, void* st
     return fail(PIM_ERR_NOMEM, "host allocation failed");
   } catch (...) {
     return fail(PIM_ERR_INVALID, "internal error in pim_run");
+  }
+}
+
+pim_status pim_states(pim_batch* b, int32_t inst, int32_t trial, int8_t* states) {
+  try {
+    pim_status st = check_batch_ready(b, inst);
+    if (st != PIM_OK) return st;
+    if (!b->recorded) return fail(PIM_ERR_STATE, "the last run did not record its states");
+    if (trial < 0 || trial >= b->R) return fail(PIM_ERR_INVALID, "trial %d outside [0, %d)", trial, b->R);
+    if (!states) return fail(PIM_ERR_INVALID, "states is NULL");
+    const size_t rows = (size_t)b->last_T + 1;
+    const int8_t* src = b->d_trace + ((size_t)inst * b->R + trial) * rows * b->npad;
+    HIP_TRY(hipMemcpy2DAsync(states, b->n, src, b->npad, b->n, rows, hipMemcpyDeviceToHost, b->stream));
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    return PIM_OK;
+  } catch (...) {
+    return fail(PIM_ERR_INVALID, "internal error in pim_states");
+  }
+}
+
+pim_status pim_flip_counts(pim_batch* b, int32_t inst, int64_t* num, int64_t* den) {
+  try {
+    pim_status st = check_batch_ready(b, inst);
+    if (st != PIM_OK) return st;
+    if (!b->recorded) return fail(PIM_ERR_STATE, "the last run did not record its states");
+    if (!num || !den) return fail(PIM_ERR_INVALID, "NULL argument");
+    const int T = b->last_T;
+    unsigned long long* d = nullptr;
+    st = alloc_dev(&d, 2 * (size_t)T, b->stream);
+    if (st != PIM_OK) return st;
+    FlipRateArgs fa{};
+    fa.trace = b->d_trace + (size_t)inst * b->R * ((size_t)T + 1) * b->npad;
+    fa.j8 = b->insts[inst]->d_j8;
+    fa.num = d;
+    fa.den = d + T;
+    fa.n = b->n;
+    fa.npad = b->npad;
+    fa.R = b->R;
+    fa.T = T;
+    hipError_t e = launch_flip_rate(fa, b->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(num, d, T * 8, hipMemcpyDeviceToHost, b->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(den, d + T, T * 8, hipMemcpyDeviceToHost, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    dev_free(d, b->stream);
+    if (e != hipSuccess) return fail(PIM_ERR_DEVICE, "pim_flip_counts failed: %s", hipGetErrorString(e));
+    return PIM_OK;
+  } catch (...) {
+    return fail(PIM_ERR_INVALID, "internal error in pim_flip_counts");
   }
 }
 

@@ -76,7 +76,7 @@ __device__ __forceinline__ void mfma_row_tile(const v4i* sJl, int mt, const v4i 
 // Each wave owns CB blocks of 32 trials.  Two independent blocks give the
 // in-order issue of one wave per SIMD enough independent work to keep the
 // vector ALU busy while MFMA chains and LDS lookups are in flight.
-template <int NT, int CB, bool HAS_H>
+template <int NT, int CB, bool HAS_H, bool RECORD>
 __global__ __launch_bounds__(64 * kWaves, 3) void sweep_mfma_kernel(SweepArgs a) {
   extern __shared__ __align__(16) unsigned char lds[];
   constexpr int kFragBytes = NT * NT * 1024;
@@ -265,6 +265,13 @@ __global__ __launch_bounds__(64 * kWaves, 3) void sweep_mfma_kernel(SweepArgs a)
     }
 #pragma unroll
     for (int c = 0; c < CB; ++c) {
+      if (RECORD && live[c]) {  // diagnostics: keep s(t) of every step
+        size_t off = (cell[c] * (size_t)(a.T + 1) + t) * kNpad + 16 * half;
+        PIM_FENCE(off);
+        int8_t* dst = a.trace + off;
+#pragma unroll
+        for (int mt = 0; mt < NT; ++mt) *reinterpret_cast<v4i*>(dst + 32 * mt) = B[c][mt];
+      }
       const int32_t epc = ep[c] + __shfl_xor(ep[c], 32);
       const int32_t E = -(epc / 2);
       if (E < e_best[c]) {
@@ -319,10 +326,10 @@ __global__ __launch_bounds__(64 * kWaves, 3) void sweep_mfma_kernel(SweepArgs a)
 
 constexpr int kBlocksPerWave = 1;  // CB: 32-trial column blocks per wave
 
-template <int NT, bool HAS_H>
+template <int NT, bool HAS_H, bool RECORD>
 hipError_t launch_nt(const SweepArgs& a, int count, hipStream_t s) {
   const size_t lds = (size_t)NT * NT * 1024 + (HAS_H ? NT * 32 * 4 : 0) + (size_t)kWaves * kTabBytes;
-  auto kern = sweep_mfma_kernel<NT, kBlocksPerWave, HAS_H>;
+  auto kern = sweep_mfma_kernel<NT, kBlocksPerWave, HAS_H, RECORD>;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
@@ -332,17 +339,17 @@ hipError_t launch_nt(const SweepArgs& a, int count, hipStream_t s) {
   return hipGetLastError();
 }
 
-template <bool HAS_H>
+template <bool HAS_H, bool RECORD>
 hipError_t launch_h(const SweepArgs& a, int count, int nt, hipStream_t s) {
   switch (nt) {
-    case 1: return launch_nt<1, HAS_H>(a, count, s);
-    case 2: return launch_nt<2, HAS_H>(a, count, s);
-    case 3: return launch_nt<3, HAS_H>(a, count, s);
-    case 4: return launch_nt<4, HAS_H>(a, count, s);
-    case 5: return launch_nt<5, HAS_H>(a, count, s);
-    case 6: return launch_nt<6, HAS_H>(a, count, s);
-    case 7: return launch_nt<7, HAS_H>(a, count, s);
-    case 8: return launch_nt<8, HAS_H>(a, count, s);
+    case 1: return launch_nt<1, HAS_H, RECORD>(a, count, s);
+    case 2: return launch_nt<2, HAS_H, RECORD>(a, count, s);
+    case 3: return launch_nt<3, HAS_H, RECORD>(a, count, s);
+    case 4: return launch_nt<4, HAS_H, RECORD>(a, count, s);
+    case 5: return launch_nt<5, HAS_H, RECORD>(a, count, s);
+    case 6: return launch_nt<6, HAS_H, RECORD>(a, count, s);
+    case 7: return launch_nt<7, HAS_H, RECORD>(a, count, s);
+    case 8: return launch_nt<8, HAS_H, RECORD>(a, count, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -351,7 +358,8 @@ hipError_t launch_h(const SweepArgs& a, int count, int nt, hipStream_t s) {
 
 hipError_t launch_sweep_mfma(const SweepArgs& a, int count, int nt, bool has_h, hipStream_t s) {
   if (a.npad != nt * 32) return hipErrorInvalidValue;
-  return has_h ? launch_h<true>(a, count, nt, s) : launch_h<false>(a, count, nt, s);
+  if (a.trace) return has_h ? launch_h<true, true>(a, count, nt, s) : launch_h<false, true>(a, count, nt, s);
+  return has_h ? launch_h<true, false>(a, count, nt, s) : launch_h<false, false>(a, count, nt, s);
 }
 
 void pack_mfma_fragments(const int8_t* J, int n, int nt, int8_t* out) {

@@ -243,3 +243,29 @@ def test_sequential_resume(gpu_lib):
     rest = pim.Batch([inst], trials, init_spins=part.trials_of(0)["final"][None]).run(
         beta[111:], eta[111:], seed=3, kernel="seq", start_step=111)
     np.testing.assert_array_equal(rest.trials_of(0)["final"], full.trials_of(0)["final"])
+
+
+@pytest.mark.parametrize("xi", [0.0, 0.5])
+def test_recorded_states_and_flip_rate(gpu_lib, xi):
+    """Every recorded state s(t) equals the oracle's, and the device's
+    neighbour-triggered flip counts equal the oracle's definition exactly."""
+    from oracle import diagnostics
+    _say(f"record states + P_NT xi={xi}")
+    pim = gpu_lib
+    n, trials, steps = 40, 70, 90
+    J, h = w.maxcut(n, seed=4, index=2)
+    ztab = w.gauss_table(8)
+    c = 2 / np.sqrt(n)
+    beta = w.linear_beta(steps, 0.1, 3.0)
+    eta = w.eta_sqrt_beta_over_5(beta)
+    inst = pim.Instance(J, h, j_scale=c, xi=xi, noise_table=ztab, rng_stream=6)
+    batch = pim.Batch([inst], trials).run(beta, eta, seed=2, record=True)
+    prob = pimi.Problem(J, h, c=c, xi=xi, levels=4, ztab=ztab)
+    ref = pimi.run_parallel(prob, beta, eta, 2, 6, np.arange(trials), record=True)
+    for a in (0, 31, 32, trials - 1):
+        np.testing.assert_array_equal(batch.states(0, a), ref["states"][:, :, a])
+    num, den = batch.flip_counts(0)
+    rnum, rden = diagnostics.neighbor_flip_counts(J, ref["states"])
+    np.testing.assert_array_equal(num, rnum)
+    np.testing.assert_array_equal(den, rden)
+    batch.close()
