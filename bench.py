@@ -46,6 +46,8 @@ def parse():
                     help="instances run through the plain FP32 per-instance kernel for the comparison "
                          "(0 = skip); trajectories are bit-identical, so TTS99 is equal")
     ap.add_argument("--no-mimo", action="store_true", help="skip the MIMO detection leg")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the parallel-vs-sequential comparison and the flip-rate diagnostic")
     ap.add_argument("--mimo-requests", type=int, default=512,
                     help="MIMO channels in the batched quality/throughput run")
     ap.add_argument("--mimo-latency", type=int, default=200,
@@ -203,6 +205,73 @@ def mimo_leg(args):
     return out
 
 
+def comparison_leg():
+    """The paper's comparison on the GPU (Fig. 2 / Suppl. "Estimation of
+    optimal clock cycles to solution", "Quantifying coupled oscillatory
+    dynamics"): PIMI with fully parallel updates against the conventional PIM
+    with sequential updates (Eq. (3): xi = 0, uniform noise, one spin per
+    step), on SK-1 instances of N = 20 ... 200, and the neighbour-triggered
+    flip rate of the parallel dynamics against xi.
+
+    Both run 1024 trials per instance with beta linear 0.1 -> 3.0 over their
+    T steps: PIMI T = 1000 steps (eta = sqrt(beta / 5), xi = 0.5), the
+    sequential PIM T = 1000 N single-spin steps (1000 sweeps, eta = 1).
+    Success = E <= floor(0.999 H_ref), H_ref = best energy either method
+    found; TTS99 = n99 * (kernel time / trials), the GPU time per trial run
+    with all trials in flight."""
+    import paper_2604_17109_amd as pim
+    import workloads as w
+    R, count = 1024, 4
+    rows = []
+    for n in (20, 50, 100, 200):
+        insts = [pim.Instance(*w.sk1(n, seed=5, index=k), j_scale=1 / math.sqrt(n), xi=0.5,
+                              noise_table=w.gauss_table(8), rng_stream=k) for k in range(count)]
+        seqi = [pim.Instance(*w.sk1(n, seed=5, index=k), j_scale=1 / math.sqrt(n), xi=0.0,
+                             noise_table=w.uniform_table(8), rng_stream=k) for k in range(count)]
+        bp = pim.Batch(insts, R)
+        bs = pim.Batch(seqi, R)
+        Tp, Ts = 1000, 1000 * n
+        beta_p = w.linear_beta(Tp, 0.1, 3.0)
+        beta_s = w.linear_beta(Ts, 0.1, 3.0)
+        bp.run(beta_p, w.eta_sqrt_beta_over_5(beta_p), seed=3)
+        bs.run(beta_s, w.constant(Ts, 1.0), seed=3, kernel="seq")
+        ref = [min(bp.best(k)[1], bs.best(k)[1]) for k in range(count)]
+        tgt = [math.floor(0.999 * r) for r in ref]
+        bp.run(beta_p, w.eta_sqrt_beta_over_5(beta_p), seed=4, target=tgt)
+        bs.run(beta_s, w.constant(Ts, 1.0), seed=4, kernel="seq", target=tgt)
+        kp, ks = bp.kernel_ms(), bs.kernel_ms()
+        pp = float(np.mean([(bp.trials_of(k, spins=False)["first_hit"] >= 0).mean() for k in range(count)]))
+        ps = float(np.mean([(bs.trials_of(k, spins=False)["first_hit"] >= 0).mean() for k in range(count)]))
+
+        def n99(p):
+            return 1 if p >= 1 else (None if p <= 0 else math.ceil(math.log(0.01) / math.log(1 - p)))
+        tp = n99(pp) * kp / (count * R) if n99(pp) else None
+        ts = n99(ps) * ks / (count * R) if n99(ps) else None
+        rows.append({"n": n, "p_parallel": pp, "p_sequential": ps,
+                     "kernel_ms_parallel": kp, "kernel_ms_sequential": ks,
+                     "tts99_ms_parallel": tp, "tts99_ms_sequential": ts,
+                     "tts99_speedup": (ts / tp) if (tp and ts) else None})
+        bp.close()
+        bs.close()
+    # neighbour-triggered flip rate vs xi, SK-1 N = 200
+    n, T, R2 = 200, 1000, 256
+    J, h = w.sk1(n, seed=5, index=0)
+    beta = w.linear_beta(T, 0.1, 3.0)
+    eta = w.eta_sqrt_beta_over_5(beta)
+    pnt = {}
+    for xi in (0.0, 0.2, 0.5, 0.8):
+        inst = pim.Instance(J, h, j_scale=1 / math.sqrt(n), xi=xi, noise_table=w.gauss_table(8), rng_stream=0)
+        b = pim.Batch([inst], R2).run(beta, eta, seed=1, record=True)
+        num, den = b.flip_counts(0)
+        with np.errstate(invalid="ignore", divide="ignore"):
+            p = np.where(den > 0, num / np.maximum(den, 1), np.nan)
+        pnt[str(xi)] = {f"t={t}": (None if np.isnan(p[t]) else round(float(p[t]), 4)) for t in (10, 250, 500, 750, 999)}
+        pnt[str(xi)]["mean_second_half"] = round(float(np.nanmean(p[T // 2:])), 4)
+        b.close()
+    return {"tts99_parallel_vs_sequential": rows,
+            "flip_rate_vs_xi": {"workload": f"SK-1 N={n}, {R2} trials x {T} steps", "p_nt": pnt}}
+
+
 def main():
     args = parse()
     if args.copy_probe:
@@ -308,6 +377,8 @@ def main():
         pb.close()
     if not args.no_mimo:
         line["mimo"] = mimo_leg(args)
+    if not args.no_compare:
+        line["comparison"] = comparison_leg()
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(n, args.cpu_trials, args.cpu_steps, xi, c)
     print(json.dumps(line), flush=True)

@@ -5,7 +5,7 @@
 // the same noise: u is byte i % 16 of the Philox block (i / 16, t, trial,
 // stream).
 //
-// One lane per trial (64 trials per wave, 4 waves per workgroup), the
+// One lane per trial (64 trials per wave, one wave per workgroup), the
 // instance's int8 couplings staged in LDS row-major, the trial's spins as int8
 // in registers (Npad / 4 words).  A step reads row i of J (broadcast: every
 // lane reads the same address), forms I_i = sum_j J_ij s_j + h_i with one
@@ -22,8 +22,27 @@
 namespace pim {
 namespace {
 
-constexpr int kWaves = 4;
+// One wave per workgroup: a trial's steps form one serial dependency chain, so
+// the kernel is latency-bound per wave; single-wave workgroups spread the
+// trials over as many compute units as there are 64-trial blocks.
+constexpr int kWaves = 1;
 constexpr int kTabBytes = kTabEntries * 2;
+
+// I_i = sum_j J_ij s_j over one padded row: four independent accumulators so
+// the v_dot4 chain is not one serial dependency.
+template <int NW>
+__device__ __forceinline__ int32_t row_dot(const uint4* row, const uint32_t (&sp)[NW], int32_t init) {
+  int32_t acc[4] = {init, 0, 0, 0};
+#pragma unroll
+  for (int q = 0; q < NW / 4; ++q) {
+    const uint4 jv = row[q];
+    acc[0] = __builtin_amdgcn_sdot4((int)jv.x, (int)sp[4 * q], acc[0], false);
+    acc[1] = __builtin_amdgcn_sdot4((int)jv.y, (int)sp[4 * q + 1], acc[1], false);
+    acc[2] = __builtin_amdgcn_sdot4((int)jv.z, (int)sp[4 * q + 2], acc[2], false);
+    acc[3] = __builtin_amdgcn_sdot4((int)jv.w, (int)sp[4 * q + 3], acc[3], false);
+  }
+  return (acc[0] + acc[1]) + (acc[2] + acc[3]);
+}
 
 __device__ __forceinline__ int spins_from_bits(uint32_t w) {
   return (int)(0xFFFFFFFFu - 0xFEu * ((w >> 7) & 0x01010101u));
@@ -85,16 +104,7 @@ __global__ __launch_bounds__(64 * kWaves) void sweep_seq_kernel(SeqArgs a) {
   // ---- E(0) = -1/2 sum_i s_i (I_i + h_i) ----
   int32_t twice = 0;
   for (int i = 0; i < n; ++i) {
-    int32_t acc = HAS_H ? hrow[i] : 0;
-    const uint4* row = sJ + (size_t)i * (kNpad / 16);
-#pragma unroll
-    for (int q = 0; q < NW / 4; ++q) {
-      const uint4 jv = row[q];
-      acc = __builtin_amdgcn_sdot4((int)jv.x, (int)sp[4 * q], acc, false);
-      acc = __builtin_amdgcn_sdot4((int)jv.y, (int)sp[4 * q + 1], acc, false);
-      acc = __builtin_amdgcn_sdot4((int)jv.z, (int)sp[4 * q + 2], acc, false);
-      acc = __builtin_amdgcn_sdot4((int)jv.w, (int)sp[4 * q + 3], acc, false);
-    }
+    const int32_t acc = row_dot<NW>(sJ + (size_t)i * (kNpad / 16), sp, HAS_H ? hrow[i] : 0);
     const int si = (int)(int8_t)(sp[i >> 2] >> (8 * (i & 3)));
     twice += si * (acc + (HAS_H ? hrow[i] : 0));
   }
@@ -110,22 +120,14 @@ __global__ __launch_bounds__(64 * kWaves) void sweep_seq_kernel(SeqArgs a) {
     const int tg = a.start_step + t;
     const int i = tg % n;  // wave-uniform
     const uint4 nxt = gTab4[(size_t)min(t + 1, a.T - 1) * 64 + lane];
-    const uint4* row = sJ + (size_t)i * (kNpad / 16);
-    int32_t acc = HAS_H ? hrow[i] : 0;
-#pragma unroll
-    for (int q = 0; q < NW / 4; ++q) {
-      const uint4 jv = row[q];
-      acc = __builtin_amdgcn_sdot4((int)jv.x, (int)sp[4 * q], acc, false);
-      acc = __builtin_amdgcn_sdot4((int)jv.y, (int)sp[4 * q + 1], acc, false);
-      acc = __builtin_amdgcn_sdot4((int)jv.z, (int)sp[4 * q + 2], acc, false);
-      acc = __builtin_amdgcn_sdot4((int)jv.w, (int)sp[4 * q + 3], acc, false);
-    }
+    // the step's noise block first: its Philox chain overlaps the row product
+    const Ctr4 x = philox4x32_10(Ctr4{(uint32_t)(i >> 4), (uint32_t)tg, (uint32_t)trial,
+                                      (kDomainNoise << 24) | stream}, a.k0, a.k1);
+    const int32_t acc = row_dot<NW>(sJ + (size_t)i * (kNpad / 16), sp, HAS_H ? hrow[i] : 0);
     const int word = i >> 2, sh = 8 * (i & 3);
     // wave-uniform register index (relative addressing of the VGPR array)
     const uint32_t w = sp[word];
     const int s_old = (int)(int8_t)(w >> sh);
-    const Ctr4 x = philox4x32_10(Ctr4{(uint32_t)(i >> 4), (uint32_t)tg, (uint32_t)trial,
-                                      (kDomainNoise << 24) | stream}, a.k0, a.k1);
     const uint32_t xw = ((i & 15) < 8) ? (((i & 15) < 4) ? x.x : x.y) : (((i & 15) < 12) ? x.z : x.w);
     const int u = (int)((xw >> (8 * (i & 3))) & 0xFFu);
     const int th = sTab[kNoiseVals + (u ^ s_old)];
