@@ -179,8 +179,12 @@ pim_status pim_create_real(const double* J, const double* h, const pim_params* p
  * binary64 values scale * q (J_out: N x N, may alias nothing), and the scale. */
 pim_status pim_quantize(const double* J, int32_t n, int32_t prec, double* J_out, double* scale_out);
 
-/* Groups `count` instances of equal N and kind (all integer, or all real with
- * one pim_prec) with `trials` trials each.  init_spins:
+/* Groups `count` instances of one kind (all integer, or all real with one
+ * pim_prec) with `trials` trials each.  Instances may have different N: the
+ * batch then keeps one part per distinct N and pim_run launches every part's
+ * sweep as a parallel branch of one captured HIP graph (one graph launch per
+ * run); init_spins then holds, instance after instance, trials x N_k values.
+ * init_spins:
  * host int8 [count][trials][N] of +-1, or NULL for generator-drawn initial
  * spins.  The batch keeps pointers to the instances, which must outlive it.
  * Trial a of instance k is trial id a in the generator counter. */
@@ -200,6 +204,14 @@ pim_status pim_batch_create(pim_instance* const* insts, int32_t count, int32_t t
  * with E <= target.  Resuming: pass the previous final spins as init_spins of a
  * new batch and start_step = previous start_step + T. */
 pim_status pim_run(pim_batch* batch, const pim_schedule* sched, uint64_t seed, void* stream);
+
+/* Picks, for every distinct N of an integer batch, the number of 32-trial
+ * waves per workgroup of the int8 MFMA kernel (4, 2 or 1: trials per
+ * workgroup and hence workgroups per compute unit) by timing two runs of
+ * `steps` steps (beta = 1, eta = 0.5) with each choice; later runs use the
+ * fastest.  Overwrites the batch's results.  waves_out: host [number of
+ * distinct N, ascending], or NULL.  Synchronises. */
+pim_status pim_tune(pim_batch* batch, int32_t steps, void* stream, int32_t* waves_out);
 
 /* Requests cancellation of the batch's current run: host-callable at any time
  * from any thread; the kernel stops within 256 steps.  Results of a cancelled

@@ -40,7 +40,7 @@ EXPORTED = (
     "pim_energy", "pim_best", "pim_trials", "pim_kernel_time", "pim_compile_step", "pim_compile_table",
     "pim_batch_destroy", "pim_destroy", "pim_last_error", "pim_abi_version",
     "pim_create_real", "pim_quantize", "pim_compile_table_real", "pim_mimo_ising", "pim_mimo_decode",
-    "pim_states", "pim_flip_counts",
+    "pim_states", "pim_flip_counts", "pim_tune",
 )
 
 
@@ -108,6 +108,7 @@ def _load():
         "pim_mimo_decode": (I32, [P(F64), P(ctypes.c_int8), I32, I32, I32, P(F64)]),
         "pim_states": (I32, [VP, I32, I32, P(ctypes.c_int8)]),
         "pim_flip_counts": (I32, [VP, I32, P(ctypes.c_int64), P(ctypes.c_int64)]),
+        "pim_tune": (I32, [VP, I32, VP, P(I32)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -357,18 +358,24 @@ class Instance:
 
 
 class Batch:
-    """Instances of one N x `trials` trials, with per-trial result buffers."""
+    """Instances x `trials` trials, with per-trial result buffers.  Instances
+    of different N run together (one graph launch per run)."""
 
     def __init__(self, instances, trials, init_spins=None, stream=None):
         _device_ready()
         self.instances = list(instances)  # keep the instances alive
         self.count = len(self.instances)
         self.trials = int(trials)
-        self.n = self.instances[0].n
+        self.ns = [i.n for i in self.instances]
+        self.n = self.ns[0] if len(set(self.ns)) == 1 else None
         arr = (ctypes.c_void_p * self.count)(*[i.handle.value for i in self.instances])
         init = None
         if init_spins is not None:
-            init = np.ascontiguousarray(init_spins, dtype=np.int8).reshape(self.count, self.trials, self.n)
+            if self.n is not None:
+                init = np.ascontiguousarray(init_spins, dtype=np.int8).reshape(self.count, self.trials, self.n)
+            else:  # a sequence of [trials, n_k] arrays
+                init = np.ascontiguousarray(np.concatenate(
+                    [np.asarray(a, dtype=np.int8).reshape(-1) for a in init_spins]))
         self._handle = ctypes.c_void_p()
         self.stream = stream if stream is not None else current_stream()
         _check(lib.pim_batch_create(arr, self.count, self.trials, _ptr(init, ctypes.c_int8), self.stream,
@@ -402,9 +409,15 @@ class Batch:
     def cancel(self):
         _check(lib.pim_cancel(self._handle))
 
+    def tune(self, steps=200):
+        """Autotunes waves per workgroup for every distinct N (see pim_tune)."""
+        out = np.zeros(len(set(self.ns)), np.int32)
+        _check(lib.pim_tune(self._handle, int(steps), self.stream, _ptr(out, ctypes.c_int32)))
+        return out
+
     def best(self, k):
         """(spins int8[n], energy, trial, step) of the lowest-energy candidate."""
-        spins = np.zeros(self.n, dtype=np.int8)
+        spins = np.zeros(self.ns[k], dtype=np.int8)
         e = ctypes.c_double()
         tr = ctypes.c_int32()
         st = ctypes.c_int32()
@@ -413,7 +426,7 @@ class Batch:
         return spins, e.value, tr.value, st.value
 
     def trials_of(self, k, spins=True):
-        R, n = self.trials, self.n
+        R, n = self.trials, self.ns[k]
         out = {
             "e_best": np.zeros(R, np.float64), "t_best": np.zeros(R, np.int32),
             "first_hit": np.zeros(R, np.int32), "e_final": np.zeros(R, np.float64),
@@ -431,7 +444,7 @@ class Batch:
 
     def states(self, k, trial):
         """Recorded trajectory of one trial: int8 [T + 1, n] (run with record=True)."""
-        out = np.zeros((self._steps + 1, self.n), np.int8)
+        out = np.zeros((self._steps + 1, self.ns[k]), np.int8)
         _check(lib.pim_states(self._handle, int(k), int(trial), _ptr(out, ctypes.c_int8)))
         return out
 

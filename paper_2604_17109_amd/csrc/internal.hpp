@@ -72,6 +72,7 @@ struct SweepArgs {
   const volatile int32_t* cancel;
   int32_t n, npad, R, T, start_step;
   uint32_t k0, k1;
+  int32_t waves;             // waves (32-trial blocks) per workgroup: 1, 2 or 4
 };
 
 // Real-valued instances: spins and states as in SweepArgs; energies binary32
@@ -260,6 +261,17 @@ struct pim_batch {
   // host-side class bookkeeping
   std::vector<int> inst_class;
   std::vector<int> class_rep;     // representative instance of each class
+  int waves = 4;                  // int8 MFMA kernel: 32-trial waves per workgroup (1, 2, 4)
+  // uneven N: one part (a simple batch) per padded size, launched together as
+  // the parallel branches of one captured graph
+  std::vector<pim_batch*> parts;
+  std::vector<int> part_of, local_of;  // instance -> part, index inside the part
+  std::vector<hipStream_t> fork;       // one per part (default priority)
+  std::vector<hipEvent_t> join;
+  hipEvent_t fork_ev = nullptr;
+  hipStream_t cap = nullptr;           // capture stream
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
   // run state
   bool ran = false, reranked = false, sticky_error = false;
   int last_T = 0, last_start = 0;

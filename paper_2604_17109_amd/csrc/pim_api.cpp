@@ -151,6 +151,20 @@ pim_status check_spins(const int8_t* s, size_t count) {
 }
 
 void free_batch_buffers(pim_batch* b) {
+  for (pim_batch* part : b->parts) {
+    (void)hipStreamSynchronize(part->stream);
+    free_batch_buffers(part);
+    delete part;
+  }
+  b->parts.clear();
+  for (hipStream_t f : b->fork) (void)hipStreamDestroy(f);
+  for (hipEvent_t j : b->join) (void)hipEventDestroy(j);
+  b->fork.clear();
+  b->join.clear();
+  if (b->fork_ev) (void)hipEventDestroy(b->fork_ev);
+  if (b->cap) (void)hipStreamDestroy(b->cap);
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
   hipStream_t s = b->stream;
   dev_free(b->d_jfrag, s);
   dev_free(b->d_j8pad, s);
@@ -248,6 +262,375 @@ pim_status cancelled_status(pim_batch* b, int32_t inst) {
     if (done[a] < b->last_T) return fail(PIM_ERR_CANCELLED, "run was cancelled after %d of %d steps", done[a], b->last_T);
   return PIM_OK;
 }
+
+// A batch of instances of uneven N: one simple part per distinct N, each with
+// its own buffers; the composite maps instance indices to (part, local index).
+pim_status create_composite(pim_instance* const* insts, int32_t count, int32_t trials, const int8_t* init_spins,
+                            hipStream_t s, pim_batch** out) {
+  std::vector<int> ns;
+  for (int k = 0; k < count; ++k) ns.push_back(insts[k]->rule.n);
+  std::vector<int> distinct(ns);
+  std::sort(distinct.begin(), distinct.end());
+  distinct.erase(std::unique(distinct.begin(), distinct.end()), distinct.end());
+  std::vector<size_t> init_off(count + 1, 0);
+  for (int k = 0; k < count; ++k) init_off[k + 1] = init_off[k] + (size_t)trials * ns[k];
+  if (init_spins) {
+    pim_status st = check_spins(init_spins, init_off[count]);
+    if (st != PIM_OK) return st;
+  }
+  auto* b = new pim_batch();
+  b->count = count;
+  b->R = trials;
+  b->n = 0;
+  b->real = insts[0]->rule.real;
+  b->prec = insts[0]->prec;
+  b->stream = s;
+  b->insts.assign(insts, insts + count);
+  b->part_of.assign(count, -1);
+  b->local_of.assign(count, -1);
+  auto bail = [&](pim_status st) {
+    free_batch_buffers(b);
+    delete b;
+    return st;
+  };
+  for (size_t p = 0; p < distinct.size(); ++p) {
+    std::vector<pim_instance*> sub;
+    std::vector<int8_t> sub_init;
+    for (int k = 0; k < count; ++k)
+      if (ns[k] == distinct[p]) {
+        b->part_of[k] = (int)p;
+        b->local_of[k] = (int)sub.size();
+        sub.push_back(insts[k]);
+        if (init_spins) sub_init.insert(sub_init.end(), init_spins + init_off[k], init_spins + init_off[k + 1]);
+      }
+    pim_batch* part = nullptr;
+    pim_status st = pim_batch_create(sub.data(), (int32_t)sub.size(), trials, init_spins ? sub_init.data() : nullptr,
+                                     (void*)s, &part);
+    if (st != PIM_OK) return bail(st);
+    b->parts.push_back(part);
+    b->has_h |= part->has_h;
+    hipStream_t f = nullptr;
+    hipEvent_t j = nullptr;
+    if (hipStreamCreateWithFlags(&f, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&j, hipEventDisableTiming) != hipSuccess)
+      return bail(fail(PIM_ERR_DEVICE, "stream / event creation failed"));
+    b->fork.push_back(f);
+    b->join.push_back(j);
+  }
+  if (hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&b->fork_ev, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreate(&b->ev0) != hipSuccess || hipEventCreate(&b->ev1) != hipSuccess)
+    return bail(fail(PIM_ERR_DEVICE, "stream / event creation failed"));
+  *out = b;
+  return PIM_OK;
+}
+
+struct RunCtx {
+  int T = 0, L = 0;
+  bool real = false, mfma = false, seq = false;
+  std::vector<int32_t> tgt;
+  std::vector<float> tgtf;
+};
+
+// Validates the schedule, compiles and uploads the step tables of a simple
+// (single-N) batch on stream s and fills ctx for run_launch.
+pim_status run_prepare(pim_batch* b, const pim_schedule* sc, hipStream_t s, RunCtx& ctx) {
+  {
+    if (!b) return fail(PIM_ERR_INVALID, "batch is NULL");
+    if (b->sticky_error) return fail(PIM_ERR_DEVICE, "batch is in an error state after a failed device call");
+    if (!sc) return fail(PIM_ERR_INVALID, "schedule is NULL");
+    if (sc->steps < 1) return fail(PIM_ERR_INVALID, "steps must be >= 1");
+    if (!sc->beta || !sc->eta) return fail(PIM_ERR_INVALID, "beta and eta must be non-NULL");
+    if (sc->start_step < 0 || (int64_t)sc->start_step + sc->steps >= (int64_t)1 << 31)
+      return fail(PIM_ERR_INVALID, "start_step + steps must lie in [0, 2^31)");
+    if (sc->kernel != PIM_KERNEL_MFMA_I8 && sc->kernel != PIM_KERNEL_PLAIN_F32 && sc->kernel != PIM_KERNEL_SEQ_I8)
+      return fail(PIM_ERR_INVALID, "unknown kernel %d", sc->kernel);
+    if (sc->kernel == PIM_KERNEL_SEQ_I8 && b->real)
+      return fail(PIM_ERR_UNSUPPORTED, "the sequential kernel takes integer instances");
+    if (sc->record_states && (sc->kernel != PIM_KERNEL_MFMA_I8 || b->real))
+      return fail(PIM_ERR_UNSUPPORTED, "state recording is implemented for the int8 MFMA kernel");
+    if (sc->use_target && !sc->target) return fail(PIM_ERR_INVALID, "use_target set without target energies");
+    const int T = sc->steps;
+    for (int t = 0; t < T; ++t)
+      if (!finite_nonneg(sc->beta[t]) || !finite_nonneg(sc->eta[t]))
+        return fail(PIM_ERR_INVALID, "beta[%d] / eta[%d] must be finite and >= 0", t, t);
+    for (int k = 0; sc->use_target && k < b->count; ++k)
+      if (std::isnan(sc->target[k])) return fail(PIM_ERR_INVALID, "target[%d] is NaN", k);
+    // targets: integer batches compare E <= floor(target), real ones in binary32
+    std::vector<int32_t> tgt(b->count, INT32_MIN);
+    std::vector<float> tgtf(b->count, -INFINITY);
+    if (sc->use_target)
+      for (int k = 0; k < b->count; ++k) {
+        const double f = std::floor(sc->target[k]);
+        tgt[k] = f >= (double)INT32_MAX ? INT32_MAX : (f <= (double)INT32_MIN + 1 ? INT32_MIN + 1 : (int32_t)f);
+        // largest binary32 value <= target, so E <= tgtf <=> E <= target for binary32 E
+        float tf = (float)sc->target[k];
+        if ((double)tf > sc->target[k]) tf = std::nextafter(tf, -INFINITY);
+        tgtf[k] = tf;
+      }
+    b->stream = s;
+    const int L = b->insts[0]->rule.levels;
+    const int ncls = (int)b->class_rep.size();
+    const bool real = b->real;
+    // ---- compile ----
+    std::vector<int32_t> steptab;
+    const bool seq = sc->kernel == PIM_KERNEL_SEQ_I8;
+    const bool mfma = sc->kernel == PIM_KERNEL_MFMA_I8 || seq;  // both read the (u, s) tables
+    const size_t entry = real ? 4 : 2;  // bytes per table entry
+    if (mfma) {
+      const size_t need = (size_t)ncls * T * kTabEntries * entry;
+      if (need > b->h_thtab_bytes) {
+        if (b->h_thtab) (void)hipHostFree(b->h_thtab);
+        b->h_thtab = nullptr;
+        b->h_thtab_bytes = 0;
+        if (hipHostMalloc(&b->h_thtab, need, hipHostMallocDefault) != hipSuccess)
+          return fail(PIM_ERR_NOMEM, "pinned staging allocation of %zu bytes failed", need);
+        b->h_thtab_bytes = need;
+      }
+      void* out = b->h_thtab;
+      parallel_for(T * ncls, [&](int lo, int hi) {
+        int32_t th[kMaxLevels], um[2 * kMaxLevels];
+        float thf[kMaxLevels];
+        for (int i = lo; i < hi; ++i) {
+          const int c = i / T, t = i % T;
+          const Rule& r = b->insts[b->class_rep[c]]->rule;
+          const size_t off = ((size_t)c * T + t) * kTabEntries;
+          if (real) {
+            compile_step_real(r, sc->beta[t], sc->eta[t], thf, um);
+            theta_by_noise_real(thf, um, r.levels, static_cast<float*>(out) + off);
+          } else {
+            compile_step(r, sc->beta[t], sc->eta[t], th, um);
+            theta_by_noise(th, um, r.levels, static_cast<int16_t*>(out) + off);
+          }
+        }
+      });
+    } else {
+      for (int k = 0; k < b->count; ++k)
+        if (b->insts[k]->rule.levels != L)
+          return fail(PIM_ERR_UNSUPPORTED, "the plain kernel needs one LUT size per batch");
+      const int w = (L - 1) + 2 * L;
+      steptab.resize((size_t)ncls * T * w);
+      for (int c = 0; c < ncls; ++c) {
+        const Rule& r = b->insts[b->class_rep[c]]->rule;
+        for (int t = 0; t < T; ++t) {
+          int32_t* row = &steptab[((size_t)c * T + t) * w];
+          if (real) {
+            float thf[kMaxLevels];
+            compile_step_real(r, sc->beta[t], sc->eta[t], thf, row + (L - 1));
+            std::memcpy(row, thf, (L - 1) * sizeof(float));  // float bits in the int32 row
+          } else {
+            compile_step(r, sc->beta[t], sc->eta[t], row, row + (L - 1));
+          }
+        }
+      }
+    }
+    // ---- upload ----
+    const size_t thtab_need = mfma ? (size_t)ncls * T * kTabEntries * entry : 0;
+    if (mfma && thtab_need > b->thtab_bytes) {
+      dev_free(b->d_thtab, s);
+      b->d_thtab = nullptr;
+      b->thtab_bytes = 0;
+      b->d_thtab = dev_alloc(thtab_need, s);
+      if (!b->d_thtab) return fail(PIM_ERR_NOMEM, "device allocation of %zu bytes failed", thtab_need);
+      b->thtab_bytes = thtab_need;
+    }
+    if (!mfma && steptab.size() * 4 > b->steptab_bytes) {
+      dev_free(b->d_steptab, s);
+      b->d_steptab = nullptr;
+      b->steptab_bytes = 0;
+      pim_status st = alloc_dev(&b->d_steptab, steptab.size(), s);
+      if (st != PIM_OK) return st;
+      b->steptab_bytes = steptab.size() * 4;
+    }
+    auto device_fail = [&](hipError_t e, const char* what) {
+      b->sticky_error = true;
+      return fail(PIM_ERR_DEVICE, "%s failed: %s", what, hipGetErrorString(e));
+    };
+    hipError_t e = hipSuccess;
+    b->recorded = false;
+    if (sc->record_states) {
+      const size_t need = (size_t)b->count * b->R * ((size_t)T + 1) * b->npad;
+      if (need / ((size_t)T + 1) != (size_t)b->count * b->R * b->npad)
+        return fail(PIM_ERR_INVALID, "recorded trajectory size overflows");
+      if (need > b->trace_bytes) {
+        dev_free(b->d_trace, s);
+        b->d_trace = nullptr;
+        b->trace_bytes = 0;
+        pim_status st = alloc_dev(&b->d_trace, need, s);
+        if (st != PIM_OK) return st;
+        b->trace_bytes = need;
+      }
+    }
+    if (seq && !b->d_j8pad) {
+      // row-major int8 J with rows padded to npad, for the sequential kernel
+      const size_t per = (size_t)b->npad * b->npad;
+      pim_status st = alloc_dev(&b->d_j8pad, per * b->count, s);
+      if (st != PIM_OK) return st;
+      e = hipMemsetAsync(b->d_j8pad, 0, per * b->count, s);
+      for (int k = 0; k < b->count && e == hipSuccess; ++k)
+        e = hipMemcpy2DAsync(b->d_j8pad + per * k, b->npad, b->insts[k]->d_j8, b->n, b->n, b->n,
+                             hipMemcpyDeviceToDevice, s);
+      if (e != hipSuccess) return device_fail(e, "sequential coupling layout");
+    }
+    if (mfma) e = hipMemcpyAsync(b->d_thtab, b->h_thtab, thtab_need, hipMemcpyHostToDevice, s);
+    else e = hipMemcpyAsync(b->d_steptab, steptab.data(), steptab.size() * 4, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(b->d_target, real ? (const void*)tgtf.data() : (const void*)tgt.data(), b->count * 4,
+                         hipMemcpyHostToDevice, s);
+    // the host tables must stay alive until the copies are done
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return device_fail(e, "schedule upload");
+    __atomic_store_n(b->h_cancel, 0, __ATOMIC_SEQ_CST);
+    ctx.T = T;
+    ctx.L = L;
+    ctx.real = real;
+    ctx.mfma = mfma;
+    ctx.seq = seq;
+    ctx.tgt = std::move(tgt);
+    ctx.tgtf = std::move(tgtf);
+    return PIM_OK;
+  }
+}
+
+// Launches the prepared run of a simple batch on stream s (asynchronous).
+hipError_t run_launch(pim_batch* b, const pim_schedule* sc, uint64_t seed, const RunCtx& ctx, hipStream_t s) {
+  {
+    const int T = ctx.T, L = ctx.L;
+    const bool real = ctx.real, mfma = ctx.mfma, seq = ctx.seq;
+    const std::vector<int32_t>& tgt = ctx.tgt;
+    const std::vector<float>& tgtf = ctx.tgtf;
+    hipError_t e = hipSuccess;
+    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    if (seq) {
+      SeqArgs a{};
+      a.j8pad = b->d_j8pad;
+      a.h = b->has_h ? b->d_h : nullptr;
+      a.thtab = static_cast<const int16_t*>(b->d_thtab);
+      a.inst_class = b->d_class;
+      a.inst_stream = b->d_stream_ids;
+      a.target = sc->use_target ? b->d_target : nullptr;
+      a.init = b->d_init;
+      a.final_s = b->d_final;
+      a.best_s = b->d_best;
+      a.e_best = stat_ptr(b, 0);
+      a.t_best = stat_ptr(b, 1);
+      a.first_hit = stat_ptr(b, 2);
+      a.e_final = stat_ptr(b, 3);
+      a.steps_done = stat_ptr(b, 4);
+      a.cancel = b->d_cancel;
+      a.n = b->n;
+      a.npad = b->npad;
+      a.R = b->R;
+      a.T = T;
+      a.start_step = sc->start_step;
+      a.k0 = k0;
+      a.k1 = k1;
+      e = launch_sweep_seq(a, b->count, b->nt, b->has_h, s);
+    } else if (mfma && !real) {
+      SweepArgs a{};
+      a.jfrag = b->d_jfrag;
+      a.trace = sc->record_states ? b->d_trace : nullptr;
+      a.h = b->has_h ? b->d_h : nullptr;
+      a.thtab = static_cast<const int16_t*>(b->d_thtab);
+      a.inst_class = b->d_class;
+      a.inst_stream = b->d_stream_ids;
+      a.target = sc->use_target ? b->d_target : nullptr;
+      a.init = b->d_init;
+      a.final_s = b->d_final;
+      a.best_s = b->d_best;
+      a.e_best = stat_ptr(b, 0);
+      a.t_best = stat_ptr(b, 1);
+      a.first_hit = stat_ptr(b, 2);
+      a.e_final = stat_ptr(b, 3);
+      a.steps_done = stat_ptr(b, 4);
+      a.cancel = b->d_cancel;
+      a.n = b->n;
+      a.npad = b->npad;
+      a.R = b->R;
+      a.T = T;
+      a.start_step = sc->start_step;
+      a.k0 = k0;
+      a.k1 = k1;
+      a.waves = b->waves;
+      e = launch_sweep_mfma(a, b->count, b->nt, b->has_h, s);
+    } else if (mfma) {
+      SweepRealArgs a{};
+      a.jfrag = reinterpret_cast<const uint8_t*>(b->d_jfrag);
+      a.scale = b->d_scale;
+      a.h = b->has_h ? reinterpret_cast<const float*>(b->d_h) : nullptr;
+      a.thtab = static_cast<const float*>(b->d_thtab);
+      a.inst_class = b->d_class;
+      a.inst_stream = b->d_stream_ids;
+      a.target = sc->use_target ? reinterpret_cast<const float*>(b->d_target) : nullptr;
+      a.init = b->d_init;
+      a.final_s = b->d_final;
+      a.best_s = b->d_best;
+      a.e_best = reinterpret_cast<float*>(stat_ptr(b, 0));
+      a.t_best = stat_ptr(b, 1);
+      a.first_hit = stat_ptr(b, 2);
+      a.e_final = reinterpret_cast<float*>(stat_ptr(b, 3));
+      a.steps_done = stat_ptr(b, 4);
+      a.cancel = b->d_cancel;
+      a.n = b->n;
+      a.npad = b->npad;
+      a.R = b->R;
+      a.T = T;
+      a.start_step = sc->start_step;
+      a.k0 = k0;
+      a.k1 = k1;
+      e = launch_sweep_real(a, b->count, b->nt, b->prec, b->has_h, s);
+    } else {
+      const int w = (L - 1) + 2 * L;
+      for (int k = 0; k < b->count && e == hipSuccess; ++k) {
+        const size_t cell0 = (size_t)k * b->R;
+        PlainArgs a{};
+        a.jf32 = b->insts[k]->d_jf32;
+        a.h = (!real && b->insts[k]->has_h) ? b->insts[k]->d_h : nullptr;
+        a.hf = (real && b->insts[k]->has_h) ? b->insts[k]->d_hf : nullptr;
+        a.steptab = b->d_steptab + (size_t)b->inst_class[k] * T * w;
+        a.init = b->d_init ? b->d_init + cell0 * b->npad : nullptr;
+        a.final_s = b->d_final + cell0 * b->npad;
+        a.best_s = b->d_best + cell0 * b->npad;
+        a.e_best = stat_ptr(b, 0) + cell0;
+        a.t_best = stat_ptr(b, 1) + cell0;
+        a.first_hit = stat_ptr(b, 2) + cell0;
+        a.e_final = stat_ptr(b, 3) + cell0;
+        a.steps_done = stat_ptr(b, 4) + cell0;
+        a.cancel = b->d_cancel;
+        a.n = b->n;
+        a.npad = b->npad;
+        a.jstride = b->insts[k]->jstride;
+        a.R = b->R;
+        a.T = T;
+        a.start_step = sc->start_step;
+        a.levels = L;
+        a.use_target = sc->use_target ? 1 : 0;
+        if (real) std::memcpy(&a.target, &tgtf[k], 4);
+        else a.target = tgt[k];
+        a.stream = b->insts[k]->rule.stream;
+        a.k0 = k0;
+        a.k1 = k1;
+        e = launch_sweep_plain(a, real, s);
+      }
+    }
+    return e;
+  }
+}
+
+// Run-state bookkeeping after a successful launch.
+void run_mark(pim_batch* b, const pim_schedule* sc) {
+  {
+    const int T = sc->steps;
+    b->ran = true;
+    b->recorded = sc->record_states != 0;
+    b->reranked = false;
+    b->cancelled_checked = -1;
+    b->last_T = T;
+    b->last_start = sc->start_step;
+  }
+}
+
+
 
 }  // namespace
 
@@ -474,14 +857,14 @@ pim_status pim_batch_create(pim_instance* const* insts, int32_t count, int32_t t
     if (!insts || count < 1) return fail(PIM_ERR_INVALID, "need at least one instance");
     if (trials < 1 || trials > (1 << 24)) return fail(PIM_ERR_INVALID, "trials = %d outside [1, 2^24]", trials);
     if (count > 65535) return fail(PIM_ERR_INVALID, "count = %d exceeds 65535", count);
+    bool mixed = false;
     for (int k = 0; k < count; ++k) {
       if (!insts[k]) return fail(PIM_ERR_INVALID, "instance %d is NULL", k);
-      if (insts[k]->rule.n != insts[0]->rule.n)
-        return fail(PIM_ERR_UNSUPPORTED, "instances of different N in one batch (%d vs %d)", insts[k]->rule.n,
-                    insts[0]->rule.n);
       if (insts[k]->rule.real != insts[0]->rule.real || insts[k]->prec != insts[0]->prec)
         return fail(PIM_ERR_UNSUPPORTED, "integer and real instances, or two precisions, in one batch");
+      mixed |= insts[k]->rule.n != insts[0]->rule.n;
     }
+    if (mixed) return create_composite(insts, count, trials, init_spins, (hipStream_t)stream, out);
     const int n = insts[0]->rule.n;
     if (init_spins) {
       pim_status st = check_spins(init_spins, (size_t)count * trials * n);
@@ -603,6 +986,10 @@ void pim_batch_destroy(pim_batch* b) {
 }
 
 pim_status pim_cancel(pim_batch* b) {
+  if (b && !b->parts.empty()) {
+    for (pim_batch* part : b->parts) (void)pim_cancel(part);
+    return PIM_OK;
+  }
   if (!b || !b->h_cancel) return fail(PIM_ERR_INVALID, "batch is NULL");
   __atomic_store_n(b->h_cancel, 1, __ATOMIC_SEQ_CST);
   return PIM_OK;
@@ -612,277 +999,65 @@ pim_status pim_run(pim_batch* b, const pim_schedule* sc, uint64_t seed, void* st
   try {
     if (!b) return fail(PIM_ERR_INVALID, "batch is NULL");
     if (b->sticky_error) return fail(PIM_ERR_DEVICE, "batch is in an error state after a failed device call");
-    if (!sc) return fail(PIM_ERR_INVALID, "schedule is NULL");
-    if (sc->steps < 1) return fail(PIM_ERR_INVALID, "steps must be >= 1");
-    if (!sc->beta || !sc->eta) return fail(PIM_ERR_INVALID, "beta and eta must be non-NULL");
-    if (sc->start_step < 0 || (int64_t)sc->start_step + sc->steps >= (int64_t)1 << 31)
-      return fail(PIM_ERR_INVALID, "start_step + steps must lie in [0, 2^31)");
-    if (sc->kernel != PIM_KERNEL_MFMA_I8 && sc->kernel != PIM_KERNEL_PLAIN_F32 && sc->kernel != PIM_KERNEL_SEQ_I8)
-      return fail(PIM_ERR_INVALID, "unknown kernel %d", sc->kernel);
-    if (sc->kernel == PIM_KERNEL_SEQ_I8 && b->real)
-      return fail(PIM_ERR_UNSUPPORTED, "the sequential kernel takes integer instances");
-    if (sc->record_states && (sc->kernel != PIM_KERNEL_MFMA_I8 || b->real))
-      return fail(PIM_ERR_UNSUPPORTED, "state recording is implemented for the int8 MFMA kernel");
-    if (sc->use_target && !sc->target) return fail(PIM_ERR_INVALID, "use_target set without target energies");
-    const int T = sc->steps;
-    for (int t = 0; t < T; ++t)
-      if (!finite_nonneg(sc->beta[t]) || !finite_nonneg(sc->eta[t]))
-        return fail(PIM_ERR_INVALID, "beta[%d] / eta[%d] must be finite and >= 0", t, t);
-    for (int k = 0; sc->use_target && k < b->count; ++k)
-      if (std::isnan(sc->target[k])) return fail(PIM_ERR_INVALID, "target[%d] is NaN", k);
-    // targets: integer batches compare E <= floor(target), real ones in binary32
-    std::vector<int32_t> tgt(b->count, INT32_MIN);
-    std::vector<float> tgtf(b->count, -INFINITY);
-    if (sc->use_target)
-      for (int k = 0; k < b->count; ++k) {
-        const double f = std::floor(sc->target[k]);
-        tgt[k] = f >= (double)INT32_MAX ? INT32_MAX : (f <= (double)INT32_MIN + 1 ? INT32_MIN + 1 : (int32_t)f);
-        // largest binary32 value <= target, so E <= tgtf <=> E <= target for binary32 E
-        float tf = (float)sc->target[k];
-        if ((double)tf > sc->target[k]) tf = std::nextafter(tf, -INFINITY);
-        tgtf[k] = tf;
-      }
     hipStream_t s = stream ? (hipStream_t)stream : b->stream;
+    if (b->parts.empty()) {
+      RunCtx ctx;
+      pim_status st = run_prepare(b, sc, s, ctx);
+      if (st != PIM_OK) return st;
+      hipError_t e = hipEventRecord(b->ev0, s);
+      if (e == hipSuccess) e = run_launch(b, sc, seed, ctx, s);
+      if (e == hipSuccess) e = hipEventRecord(b->ev1, s);
+      if (e != hipSuccess) {
+        b->sticky_error = true;
+        return fail(PIM_ERR_DEVICE, "sweep launch failed: %s", hipGetErrorString(e));
+      }
+      run_mark(b, sc);
+      return PIM_OK;
+    }
+    // uneven N: prepare every part, then capture all launches as parallel
+    // branches of one graph and launch it
+    if (!sc) return fail(PIM_ERR_INVALID, "schedule is NULL");
+    if (sc->use_target && !sc->target) return fail(PIM_ERR_INVALID, "use_target set without target energies");
+    const size_t P = b->parts.size();
+    std::vector<std::vector<double>> tg(P);
+    std::vector<pim_schedule> psc(P, *sc);
+    if (sc->use_target)
+      for (int k = 0; k < b->count; ++k) tg[b->part_of[k]].push_back(sc->target[k]);
+    std::vector<RunCtx> ctx(P);
+    for (size_t p = 0; p < P; ++p) {
+      if (sc->use_target) psc[p].target = tg[p].data();
+      pim_status st = run_prepare(b->parts[p], &psc[p], s, ctx[p]);
+      if (st != PIM_OK) return st;
+    }
     b->stream = s;
-    const int L = b->insts[0]->rule.levels;
-    const int ncls = (int)b->class_rep.size();
-    const bool real = b->real;
-    // ---- compile ----
-    std::vector<int32_t> steptab;
-    const bool seq = sc->kernel == PIM_KERNEL_SEQ_I8;
-    const bool mfma = sc->kernel == PIM_KERNEL_MFMA_I8 || seq;  // both read the (u, s) tables
-    const size_t entry = real ? 4 : 2;  // bytes per table entry
-    if (mfma) {
-      const size_t need = (size_t)ncls * T * kTabEntries * entry;
-      if (need > b->h_thtab_bytes) {
-        if (b->h_thtab) (void)hipHostFree(b->h_thtab);
-        b->h_thtab = nullptr;
-        b->h_thtab_bytes = 0;
-        if (hipHostMalloc(&b->h_thtab, need, hipHostMallocDefault) != hipSuccess)
-          return fail(PIM_ERR_NOMEM, "pinned staging allocation of %zu bytes failed", need);
-        b->h_thtab_bytes = need;
+    if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->gexec = nullptr;
+    b->graph = nullptr;
+    hipError_t e = hipEventRecord(b->fork_ev, s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(b->cap, b->fork_ev, 0);
+    if (e == hipSuccess) e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      hipError_t ce = hipEventRecord(b->fork_ev, b->cap);
+      for (size_t p = 0; p < P && ce == hipSuccess; ++p) {
+        ce = hipStreamWaitEvent(b->fork[p], b->fork_ev, 0);
+        if (ce == hipSuccess) ce = run_launch(b->parts[p], &psc[p], seed, ctx[p], b->fork[p]);
+        if (ce == hipSuccess) ce = hipEventRecord(b->join[p], b->fork[p]);
+        if (ce == hipSuccess) ce = hipStreamWaitEvent(b->cap, b->join[p], 0);
       }
-      void* out = b->h_thtab;
-      parallel_for(T * ncls, [&](int lo, int hi) {
-        int32_t th[kMaxLevels], um[2 * kMaxLevels];
-        float thf[kMaxLevels];
-        for (int i = lo; i < hi; ++i) {
-          const int c = i / T, t = i % T;
-          const Rule& r = b->insts[b->class_rep[c]]->rule;
-          const size_t off = ((size_t)c * T + t) * kTabEntries;
-          if (real) {
-            compile_step_real(r, sc->beta[t], sc->eta[t], thf, um);
-            theta_by_noise_real(thf, um, r.levels, static_cast<float*>(out) + off);
-          } else {
-            compile_step(r, sc->beta[t], sc->eta[t], th, um);
-            theta_by_noise(th, um, r.levels, static_cast<int16_t*>(out) + off);
-          }
-        }
-      });
-    } else {
-      for (int k = 0; k < b->count; ++k)
-        if (b->insts[k]->rule.levels != L)
-          return fail(PIM_ERR_UNSUPPORTED, "the plain kernel needs one LUT size per batch");
-      const int w = (L - 1) + 2 * L;
-      steptab.resize((size_t)ncls * T * w);
-      for (int c = 0; c < ncls; ++c) {
-        const Rule& r = b->insts[b->class_rep[c]]->rule;
-        for (int t = 0; t < T; ++t) {
-          int32_t* row = &steptab[((size_t)c * T + t) * w];
-          if (real) {
-            float thf[kMaxLevels];
-            compile_step_real(r, sc->beta[t], sc->eta[t], thf, row + (L - 1));
-            std::memcpy(row, thf, (L - 1) * sizeof(float));  // float bits in the int32 row
-          } else {
-            compile_step(r, sc->beta[t], sc->eta[t], row, row + (L - 1));
-          }
-        }
-      }
+      e = hipStreamEndCapture(b->cap, &b->graph);  // always end the capture
+      if (ce != hipSuccess) e = ce;
     }
-    // ---- upload ----
-    const size_t thtab_need = mfma ? (size_t)ncls * T * kTabEntries * entry : 0;
-    if (mfma && thtab_need > b->thtab_bytes) {
-      dev_free(b->d_thtab, s);
-      b->d_thtab = nullptr;
-      b->thtab_bytes = 0;
-      b->d_thtab = dev_alloc(thtab_need, s);
-      if (!b->d_thtab) return fail(PIM_ERR_NOMEM, "device allocation of %zu bytes failed", thtab_need);
-      b->thtab_bytes = thtab_need;
-    }
-    if (!mfma && steptab.size() * 4 > b->steptab_bytes) {
-      dev_free(b->d_steptab, s);
-      b->d_steptab = nullptr;
-      b->steptab_bytes = 0;
-      pim_status st = alloc_dev(&b->d_steptab, steptab.size(), s);
-      if (st != PIM_OK) return st;
-      b->steptab_bytes = steptab.size() * 4;
-    }
-    auto device_fail = [&](hipError_t e, const char* what) {
+    if (e == hipSuccess) e = hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0);
+    if (e == hipSuccess) e = hipEventRecord(b->ev0, s);
+    if (e == hipSuccess) e = hipGraphLaunch(b->gexec, s);
+    if (e == hipSuccess) e = hipEventRecord(b->ev1, s);
+    if (e != hipSuccess) {
       b->sticky_error = true;
-      return fail(PIM_ERR_DEVICE, "%s failed: %s", what, hipGetErrorString(e));
-    };
-    hipError_t e = hipSuccess;
-    b->recorded = false;
-    if (sc->record_states) {
-      const size_t need = (size_t)b->count * b->R * ((size_t)T + 1) * b->npad;
-      if (need / ((size_t)T + 1) != (size_t)b->count * b->R * b->npad)
-        return fail(PIM_ERR_INVALID, "recorded trajectory size overflows");
-      if (need > b->trace_bytes) {
-        dev_free(b->d_trace, s);
-        b->d_trace = nullptr;
-        b->trace_bytes = 0;
-        pim_status st = alloc_dev(&b->d_trace, need, s);
-        if (st != PIM_OK) return st;
-        b->trace_bytes = need;
-      }
+      return fail(PIM_ERR_DEVICE, "graph launch failed: %s", hipGetErrorString(e));
     }
-    if (seq && !b->d_j8pad) {
-      // row-major int8 J with rows padded to npad, for the sequential kernel
-      const size_t per = (size_t)b->npad * b->npad;
-      pim_status st = alloc_dev(&b->d_j8pad, per * b->count, s);
-      if (st != PIM_OK) return st;
-      e = hipMemsetAsync(b->d_j8pad, 0, per * b->count, s);
-      for (int k = 0; k < b->count && e == hipSuccess; ++k)
-        e = hipMemcpy2DAsync(b->d_j8pad + per * k, b->npad, b->insts[k]->d_j8, b->n, b->n, b->n,
-                             hipMemcpyDeviceToDevice, s);
-      if (e != hipSuccess) return device_fail(e, "sequential coupling layout");
-    }
-    if (mfma) e = hipMemcpyAsync(b->d_thtab, b->h_thtab, thtab_need, hipMemcpyHostToDevice, s);
-    else e = hipMemcpyAsync(b->d_steptab, steptab.data(), steptab.size() * 4, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess)
-      e = hipMemcpyAsync(b->d_target, real ? (const void*)tgtf.data() : (const void*)tgt.data(), b->count * 4,
-                         hipMemcpyHostToDevice, s);
-    // the host tables must stay alive until the copies are done
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return device_fail(e, "schedule upload");
-    __atomic_store_n(b->h_cancel, 0, __ATOMIC_SEQ_CST);
-    // ---- launch ----
-    e = hipEventRecord(b->ev0, s);
-    if (e != hipSuccess) return device_fail(e, "hipEventRecord");
-    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
-    if (seq) {
-      SeqArgs a{};
-      a.j8pad = b->d_j8pad;
-      a.h = b->has_h ? b->d_h : nullptr;
-      a.thtab = static_cast<const int16_t*>(b->d_thtab);
-      a.inst_class = b->d_class;
-      a.inst_stream = b->d_stream_ids;
-      a.target = sc->use_target ? b->d_target : nullptr;
-      a.init = b->d_init;
-      a.final_s = b->d_final;
-      a.best_s = b->d_best;
-      a.e_best = stat_ptr(b, 0);
-      a.t_best = stat_ptr(b, 1);
-      a.first_hit = stat_ptr(b, 2);
-      a.e_final = stat_ptr(b, 3);
-      a.steps_done = stat_ptr(b, 4);
-      a.cancel = b->d_cancel;
-      a.n = b->n;
-      a.npad = b->npad;
-      a.R = b->R;
-      a.T = T;
-      a.start_step = sc->start_step;
-      a.k0 = k0;
-      a.k1 = k1;
-      e = launch_sweep_seq(a, b->count, b->nt, b->has_h, s);
-      if (e != hipSuccess) return device_fail(e, "sequential sweep launch");
-    } else if (mfma && !real) {
-      SweepArgs a{};
-      a.jfrag = b->d_jfrag;
-      a.trace = sc->record_states ? b->d_trace : nullptr;
-      a.h = b->has_h ? b->d_h : nullptr;
-      a.thtab = static_cast<const int16_t*>(b->d_thtab);
-      a.inst_class = b->d_class;
-      a.inst_stream = b->d_stream_ids;
-      a.target = sc->use_target ? b->d_target : nullptr;
-      a.init = b->d_init;
-      a.final_s = b->d_final;
-      a.best_s = b->d_best;
-      a.e_best = stat_ptr(b, 0);
-      a.t_best = stat_ptr(b, 1);
-      a.first_hit = stat_ptr(b, 2);
-      a.e_final = stat_ptr(b, 3);
-      a.steps_done = stat_ptr(b, 4);
-      a.cancel = b->d_cancel;
-      a.n = b->n;
-      a.npad = b->npad;
-      a.R = b->R;
-      a.T = T;
-      a.start_step = sc->start_step;
-      a.k0 = k0;
-      a.k1 = k1;
-      e = launch_sweep_mfma(a, b->count, b->nt, b->has_h, s);
-      if (e != hipSuccess) return device_fail(e, "sweep launch");
-    } else if (mfma) {
-      SweepRealArgs a{};
-      a.jfrag = reinterpret_cast<const uint8_t*>(b->d_jfrag);
-      a.scale = b->d_scale;
-      a.h = b->has_h ? reinterpret_cast<const float*>(b->d_h) : nullptr;
-      a.thtab = static_cast<const float*>(b->d_thtab);
-      a.inst_class = b->d_class;
-      a.inst_stream = b->d_stream_ids;
-      a.target = sc->use_target ? reinterpret_cast<const float*>(b->d_target) : nullptr;
-      a.init = b->d_init;
-      a.final_s = b->d_final;
-      a.best_s = b->d_best;
-      a.e_best = reinterpret_cast<float*>(stat_ptr(b, 0));
-      a.t_best = stat_ptr(b, 1);
-      a.first_hit = stat_ptr(b, 2);
-      a.e_final = reinterpret_cast<float*>(stat_ptr(b, 3));
-      a.steps_done = stat_ptr(b, 4);
-      a.cancel = b->d_cancel;
-      a.n = b->n;
-      a.npad = b->npad;
-      a.R = b->R;
-      a.T = T;
-      a.start_step = sc->start_step;
-      a.k0 = k0;
-      a.k1 = k1;
-      e = launch_sweep_real(a, b->count, b->nt, b->prec, b->has_h, s);
-      if (e != hipSuccess) return device_fail(e, "sweep launch");
-    } else {
-      const int w = (L - 1) + 2 * L;
-      for (int k = 0; k < b->count && e == hipSuccess; ++k) {
-        const size_t cell0 = (size_t)k * b->R;
-        PlainArgs a{};
-        a.jf32 = b->insts[k]->d_jf32;
-        a.h = (!real && b->insts[k]->has_h) ? b->insts[k]->d_h : nullptr;
-        a.hf = (real && b->insts[k]->has_h) ? b->insts[k]->d_hf : nullptr;
-        a.steptab = b->d_steptab + (size_t)b->inst_class[k] * T * w;
-        a.init = b->d_init ? b->d_init + cell0 * b->npad : nullptr;
-        a.final_s = b->d_final + cell0 * b->npad;
-        a.best_s = b->d_best + cell0 * b->npad;
-        a.e_best = stat_ptr(b, 0) + cell0;
-        a.t_best = stat_ptr(b, 1) + cell0;
-        a.first_hit = stat_ptr(b, 2) + cell0;
-        a.e_final = stat_ptr(b, 3) + cell0;
-        a.steps_done = stat_ptr(b, 4) + cell0;
-        a.cancel = b->d_cancel;
-        a.n = b->n;
-        a.npad = b->npad;
-        a.jstride = b->insts[k]->jstride;
-        a.R = b->R;
-        a.T = T;
-        a.start_step = sc->start_step;
-        a.levels = L;
-        a.use_target = sc->use_target ? 1 : 0;
-        if (real) std::memcpy(&a.target, &tgtf[k], 4);
-        else a.target = tgt[k];
-        a.stream = b->insts[k]->rule.stream;
-        a.k0 = k0;
-        a.k1 = k1;
-        e = launch_sweep_plain(a, real, s);
-      }
-      if (e != hipSuccess) return device_fail(e, "plain sweep launch");
-    }
-    e = hipEventRecord(b->ev1, s);
-    if (e != hipSuccess) return device_fail(e, "hipEventRecord");
-    b->ran = true;
-    b->recorded = sc->record_states != 0;
-    b->reranked = false;
-    b->cancelled_checked = -1;
-    b->last_T = T;
-    b->last_start = sc->start_step;
+    for (size_t p = 0; p < P; ++p) run_mark(b->parts[p], &psc[p]);
+    run_mark(b, sc);
     return PIM_OK;
   } catch (const std::bad_alloc&) {
     return fail(PIM_ERR_NOMEM, "host allocation failed");
@@ -891,8 +1066,50 @@ pim_status pim_run(pim_batch* b, const pim_schedule* sc, uint64_t seed, void* st
   }
 }
 
+pim_status pim_tune(pim_batch* b, int32_t steps, void* stream, int32_t* waves_out) {
+  try {
+    if (!b) return fail(PIM_ERR_INVALID, "batch is NULL");
+    if (steps < 1) return fail(PIM_ERR_INVALID, "steps must be >= 1");
+    if (b->real) return fail(PIM_ERR_UNSUPPORTED, "tuning is implemented for the int8 MFMA kernel");
+    std::vector<pim_batch*> targets = b->parts;
+    if (targets.empty()) targets.push_back(b);
+    std::vector<double> beta(steps, 1.0), eta(steps, 0.5);
+    pim_schedule sc{};
+    sc.steps = steps;
+    sc.beta = beta.data();
+    sc.eta = eta.data();
+    sc.kernel = PIM_KERNEL_MFMA_I8;
+    for (size_t p = 0; p < targets.size(); ++p) {
+      pim_batch* t = targets[p];
+      const int cand[3] = {4, 2, 1};
+      int best_w = 4;
+      float best_ms = 0.0f;
+      for (int w : cand) {
+        t->waves = w;
+        float ms = 0.0f;
+        for (int rep = 0; rep < 2; ++rep) {  // first run warms up
+          pim_status st = pim_run(t, &sc, 12345, stream);
+          if (st == PIM_OK) st = pim_kernel_time(t, &ms);
+          if (st != PIM_OK) return st;
+        }
+        if (w == cand[0] || ms < best_ms) {
+          best_ms = ms;
+          best_w = w;
+        }
+      }
+      t->waves = best_w;
+      if (waves_out) waves_out[p] = best_w;
+    }
+    return PIM_OK;
+  } catch (...) {
+    return fail(PIM_ERR_INVALID, "internal error in pim_tune");
+  }
+}
+
 pim_status pim_states(pim_batch* b, int32_t inst, int32_t trial, int8_t* states) {
   try {
+    if (b && !b->parts.empty() && inst >= 0 && inst < b->count)
+      return pim_states(b->parts[b->part_of[inst]], b->local_of[inst], trial, states);
     pim_status st = check_batch_ready(b, inst);
     if (st != PIM_OK) return st;
     if (!b->recorded) return fail(PIM_ERR_STATE, "the last run did not record its states");
@@ -910,6 +1127,8 @@ pim_status pim_states(pim_batch* b, int32_t inst, int32_t trial, int8_t* states)
 
 pim_status pim_flip_counts(pim_batch* b, int32_t inst, int64_t* num, int64_t* den) {
   try {
+    if (b && !b->parts.empty() && inst >= 0 && inst < b->count)
+      return pim_flip_counts(b->parts[b->part_of[inst]], b->local_of[inst], num, den);
     pim_status st = check_batch_ready(b, inst);
     if (st != PIM_OK) return st;
     if (!b->recorded) return fail(PIM_ERR_STATE, "the last run did not record its states");
@@ -990,6 +1209,10 @@ pim_status pim_energy(const pim_instance* inst, const int8_t* spins, int32_t cou
 pim_status pim_best(pim_batch* b, int32_t inst, int8_t* spins_out, double* e_out, int32_t* trial_out,
                     int32_t* step_out) {
   try {
+    if (b && !b->parts.empty() && inst >= 0 && inst < b->count) {
+      if (b->sticky_error) return fail(PIM_ERR_DEVICE, "batch is in an error state after a failed device call");
+      return pim_best(b->parts[b->part_of[inst]], b->local_of[inst], spins_out, e_out, trial_out, step_out);
+    }
     pim_status st = check_batch_ready(b, inst);
     if (st != PIM_OK) return st;
     st = ensure_selection(b);
@@ -1022,6 +1245,11 @@ pim_status pim_best(pim_batch* b, int32_t inst, int8_t* spins_out, double* e_out
 pim_status pim_trials(pim_batch* b, int32_t inst, double* best_e, int32_t* best_step, int32_t* first_hit,
                       double* final_e, int8_t* best_spins, int8_t* final_spins) {
   try {
+    if (b && !b->parts.empty() && inst >= 0 && inst < b->count) {
+      if (b->sticky_error) return fail(PIM_ERR_DEVICE, "batch is in an error state after a failed device call");
+      return pim_trials(b->parts[b->part_of[inst]], b->local_of[inst], best_e, best_step, first_hit, final_e,
+                        best_spins, final_spins);
+    }
     pim_status st = check_batch_ready(b, inst);
     if (st != PIM_OK) return st;
     const int R = b->R;

@@ -36,7 +36,7 @@ namespace {
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 
-constexpr int kWaves = 4;                 // waves (32-trial blocks) per workgroup
+constexpr int kWaves = 4;                 // most waves (32-trial blocks) per workgroup
 constexpr int kTabBytes = kTabEntries * 2;  // 1 KB per step table
 static_assert(kTabBytes == 64 * 16, "one 16-byte chunk per lane");
 
@@ -91,10 +91,10 @@ __global__ __launch_bounds__(64 * kWaves, 3) void sweep_mfma_kernel(SweepArgs a)
   {  // stage the instance: J fragments and h
     const uint4* src = reinterpret_cast<const uint4*>(a.jfrag + (size_t)inst * kFragBytes);
     uint4* dst = reinterpret_cast<uint4*>(lds);
-    for (int i = threadIdx.x; i < kFragBytes / 16; i += 64 * kWaves) dst[i] = src[i];
+    for (int i = threadIdx.x; i < kFragBytes / 16; i += blockDim.x) dst[i] = src[i];
     if (HAS_H) {
       int32_t* sh = reinterpret_cast<int32_t*>(lds + kFragBytes);
-      for (int i = threadIdx.x; i < kNpad; i += 64 * kWaves) sh[i] = a.h[(size_t)inst * kNpad + i];
+      for (int i = threadIdx.x; i < kNpad; i += blockDim.x) sh[i] = a.h[(size_t)inst * kNpad + i];
     }
   }
   const v4i* sJ = reinterpret_cast<const v4i*>(lds);
@@ -103,7 +103,7 @@ __global__ __launch_bounds__(64 * kWaves, 3) void sweep_mfma_kernel(SweepArgs a)
   uint4* sTab4 = reinterpret_cast<uint4*>(sTab);
   __syncthreads();  // the only workgroup barrier
 
-  const int tbase = (blockIdx.x * kWaves + wave) * 32 * CB;
+  const int tbase = (blockIdx.x * (int)(blockDim.x >> 6) + wave) * 32 * CB;
   if (tbase >= a.R) return;
   int trial[CB];
   bool live[CB];
@@ -328,14 +328,15 @@ constexpr int kBlocksPerWave = 1;  // CB: 32-trial column blocks per wave
 
 template <int NT, bool HAS_H, bool RECORD>
 hipError_t launch_nt(const SweepArgs& a, int count, hipStream_t s) {
-  const size_t lds = (size_t)NT * NT * 1024 + (HAS_H ? NT * 32 * 4 : 0) + (size_t)kWaves * kTabBytes;
+  const int waves = a.waves;  // 1, 2 or 4 (checked by the caller)
+  const size_t lds = (size_t)NT * NT * 1024 + (HAS_H ? NT * 32 * 4 : 0) + (size_t)waves * kTabBytes;
   auto kern = sweep_mfma_kernel<NT, kBlocksPerWave, HAS_H, RECORD>;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  const int per_wg = 32 * kBlocksPerWave * kWaves;
+  const int per_wg = 32 * kBlocksPerWave * waves;
   const dim3 grid((a.R + per_wg - 1) / per_wg, count);
-  hipLaunchKernelGGL(kern, grid, dim3(64 * kWaves), lds, s, a);
+  hipLaunchKernelGGL(kern, grid, dim3(64 * waves), lds, s, a);
   return hipGetLastError();
 }
 
@@ -358,6 +359,7 @@ hipError_t launch_h(const SweepArgs& a, int count, int nt, hipStream_t s) {
 
 hipError_t launch_sweep_mfma(const SweepArgs& a, int count, int nt, bool has_h, hipStream_t s) {
   if (a.npad != nt * 32) return hipErrorInvalidValue;
+  if (a.waves != 1 && a.waves != 2 && a.waves != kWaves) return hipErrorInvalidValue;
   if (a.trace) return has_h ? launch_h<true, true>(a, count, nt, s) : launch_h<false, true>(a, count, nt, s);
   return has_h ? launch_h<true, false>(a, count, nt, s) : launch_h<false, false>(a, count, nt, s);
 }

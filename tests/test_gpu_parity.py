@@ -269,3 +269,59 @@ def test_recorded_states_and_flip_rate(gpu_lib, xi):
     np.testing.assert_array_equal(num, rnum)
     np.testing.assert_array_equal(den, rden)
     batch.close()
+
+
+def test_uneven_n_batch_one_graph(gpu_lib):
+    """Instances of different N in one batch (one graph launch per run): every
+    instance bit-exact against the oracle, with caller initial spins for some
+    and a repeated run giving identical results."""
+    _say("uneven N batch (graph)")
+    pim = gpu_lib
+    ns = [20, 200, 33, 64, 100, 20]
+    trials, steps = 70, 150
+    ztab = w.gauss_table(8)
+    beta = w.linear_beta(steps, 0.1, 3.0)
+    eta = w.eta_sqrt_beta_over_5(beta)
+    probs, insts = [], []
+    for k, n in enumerate(ns):
+        J, h = w.random_int8(n, seed=31, index=k, jmax=2, hmax=3 if k % 2 else 0)
+        c = 1.0 / np.sqrt(n)
+        probs.append((J, h, c))
+        insts.append(pim.Instance(J, h, j_scale=c, xi=0.5, noise_table=ztab, rng_stream=40 + k))
+    rng = np.random.default_rng(8)
+    init = [rng.choice([-1, 1], size=(trials, n)).astype(np.int8) for n in ns]
+    batch = pim.Batch(insts, trials, init_spins=init)
+    targets = [float(pimi.energy(J, h, np.ones(len(h), dtype=np.int64))) - 1 for (J, h, c) in probs]
+    for rep in range(2):
+        batch.run(beta, eta, seed=17, target=targets)
+        for k, (J, h, c) in enumerate(probs):
+            ref = _oracle(J, h, c, 0.5, 4, ztab, beta, eta, 17, 40 + k, np.arange(trials),
+                          init=init[k].T.astype(np.int64), target=targets[k])
+            _compare(batch, k, ref, np.arange(trials), len(h))
+    assert batch.kernel_ms() > 0
+    spins, e, trial, step = batch.best(1)
+    assert len(spins) == 200 and e == pimi.energy(probs[1][0], probs[1][1], spins.astype(np.int64))
+    batch.close()
+
+
+def test_tune_keeps_trajectories(gpu_lib):
+    _say("autotune waves per workgroup")
+    pim = gpu_lib
+    ns = [64, 200]
+    trials, steps = 300, 120
+    ztab = w.gauss_table(8)
+    insts, probs = [], []
+    for k, n in enumerate(ns):
+        J, h = w.sk1(n, seed=3, index=k)
+        insts.append(pim.Instance(J, h, j_scale=1 / np.sqrt(n), xi=0.5, noise_table=ztab, rng_stream=k))
+        probs.append((J, h, 1 / np.sqrt(n)))
+    batch = pim.Batch(insts, trials)
+    waves = batch.tune(steps=50)
+    assert len(waves) == 2 and set(waves.tolist()) <= {1, 2, 4}
+    beta = w.linear_beta(steps, 0.1, 3.0)
+    eta = w.eta_sqrt_beta_over_5(beta)
+    batch.run(beta, eta, seed=5)
+    for k, (J, h, c) in enumerate(probs):
+        ref = _oracle(J, h, c, 0.5, 4, ztab, beta, eta, 5, k, np.arange(trials))
+        _compare(batch, k, ref, np.arange(trials), len(h))
+    batch.close()
