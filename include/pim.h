@@ -71,8 +71,13 @@ extern "C" {
 
 #define PIM_ABI_VERSION 2
 
-/* Largest N accepted by pim_create (int8 couplings staged on chip). */
-#define PIM_MAX_N 256
+/* Largest N accepted by pim_create (integer instances). */
+#define PIM_MAX_N 1024
+/* Largest N of the kernels that keep an instance's couplings in LDS: the
+ * plain FP32 and sequential kernels, real-valued instances and state
+ * recording.  Integer batches with larger N run the int8 MFMA sweep with the
+ * couplings streamed from global memory. */
+#define PIM_MAX_N_LDS 256
 
 typedef enum {
   PIM_OK = 0,
@@ -112,7 +117,8 @@ typedef enum {
 
 /* Per-instance constants of the update rule. */
 typedef struct {
-  int32_t n;                 /* number of spins N, 1 <= N <= PIM_MAX_N            */
+  int32_t n;                 /* number of spins N, 1 <= N <= PIM_MAX_N (real-valued
+                                instances: N <= PIM_MAX_N_LDS)                      */
   double j_scale;            /* c > 0, finite                                      */
   double xi;                 /* inertia xi >= 0, finite                             */
   int32_t levels;            /* L, 2 <= L <= 16                                     */
@@ -289,7 +295,7 @@ pim_status pim_compile_table_real(const pim_params* params, double beta, double 
  * so E(s) of Eq. (1) = ||yr - Hr(x_m + T s)||^2 - const.  Outputs (host,
  * binary64): J [n][n], h [n], x_m [2 nt] (real parts then imaginary parts);
  * *n_out = 2 nt (ML, 4-QAM) or 4 nt.  Buffers must hold 4 nt x 4 nt, 4 nt and
- * 2 nt values; 4 nt <= PIM_MAX_N. */
+ * 2 nt values; 4 nt <= PIM_MAX_N_LDS. */
 pim_status pim_mimo_ising(const double* H, const double* y, int32_t nr, int32_t nt, int32_t qam, int32_t map,
                           double esn0, double* J, double* h, double* xm, int32_t* n_out);
 

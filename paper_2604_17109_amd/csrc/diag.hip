@@ -14,14 +14,14 @@
 namespace pim {
 namespace {
 
-constexpr int kWords = PIM_MAX_N / 32;
+constexpr int kWords = PIM_MAX_N_LDS / 32;
 constexpr int kThreads = 256;
 
 __global__ __launch_bounds__(kThreads) void flip_rate_kernel(FlipRateArgs a) {
-  __shared__ uint32_t adj[PIM_MAX_N][kWords];
+  __shared__ uint32_t adj[PIM_MAX_N_LDS][kWords];
   __shared__ unsigned long long red[2][kThreads];
   const int n = a.n;
-  for (int e = threadIdx.x; e < PIM_MAX_N * kWords; e += kThreads) {
+  for (int e = threadIdx.x; e < PIM_MAX_N_LDS * kWords; e += kThreads) {
     const int i = e / kWords, k = e % kWords;
     uint32_t m = 0;
     if (i < n)
@@ -74,7 +74,7 @@ __global__ __launch_bounds__(kThreads) void flip_rate_kernel(FlipRateArgs a) {
 }  // namespace
 
 hipError_t launch_flip_rate(const FlipRateArgs& a, hipStream_t s) {
-  if (a.n < 1 || a.n > PIM_MAX_N || a.T < 1) return hipErrorInvalidValue;
+  if (a.n < 1 || a.n > PIM_MAX_N_LDS || a.T < 1) return hipErrorInvalidValue;
   hipLaunchKernelGGL(flip_rate_kernel, dim3(a.T), dim3(kThreads), 0, s, a);
   return hipGetLastError();
 }

@@ -61,7 +61,7 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void energy_f64_kernel(EnergyA
 // Re-rank for real-valued instances: one wave per candidate, binary64 J rows
 // read from global memory (too large for LDS at N = 256), lanes over columns.
 __global__ __launch_bounds__(64 * kWavesPerBlock) void rerank_real_kernel(RerankArgs a) {
-  __shared__ __align__(16) int8_t sS[kWavesPerBlock][PIM_MAX_N];
+  __shared__ __align__(16) int8_t sS[kWavesPerBlock][PIM_MAX_N_LDS];
   const int inst = blockIdx.y;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int trial = blockIdx.x * kWavesPerBlock + wave;
@@ -83,16 +83,16 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void rerank_real_kernel(Rerank
 constexpr int kRerankTrialsPerBlock = 16;
 
 __global__ __launch_bounds__(64 * kWavesPerBlock) void rerank_kernel(RerankArgs a) {
-  __shared__ __align__(16) int8_t sJ[PIM_MAX_N * PIM_MAX_N];
-  __shared__ __align__(16) int8_t sS[kWavesPerBlock][PIM_MAX_N];
+  __shared__ __align__(16) int8_t sJ[PIM_MAX_N_LDS * PIM_MAX_N_LDS];
+  __shared__ __align__(16) int8_t sS[kWavesPerBlock][PIM_MAX_N_LDS];
   const int inst = blockIdx.y;
   const int n = a.n, npad = a.npad;
   const int8_t* J = a.j8[inst];
-  // row stride PIM_MAX_N; columns >= n are never initialised, which is
+  // row stride PIM_MAX_N_LDS; columns >= n are never initialised, which is
   // harmless: the candidate's spins there are 0, so they add 0 to every dot
   for (int i = threadIdx.x; i < n * n; i += 64 * kWavesPerBlock) {
     const int r = i / n, c = i - r * n;
-    sJ[r * PIM_MAX_N + c] = J[i];
+    sJ[r * PIM_MAX_N_LDS + c] = J[i];
   }
   __syncthreads();
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -102,13 +102,13 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void rerank_kernel(RerankArgs 
     if (trial >= a.R) break;  // wave-uniform
     const size_t cell = (size_t)inst * a.R + trial;
     const int8_t* s = a.best_s + cell * npad;
-    for (int i = lane; i < PIM_MAX_N; i += 64) sS[wave][i] = (i < n) ? s[i] : (int8_t)0;
+    for (int i = lane; i < PIM_MAX_N_LDS; i += 64) sS[wave][i] = (i < n) ? s[i] : (int8_t)0;
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     const int32_t s4 = reinterpret_cast<const int32_t*>(sS[wave])[lane];  // columns 4l..4l+3
     double acc = 0.0;
     for (int i = 0; i < n; ++i) {
-      const int32_t j4 = reinterpret_cast<const int32_t*>(sJ + i * PIM_MAX_N)[lane];
+      const int32_t j4 = reinterpret_cast<const int32_t*>(sJ + i * PIM_MAX_N_LDS)[lane];
       const int dot = __builtin_amdgcn_sdot4(j4, s4, 0, false);  // sum_j J_ij s_j over 4 columns
       acc += (double)(sS[wave][i] * dot);
     }
@@ -122,6 +122,35 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void rerank_kernel(RerankArgs 
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
   }
+}
+
+// Re-rank for N > PIM_MAX_N_LDS (couplings too large for LDS): one wave per
+// candidate; lane l covers columns l, l + 64, ...; every row's exact integer
+// sum is accumulated in binary64 as in rerank_kernel.
+__global__ __launch_bounds__(64 * kWavesPerBlock) void rerank_big_kernel(RerankArgs a) {
+  __shared__ __align__(16) int8_t sS[kWavesPerBlock][PIM_MAX_N];
+  const int inst = blockIdx.y;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int trial = blockIdx.x * kWavesPerBlock + wave;
+  if (trial >= a.R) return;  // wave-uniform; no block barrier follows
+  const int n = a.n;
+  const size_t cell = (size_t)inst * a.R + trial;
+  const int8_t* s = a.best_s + cell * a.npad;
+  for (int i = lane; i < n; i += 64) sS[wave][i] = s[i];
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  const int8_t* J = a.j8[inst];
+  double acc = 0.0;
+  for (int i = 0; i < n; ++i) {
+    int row = 0;
+    for (int j = lane; j < n; j += 64) row += (int)J[(size_t)i * n + j] * (int)sS[wave][j];
+    acc += (double)(sS[wave][i] * row);
+  }
+  const int32_t* hp = a.h ? a.h[inst] : nullptr;
+  if (hp)
+    for (int j = lane; j < n; j += 64) acc += 2.0 * (double)hp[j] * (double)sS[wave][j];
+  const double e = -0.5 * wave_sum(acc);
+  if (lane == 0) a.energy[cell] = e;
 }
 
 // One block per instance: lowest binary64 energy, ties to the lowest trial;
@@ -178,6 +207,9 @@ hipError_t launch_rerank_select(const RerankArgs& a, hipStream_t s) {
   if (a.j64) {
     const dim3 grid((a.R + kWavesPerBlock - 1) / kWavesPerBlock, a.count);
     hipLaunchKernelGGL(rerank_real_kernel, grid, dim3(64 * kWavesPerBlock), 0, s, a);
+  } else if (a.n > PIM_MAX_N_LDS) {
+    const dim3 grid((a.R + kWavesPerBlock - 1) / kWavesPerBlock, a.count);
+    hipLaunchKernelGGL(rerank_big_kernel, grid, dim3(64 * kWavesPerBlock), 0, s, a);
   } else {
     const dim3 grid((a.R + kRerankTrialsPerBlock - 1) / kRerankTrialsPerBlock, a.count);
     hipLaunchKernelGGL(rerank_kernel, grid, dim3(64 * kWavesPerBlock), 0, s, a);

@@ -73,6 +73,7 @@ struct SweepArgs {
   int32_t n, npad, R, T, start_step;
   uint32_t k0, k1;
   int32_t waves;             // waves (32-trial blocks) per workgroup: 1, 2 or 4
+  int32_t count;             // instances
 };
 
 // Real-valued instances: spins and states as in SweepArgs; energies binary32
@@ -167,6 +168,9 @@ struct RerankArgs {
 hipError_t launch_rerank_select(const RerankArgs& a, hipStream_t s);
 hipError_t launch_sweep_mfma(const SweepArgs& a, int count, int nt, bool has_h, hipStream_t s);
 hipError_t launch_sweep_plain(const PlainArgs& a, bool real, hipStream_t s);
+// 256 < N <= 1024: couplings streamed from global memory, spins in LDS.
+hipError_t launch_sweep_big(const SweepArgs& a, int count, int nt, bool has_h, hipStream_t s);
+int big_tiles(int n);  // row tiles of the streamed kernel (a multiple of 4)
 hipError_t launch_sweep_seq(const SeqArgs& a, int count, int nt, bool has_h, hipStream_t s);
 hipError_t launch_sweep_real(const SweepRealArgs& a, int count, int nt, int prec, bool has_h, hipStream_t s);
 size_t real_frag_bytes(int prec, int nt);

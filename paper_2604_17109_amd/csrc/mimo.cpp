@@ -105,8 +105,8 @@ pim_status pim_mimo_ising(const double* Hc, const double* yc, int32_t nr, int32_
                           double esn0, double* J, double* h, double* xm, int32_t* n_out) {
   try {
     if (!Hc || !yc || !J || !h || !xm || !n_out) return fail(PIM_ERR_INVALID, "NULL argument");
-    if (nr < 1 || nt < 1 || 4 * nt > PIM_MAX_N)
-      return fail(PIM_ERR_INVALID, "nr = %d, nt = %d: need nr, nt >= 1 and 4 nt <= %d", nr, nt, PIM_MAX_N);
+    if (nr < 1 || nt < 1 || 4 * nt > PIM_MAX_N_LDS)
+      return fail(PIM_ERR_INVALID, "nr = %d, nt = %d: need nr, nt >= 1 and 4 nt <= %d", nr, nt, PIM_MAX_N_LDS);
     if (qam != 4 && qam != 16) return fail(PIM_ERR_UNSUPPORTED, "qam = %d (4 and 16 are implemented)", qam);
     if (map != PIM_MIMO_ML && map != PIM_MIMO_DI) return fail(PIM_ERR_INVALID, "unknown mapping %d", map);
     if (map == PIM_MIMO_DI && !(std::isfinite(esn0) && esn0 > 0.0))
@@ -177,7 +177,7 @@ pim_status pim_mimo_ising(const double* Hc, const double* yc, int32_t nr, int32_
 
 pim_status pim_mimo_decode(const double* xm, const int8_t* s, int32_t nt, int32_t qam, int32_t map, double* x) {
   if (!xm || !s || !x) return fail(PIM_ERR_INVALID, "NULL argument");
-  if (nt < 1 || 4 * nt > PIM_MAX_N) return fail(PIM_ERR_INVALID, "nt = %d out of range", nt);
+  if (nt < 1 || 4 * nt > PIM_MAX_N_LDS) return fail(PIM_ERR_INVALID, "nt = %d out of range", nt);
   if (qam != 4 && qam != 16) return fail(PIM_ERR_UNSUPPORTED, "qam = %d (4 and 16 are implemented)", qam);
   if (map != PIM_MIMO_ML && map != PIM_MIMO_DI) return fail(PIM_ERR_INVALID, "unknown mapping %d", map);
   double w[2];

@@ -349,6 +349,9 @@ pim_status run_prepare(pim_batch* b, const pim_schedule* sc, hipStream_t s, RunC
       return fail(PIM_ERR_UNSUPPORTED, "the sequential kernel takes integer instances");
     if (sc->record_states && (sc->kernel != PIM_KERNEL_MFMA_I8 || b->real))
       return fail(PIM_ERR_UNSUPPORTED, "state recording is implemented for the int8 MFMA kernel");
+    if (b->n > PIM_MAX_N_LDS && (sc->kernel != PIM_KERNEL_MFMA_I8 || sc->record_states))
+      return fail(PIM_ERR_UNSUPPORTED, "N = %d > %d runs only the int8 MFMA kernel, without state recording", b->n,
+                  PIM_MAX_N_LDS);
     if (sc->use_target && !sc->target) return fail(PIM_ERR_INVALID, "use_target set without target energies");
     const int T = sc->steps;
     for (int t = 0; t < T; ++t)
@@ -552,7 +555,9 @@ hipError_t run_launch(pim_batch* b, const pim_schedule* sc, uint64_t seed, const
       a.k0 = k0;
       a.k1 = k1;
       a.waves = b->waves;
-      e = launch_sweep_mfma(a, b->count, b->nt, b->has_h, s);
+      a.count = b->count;
+      e = b->nt * 32 > PIM_MAX_N_LDS ? launch_sweep_big(a, b->count, b->nt, b->has_h, s)
+                                     : launch_sweep_mfma(a, b->count, b->nt, b->has_h, s);
     } else if (mfma) {
       SweepRealArgs a{};
       a.jfrag = reinterpret_cast<const uint8_t*>(b->d_jfrag);
@@ -699,7 +704,7 @@ pim_status pim_compile_table_real(const pim_params* params, double beta, double 
 
 pim_status pim_quantize(const double* J, int32_t n, int32_t prec, double* J_out, double* scale_out) {
   if (!J || !J_out) return fail(PIM_ERR_INVALID, "NULL argument");
-  if (n < 1 || n > PIM_MAX_N) return fail(PIM_ERR_INVALID, "n = %d outside [1, %d]", n, PIM_MAX_N);
+  if (n < 1 || n > PIM_MAX_N_LDS) return fail(PIM_ERR_INVALID, "n = %d outside [1, %d]", n, PIM_MAX_N_LDS);
   if (prec != PIM_PREC_FP8 && prec != PIM_PREC_BF16) return fail(PIM_ERR_INVALID, "unknown precision %d", prec);
   const size_t nn = (size_t)n * n;
   for (size_t i = 0; i < nn; ++i)
@@ -721,6 +726,8 @@ pim_status pim_create_real(const double* J, const double* h, const pim_params* p
     if (prec != PIM_PREC_FP8 && prec != PIM_PREC_BF16) return fail(PIM_ERR_INVALID, "unknown precision %d", prec);
     if (!J) return fail(PIM_ERR_INVALID, "J is NULL");
     const int n = r.n;
+    if (n > PIM_MAX_N_LDS)
+      return fail(PIM_ERR_UNSUPPORTED, "real-valued instances need N <= %d (N = %d)", PIM_MAX_N_LDS, n);
     for (int i = 0; i < n; ++i) {
       if (J[(size_t)i * n + i] != 0.0) return fail(PIM_ERR_INVALID, "J[%d][%d] != 0 (diagonal must be zero)", i, i);
       if (h && !std::isfinite(h[i])) return fail(PIM_ERR_INVALID, "h[%d] is not finite", i);
@@ -797,7 +804,7 @@ pim_status pim_create(const int8_t* J, const int32_t* h, const pim_params* param
     auto* inst = new pim_instance();
     inst->rule = std::move(r);
     const int n = inst->rule.n;
-    inst->nt = (n + 31) / 32;
+    inst->nt = n <= PIM_MAX_N_LDS ? (n + 31) / 32 : big_tiles(n);
     inst->npad = inst->nt * 32;
     inst->has_h = false;
     if (h)
@@ -1081,6 +1088,10 @@ pim_status pim_tune(pim_batch* b, int32_t steps, void* stream, int32_t* waves_ou
     sc.kernel = PIM_KERNEL_MFMA_I8;
     for (size_t p = 0; p < targets.size(); ++p) {
       pim_batch* t = targets[p];
+      if (t->npad > PIM_MAX_N_LDS) {  // the streamed kernel has a fixed 4-wave workgroup
+        if (waves_out) waves_out[p] = 4;
+        continue;
+      }
       const int cand[3] = {4, 2, 1};
       int best_w = 4;
       float best_ms = 0.0f;

@@ -27,9 +27,9 @@ namespace pim {
 namespace {
 
 constexpr int kTrials = 32;
-constexpr int kBlocks = PIM_MAX_N / 16;  // spin blocks of 16
+constexpr int kBlocks = PIM_MAX_N_LDS / 16;  // spin blocks of 16
 constexpr int kThreads = kTrials * kBlocks;
-constexpr int kRow = PIM_MAX_N + 8;      // LDS row stride (floats) of one trial's spins
+constexpr int kRow = PIM_MAX_N_LDS + 8;      // LDS row stride (floats) of one trial's spins
 
 template <bool REAL>
 __global__ __launch_bounds__(kThreads) void sweep_plain_kernel(PlainArgs a) {
@@ -187,7 +187,7 @@ __global__ __launch_bounds__(kThreads) void sweep_plain_kernel(PlainArgs a) {
 }  // namespace
 
 hipError_t launch_sweep_plain(const PlainArgs& a, bool real, hipStream_t s) {
-  if (a.n > PIM_MAX_N) return hipErrorInvalidValue;
+  if (a.n > PIM_MAX_N_LDS) return hipErrorInvalidValue;
   const dim3 grid((a.R + kTrials - 1) / kTrials);
   if (real) hipLaunchKernelGGL(sweep_plain_kernel<true>, grid, dim3(kThreads), 0, s, a);
   else hipLaunchKernelGGL(sweep_plain_kernel<false>, grid, dim3(kThreads), 0, s, a);

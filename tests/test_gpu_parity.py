@@ -325,3 +325,45 @@ def test_tune_keeps_trajectories(gpu_lib):
         ref = _oracle(J, h, c, 0.5, 4, ztab, beta, eta, 5, k, np.arange(trials))
         _compare(batch, k, ref, np.arange(trials), len(h))
     batch.close()
+
+
+BIG_CASES = [
+    # n, trials, steps, jmax, hmax
+    (257, 64, 60, 3, 0),
+    (300, 40, 50, 1, 5),
+    (512, 33, 40, 2, 0),
+    (777, 64, 30, 1, 0),
+    (1000, 32, 30, 1, 0),
+    (1024, 70, 24, 30, 40),
+]
+
+
+@pytest.mark.parametrize("case", BIG_CASES, ids=lambda c: "-".join(map(str, c)))
+def test_streamed_large_n_parity(gpu_lib, case):
+    """N > 256: couplings streamed from global memory, four waves per trial
+    block sharing the spins in LDS; bit-exact against the oracle."""
+    n, trials, steps, jmax, hmax = case
+    _say(f"large N streamed n={n} trials={trials} steps={steps}")
+    _run_case(gpu_lib, "int", n, trials, steps, "mfma", seed=13, count=2, jmax=jmax, hmax=hmax)
+
+
+def test_mixed_small_and_large_n_graph(gpu_lib):
+    _say("mixed small/large N in one graph")
+    pim = gpu_lib
+    ns = [100, 400, 200, 1000]
+    trials, steps = 48, 40
+    ztab = w.gauss_table(8)
+    beta = w.linear_beta(steps, 0.1, 3.0)
+    eta = w.eta_sqrt_beta_over_5(beta)
+    probs, insts = [], []
+    for k, n in enumerate(ns):
+        J, h = w.sk1(n, seed=21, index=k)
+        probs.append((J, h, 1 / np.sqrt(n)))
+        insts.append(pim.Instance(J, h, j_scale=1 / np.sqrt(n), xi=0.5, noise_table=ztab, rng_stream=k))
+    batch = pim.Batch(insts, trials).run(beta, eta, seed=2)
+    for k, (J, h, c) in enumerate(probs):
+        ref = _oracle(J, h, c, 0.5, 4, ztab, beta, eta, 2, k, np.arange(trials))
+        _compare(batch, k, ref, np.arange(trials), len(h))
+        spins, e, trial, step = batch.best(k)
+        assert e == pimi.energy(J, h, spins.astype(np.int64))
+    batch.close()
