@@ -46,6 +46,9 @@ def parse():
                     help="instances run through the plain FP32 per-instance kernel for the comparison "
                          "(0 = skip); trajectories are bit-identical, so TTS99 is equal")
     ap.add_argument("--no-mimo", action="store_true", help="skip the MIMO detection leg")
+    ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-N batched leg")
+    ap.add_argument("--uneven-steps", type=int, default=2000,
+                    help="steps of the uneven-N batched leg (the workload states 10^4; shortened to bound the run)")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the parallel-vs-sequential comparison and the flip-rate diagnostic")
     ap.add_argument("--mimo-requests", type=int, default=512,
@@ -202,6 +205,53 @@ def mimo_leg(args):
         be += int(np.count_nonzero(w.mimo.bits_from_symbols(x, qam) != p["bits"]))
     quality["mmse"] = {"ser": se / (M * nt), "ber": be / (M * nt * bits_per_sym)}
     out["batched"] = quality
+    return out
+
+
+def uneven_leg(args):
+    """Batched SK-1 with uneven N: 128 instances, N_k = [100, 200, 400, 800,
+    1000][k mod 5], J = +-1, h = 0, c = 1/sqrt(N_k), xi = 0.5, 1024 replicas
+    each, beta linear 0.1 -> 3.0 with eta = sqrt(beta / 5).  All instances run
+    in one batch: one part per N, launched together as one captured graph.
+    Also each N bucket alone, for per-N rates and the int8 MFMA fraction
+    (2 N^2 ops per replica-step)."""
+    import paper_2604_17109_amd as pim
+    import workloads as w
+    sizes = [100, 200, 400, 800, 1000]
+    count, R, T = 128, 1024, args.uneven_steps
+    beta = w.linear_beta(T, 0.1, 3.0)
+    eta = w.eta_sqrt_beta_over_5(beta)
+    ns = [sizes[k % 5] for k in range(count)]
+    insts = [pim.Instance(*w.sk1(ns[k], seed=9, index=k), j_scale=1 / math.sqrt(ns[k]), xi=0.5,
+                          noise_table=w.gauss_table(8), rng_stream=k) for k in range(count)]
+    batch = pim.Batch(insts, R)
+    waves = batch.tune(steps=100).tolist()
+    batch.run(beta, eta, seed=1)  # warm-up; also the reference energies
+    ref = [batch.best(k)[1] for k in range(count)]
+    tgt = [math.floor(0.999 * r) for r in ref]
+    batch.run(beta, eta, seed=2, target=tgt)
+    kms = batch.kernel_ms()
+    updates = float(sum(ns)) * R * T
+    ops = float(sum(2 * n * n for n in ns)) * R * (T + 1)
+    hits = [(batch.trials_of(k, spins=False)["first_hit"] >= 0).mean() for k in range(count)]
+    out = {"workload": f"{count} SK-1 instances, N in {sizes}, {R} replicas x {T} steps, one graph launch",
+           "kernel_ms": kms, "spin_updates_per_s": updates / (kms / 1e3),
+           "int8_mfma_frac": ops / (kms / 1e3) / INT8_MFMA_PEAK, "waves_per_workgroup": dict(zip(map(str, sizes), waves)),
+           "p_bar_relaxed": float(np.mean(hits)), "per_n": {}}
+    batch.close()
+    for n in sizes:
+        sub = [i for i, m in zip(insts, ns) if m == n]
+        b = pim.Batch(sub, R)
+        b.run(beta, eta, seed=2)
+        b.run(beta, eta, seed=2)
+        k = b.kernel_ms()
+        u = float(len(sub)) * n * R * T
+        o = 2.0 * n * n * len(sub) * R * (T + 1)
+        out["per_n"][str(n)] = {"instances": len(sub), "kernel_ms": k, "spin_updates_per_s": u / (k / 1e3),
+                                "int8_mfma_frac": o / (k / 1e3) / INT8_MFMA_PEAK}
+        b.close()
+    for i in insts:
+        i.close()
     return out
 
 
@@ -377,6 +427,8 @@ def main():
         pb.close()
     if not args.no_mimo:
         line["mimo"] = mimo_leg(args)
+    if not args.no_uneven:
+        line["uneven_n"] = uneven_leg(args)
     if not args.no_compare:
         line["comparison"] = comparison_leg()
     if not args.no_cpu_baseline:
