@@ -305,6 +305,65 @@ pim_status pim_mimo_ising(const double* H, const double* y, int32_t nr, int32_t 
  * interleaved (re, im) binary64. */
 pim_status pim_mimo_decode(const double* xm, const int8_t* s, int32_t nt, int32_t qam, int32_t map, double* x);
 
+/* ---- request server with continuous batching -----------------------------
+ * For streams of small real-valued requests (MIMO detection: Suppl. "PIMI
+ * FPGA implementation for MIMO detection", host-side task scheduling).  Every
+ * request is one Ising instance (binary64 J, h, N <= max_n) solved with the
+ * server's fixed rule and schedule by `trials` trials on the FP8 / BF16 MFMA
+ * sweep, then re-ranked in binary64; the result is the best state and its
+ * energy.  The noise counter stream of a request is its id, so its result is
+ * the same whatever else is in flight.
+ *
+ * Device memory: per N class (N rounded up to 32) up to slots_per_class slots,
+ * allocated in chunks of max_batch as requests arrive, while the total stays
+ * within hbm_budget bytes (0 = unbounded).  A chunk is one launch. */
+typedef struct pim_server pim_server;
+typedef struct {
+  int32_t max_n;             /* largest request N, <= PIM_MAX_N_LDS                  */
+  int32_t slots_per_class;   /* >= max_batch                                          */
+  int32_t max_batch;         /* requests per launch and class, 1..65535              */
+  int32_t trials;            /* trials per request                                    */
+  int32_t steps;             /* T                                                      */
+  const double* beta;        /* host [steps] (copied)                                 */
+  const double* eta;         /* host [steps] (copied)                                 */
+  double j_scale;            /* c                                                      */
+  double xi;
+  int32_t levels;
+  int32_t noise;             /* pim_noise                                              */
+  const double* noise_table; /* host [256] or NULL (copied)                            */
+  int32_t prec;              /* pim_prec                                               */
+  int32_t streams;           /* concurrent launch streams, 1..8                        */
+  uint64_t seed;
+  size_t hbm_budget;         /* bytes, 0 = no limit                                    */
+} pim_server_config;
+
+pim_status pim_server_create(const pim_server_config* cfg, pim_server** out);
+
+/* Admits up to `count` requests in order: ids[r] < 2^24 (also the noise
+ * stream), ns[r], host J[r] (ns[r] x ns[r] binary64, symmetric, zero diagonal)
+ * and h[r] (NULL, or per-request NULL, for zeros).  Quantises and stages them
+ * on the host; *admitted is how many were taken (fewer when no slot or budget
+ * is free: poll, then submit the rest).  No device work. */
+pim_status pim_server_submit(pim_server* server, int32_t count, const uint32_t* ids, const int32_t* ns,
+                             const double* const* J, const double* const* h, int32_t* admitted);
+
+/* Launches every staged request (one launch per chunk, round-robin over the
+ * server's streams; upload, sweep, re-rank and readback are asynchronous) and
+ * returns; *launched: requests launched. */
+pim_status pim_server_flush(pim_server* server, int32_t* launched);
+
+/* Collects up to `max` finished requests without blocking: ids [max], states
+ * (host int8 [max][PIM_MAX_N_LDS], first N entries used; may be NULL),
+ * binary64 energies [max] (may be NULL); *done: how many. */
+pim_status pim_server_poll(pim_server* server, int32_t max, uint32_t* ids, int8_t* states, double* energies,
+                           int32_t* done);
+
+/* Requests staged but not launched, and launched but not yet polled. */
+pim_status pim_server_pending(pim_server* server, int32_t* staged, int32_t* in_flight);
+
+/* Waits for launched work and frees everything. */
+void pim_server_destroy(pim_server* server);
+
 void pim_batch_destroy(pim_batch* batch);
 void pim_destroy(pim_instance* inst);
 

@@ -41,7 +41,10 @@ EXPORTED = (
     "pim_batch_destroy", "pim_destroy", "pim_last_error", "pim_abi_version",
     "pim_create_real", "pim_quantize", "pim_compile_table_real", "pim_mimo_ising", "pim_mimo_decode",
     "pim_states", "pim_flip_counts", "pim_tune",
+    "pim_server_create", "pim_server_submit", "pim_server_flush", "pim_server_poll", "pim_server_pending",
+    "pim_server_destroy",
 )
+MAX_N_LDS = 256
 
 
 class PimError(RuntimeError):
@@ -73,6 +76,27 @@ class Schedule(ctypes.Structure):
         ("use_target", ctypes.c_int32),
         ("target", ctypes.POINTER(ctypes.c_double)),
         ("record_states", ctypes.c_int32),
+    ]
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [
+        ("max_n", ctypes.c_int32),
+        ("slots_per_class", ctypes.c_int32),
+        ("max_batch", ctypes.c_int32),
+        ("trials", ctypes.c_int32),
+        ("steps", ctypes.c_int32),
+        ("beta", ctypes.POINTER(ctypes.c_double)),
+        ("eta", ctypes.POINTER(ctypes.c_double)),
+        ("j_scale", ctypes.c_double),
+        ("xi", ctypes.c_double),
+        ("levels", ctypes.c_int32),
+        ("noise", ctypes.c_int32),
+        ("noise_table", ctypes.POINTER(ctypes.c_double)),
+        ("prec", ctypes.c_int32),
+        ("streams", ctypes.c_int32),
+        ("seed", ctypes.c_uint64),
+        ("hbm_budget", ctypes.c_size_t),
     ]
 
 
@@ -109,6 +133,12 @@ def _load():
         "pim_states": (I32, [VP, I32, I32, P(ctypes.c_int8)]),
         "pim_flip_counts": (I32, [VP, I32, P(ctypes.c_int64), P(ctypes.c_int64)]),
         "pim_tune": (I32, [VP, I32, VP, P(I32)]),
+        "pim_server_create": (I32, [P(ServerConfig), P(VP)]),
+        "pim_server_submit": (I32, [VP, I32, P(ctypes.c_uint32), P(I32), P(P(F64)), P(P(F64)), P(I32)]),
+        "pim_server_flush": (I32, [VP, P(I32)]),
+        "pim_server_poll": (I32, [VP, I32, P(ctypes.c_uint32), P(ctypes.c_int8), P(F64), P(I32)]),
+        "pim_server_pending": (I32, [VP, P(I32), P(I32)]),
+        "pim_server_destroy": (None, [VP]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -463,6 +493,79 @@ class Batch:
     def close(self):
         if self._handle:
             lib.pim_batch_destroy(self._handle)
+            self._handle = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # noqa: BLE001
+            pass
+
+
+class Server:
+    """Request server with continuous batching (see pim_server_* in pim.h):
+    submit real-valued Ising requests as they arrive, flush to launch what is
+    staged, poll for finished requests."""
+
+    def __init__(self, *, max_n, trials, beta, eta, j_scale=1.0, xi=2.0, levels=4, noise="gauss",
+                 noise_table=None, prec="fp8", slots_per_class=4096, max_batch=256, streams=4, seed=1,
+                 hbm_budget=0):
+        _device_ready()
+        self._beta = np.ascontiguousarray(beta, dtype=np.float64)
+        self._eta = np.ascontiguousarray(eta, dtype=np.float64)
+        self._ztab = None if noise_table is None else np.ascontiguousarray(noise_table, dtype=np.float64)
+        c = ServerConfig()
+        c.max_n, c.slots_per_class, c.max_batch = int(max_n), int(slots_per_class), int(max_batch)
+        c.trials, c.steps = int(trials), self._beta.size
+        c.beta, c.eta = _ptr(self._beta, ctypes.c_double), _ptr(self._eta, ctypes.c_double)
+        c.j_scale, c.xi, c.levels = float(j_scale), float(xi), int(levels)
+        c.noise = _NOISES[noise] if isinstance(noise, str) else int(noise)
+        c.noise_table = _ptr(self._ztab, ctypes.c_double)
+        c.prec = _PRECS[prec]
+        c.streams, c.seed, c.hbm_budget = int(streams), int(seed), int(hbm_budget)
+        self._handle = ctypes.c_void_p()
+        _check(lib.pim_server_create(ctypes.byref(c), ctypes.byref(self._handle)))
+
+    def submit(self, ids, Js, hs=None):
+        """Stages requests (ids, J arrays, h arrays); returns how many were admitted."""
+        k = len(ids)
+        if k == 0:
+            return 0
+        Js = [np.ascontiguousarray(J, dtype=np.float64) for J in Js]
+        hs = None if hs is None else [np.ascontiguousarray(h, dtype=np.float64) for h in hs]
+        idarr = np.ascontiguousarray(ids, dtype=np.uint32)
+        ns = np.array([J.shape[0] for J in Js], dtype=np.int32)
+        jp = (ctypes.POINTER(ctypes.c_double) * k)(*[_ptr(J, ctypes.c_double) for J in Js])
+        hp = None if hs is None else (ctypes.POINTER(ctypes.c_double) * k)(*[_ptr(h, ctypes.c_double) for h in hs])
+        adm = ctypes.c_int32()
+        _check(lib.pim_server_submit(self._handle, k, _ptr(idarr, ctypes.c_uint32), _ptr(ns, ctypes.c_int32), jp,
+                                     hp, ctypes.byref(adm)))
+        return adm.value
+
+    def flush(self):
+        n = ctypes.c_int32()
+        _check(lib.pim_server_flush(self._handle, ctypes.byref(n)))
+        return n.value
+
+    def poll(self, max_results=65536, states=True):
+        """Finished requests: (ids uint32 [k], states int8 [k, MAX_N_LDS] or None, energies [k])."""
+        ids = np.zeros(max_results, np.uint32)
+        st = np.zeros((max_results, MAX_N_LDS), np.int8) if states else None
+        e = np.zeros(max_results, np.float64)
+        done = ctypes.c_int32()
+        _check(lib.pim_server_poll(self._handle, int(max_results), _ptr(ids, ctypes.c_uint32),
+                                   _ptr(st, ctypes.c_int8), _ptr(e, ctypes.c_double), ctypes.byref(done)))
+        k = done.value
+        return ids[:k], (st[:k] if states else None), e[:k]
+
+    def pending(self):
+        a, b = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib.pim_server_pending(self._handle, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    def close(self):
+        if self._handle:
+            lib.pim_server_destroy(self._handle)
             self._handle = ctypes.c_void_p()
 
     def __del__(self):

@@ -1,0 +1,99 @@
+"""GPU tests of the request server (continuous batching): results equal the
+batch API's for the same request (same rule, seed and noise stream = id),
+are the same alone and in a mixed stream, and admission honours the slot
+table and the device-memory budget."""
+import time
+
+import numpy as np
+import pytest
+
+import workloads as w
+
+pytestmark = pytest.mark.gpu
+
+STEPS = 32
+BETA = w.constant(STEPS, 1.0)
+ETA = w.mimo_eta(STEPS, 0.05, 0.3)
+
+
+def _say(msg):
+    print(f"\n[gpu-case] {msg}", flush=True)
+
+
+def _request(pim, k, nt, qam):
+    p = w.mimo.mimo_problem(nt, nt, qam, 15.0, seed=4, index=k)
+    return pim.mimo_ising(p["H"], p["y"], qam, "di", p["esn0"])[:2]
+
+
+def _drain(srv, want, timeout=60.0):
+    got = {}
+    t0 = time.time()
+    while len(got) < want:
+        ids, st, e = srv.poll()
+        for i, s, x in zip(ids, st, e):
+            got[int(i)] = (s.copy(), float(x))
+        if time.time() - t0 > timeout:
+            raise TimeoutError(f"{len(got)} of {want} requests finished")
+    return got
+
+
+def _server(pim, **kw):
+    args = dict(max_n=128, trials=32, beta=BETA, eta=ETA, xi=2.0, noise_table=w.gauss_table(8), prec="fp8",
+                slots_per_class=256, max_batch=32, streams=3, seed=7)
+    args.update(kw)
+    return pim.Server(**args)
+
+
+def test_server_matches_batch_api_and_alone_equals_mix(gpu_lib):
+    _say("server: batch-API equality, alone vs mix")
+    pim = gpu_lib
+    J, h = _request(pim, 0, 8, 16)
+    n = J.shape[0]
+    # batch API reference: same rule, seed, stream = request id
+    inst = pim.Instance(J, h, j_scale=1.0, xi=2.0, noise_table=w.gauss_table(8), rng_stream=777, prec="fp8")
+    b = pim.Batch([inst], 32).run(BETA, ETA, seed=7)
+    ref_s, ref_e, _, _ = b.best(0)
+    b.close()
+    srv = _server(pim)
+    assert srv.submit([777], [J], [h]) == 1
+    assert srv.flush() == 1
+    alone = _drain(srv, 1)[777]
+    assert np.array_equal(alone[0][:n], ref_s) and alone[1] == ref_e
+    # the same request among 150 others of mixed sizes, submitted in waves
+    shapes = [(8, 4), (16, 16), (4, 16), (32, 4), (8, 16)]
+    reqs = [(5000 + k, *_request(pim, k + 1, *shapes[k % len(shapes)])) for k in range(150)]
+    reqs.insert(77, (777, J, h))
+    for start in range(0, len(reqs), 40):
+        part = reqs[start:start + 40]
+        left = part
+        while left:
+            took = srv.submit([r[0] for r in left], [r[1] for r in left], [r[2] for r in left])
+            srv.flush()
+            left = left[took:]
+            if left:
+                time.sleep(0.001)
+    got = _drain(srv, len(reqs) - 0)
+    assert set(got) == {r[0] for r in reqs}
+    assert np.array_equal(got[777][0][:n], alone[0][:n]) and got[777][1] == alone[1]
+    srv.close()
+
+
+def test_server_admission_limits(gpu_lib):
+    _say("server: admission by slots and budget")
+    pim = gpu_lib
+    J, h = _request(pim, 3, 8, 4)  # N = 32
+    srv = _server(pim, slots_per_class=8, max_batch=8)
+    ids = list(range(20))
+    assert srv.submit(ids, [J] * 20, [h] * 20) == 8     # one chunk of 8 slots
+    assert srv.pending() == (8, 0)
+    assert srv.flush() == 8
+    assert srv.submit(ids[8:], [J] * 12, [h] * 12) == 0  # the only chunk is in flight
+    got = _drain(srv, 8)
+    assert set(got) == set(range(8))
+    assert srv.submit(ids[8:], [J] * 12, [h] * 12) == 8  # the chunk is free again
+    srv.flush()
+    _drain(srv, 8)
+    srv.close()
+    tiny = _server(pim, hbm_budget=1024)
+    assert tiny.submit([1], [J], [h]) == 0               # a chunk needs more than the budget
+    tiny.close()
