@@ -47,6 +47,8 @@ def parse():
                          "(0 = skip); trajectories are bit-identical, so TTS99 is equal")
     ap.add_argument("--no-mimo", action="store_true", help="skip the MIMO detection leg")
     ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-N batched leg")
+    ap.add_argument("--no-serving", action="store_true", help="skip the MIMO serving leg")
+    ap.add_argument("--serving-requests", type=int, default=4000)
     ap.add_argument("--uneven-steps", type=int, default=2000,
                     help="steps of the uneven-N batched leg (the workload states 10^4; shortened to bound the run)")
     ap.add_argument("--no-compare", action="store_true",
@@ -255,6 +257,83 @@ def uneven_leg(args):
     return out
 
 
+def serving_leg(args):
+    """MIMO detection serving with continuous batching.  Two request mixes at
+    Eb/N0 = 20 dB, DI mapping (N = 4 Nt spins), 32 trials x 64 steps each,
+    FP8 MFMA sweep, binary64 re-rank, served by the request server:
+    * "5g": Nt = Nr in {8, 16} x {4-QAM, 16-QAM} (N = 32, 64), the sizes the
+      paper's real-time design targets;
+    * "full": Nt = Nr in {8, 16, 32, 64} x {4-QAM, 16-QAM} (N = 32 ... 256).
+    Poisson arrivals at each rate; latency from arrival to a host-readable
+    result (p50 / p99), sustained throughput, and the share finished within
+    the 1 ms slot budget of 5G NR at 15 kHz subcarrier spacing (Suppl.
+    "Throughput requirement for LTE/5G systems")."""
+    import paper_2604_17109_amd as pim
+    import workloads as w
+    cfg = MIMO
+    T = cfg["steps"]
+    beta = w.constant(T, cfg["beta"])
+    eta = w.mimo_eta(T, *cfg["gamma"])
+    M = args.serving_requests
+    out = {}
+    for mix, nts, rates in (("5g", (8, 16), (1e4, 1e5, 1e6)), ("full", (8, 16, 32, 64), (1e4, 1e5))):
+        pairs = [(nt, q) for nt in nts for q in (4, 16)]
+        probs, Js, hs, xms = [], [], [], []
+        for k in range(M):
+            nt, q = pairs[k % len(pairs)]
+            p = w.mimo.mimo_problem(nt, nt, q, 20.0, seed=23, index=k)
+            J, h, xm = pim.mimo_ising(p["H"], p["y"], q, "di", p["esn0"])
+            probs.append(p)
+            Js.append(J)
+            hs.append(h)
+            xms.append(xm)
+        ns = [J.shape[0] for J in Js]
+        res = {"workload": f"{M} requests uniform over Nt = Nr in {list(nts)} x {{4,16}}-QAM, 20 dB, "
+                           f"N = {min(ns)}..{max(ns)}, {cfg['trials']} trials x {T} steps, fp8", "rates": {}}
+        srv = pim.Server(max_n=max(ns), trials=cfg["trials"], beta=beta, eta=eta, xi=cfg["xi"],
+                         noise_table=w.gauss_table(8), prec="fp8", slots_per_class=4096, max_batch=256, streams=4,
+                         seed=11, max_wait_us=150.0, prealloc_chunks=4)
+        for k in range(len(pairs)):  # warm-up: every size class once
+            srv.submit([k], [Js[k]], [hs[k]])
+        left = len(pairs)
+        while left:
+            srv.flush()
+            left -= len(srv.poll(states=False)[0])
+        rng = np.random.default_rng(29)
+        for lam in rates:
+            arrive = np.cumsum(rng.exponential(1.0 / lam, size=M))
+            done_t = np.full(M, np.nan)
+            states = {}
+            nxt = finished = 0
+            t0 = time.perf_counter()
+            while finished < M:
+                now = time.perf_counter() - t0
+                if nxt < M and arrive[nxt] <= now:
+                    k = int(np.searchsorted(arrive, now, side="right"))
+                    nxt += srv.submit(list(range(nxt, k)), Js[nxt:k], hs[nxt:k])
+                srv.flush()
+                ids, st, _ = srv.poll()
+                if len(ids):
+                    done_t[ids] = time.perf_counter() - t0
+                    for i, sv in zip(ids, st):
+                        states[int(i)] = sv
+                    finished += len(ids)
+            lat = (done_t - arrive) * 1e6
+            se = 0
+            for k in range(M):
+                x = pim.mimo_decode(xms[k], states[k][:ns[k]], probs[k]["qam"], "di")
+                se += int(np.count_nonzero(x != probs[k]["x"]))
+            span = float(np.nanmax(done_t) - arrive[0])
+            res["rates"][f"{lam:.0e}"] = {
+                "offered_req_per_s": lam, "served_req_per_s": M / span,
+                "p50_us": float(np.percentile(lat, 50)), "p99_us": float(np.percentile(lat, 99)),
+                "within_1ms": float(np.mean(lat <= 1000.0)),
+                "ser": se / float(sum(p["nt"] for p in probs))}
+        srv.close()
+        out[mix] = res
+    return out
+
+
 def comparison_leg():
     """The paper's comparison on the GPU (Fig. 2 / Suppl. "Estimation of
     optimal clock cycles to solution", "Quantifying coupled oscillatory
@@ -427,6 +506,8 @@ def main():
         pb.close()
     if not args.no_mimo:
         line["mimo"] = mimo_leg(args)
+    if not args.no_serving:
+        line["serving"] = serving_leg(args)
     if not args.no_uneven:
         line["uneven_n"] = uneven_leg(args)
     if not args.no_compare:

@@ -335,21 +335,27 @@ typedef struct {
   int32_t streams;           /* concurrent launch streams, 1..8                        */
   uint64_t seed;
   size_t hbm_budget;         /* bytes, 0 = no limit                                    */
+  double max_wait_us;        /* pim_server_flush holds a partly filled chunk until its
+                                first request has waited this long (0 = never)      */
+  int32_t prealloc_chunks;   /* chunks allocated at creation per class up to max_n
+                                (within slots_per_class and hbm_budget)             */
 } pim_server_config;
 
 pim_status pim_server_create(const pim_server_config* cfg, pim_server** out);
 
 /* Admits up to `count` requests in order: ids[r] < 2^24 (also the noise
  * stream), ns[r], host J[r] (ns[r] x ns[r] binary64, symmetric, zero diagonal)
- * and h[r] (NULL, or per-request NULL, for zeros).  Quantises and stages them
- * on the host; *admitted is how many were taken (fewer when no slot or budget
- * is free: poll, then submit the rest).  No device work. */
+ * and h[r] (NULL for zeros).  Validates them and copies them into pinned
+ * staging (quantisation happens on the device at launch); *admitted is how
+ * many were taken (fewer when no slot or budget is free: poll, then submit
+ * the rest).  No device work. */
 pim_status pim_server_submit(pim_server* server, int32_t count, const uint32_t* ids, const int32_t* ns,
                              const double* const* J, const double* const* h, int32_t* admitted);
 
-/* Launches every staged request (one launch per chunk, round-robin over the
- * server's streams; upload, sweep, re-rank and readback are asynchronous) and
- * returns; *launched: requests launched. */
+/* Launches staged requests, one launch per chunk, round-robin over the
+ * server's streams (upload, sweep, re-rank and readback are asynchronous),
+ * and returns: full chunks always, partly filled ones once their first request
+ * has waited max_wait_us.  *launched: requests launched. */
 pim_status pim_server_flush(pim_server* server, int32_t* launched);
 
 /* Collects up to `max` finished requests without blocking: ids [max], states

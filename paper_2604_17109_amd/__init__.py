@@ -97,6 +97,8 @@ class ServerConfig(ctypes.Structure):
         ("streams", ctypes.c_int32),
         ("seed", ctypes.c_uint64),
         ("hbm_budget", ctypes.c_size_t),
+        ("max_wait_us", ctypes.c_double),
+        ("prealloc_chunks", ctypes.c_int32),
     ]
 
 
@@ -509,8 +511,12 @@ class Server:
 
     def __init__(self, *, max_n, trials, beta, eta, j_scale=1.0, xi=2.0, levels=4, noise="gauss",
                  noise_table=None, prec="fp8", slots_per_class=4096, max_batch=256, streams=4, seed=1,
-                 hbm_budget=0):
+                 hbm_budget=0, poll_max=4096, max_wait_us=0.0, prealloc_chunks=0):
         _device_ready()
+        self._poll_max = max(int(poll_max), int(max_batch))
+        self._ids = np.zeros(self._poll_max, np.uint32)
+        self._states = np.zeros((self._poll_max, MAX_N_LDS), np.int8)
+        self._e = np.zeros(self._poll_max, np.float64)
         self._beta = np.ascontiguousarray(beta, dtype=np.float64)
         self._eta = np.ascontiguousarray(eta, dtype=np.float64)
         self._ztab = None if noise_table is None else np.ascontiguousarray(noise_table, dtype=np.float64)
@@ -523,6 +529,8 @@ class Server:
         c.noise_table = _ptr(self._ztab, ctypes.c_double)
         c.prec = _PRECS[prec]
         c.streams, c.seed, c.hbm_budget = int(streams), int(seed), int(hbm_budget)
+        c.max_wait_us = float(max_wait_us)
+        c.prealloc_chunks = int(prealloc_chunks)
         self._handle = ctypes.c_void_p()
         _check(lib.pim_server_create(ctypes.byref(c), ctypes.byref(self._handle)))
 
@@ -547,16 +555,15 @@ class Server:
         _check(lib.pim_server_flush(self._handle, ctypes.byref(n)))
         return n.value
 
-    def poll(self, max_results=65536, states=True):
-        """Finished requests: (ids uint32 [k], states int8 [k, MAX_N_LDS] or None, energies [k])."""
-        ids = np.zeros(max_results, np.uint32)
-        st = np.zeros((max_results, MAX_N_LDS), np.int8) if states else None
-        e = np.zeros(max_results, np.float64)
+    def poll(self, states=True):
+        """Finished requests (copies): (ids uint32 [k], states int8 [k, MAX_N_LDS]
+        or None, energies [k]); at most `poll_max` per call."""
         done = ctypes.c_int32()
-        _check(lib.pim_server_poll(self._handle, int(max_results), _ptr(ids, ctypes.c_uint32),
-                                   _ptr(st, ctypes.c_int8), _ptr(e, ctypes.c_double), ctypes.byref(done)))
+        _check(lib.pim_server_poll(self._handle, self._poll_max, _ptr(self._ids, ctypes.c_uint32),
+                                   _ptr(self._states, ctypes.c_int8) if states else None,
+                                   _ptr(self._e, ctypes.c_double), ctypes.byref(done)))
         k = done.value
-        return ids[:k], (st[:k] if states else None), e[:k]
+        return self._ids[:k].copy(), (self._states[:k].copy() if states else None), self._e[:k].copy()
 
     def pending(self):
         a, b = ctypes.c_int32(), ctypes.c_int32()

@@ -2,8 +2,10 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "pim.h"
@@ -14,6 +16,25 @@ namespace pim {
 pim_status fail(pim_status st, const char* fmt, ...);
 void* dev_alloc(size_t bytes, hipStream_t s);
 void dev_free(void* p, hipStream_t s);
+
+// Runs fn(lo, hi) over [0, n) in chunks of at least `grain` items on up to
+// hardware_concurrency threads (host).
+template <typename F>
+void parallel_for(int n, F&& fn, int grain = 256) {
+  const int hw = (int)std::max(1u, std::thread::hardware_concurrency());
+  const int nt = std::min(hw, std::max(1, n / std::max(1, grain)));
+  if (nt <= 1) {
+    fn(0, n);
+    return;
+  }
+  std::vector<std::thread> pool;
+  const int chunk = (n + nt - 1) / nt;
+  for (int k = 0; k < nt; ++k) {
+    const int lo = k * chunk, hi = std::min(n, lo + chunk);
+    if (lo < hi) pool.emplace_back([&fn, lo, hi] { fn(lo, hi); });
+  }
+  for (auto& th : pool) th.join();
+}
 
 // ---- update-rule constants of one instance --------------------------------
 constexpr int kNoiseBits = 8;              // B
@@ -174,6 +195,17 @@ int big_tiles(int n);  // row tiles of the streamed kernel (a multiple of 4)
 hipError_t launch_sweep_seq(const SeqArgs& a, int count, int nt, bool has_h, hipStream_t s);
 hipError_t launch_sweep_real(const SweepRealArgs& a, int count, int nt, int prec, bool has_h, hipStream_t s);
 size_t real_frag_bytes(int prec, int nt);
+// Device-side quantisation of real instances (request server).
+struct RealPackArgs {
+  const double* j64;   // [count][npad][npad] binary64 J, zero-padded
+  const double* h64;   // [count][npad]
+  uint8_t* frag;       // [count][frag_bytes]
+  float* hf;           // [count][npad]
+  float* scale;        // [count]
+  size_t frag_bytes;
+  int32_t npad, count;
+};
+hipError_t launch_pack_real(const RealPackArgs& a, int prec, hipStream_t s);
 hipError_t launch_energy_f64(const EnergyArgs& a, hipStream_t s);
 
 // Neighbour-triggered flip counts of one instance's recorded states.

@@ -126,24 +126,6 @@ pim_status validate_couplings(const int8_t* J, const int32_t* h, int n) {
   return PIM_OK;
 }
 
-// Runs fn(lo, hi) over [0, n) on up to hardware_concurrency threads.
-template <typename F>
-void parallel_for(int n, F&& fn) {
-  const int hw = (int)std::max(1u, std::thread::hardware_concurrency());
-  const int nt = std::min(hw, std::max(1, n / 256));
-  if (nt <= 1) {
-    fn(0, n);
-    return;
-  }
-  std::vector<std::thread> pool;
-  const int chunk = (n + nt - 1) / nt;
-  for (int k = 0; k < nt; ++k) {
-    const int lo = k * chunk, hi = std::min(n, lo + chunk);
-    if (lo < hi) pool.emplace_back([&fn, lo, hi] { fn(lo, hi); });
-  }
-  for (auto& th : pool) th.join();
-}
-
 pim_status check_spins(const int8_t* s, size_t count) {
   for (size_t i = 0; i < count; ++i)
     if (s[i] != 1 && s[i] != -1) return fail(PIM_ERR_INVALID, "spin value %d at %zu is not +-1", (int)s[i], i);

@@ -5,8 +5,8 @@
 // Device-resident slot table: per N class (N rounded up to 32) a fixed array
 // of slots split into chunks of `max_batch` slots.  A request is admitted into
 // the open chunk of its class when a chunk and the device-memory budget allow;
-// its couplings are quantised and packed on the host into the chunk's pinned
-// staging area.  pim_server_flush launches every open chunk on the next of
+// its binary64 couplings are copied into the chunk's pinned staging area and
+// quantised and packed into MFMA fragments on the device at launch.  pim_server_flush launches every open chunk on the next of
 // several streams: upload, the persistent FP8/BF16 sweep over the chunk's
 // requests (32-trial waves), the binary64 re-rank and selection, and the
 // readback of the selected states into pinned memory, all asynchronous.  New
@@ -19,6 +19,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <deque>
@@ -34,10 +35,18 @@ struct Chunk {
   int cls = 0;
   int count = 0;                 // requests admitted into this chunk
   bool launched = false;
+  std::chrono::steady_clock::time_point first;  // admission of its first request
   hipEvent_t done = nullptr;
   std::vector<uint32_t> ids;
   std::vector<int32_t> ns;
-  // pinned host staging (inputs) and results
+  // pinned host staging (inputs) and results, each one contiguous block
+  // (h_in / d_in, h_out / d_out) of sections; the result block is read back
+  // by one copy
+  uint8_t* h_in = nullptr;
+  uint8_t* d_in = nullptr;
+  uint8_t* h_out = nullptr;
+  uint8_t* d_out = nullptr;
+  size_t in_bytes = 0, out_bytes = 0;
   uint8_t* h_frag = nullptr;
   float* h_hf = nullptr;
   float* h_scale = nullptr;
@@ -93,21 +102,15 @@ using namespace pim;
 
 namespace {
 
-size_t chunk_device_bytes(const pim_server* s, const Klass& k) {
-  const size_t B = s->cfg.max_batch, R = s->cfg.trials, np = k.npad;
-  return B * (k.frag + np * 4 + 4 + np * np * 8 + np * 8 + 4 + 2 * sizeof(void*)) +
-         B * R * (2 * np + 5 * 4 + 8) + B * (np + 8 + 12);
-}
+struct Layout;
+Layout layout(const pim_server* s, const Klass& k);
 
 void free_chunk(Chunk* c) {
   if (c->done) (void)hipEventDestroy(c->done);
-  for (void* p : {(void*)c->h_frag, (void*)c->h_hf, (void*)c->h_scale, (void*)c->h_j64, (void*)c->h_h64,
-                  (void*)c->h_sid, (void*)c->h_spins, (void*)c->h_e, (void*)c->h_sel})
+  for (void* p : {(void*)c->h_in, (void*)c->h_out})
     if (p) (void)hipHostFree(p);
-  for (void* p : {(void*)c->d_frag, (void*)c->d_hf, (void*)c->d_scale, (void*)c->d_j64, (void*)c->d_h64,
-                  (void*)c->d_sid, (void*)c->d_j64p, (void*)c->d_h64p, (void*)c->d_final, (void*)c->d_best,
-                  (void*)c->d_stats, (void*)c->d_rerank, (void*)c->d_sel_spins, (void*)c->d_sel_e,
-                  (void*)c->d_sel_i})
+  for (void* p : {(void*)c->d_in, (void*)c->d_out, (void*)c->d_j64p, (void*)c->d_h64p, (void*)c->d_final,
+                  (void*)c->d_best, (void*)c->d_stats, (void*)c->d_rerank})
     dev_free(p, nullptr);
   delete c;
 }
@@ -122,22 +125,64 @@ bool dev_alloc_n(T** p, size_t count) {
   return *p != nullptr;
 }
 
+// Offsets of the input block: frag | hf | scale | j64 | h64 | sid (each 256-B
+// aligned), and of the result block: spins | energies | (trial, step, tracked).
+struct Layout {
+  size_t frag, hf, scale, j64, h64, sid, in_bytes;
+  size_t spins, e, sel, out_bytes;
+};
+size_t al(size_t x) { return (x + 255) & ~size_t(255); }
+Layout layout(const pim_server* s, const Klass& k) {
+  const size_t B = s->cfg.max_batch, np = k.npad;
+  Layout L{};
+  L.frag = 0;
+  L.hf = al(L.frag + B * k.frag);
+  L.scale = al(L.hf + B * np * 4);
+  L.j64 = al(L.scale + B * 4);
+  L.h64 = al(L.j64 + B * np * np * 8);
+  L.sid = al(L.h64 + B * np * 8);
+  L.in_bytes = al(L.sid + B * 4);
+  L.spins = 0;
+  L.e = al(B * np);
+  L.sel = al(L.e + B * 8);
+  L.out_bytes = al(L.sel + 3 * B * 4);
+  return L;
+}
+
 Chunk* new_chunk(pim_server* s, int cls) {
   const Klass& k = s->classes[cls];
   const size_t B = s->cfg.max_batch, R = s->cfg.trials, np = k.npad;
+  const Layout L = layout(s, k);
   auto* c = new Chunk();
   c->cls = cls;
+  c->in_bytes = L.in_bytes;
+  c->out_bytes = L.out_bytes;
   bool ok = hipEventCreateWithFlags(&c->done, hipEventDisableTiming) == hipSuccess;
-  ok = ok && host_alloc(&c->h_frag, B * k.frag) && host_alloc(&c->h_hf, B * np) && host_alloc(&c->h_scale, B) &&
-       host_alloc(&c->h_j64, B * np * np) && host_alloc(&c->h_h64, B * np) && host_alloc(&c->h_sid, B) &&
-       host_alloc(&c->h_spins, B * np) && host_alloc(&c->h_e, B) && host_alloc(&c->h_sel, 3 * B);
-  ok = ok && dev_alloc_n(&c->d_frag, B * k.frag) && dev_alloc_n(&c->d_hf, B * np) && dev_alloc_n(&c->d_scale, B) &&
-       dev_alloc_n(&c->d_j64, B * np * np) && dev_alloc_n(&c->d_h64, B * np) && dev_alloc_n(&c->d_sid, B) &&
-       dev_alloc_n(&c->d_j64p, B) && dev_alloc_n(&c->d_h64p, B) && dev_alloc_n(&c->d_final, B * R * np) &&
+  ok = ok && host_alloc(&c->h_in, L.in_bytes) && host_alloc(&c->h_out, L.out_bytes) &&
+       dev_alloc_n(&c->d_in, L.in_bytes) && dev_alloc_n(&c->d_out, L.out_bytes);
+  ok = ok && dev_alloc_n(&c->d_j64p, B) && dev_alloc_n(&c->d_h64p, B) && dev_alloc_n(&c->d_final, B * R * np) &&
        dev_alloc_n(&c->d_best, B * R * np) && dev_alloc_n(&c->d_stats, 5 * B * R) &&
-       dev_alloc_n(&c->d_rerank, B * R) && dev_alloc_n(&c->d_sel_spins, B * np) && dev_alloc_n(&c->d_sel_e, B) &&
-       dev_alloc_n(&c->d_sel_i, 3 * B);
-  if (ok) {  // per-request pointer tables of the re-rank, fixed for the chunk's lifetime
+       dev_alloc_n(&c->d_rerank, B * R);
+  if (ok) {
+    c->h_frag = c->h_in + L.frag;
+    c->h_hf = reinterpret_cast<float*>(c->h_in + L.hf);
+    c->h_scale = reinterpret_cast<float*>(c->h_in + L.scale);
+    c->h_j64 = reinterpret_cast<double*>(c->h_in + L.j64);
+    c->h_h64 = reinterpret_cast<double*>(c->h_in + L.h64);
+    c->h_sid = reinterpret_cast<uint32_t*>(c->h_in + L.sid);
+    c->d_frag = c->d_in + L.frag;
+    c->d_hf = reinterpret_cast<float*>(c->d_in + L.hf);
+    c->d_scale = reinterpret_cast<float*>(c->d_in + L.scale);
+    c->d_j64 = reinterpret_cast<double*>(c->d_in + L.j64);
+    c->d_h64 = reinterpret_cast<double*>(c->d_in + L.h64);
+    c->d_sid = reinterpret_cast<uint32_t*>(c->d_in + L.sid);
+    c->h_spins = reinterpret_cast<int8_t*>(c->h_out + L.spins);
+    c->h_e = reinterpret_cast<double*>(c->h_out + L.e);
+    c->h_sel = reinterpret_cast<int32_t*>(c->h_out + L.sel);
+    c->d_sel_spins = reinterpret_cast<int8_t*>(c->d_out + L.spins);
+    c->d_sel_e = reinterpret_cast<double*>(c->d_out + L.e);
+    c->d_sel_i = reinterpret_cast<int32_t*>(c->d_out + L.sel);
+    // per-request pointer tables of the re-rank, fixed for the chunk's lifetime
     std::vector<const double*> jp(B), hp(B);
     for (size_t i = 0; i < B; ++i) {
       jp[i] = c->d_j64 + i * np * np;
@@ -166,7 +211,9 @@ Chunk* chunk_for(pim_server* s, int cls) {
       return k.chunks[i];
     }
   if ((int)k.chunks.size() >= s->cfg.slots_per_class / s->cfg.max_batch) return nullptr;
-  const size_t need = chunk_device_bytes(s, k);
+  const Layout L = layout(s, k);
+  const size_t B = s->cfg.max_batch, R = s->cfg.trials;
+  const size_t need = L.in_bytes + L.out_bytes + B * (2 * sizeof(void*) + R * (2 * (size_t)k.npad + 5 * 4 + 8));
   if (s->cfg.hbm_budget && s->bytes + need > s->cfg.hbm_budget) return nullptr;
   Chunk* c = new_chunk(s, cls);
   if (!c) return nullptr;
@@ -179,12 +226,22 @@ Chunk* chunk_for(pim_server* s, int cls) {
 hipError_t launch_chunk(pim_server* s, Chunk* c, hipStream_t st) {
   const Klass& k = s->classes[c->cls];
   const size_t B = c->count, R = s->cfg.trials, np = k.npad;
-  hipError_t e = hipMemcpyAsync(c->d_frag, c->h_frag, B * k.frag, hipMemcpyHostToDevice, st);
-  if (e == hipSuccess) e = hipMemcpyAsync(c->d_hf, c->h_hf, B * np * 4, hipMemcpyHostToDevice, st);
-  if (e == hipSuccess) e = hipMemcpyAsync(c->d_scale, c->h_scale, B * 4, hipMemcpyHostToDevice, st);
-  if (e == hipSuccess) e = hipMemcpyAsync(c->d_j64, c->h_j64, B * np * np * 8, hipMemcpyHostToDevice, st);
+  // the used part of each input section (the result block is small and read
+  // back whole)
+  hipError_t e = hipMemcpyAsync(c->d_j64, c->h_j64, B * np * np * 8, hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = hipMemcpyAsync(c->d_h64, c->h_h64, B * np * 8, hipMemcpyHostToDevice, st);
   if (e == hipSuccess) e = hipMemcpyAsync(c->d_sid, c->h_sid, B * 4, hipMemcpyHostToDevice, st);
+  if (e != hipSuccess) return e;
+  RealPackArgs pa{};
+  pa.j64 = c->d_j64;
+  pa.h64 = c->d_h64;
+  pa.frag = c->d_frag;
+  pa.hf = c->d_hf;
+  pa.scale = c->d_scale;
+  pa.frag_bytes = k.frag;
+  pa.npad = (int)np;
+  pa.count = (int)B;
+  e = launch_pack_real(pa, s->cfg.prec, st);
   if (e != hipSuccess) return e;
   SweepRealArgs a{};
   a.jfrag = c->d_frag;
@@ -229,9 +286,7 @@ hipError_t launch_chunk(pim_server* s, Chunk* c, hipStream_t st) {
   ra.R = (int)R;
   ra.count = (int)B;
   e = launch_rerank_select(ra, st);
-  if (e == hipSuccess) e = hipMemcpyAsync(c->h_spins, c->d_sel_spins, B * np, hipMemcpyDeviceToHost, st);
-  if (e == hipSuccess) e = hipMemcpyAsync(c->h_e, c->d_sel_e, B * 8, hipMemcpyDeviceToHost, st);
-  if (e == hipSuccess) e = hipMemcpyAsync(c->h_sel, c->d_sel_i, 3 * B * 4, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(c->h_out, c->d_out, c->out_bytes, hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipEventRecord(c->done, st);
   return e;
 }
@@ -313,6 +368,20 @@ pim_status pim_server_create(const pim_server_config* cfg, pim_server** out) {
       s->classes[c].npad = 32 * ((int)c + 1);
       s->classes[c].frag = real_frag_bytes(cfg->prec, (int)c + 1);
     }
+    // chunks allocated up front for every class up to max_n (pinned and
+    // device allocations are slow; doing them here keeps them off the
+    // request path)
+    for (size_t c = 0; ok && c < s->classes.size(); ++c) {
+      if (s->classes[c].npad - 31 > cfg->max_n) break;
+      const int want = std::min(cfg->prealloc_chunks, cfg->slots_per_class / cfg->max_batch);
+      for (int i = 0; ok && i < want; ++i) {
+        Chunk* ch = chunk_for(s, (int)c);
+        ok = ch != nullptr;
+        if (ok) s->classes[c].open = -1;
+        if (ok && i + 1 < want) ch->launched = true;  // keep chunk_for from handing it out again
+      }
+      for (Chunk* ch : s->classes[c].chunks) ch->launched = false;
+    }
     if (!ok) {
       pim_server_destroy(s);
       return fail(PIM_ERR_NOMEM, "server set-up failed");
@@ -329,46 +398,47 @@ pim_status pim_server_submit(pim_server* s, int32_t count, const uint32_t* ids, 
   try {
     if (!s || !ids || !ns || !J || !admitted) return fail(PIM_ERR_INVALID, "NULL argument");
     *admitted = 0;
-    for (int r = 0; r < count; ++r) {
+    if (count <= 0) return PIM_OK;
+    // validation, then slots in order until none is free, then staging of the
+    // binary64 couplings (quantisation and packing happen on the device)
+    int took = 0;
+    for (; took < count; ++took) {
+      const int r = took;
       const int n = ns[r];
-      if (n < 1 || n > s->cfg.max_n) return fail(PIM_ERR_INVALID, "request %d: n = %d outside [1, %d]", r, n, s->cfg.max_n);
-      if (ids[r] >= (1u << 24)) return fail(PIM_ERR_INVALID, "request id must be < 2^24");
+      if (n < 1 || n > s->cfg.max_n || ids[r] >= (1u << 24) || !J[r])
+        return fail(PIM_ERR_INVALID, "request %d (id %u): n outside [1, max_n], id >= 2^24 or J NULL", r, ids[r]);
       const double* Jr = J[r];
       const double* hr = h ? h[r] : nullptr;
       for (int i = 0; i < n; ++i) {
-        if (Jr[(size_t)i * n + i] != 0.0) return fail(PIM_ERR_INVALID, "request %d: J diagonal must be zero", r);
-        if (hr && !std::isfinite(hr[i])) return fail(PIM_ERR_INVALID, "request %d: h is not finite", r);
-        for (int j = 0; j < n; ++j)
-          if (!std::isfinite(Jr[(size_t)i * n + j]) || Jr[(size_t)i * n + j] != Jr[(size_t)j * n + i])
-            return fail(PIM_ERR_INVALID, "request %d: J must be finite and symmetric", r);
+        const double* row = Jr + (size_t)i * n;
+        bool ok = row[i] == 0.0 && (!hr || std::isfinite(hr[i]));
+        for (int j = i + 1; j < n && ok; ++j) ok = std::isfinite(row[j]) && row[j] == Jr[(size_t)j * n + i];
+        if (!ok)
+          return fail(PIM_ERR_INVALID, "request %d (id %u): J must be finite and symmetric with a zero diagonal, "
+                      "h finite", r, ids[r]);
       }
       const int cls = (n + 31) / 32 - 1;
       Chunk* c = chunk_for(s, cls);
       if (!c) break;  // no slot: the caller polls and submits the rest later
-      const Klass& k = s->classes[cls];
-      const size_t np = k.npad, slot = c->count;
-      const float scale = real_scale(Jr, (size_t)n * n, s->cfg.prec);
-      pack_real_fragments(Jr, n, k.nt, s->cfg.prec, scale, c->h_frag + slot * k.frag);
-      c->h_scale[slot] = scale;
-      float* hf = c->h_hf + slot * np;
-      double* h64 = c->h_h64 + slot * np;
-      double* j64 = c->h_j64 + slot * np * np;
-      std::fill(hf, hf + np, 0.0f);
-      std::fill(h64, h64 + np, 0.0);
-      std::fill(j64, j64 + np * np, 0.0);
-      for (int i = 0; i < n; ++i) {
-        if (hr) {
-          hf[i] = (float)hr[i];
-          h64[i] = hr[i];
-        }
-        std::memcpy(j64 + (size_t)i * np, Jr + (size_t)i * n, n * sizeof(double));
+      const size_t np = s->classes[cls].npad, sl = c->count;
+      if (c->count == 0) c->first = std::chrono::steady_clock::now();
+      double* h64 = c->h_h64 + sl * np;
+      double* j64 = c->h_j64 + sl * np * np;
+      if (hr) std::memcpy(h64, hr, n * sizeof(double));
+      else std::fill(h64, h64 + n, 0.0);
+      std::fill(h64 + n, h64 + np, 0.0);
+      if ((size_t)n == np) {
+        std::memcpy(j64, Jr, (size_t)n * n * sizeof(double));
+      } else {
+        std::fill(j64, j64 + np * np, 0.0);
+        for (int i = 0; i < n; ++i) std::memcpy(j64 + (size_t)i * np, Jr + (size_t)i * n, n * sizeof(double));
       }
-      c->h_sid[slot] = ids[r];
+      c->h_sid[sl] = ids[r];
       c->ids.push_back(ids[r]);
       c->ns.push_back(n);
       ++c->count;
-      ++*admitted;
     }
+    *admitted = took;
     return PIM_OK;
   } catch (const std::bad_alloc&) {
     return fail(PIM_ERR_NOMEM, "host allocation failed");
@@ -381,10 +451,16 @@ pim_status pim_server_flush(pim_server* s, int32_t* launched) {
   try {
     if (!s) return fail(PIM_ERR_INVALID, "server is NULL");
     int total = 0;
+    const auto now = std::chrono::steady_clock::now();
+    const double wait = s->cfg.max_wait_us;
     for (Klass& k : s->classes) {
-      k.open = -1;
-      for (Chunk* c : k.chunks) {
+      for (size_t ci = 0; ci < k.chunks.size(); ++ci) {
+      Chunk* c = k.chunks[ci];
       if (c->launched || c->count == 0) continue;
+      // a partly filled chunk waits for company up to max_wait_us
+      const double age = std::chrono::duration<double, std::micro>(now - c->first).count();
+      if (c->count < s->cfg.max_batch && wait > 0.0 && age < wait) continue;
+      if (k.open == (int)ci) k.open = -1;
       hipStream_t st = s->streams[s->next_stream];
       s->next_stream = (s->next_stream + 1) % (int)s->streams.size();
       hipError_t e = launch_chunk(s, c, st);

@@ -384,9 +384,112 @@ hipError_t launch_p(const SweepRealArgs& a, int count, int nt, hipStream_t s) {
   }
 }
 
+// Device quantisers: the same round-to-nearest-even from binary64 as the host
+// ones (frexp, ldexp and rint are exact), so both produce identical codes.
+__device__ uint8_t d_fp8(double x) {
+  if (x == 0.0 || isnan(x)) return 0;
+  const uint8_t sign = x < 0.0 ? 0x80 : 0x00;
+  const double a = fabs(x);
+  if (a >= 448.0) return sign | 0x7E;
+  if (a < 0.015625) return sign | (uint8_t)rint(a * 512.0);
+  int e;
+  (void)frexp(a, &e);
+  int E = e - 1;
+  double q = rint(ldexp(a, 3 - E));
+  if (q == 16.0) {
+    q = 8.0;
+    ++E;
+  }
+  if (E > 8 || (E == 8 && q > 14.0)) return sign | 0x7E;
+  return sign | (uint8_t)(((E + 7) << 3) | ((int)q - 8));
+}
+
+__device__ uint16_t d_bf16(double x) {
+  if (x == 0.0 || isnan(x)) return 0;
+  const uint16_t sign = x < 0.0 ? 0x8000 : 0x0000;
+  const double a = fabs(x);
+  int e;
+  (void)frexp(a, &e);
+  int E = e - 1;
+  if (E < -126) return sign | (uint16_t)rint(ldexp(a, 133));
+  double q = rint(ldexp(a, 7 - E));
+  if (q == 256.0) {
+    q = 128.0;
+    ++E;
+  }
+  if (E > 127) return sign | 0x7F80;
+  return sign | (uint16_t)(((E + 127) << 7) | ((int)q - 128));
+}
+
+// One block per instance: scale = max|J| / 448 (FP8, rounded to binary32) or
+// the power of two with max|J| / scale in [1, 2) (BF16); J / scale quantised
+// into the fragment order of pack_real_fragments; h converted to binary32.
+// J and h are the instance's binary64 values, zero-padded to npad.
+template <int PREC>
+__global__ __launch_bounds__(256) void pack_real_kernel(RealPackArgs a) {
+  __shared__ double red[256];
+  const int inst = blockIdx.x;
+  const int np = a.npad, nt = np / 32;
+  const double* J = a.j64 + (size_t)inst * np * np;
+  double m = 0.0;
+  for (int i = threadIdx.x; i < np * np; i += 256) m = fmax(m, fabs(J[i]));
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  m = red[0];
+  float scale = 1.0f;
+  if (m > 0.0) {
+    if (PREC == PIM_PREC_FP8) {
+      scale = (float)(m / 448.0);
+    } else {
+      int e;
+      (void)frexp(m, &e);
+      scale = (float)ldexp(1.0, e - 1);
+    }
+  }
+  if (threadIdx.x == 0) a.scale[inst] = scale;
+  auto row_of = [](int mt, int r) { return 32 * mt + 16 * ((r >> 2) & 1) + 4 * (r >> 3) + (r & 3); };
+  uint8_t* out = a.frag + (size_t)inst * a.frag_bytes;
+  if (PREC == PIM_PREC_FP8) {
+    const int nk = (nt + 1) / 2;
+    const int total = nt * nk * 64 * 32;
+    for (int b = threadIdx.x; b < total; b += 256) {
+      const int p = b & 31, l = (b >> 5) & 63, blk = b >> 11;  // blk = mt * nk + kk
+      const int mt = blk / nk, kk = blk % nk;
+      const int row = row_of(mt, l & 31);
+      const int colj = 32 * (2 * kk + p / 16) + 16 * (l >> 5) + (p % 16);
+      const double v = (colj < np) ? J[(size_t)row * np + colj] / (double)scale : 0.0;
+      out[b] = d_fp8(v);
+    }
+  } else {
+    uint16_t* o16 = reinterpret_cast<uint16_t*>(out);
+    const int total = nt * nt * 2 * 64 * 8;
+    for (int b = threadIdx.x; b < total; b += 256) {
+      const int p = b & 7, l = (b >> 3) & 63, blk = b >> 9;  // blk = (mt * nt + kt) * 2 + j
+      const int j = blk & 1, kt = (blk >> 1) % nt, mt = (blk >> 1) / nt;
+      const int row = row_of(mt, l & 31);
+      const int colj = 32 * kt + 16 * (l >> 5) + 8 * j + p;
+      o16[b] = d_bf16(J[(size_t)row * np + colj] / (double)scale);
+    }
+  }
+  for (int i = threadIdx.x; i < np; i += 256) a.hf[(size_t)inst * np + i] = (float)a.h64[(size_t)inst * np + i];
+}
+
 }  // namespace
 
 size_t real_frag_bytes(int prec, int nt) { return frag_bytes(prec, nt); }
+
+hipError_t launch_pack_real(const RealPackArgs& a, int prec, hipStream_t s) {
+  if (a.count < 1) return hipSuccess;
+  if (a.npad < 32 || a.npad > PIM_MAX_N_LDS || a.npad % 32) return hipErrorInvalidValue;
+  if (prec == PIM_PREC_FP8) hipLaunchKernelGGL(pack_real_kernel<PIM_PREC_FP8>, dim3(a.count), dim3(256), 0, s, a);
+  else if (prec == PIM_PREC_BF16) hipLaunchKernelGGL(pack_real_kernel<PIM_PREC_BF16>, dim3(a.count), dim3(256), 0, s, a);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
 
 hipError_t launch_sweep_real(const SweepRealArgs& a, int count, int nt, int prec, bool has_h, hipStream_t s) {
   if (a.npad != nt * 32 || a.R < 1) return hipErrorInvalidValue;
