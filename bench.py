@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--plain-instances", type=int, default=8,
                     help="instances run through the plain FP32 per-instance kernel for the comparison "
                          "(0 = skip); trajectories are bit-identical, so TTS99 is equal")
+    ap.add_argument("--core-only", action="store_true",
+                    help="only the SK-1 N=200 sweep (no plain, MIMO, serving, uneven-N, comparison or CPU legs)")
     ap.add_argument("--no-mimo", action="store_true", help="skip the MIMO detection leg")
     ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-N batched leg")
     ap.add_argument("--no-serving", action="store_true", help="skip the MIMO serving leg")
@@ -403,6 +405,9 @@ def comparison_leg():
 
 def main():
     args = parse()
+    if args.core_only:
+        args.no_mimo = args.no_serving = args.no_uneven = args.no_compare = args.no_cpu_baseline = True
+        args.plain_instances = 0
     if args.copy_probe:
         copy_probe(args.copy_probe)
         return
