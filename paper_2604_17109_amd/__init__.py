@@ -17,6 +17,10 @@ import ctypes
 import os
 
 import numpy as np
+# torch first: its HIP runtime must be the one libpim.so binds to, or a
+# process that loads the library before touching torch ends up with two
+# runtimes and the library's sees no device
+import torch  # noqa: F401
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpim.so")
