@@ -191,7 +191,7 @@ hipError_t launch_sweep_mfma(const SweepArgs& a, int count, int nt, bool has_h, 
 hipError_t launch_sweep_plain(const PlainArgs& a, bool real, hipStream_t s);
 // 256 < N <= 1024: couplings streamed from global memory, spins in LDS.
 hipError_t launch_sweep_big(const SweepArgs& a, int count, int nt, bool has_h, hipStream_t s);
-int big_tiles(int n);  // row tiles of the streamed kernel (a multiple of 4)
+int big_tiles(int n);  // row tiles of the streamed kernel: ceil(n / 32)
 hipError_t launch_sweep_seq(const SeqArgs& a, int count, int nt, bool has_h, hipStream_t s);
 hipError_t launch_sweep_real(const SweepRealArgs& a, int count, int nt, int prec, bool has_h, hipStream_t s);
 size_t real_frag_bytes(int prec, int nt);

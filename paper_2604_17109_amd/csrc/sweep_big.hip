@@ -1,17 +1,25 @@
 // PIMI sweep on int8 MFMA for 256 < N <= 1024, where N^2 bytes of couplings no
-// longer fit in LDS.
+// longer fit in LDS and the step is a true dense contraction
+// I[N x R] = J[N x N] . S[N x R] (Eq. (2)) that has to stream J.
 //
-// One workgroup = 4 waves sharing one block of 32 trials of one instance.
-// Wave w owns the row tiles mt = w, w + 4, w + 8, ...; each row tile's field
-// (Eq. (2)) is a chain of NT v_mfma_i32_32x32x32_i8 over the K tiles, with the
-// A fragments (the same permuted fragment order as the LDS-resident kernel)
-// read from global memory (L2 / the last-level cache) and the B operand, the
-// current spins of all 32 trials, read from an LDS spin buffer that the four
-// waves fill together: each wave writes the new spins of its own row tiles
-// into the other half of a double buffer, and one workgroup barrier per step
-// makes s(t+1) complete.  Decisions (Eq. (4)) use the same integer
-// (u, s) threshold table, shared by the workgroup and double-buffered in LDS;
-// the energy (Eq. (1)) of each trial is reduced over the waves in LDS.
+// One workgroup = 8 waves (two per SIMD) on 128 trials (four 32-trial column
+// blocks) of one instance.  The waves split the row tiles: wave w owns row
+// tiles mt = w, w + 8, w + 16, w + 24.  For a row tile the wave runs the
+// contraction of all four column blocks at once: every A fragment of J (read
+// from global memory, i.e. L2 / the last-level cache) feeds four
+// v_mfma_i32_32x32x32_i8, so J is read once per workgroup and step for 128
+// trials.  The B operand, the spins s(t) of the 128 trials, lives in one LDS
+// buffer that every wave reads.
+//
+// A step runs in two phases separated by workgroup barriers:
+//   1. contraction and decisions (Eq. (4)) of the wave's row tiles; the new
+//      spins s(t+1) stay in registers, the per-trial partial energies
+//      (Eq. (1)) go to LDS;
+//   -- barrier: every wave has finished reading s(t) --
+//   2. energies of s(t) reduced over the waves, best-state bookkeeping (s(t)
+//      is still in LDS), then s(t+1) and the next step's threshold table are
+//      written in place;
+//   -- barrier: s(t+1) is complete --
 //
 // Workgroups are mapped so that all blocks of one instance run on one XCD
 // (hardware dispatch sends consecutive workgroups to consecutive XCDs), which
@@ -30,9 +38,13 @@ namespace {
 typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 
-constexpr int kWaves = 4;
+constexpr int kWaves = 8;            // two waves per SIMD
+constexpr int kCB = 4;               // 32-trial column blocks per workgroup
+constexpr int kTrialsWG = 32 * kCB;  // trials per workgroup
 constexpr int kXcds = 8;
 constexpr int kTabBytes = kTabEntries * 2;
+constexpr int kMinTiles = PIM_MAX_N_LDS / 32 + 1;  // 9
+constexpr int kMaxTiles = PIM_MAX_N / 32;          // 32
 
 #define PIM_FENCE(v) asm volatile("" : "+v"(v))
 
@@ -45,33 +57,77 @@ __device__ __forceinline__ Ctr4 noise_block(uint32_t block, int tg, uint32_t tri
   return philox4x32_10(Ctr4{block, (uint32_t)tg, trial, (kDomainNoise << 24) | stream}, k0, k1);
 }
 
-// Field of row tile mt: A fragments from global memory, B from the LDS spin
-// buffer (tile kt of lane l at (kt * 64 + l)).
-template <int NT>
-__device__ __forceinline__ v16i big_row_tile(const v4i* __restrict__ gA, const v4i* sB, int lane, int mt) {
-  v16i acc = v16i{};
-  const v4i* a = gA + (size_t)mt * NT * 64 + lane;
-  // partial unroll: a full unroll lets the compiler hoist all 2 NT operand
-  // loads ahead of the chain, which does not fit the register file at large NT
-#pragma unroll 4
-  for (int kt = 0; kt < NT; ++kt) acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[kt * 64], sB[kt * 64 + lane], acc, 0, 0, 0);
-  return acc;
+// LDS spin buffer: tile kt of column block c, lane l at ((kt * kCB + c) * 64 + l).
+__device__ __forceinline__ int sb_index(int kt, int c, int lane) { return (kt * kCB + c) * 64 + lane; }
+
+// Field of row tile mt for the four column blocks: nt K steps, each one A
+// fragment from global memory and four B fragments from LDS.
+//
+// The A fragments stream through a four-slot register ring: K step kt uses
+// slot kt % 4 and, right after its MFMAs are issued, refills that slot with
+// the fragment four K steps ahead.  Past the end of the row the stream
+// continues into the next row tile the wave owns (mt_next; after the wave's
+// last row tile, its first one of the next step, whose couplings do not
+// depend on the spins): the last four K steps, which cover every slot once,
+// load K steps 0..3 of mt_next into the slots those steps use.  So no row
+// tile starts on a cold global load.  Every index stays inside the instance's
+// fragments.  The B fragments of the next K step are read into the same
+// registers right after the MFMAs that consume them are issued.  The K steps
+// run in unconditional groups of four followed by a tail of at most three;
+// a scheduling barrier per K step keeps the compiler from hoisting more
+// operand loads than these registers.
+__device__ __forceinline__ void big_row_tile(const v4i* __restrict__ gAl, const v4i* sB, int lane, int mt,
+                                             int mt_next, int nt, v4i (&ar)[4], v16i (&acc)[kCB]) {
+#pragma unroll
+  for (int c = 0; c < kCB; ++c) acc[c] = v16i{};
+  v4i b[kCB];
+#pragma unroll
+  for (int c = 0; c < kCB; ++c) b[c] = sB[sb_index(0, c, lane)];
+  // fragment indices are wave-uniform (scalar); one 64-bit add per load
+  const int fa = mt * nt, fn = mt_next * nt;
+  const int nfull = nt & ~3;
+  int kt = 0;
+  for (; kt < nfull; kt += 4) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+#pragma unroll
+      for (int c = 0; c < kCB; ++c) acc[c] = __builtin_amdgcn_mfma_i32_32x32x32_i8(ar[i], b[c], acc[c], 0, 0, 0);
+      // refill the slot after its last use, so the load lands in place
+      const int f = (kt + i + 4 < nt) ? fa + kt + i + 4 : fn + i;
+      ar[i] = gAl[(size_t)f * 64];
+      const int kn = min(kt + i + 1, nt - 1);
+#pragma unroll
+      for (int c = 0; c < kCB; ++c) b[c] = sB[sb_index(kn, c, lane)];
+      __builtin_amdgcn_sched_barrier(0);
+    }
+  }
+  // tail: the last nt - nfull (< 4) K steps, in ring slots 0, 1, 2
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    if (kt + i < nt) {  // uniform
+#pragma unroll
+      for (int c = 0; c < kCB; ++c) acc[c] = __builtin_amdgcn_mfma_i32_32x32x32_i8(ar[i], b[c], acc[c], 0, 0, 0);
+      ar[i] = gAl[(size_t)(fn + i) * 64];  // kt + i + 4 >= nt here
+      if (kt + i + 1 < nt) {
+#pragma unroll
+        for (int c = 0; c < kCB; ++c) b[c] = sB[sb_index(kt + i + 1, c, lane)];
+      }
+    }
+  }
 }
 
-template <int NT, bool HAS_H>
-__global__ __launch_bounds__(64 * kWaves) void sweep_big_kernel(SweepArgs a, int blocks_per_inst) {
+template <int RPW, bool HAS_H>
+__global__ __launch_bounds__(64 * kWaves, 2) void sweep_big_kernel(SweepArgs a, int nt, int blocks_per_inst) {
   extern __shared__ __align__(16) unsigned char lds[];
-  constexpr int kNpad = NT * 32;
-  constexpr int kPerWave = NT / kWaves;  // row tiles per wave
-  // LDS: spins [2][NT][64] x 16 B | table [2] x 1 KB | energy partials
-  // [2][4][32] | cancel flag | h.  Spins, tables and partials are double-
-  // buffered by step parity, so one barrier per step orders everything: a
-  // buffer is rewritten two steps after it was read, and every wave has
-  // passed the intervening barrier.
+  const int npad = nt * 32;
+  // LDS: spins [nt][kCB][64] x 16 B | table 1 KB | energy partials
+  // [kWaves][kCB][32] | per-trial t_best, first_hit, e_cur [3][kCB][32] |
+  // cancel flag | h
   v4i* sB = reinterpret_cast<v4i*>(lds);
-  int16_t* sTab = reinterpret_cast<int16_t*>(lds + 2 * NT * 1024);
-  int32_t* sE = reinterpret_cast<int32_t*>(lds + 2 * NT * 1024 + 2 * kTabBytes);
-  int32_t* sFlag = sE + 2 * kWaves * 32;
+  int16_t* sTab = reinterpret_cast<int16_t*>(lds + (size_t)nt * kCB * 1024);
+  int32_t* sE = reinterpret_cast<int32_t*>(lds + (size_t)nt * kCB * 1024 + kTabBytes);
+  int32_t* sStat = sE + kWaves * kCB * 32;
+  int32_t* sFlag = sStat + 3 * kCB * 32;
   int32_t* sH = sFlag + 4;
 
   // workgroup -> (instance, trial block): the blocks of instance k all have
@@ -80,188 +136,251 @@ __global__ __launch_bounds__(64 * kWaves) void sweep_big_kernel(SweepArgs a, int
   const int inst = (lin % kXcds) + kXcds * ((lin / kXcds) / blocks_per_inst);
   const int tblk = (lin / kXcds) % blocks_per_inst;
   if (inst >= a.count) return;  // whole workgroup: before any barrier
-  const int wave = threadIdx.x >> 6;
+  // wave index made scalar: every row-tile index below is wave-uniform
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const int col = lane & 31;
   const int half = lane >> 5;
-  const int trial = tblk * 32 + col;
-  const bool live = trial < a.R;
-  const size_t cell = (size_t)inst * a.R + trial;
+  // trial of column block c: trial0 + 32 c (recomputed where used, which
+  // keeps the per-lane bookkeeping out of the register budget)
+  const int trial0 = tblk * kTrialsWG + col;
+  const size_t cell0 = (size_t)inst * a.R + trial0;
+  // the writer of the per-trial statistics: one lane per trial
+  const bool writer = wave == 0 && half == 0;
   const uint32_t stream = a.inst_stream[inst];
   const int cls = a.inst_class[inst];
   const uint4* gTab4 = reinterpret_cast<const uint4*>(a.thtab + (size_t)cls * a.T * kTabEntries);
   const int32_t target = a.target ? a.target[inst] : INT_MIN;
   const uint32_t k0 = a.k0, k1 = a.k1;
-  const v4i* gA = reinterpret_cast<const v4i*>(a.jfrag + (size_t)inst * NT * NT * 1024);
+  // this lane's view of the instance's A fragments: fragment f at gAl[f * 64]
+  const v4i* gAl = reinterpret_cast<const v4i*>(a.jfrag + (size_t)inst * nt * nt * 1024) + lane;
 
   if (HAS_H)
-    for (int i = threadIdx.x; i < kNpad; i += 64 * kWaves) sH[i] = a.h[(size_t)inst * kNpad + i];
+    for (int i = threadIdx.x; i < npad; i += 64 * kWaves) sH[i] = a.h[(size_t)inst * npad + i];
   // s(0): each wave its own row tiles
 #pragma unroll
-  for (int j = 0; j < kPerWave; ++j) {
+  for (int j = 0; j < RPW; ++j) {
     const int mt = wave + kWaves * j;
-    v4i v;
-    if (a.init) {
-      v = live ? *reinterpret_cast<const v4i*>(a.init + cell * kNpad + 32 * mt + 16 * half)
-               : v4i{0x01010101, 0x01010101, 0x01010101, 0x01010101};
-    } else {
-      const Ctr4 x = philox4x32_10(Ctr4{(uint32_t)(2 * mt + half), 0u, (uint32_t)trial,
-                                        (kDomainInit << 24) | stream}, k0, k1);
-      v = v4i{spins_from_bits(x.x), spins_from_bits(x.y), spins_from_bits(x.z), spins_from_bits(x.w)};
+    if (mt >= nt) break;  // uniform
+#pragma unroll
+    for (int c = 0; c < kCB; ++c) {
+      v4i v;
+      if (a.init) {
+        v = (trial0 + 32 * c < a.R) ? *reinterpret_cast<const v4i*>(a.init + (cell0 + 32 * c) * npad + 32 * mt + 16 * half)
+                    : v4i{0x01010101, 0x01010101, 0x01010101, 0x01010101};
+      } else {
+        const Ctr4 x = philox4x32_10(Ctr4{(uint32_t)(2 * mt + half), 0u, (uint32_t)(trial0 + 32 * c),
+                                          (kDomainInit << 24) | stream}, k0, k1);
+        v = v4i{spins_from_bits(x.x), spins_from_bits(x.y), spins_from_bits(x.z), spins_from_bits(x.w)};
+      }
+      sB[sb_index(mt, c, lane)] = v;
     }
-    sB[mt * 64 + lane] = v;
   }
   if (wave == 0) reinterpret_cast<uint4*>(sTab)[lane] = gTab4[lane];
   if (threadIdx.x == 0) sFlag[0] = 0;
+  if (writer)
+#pragma unroll
+    for (int c = 0; c < kCB; ++c) {
+      sStat[(0 * kCB + c) * 32 + col] = -1;  // t_best
+      sStat[(1 * kCB + c) * 32 + col] = -1;  // first_hit
+      sStat[(2 * kCB + c) * 32 + col] = 0;   // e_cur
+    }
   __syncthreads();
 
-  int32_t e_best = INT_MAX, t_best = -1, first_hit = -1, e_cur = 0;
+  int32_t e_best[kCB];
+#pragma unroll
+  for (int c = 0; c < kCB; ++c) e_best[c] = INT_MAX;
   int done = a.T;
-  int cur = 0;
+  // A-fragment ring: the first four K steps of the wave's first row tile
+  v4i ar[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) ar[i] = gAl[(size_t)wave * nt * 64 + (size_t)i * 64];  // nt >= 9 > wave
+  // centre of the step table: entry idx in [-256, 256) holds the field
+  // threshold for (u, s) with idx = u ^ s (s = +1 -> u ^ 1, s = -1 -> ~u)
+  const int16_t* tab = sTab + kNoiseVals;
   for (int t = 0;; ++t) {
     const int tg = a.start_step + t;
-    const v4i* sCur = sB + cur * NT * 64;
-    v4i* sNxt = sB + (cur ^ 1) * NT * 64;
-    const int16_t* tab = sTab + (t & 1) * kTabEntries + kNoiseVals;
-    // wave 0 fetches the table of step t+1 (written before this step's barrier)
+    // wave 0 fetches the table of step t+1 (written after the first barrier)
     uint4 nxt = uint4{0, 0, 0, 0};
     if (wave == 0) nxt = gTab4[(size_t)min(t + 1, a.T - 1) * 64 + lane];
-    int32_t ep = 0;
-    Ctr4 x_next = noise_block(2u * wave + half, tg, (uint32_t)trial, stream, k0, k1);
-    v16i acc_next = big_row_tile<NT>(gA, sCur, lane, wave);
+    int32_t ep[kCB];
+    v4i Bn[RPW][kCB];
 #pragma unroll
-    for (int j = 0; j < kPerWave; ++j) {
+    for (int c = 0; c < kCB; ++c) ep[c] = 0;
+    // counter words and lane offsets re-materialised each step through
+    // fences: otherwise the loop-invariant parts of every (row tile, column
+    // block) noise block and LDS address are hoisted out of the step loop
+    // into registers this kernel does not have
+    uint32_t ctr_half = (uint32_t)half, ctr_trial = (uint32_t)trial0;
+    int lane_off = lane;
+    PIM_FENCE(ctr_half);
+    PIM_FENCE(ctr_trial);
+    PIM_FENCE(lane_off);
+    // ---- phase 1: contraction and decisions of the wave's row tiles ----
+#pragma unroll
+    for (int j = 0; j < RPW; ++j) {
       const int mt = wave + kWaves * j;
-      const v16i acc = acc_next;
-      uint32_t xw[4] = {x_next.x, x_next.y, x_next.z, x_next.w};
-      const v4i cv = sCur[mt * 64 + lane];
-      uint32_t bw[4] = {(uint32_t)cv[0], (uint32_t)cv[1], (uint32_t)cv[2], (uint32_t)cv[3]};
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        PIM_FENCE(xw[q]);
-        PIM_FENCE(bw[q]);
-      }
-      int th[16];
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int sv = (int)(int8_t)(bw[r >> 2] >> (8 * (r & 3)));
-        th[r] = tab[(int)((xw[r >> 2] >> (8 * (r & 3))) & 0xFFu) ^ sv];
-      }
-      if (j + 1 < kPerWave) {
-        acc_next = big_row_tile<NT>(gA, sCur, lane, mt + kWaves);
-        x_next = noise_block(2u * (mt + kWaves) + half, tg, (uint32_t)trial, stream, k0, k1);
-      }
+      if (mt >= nt) break;  // uniform
+      v16i acc[kCB];
+      const int mt_next = mt + kWaves < nt ? mt + kWaves : wave;
+      big_row_tile(gAl, sB, lane_off, mt, mt_next, nt, ar, acc);
       const int hoff = 32 * mt + 16 * half;
-      v4i o;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        int d[4];
+      for (int c = 0; c < kCB; ++c) {
+        const Ctr4 x = noise_block(2u * mt + ctr_half, tg, ctr_trial + 32u * c, stream, k0, k1);
+        uint32_t xw[4] = {x.x, x.y, x.z, x.w};
+        const v4i cv = sB[sb_index(mt, c, lane_off)];
+        uint32_t bw[4] = {(uint32_t)cv[0], (uint32_t)cv[1], (uint32_t)cv[2], (uint32_t)cv[3]};
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-          const int r = 4 * q + b;
-          const int sv = (int)(int8_t)(bw[q] >> (8 * b));
-          int I = acc[r];
-          int v = I;
-          if (HAS_H) {
-            const int hv = sH[hoff + r];
-            I += hv;
-            v = I + hv;
-          }
-          ep += __mul24(sv, v);
-          d[b] = I - th[r];
+        for (int q = 0; q < 4; ++q) {
+          PIM_FENCE(xw[q]);
+          PIM_FENCE(bw[q]);
         }
-        const uint32_t p01 = __builtin_amdgcn_perm((uint32_t)d[1], (uint32_t)d[0], 0x0C0C0B09u);
-        const uint32_t p23 = __builtin_amdgcn_perm((uint32_t)d[3], (uint32_t)d[2], 0x0B090C0Cu);
-        o[q] = (int)(p01 | p23 | 0x01010101u);
+        int th[16];
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int sv = (int)(int8_t)(bw[r >> 2] >> (8 * (r & 3)));
+          th[r] = tab[(int)((xw[r >> 2] >> (8 * (r & 3))) & 0xFFu) ^ sv];
+        }
+        // h of this row tile re-read for every column block (fenced offset)
+        int hoff_c = hoff;
+        if (HAS_H) PIM_FENCE(hoff_c);
+        v4i o;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          int d[4];
+#pragma unroll
+          for (int b = 0; b < 4; ++b) {
+            const int r = 4 * q + b;
+            const int sv = (int)(int8_t)(bw[q] >> (8 * b));
+            int I = acc[c][r];
+            int v = I;
+            if (HAS_H) {
+              const int hv = sH[hoff_c + r];
+              I += hv;
+              v = I + hv;
+            }
+            ep[c] += __mul24(sv, v);  // |v| < 2^23
+            d[b] = I - th[r];         // >= 0  <=>  s(t+1) = +1
+          }
+          // sign bytes of d via byte-permute sign replication, | 0x01 -> +1 / -1
+          const uint32_t p01 = __builtin_amdgcn_perm((uint32_t)d[1], (uint32_t)d[0], 0x0C0C0B09u);
+          const uint32_t p23 = __builtin_amdgcn_perm((uint32_t)d[3], (uint32_t)d[2], 0x0B090C0Cu);
+          o[q] = (int)(p01 | p23 | 0x01010101u);
+        }
+        Bn[j][c] = o;
+        PIM_FENCE(ep[c]);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) PIM_FENCE(Bn[j][c][q]);
+        // one column block's decisions at a time (bounds the live temporaries)
+        __builtin_amdgcn_sched_barrier(0);
       }
-      sNxt[mt * 64 + lane] = o;
-      PIM_FENCE(ep);
-      __builtin_amdgcn_sched_barrier(0);
     }
-    // per-trial partial energy of this wave's rows (both lane halves)
-    const int32_t epc = ep + __shfl_xor(ep, 32);
-    int32_t* sEt = sE + (t & 1) * kWaves * 32;
-    if (half == 0) sEt[wave * 32 + col] = epc;
-    if (wave == 0) reinterpret_cast<uint4*>(sTab + ((t + 1) & 1) * kTabEntries)[lane] = nxt;
+    // per-trial partial energies of this wave's rows (both lane halves)
+#pragma unroll
+    for (int c = 0; c < kCB; ++c) {
+      const int32_t epc = ep[c] + __shfl_xor(ep[c], 32);
+      if (half == 0) sE[(wave * kCB + c) * 32 + col] = epc;
+    }
     if (threadIdx.x == 0 && (t & 255) == 0 && t < a.T)
       sFlag[0] = __atomic_load_n(a.cancel, __ATOMIC_RELAXED) != 0 ? 1 : 0;
-    __syncthreads();  // s(t+1), the energies of s(t) and the next table are complete
-    int32_t tot = 0;
+    __syncthreads();  // every read of s(t) and of the table is done; energies of s(t) complete
+    // ---- phase 2: energies, bookkeeping, s(t+1) in place ----
 #pragma unroll
-    for (int w = 0; w < kWaves; ++w) tot += sEt[w * 32 + col];
-    const int32_t E = -(tot / 2);
-    if (E < e_best) {
-      e_best = E;
-      t_best = tg;
-      if (live) {
+    for (int c = 0; c < kCB; ++c) {
+      int32_t tot = 0;
 #pragma unroll
-        for (int j = 0; j < kPerWave; ++j) {
-          const int mt = wave + kWaves * j;
-          *reinterpret_cast<v4i*>(a.best_s + cell * kNpad + 32 * mt + 16 * half) = sCur[mt * 64 + lane];
+      for (int w = 0; w < kWaves; ++w) tot += sE[(w * kCB + c) * 32 + col];
+      const int32_t E = -(tot / 2);
+      if (E < e_best[c]) {
+        e_best[c] = E;
+        if (writer) sStat[(0 * kCB + c) * 32 + col] = tg;
+        if ((trial0 + 32 * c < a.R)) {
+#pragma unroll
+          for (int j = 0; j < RPW; ++j) {
+            const int mt = wave + kWaves * j;
+            if (mt < nt)
+              *reinterpret_cast<v4i*>(a.best_s + (cell0 + 32 * c) * npad + 32 * mt + 16 * half) = sB[sb_index(mt, c, lane)];
+          }
         }
       }
+      if (writer) {
+        if (sStat[(1 * kCB + c) * 32 + col] < 0 && E <= target) sStat[(1 * kCB + c) * 32 + col] = tg;
+        sStat[(2 * kCB + c) * 32 + col] = E;
+      }
     }
-    if (first_hit < 0 && E <= target) first_hit = tg;
-    e_cur = E;
-    if (t == a.T) break;  // uniform
-    const bool stop = (t & 255) == 0 && sFlag[0] != 0;  // uniform: read after the barrier
+    if (t == a.T) break;  // uniform: s(T) stays in LDS
+    const bool stop = (t & 255) == 0 && sFlag[0] != 0;  // uniform: written before the barrier
     if (stop) {
-      done = t;
+      done = t;  // s(t) stays the final state
       break;
     }
-    cur ^= 1;
-  }
-  // final state: s(t) of the last step (in sCur)
-  if (live) {
-    const v4i* sCur = sB + cur * NT * 64;
 #pragma unroll
-    for (int j = 0; j < kPerWave; ++j) {
+    for (int j = 0; j < RPW; ++j) {
       const int mt = wave + kWaves * j;
-      *reinterpret_cast<v4i*>(a.final_s + cell * kNpad + 32 * mt + 16 * half) = sCur[mt * 64 + lane];
+      if (mt >= nt) break;
+#pragma unroll
+      for (int c = 0; c < kCB; ++c) sB[sb_index(mt, c, lane)] = Bn[j][c];
     }
-    if (wave == 0 && half == 0) {
-      a.e_best[cell] = e_best;
-      a.t_best[cell] = t_best;
-      a.first_hit[cell] = first_hit;
-      a.e_final[cell] = e_cur;
-      a.steps_done[cell] = done;
+    if (wave == 0) reinterpret_cast<uint4*>(sTab)[lane] = nxt;
+    __syncthreads();  // s(t+1) and the table of step t+1 are complete
+  }
+  // final state: the s(t) left in LDS
+#pragma unroll
+  for (int c = 0; c < kCB; ++c) {
+    if (!(trial0 + 32 * c < a.R)) continue;
+#pragma unroll
+    for (int j = 0; j < RPW; ++j) {
+      const int mt = wave + kWaves * j;
+      if (mt < nt)
+        *reinterpret_cast<v4i*>(a.final_s + (cell0 + 32 * c) * npad + 32 * mt + 16 * half) = sB[sb_index(mt, c, lane)];
+    }
+    if (writer) {
+      a.e_best[cell0 + 32 * c] = e_best[c];
+      a.t_best[cell0 + 32 * c] = sStat[(0 * kCB + c) * 32 + col];
+      a.first_hit[cell0 + 32 * c] = sStat[(1 * kCB + c) * 32 + col];
+      a.e_final[cell0 + 32 * c] = sStat[(2 * kCB + c) * 32 + col];
+      a.steps_done[cell0 + 32 * c] = done;
     }
   }
 }
 
-template <int NT, bool HAS_H>
-hipError_t launch_nt(const SweepArgs& a, int count, hipStream_t s) {
-  const size_t lds = 2 * (size_t)NT * 1024 + 2 * kTabBytes + (2 * kWaves * 32 + 4) * 4 + (HAS_H ? NT * 32 * 4 : 0);
-  auto kern = sweep_big_kernel<NT, HAS_H>;
+size_t big_lds_bytes(int nt, bool has_h) {
+  return (size_t)nt * kCB * 1024 + kTabBytes + (size_t)(kWaves + 3) * kCB * 32 * 4 + 16 +
+         (has_h ? (size_t)nt * 32 * 4 : 0);
+}
+
+template <int RPW, bool HAS_H>
+hipError_t launch_rpw(const SweepArgs& a, int count, int nt, hipStream_t s) {
+  const size_t lds = big_lds_bytes(nt, HAS_H);
+  auto kern = sweep_big_kernel<RPW, HAS_H>;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  const int bpi = (a.R + 31) / 32;
+  const int bpi = (a.R + kTrialsWG - 1) / kTrialsWG;
   const int groups = (count + kXcds - 1) / kXcds;
   const dim3 grid((unsigned)(bpi * groups * kXcds));
-  hipLaunchKernelGGL(kern, grid, dim3(64 * kWaves), lds, s, a, bpi);
+  hipLaunchKernelGGL(kern, grid, dim3(64 * kWaves), lds, s, a, nt, bpi);
   return hipGetLastError();
 }
 
 template <bool HAS_H>
 hipError_t launch_h(const SweepArgs& a, int count, int nt, hipStream_t s) {
-  switch (nt) {
-    case 12: return launch_nt<12, HAS_H>(a, count, s);
-    case 16: return launch_nt<16, HAS_H>(a, count, s);
-    case 20: return launch_nt<20, HAS_H>(a, count, s);
-    case 24: return launch_nt<24, HAS_H>(a, count, s);
-    case 28: return launch_nt<28, HAS_H>(a, count, s);
-    case 32: return launch_nt<32, HAS_H>(a, count, s);
+  switch ((nt + kWaves - 1) / kWaves) {  // row tiles per wave
+    case 2: return launch_rpw<2, HAS_H>(a, count, nt, s);
+    case 3: return launch_rpw<3, HAS_H>(a, count, nt, s);
+    case 4: return launch_rpw<4, HAS_H>(a, count, nt, s);
     default: return hipErrorInvalidValue;
   }
 }
 
 }  // namespace
 
-int big_tiles(int n) { return kWaves * ((n + 32 * kWaves - 1) / (32 * kWaves)); }
+int big_tiles(int n) { return (n + 31) / 32; }
 
 hipError_t launch_sweep_big(const SweepArgs& a, int count, int nt, bool has_h, hipStream_t s) {
-  if (a.npad != nt * 32 || nt % kWaves != 0 || a.T < 1) return hipErrorInvalidValue;
+  if (a.npad != nt * 32 || nt < kMinTiles || nt > kMaxTiles || a.T < 1 || count < 1 || a.R < 1)
+    return hipErrorInvalidValue;
   return has_h ? launch_h<true>(a, count, nt, s) : launch_h<false>(a, count, nt, s);
 }
 

@@ -332,6 +332,8 @@ BIG_CASES = [
     (257, 64, 60, 3, 0),
     (300, 40, 50, 1, 5),
     (512, 33, 40, 2, 0),
+    (600, 130, 30, 2, 3),   # three row tiles per wave; a second, mostly idle trial block
+    (700, 200, 20, 1, 0),
     (777, 64, 30, 1, 0),
     (1000, 32, 30, 1, 0),
     (1024, 70, 24, 30, 40),
@@ -340,8 +342,9 @@ BIG_CASES = [
 
 @pytest.mark.parametrize("case", BIG_CASES, ids=lambda c: "-".join(map(str, c)))
 def test_streamed_large_n_parity(gpu_lib, case):
-    """N > 256: couplings streamed from global memory, four waves per trial
-    block sharing the spins in LDS; bit-exact against the oracle."""
+    """N > 256: couplings streamed from global memory by eight waves that
+    share 128 trials' spins in LDS (two, three or four row tiles per wave,
+    partial trial blocks, fields); bit-exact against the oracle."""
     n, trials, steps, jmax, hmax = case
     _say(f"large N streamed n={n} trials={trials} steps={steps}")
     _run_case(gpu_lib, "int", n, trials, steps, "mfma", seed=13, count=2, jmax=jmax, hmax=hmax)
