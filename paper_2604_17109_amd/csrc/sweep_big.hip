@@ -60,59 +60,135 @@ __device__ __forceinline__ Ctr4 noise_block(uint32_t block, int tg, uint32_t tri
 // LDS spin buffer: tile kt of column block c, lane l at ((kt * kCB + c) * 64 + l).
 __device__ __forceinline__ int sb_index(int kt, int c, int lane) { return (kt * kCB + c) * 64 + lane; }
 
-// Field of row tile mt for the four column blocks: nt K steps, each one A
-// fragment from global memory and four B fragments from LDS.
+// Fields of MT (1 or 2) row tiles mt0, mt0 + kWaves for the four column
+// blocks: nt K steps, each MT A fragments from global memory and four B
+// fragments from LDS, MT x 4 MFMAs.  With two row tiles every B fragment read
+// from LDS feeds two MFMAs, which halves the LDS traffic per MFMA and doubles
+// the matrix work that covers each LDS read.
 //
-// The A fragments stream through a four-slot register ring: K step kt uses
-// slot kt % 4 and, right after its MFMAs are issued, refills that slot with
-// the fragment four K steps ahead.  Past the end of the row the stream
-// continues into the next row tile the wave owns (mt_next; after the wave's
-// last row tile, its first one of the next step, whose couplings do not
-// depend on the spins): the last four K steps, which cover every slot once,
-// load K steps 0..3 of mt_next into the slots those steps use.  So no row
-// tile starts on a cold global load.  Every index stays inside the instance's
-// fragments.  The B fragments of the next K step are read into the same
-// registers right after the MFMAs that consume them are issued.  The K steps
-// run in unconditional groups of four followed by a tail of at most three;
+// The A fragments stream through a register ring of D slots per row tile (K
+// step kt uses slot kt % D and, right after its MFMAs are issued, refills
+// that slot with the fragment D K steps ahead, from a clamped, always
+// in-bounds index); the B fragments of the next K step are read into the
+// same registers right after the MFMAs that consume them are issued.  The K
+// steps run in unconditional groups of D followed by a tail of fewer than D;
 // a scheduling barrier per K step keeps the compiler from hoisting more
-// operand loads than these registers.
-__device__ __forceinline__ void big_row_tile(const v4i* __restrict__ gAl, const v4i* sB, int lane, int mt,
-                                             int mt_next, int nt, v4i (&ar)[4], v16i (&acc)[kCB]) {
+// operand loads than these registers.  Fragment indices are wave-uniform
+// (scalar) and the lane offset is a 32-bit register: each load is a scalar
+// base plus one 32-bit vector offset.
+template <int MT>
+__device__ __forceinline__ void big_rows(const v4i* __restrict__ gA, const v4i* sB, int lane, int mt0, int nt,
+                                         v16i (&acc)[MT][kCB]) {
+  constexpr int D = MT == 1 ? 4 : 2;
+  int fa[MT];
 #pragma unroll
-  for (int c = 0; c < kCB; ++c) acc[c] = v16i{};
-  v4i b[kCB];
+  for (int r = 0; r < MT; ++r) {
+    fa[r] = (mt0 + kWaves * r) * nt;
+#pragma unroll
+    for (int c = 0; c < kCB; ++c) acc[r][c] = v16i{};
+  }
+  v4i ar[MT][D], b[kCB];
+#pragma unroll
+  for (int r = 0; r < MT; ++r)
+#pragma unroll
+    for (int i = 0; i < D; ++i) ar[r][i] = gA[(fa[r] + i) * 64 + lane];  // nt >= 9 > D
 #pragma unroll
   for (int c = 0; c < kCB; ++c) b[c] = sB[sb_index(0, c, lane)];
-  // fragment indices are wave-uniform (scalar); one 64-bit add per load
-  const int fa = mt * nt, fn = mt_next * nt;
-  const int nfull = nt & ~3;
+  const int nfull = nt - nt % D;
   int kt = 0;
-  for (; kt < nfull; kt += 4) {
+  for (; kt < nfull; kt += D) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < D; ++i) {
 #pragma unroll
-      for (int c = 0; c < kCB; ++c) acc[c] = __builtin_amdgcn_mfma_i32_32x32x32_i8(ar[i], b[c], acc[c], 0, 0, 0);
-      // refill the slot after its last use, so the load lands in place
-      const int f = (kt + i + 4 < nt) ? fa + kt + i + 4 : fn + i;
-      ar[i] = gAl[(size_t)f * 64];
+      for (int c = 0; c < kCB; ++c)
+#pragma unroll
+        for (int r = 0; r < MT; ++r)
+          acc[r][c] = __builtin_amdgcn_mfma_i32_32x32x32_i8(ar[r][i], b[c], acc[r][c], 0, 0, 0);
+      // refill the slots after their last use, so the loads land in place
+      const int kf = min(kt + i + D, nt - 1);
+#pragma unroll
+      for (int r = 0; r < MT; ++r) ar[r][i] = gA[(fa[r] + kf) * 64 + lane];
       const int kn = min(kt + i + 1, nt - 1);
 #pragma unroll
       for (int c = 0; c < kCB; ++c) b[c] = sB[sb_index(kn, c, lane)];
       __builtin_amdgcn_sched_barrier(0);
     }
   }
-  // tail: the last nt - nfull (< 4) K steps, in ring slots 0, 1, 2
+  // tail: the last nt - nfull (< D) K steps, in ring slots 0 .. D - 2
 #pragma unroll
-  for (int i = 0; i < 3; ++i) {
+  for (int i = 0; i < D - 1; ++i) {
     if (kt + i < nt) {  // uniform
 #pragma unroll
-      for (int c = 0; c < kCB; ++c) acc[c] = __builtin_amdgcn_mfma_i32_32x32x32_i8(ar[i], b[c], acc[c], 0, 0, 0);
-      ar[i] = gAl[(size_t)(fn + i) * 64];  // kt + i + 4 >= nt here
+      for (int c = 0; c < kCB; ++c)
+#pragma unroll
+        for (int r = 0; r < MT; ++r)
+          acc[r][c] = __builtin_amdgcn_mfma_i32_32x32x32_i8(ar[r][i], b[c], acc[r][c], 0, 0, 0);
       if (kt + i + 1 < nt) {
 #pragma unroll
         for (int c = 0; c < kCB; ++c) b[c] = sB[sb_index(kt + i + 1, c, lane)];
       }
     }
+  }
+}
+
+// Eq. (4) decisions and the Eq. (1) energy terms of row tile mt for the four
+// column blocks, one block at a time: s(t+1) of the tile into bn, the partial
+// sums s_i (I_i + h_i) into ep.
+template <bool HAS_H>
+__device__ __forceinline__ void big_decide(const v16i (&acc)[kCB], const v4i* sB, const int32_t* sH,
+                                           const int16_t* tab, int mt, int lane_off, int half, uint32_t ctr_half,
+                                           uint32_t ctr_trial, int tg, uint32_t stream, uint32_t k0, uint32_t k1,
+                                           v4i (&bn)[kCB], int32_t (&ep)[kCB]) {
+  const int hoff = 32 * mt + 16 * half;
+#pragma unroll
+  for (int c = 0; c < kCB; ++c) {
+    const Ctr4 x = noise_block(2u * mt + ctr_half, tg, ctr_trial + 32u * c, stream, k0, k1);
+    uint32_t xw[4] = {x.x, x.y, x.z, x.w};
+    const v4i cv = sB[sb_index(mt, c, lane_off)];
+    uint32_t bw[4] = {(uint32_t)cv[0], (uint32_t)cv[1], (uint32_t)cv[2], (uint32_t)cv[3]};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      PIM_FENCE(xw[q]);
+      PIM_FENCE(bw[q]);
+    }
+    int th[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int sv = (int)(int8_t)(bw[r >> 2] >> (8 * (r & 3)));
+      th[r] = tab[(int)((xw[r >> 2] >> (8 * (r & 3))) & 0xFFu) ^ sv];
+    }
+    // h of this row tile re-read for every column block (fenced offset)
+    int hoff_c = hoff;
+    if (HAS_H) PIM_FENCE(hoff_c);
+    v4i o;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      int d[4];
+#pragma unroll
+      for (int bb = 0; bb < 4; ++bb) {
+        const int r = 4 * q + bb;
+        const int sv = (int)(int8_t)(bw[q] >> (8 * bb));
+        int I = acc[c][r];
+        int v = I;
+        if (HAS_H) {
+          const int hv = sH[hoff_c + r];
+          I += hv;
+          v = I + hv;
+        }
+        ep[c] += __mul24(sv, v);  // |v| < 2^23
+        d[bb] = I - th[r];        // >= 0  <=>  s(t+1) = +1
+      }
+      // sign bytes of d via byte-permute sign replication, | 0x01 -> +1 / -1
+      const uint32_t p01 = __builtin_amdgcn_perm((uint32_t)d[1], (uint32_t)d[0], 0x0C0C0B09u);
+      const uint32_t p23 = __builtin_amdgcn_perm((uint32_t)d[3], (uint32_t)d[2], 0x0B090C0Cu);
+      o[q] = (int)(p01 | p23 | 0x01010101u);
+    }
+    bn[c] = o;
+    PIM_FENCE(ep[c]);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) PIM_FENCE(bn[c][q]);
+    // one column block's decisions at a time (bounds the live temporaries)
+    __builtin_amdgcn_sched_barrier(0);
   }
 }
 
@@ -152,8 +228,9 @@ __global__ __launch_bounds__(64 * kWaves, 2) void sweep_big_kernel(SweepArgs a, 
   const uint4* gTab4 = reinterpret_cast<const uint4*>(a.thtab + (size_t)cls * a.T * kTabEntries);
   const int32_t target = a.target ? a.target[inst] : INT_MIN;
   const uint32_t k0 = a.k0, k1 = a.k1;
-  // this lane's view of the instance's A fragments: fragment f at gAl[f * 64]
-  const v4i* gAl = reinterpret_cast<const v4i*>(a.jfrag + (size_t)inst * nt * nt * 1024) + lane;
+  // the instance's A fragments (fragment f, lane l at gA[f * 64 + l]; at most
+  // 32 * 32 * 64 entries, so 32-bit indices)
+  const v4i* gA = reinterpret_cast<const v4i*>(a.jfrag + (size_t)inst * nt * nt * 1024);
 
   if (HAS_H)
     for (int i = threadIdx.x; i < npad; i += 64 * kWaves) sH[i] = a.h[(size_t)inst * npad + i];
@@ -191,10 +268,8 @@ __global__ __launch_bounds__(64 * kWaves, 2) void sweep_big_kernel(SweepArgs a, 
 #pragma unroll
   for (int c = 0; c < kCB; ++c) e_best[c] = INT_MAX;
   int done = a.T;
-  // A-fragment ring: the first four K steps of the wave's first row tile
-  v4i ar[4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i) ar[i] = gAl[(size_t)wave * nt * 64 + (size_t)i * 64];  // nt >= 9 > wave
+  // row tiles of this wave: wave + kWaves j for j < rw (rw >= 1: nt >= 9 > wave)
+  const int rw = (nt - wave + kWaves - 1) / kWaves;
   // centre of the step table: entry idx in [-256, 256) holds the field
   // threshold for (u, s) with idx = u ^ s (s = +1 -> u ^ 1, s = -1 -> ~u)
   const int16_t* tab = sTab + kNoiseVals;
@@ -217,63 +292,26 @@ __global__ __launch_bounds__(64 * kWaves, 2) void sweep_big_kernel(SweepArgs a, 
     PIM_FENCE(ctr_trial);
     PIM_FENCE(lane_off);
     // ---- phase 1: contraction and decisions of the wave's row tiles ----
+    // row tiles mt = wave + kWaves j, j < rw, taken in pairs (j, j + 1); an
+    // odd last one alone
 #pragma unroll
-    for (int j = 0; j < RPW; ++j) {
-      const int mt = wave + kWaves * j;
-      if (mt >= nt) break;  // uniform
-      v16i acc[kCB];
-      const int mt_next = mt + kWaves < nt ? mt + kWaves : wave;
-      big_row_tile(gAl, sB, lane_off, mt, mt_next, nt, ar, acc);
-      const int hoff = 32 * mt + 16 * half;
-#pragma unroll
-      for (int c = 0; c < kCB; ++c) {
-        const Ctr4 x = noise_block(2u * mt + ctr_half, tg, ctr_trial + 32u * c, stream, k0, k1);
-        uint32_t xw[4] = {x.x, x.y, x.z, x.w};
-        const v4i cv = sB[sb_index(mt, c, lane_off)];
-        uint32_t bw[4] = {(uint32_t)cv[0], (uint32_t)cv[1], (uint32_t)cv[2], (uint32_t)cv[3]};
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          PIM_FENCE(xw[q]);
-          PIM_FENCE(bw[q]);
-        }
-        int th[16];
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const int sv = (int)(int8_t)(bw[r >> 2] >> (8 * (r & 3)));
-          th[r] = tab[(int)((xw[r >> 2] >> (8 * (r & 3))) & 0xFFu) ^ sv];
-        }
-        // h of this row tile re-read for every column block (fenced offset)
-        int hoff_c = hoff;
-        if (HAS_H) PIM_FENCE(hoff_c);
-        v4i o;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          int d[4];
-#pragma unroll
-          for (int b = 0; b < 4; ++b) {
-            const int r = 4 * q + b;
-            const int sv = (int)(int8_t)(bw[q] >> (8 * b));
-            int I = acc[c][r];
-            int v = I;
-            if (HAS_H) {
-              const int hv = sH[hoff_c + r];
-              I += hv;
-              v = I + hv;
-            }
-            ep[c] += __mul24(sv, v);  // |v| < 2^23
-            d[b] = I - th[r];         // >= 0  <=>  s(t+1) = +1
-          }
-          // sign bytes of d via byte-permute sign replication, | 0x01 -> +1 / -1
-          const uint32_t p01 = __builtin_amdgcn_perm((uint32_t)d[1], (uint32_t)d[0], 0x0C0C0B09u);
-          const uint32_t p23 = __builtin_amdgcn_perm((uint32_t)d[3], (uint32_t)d[2], 0x0B090C0Cu);
-          o[q] = (int)(p01 | p23 | 0x01010101u);
-        }
-        Bn[j][c] = o;
-        PIM_FENCE(ep[c]);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) PIM_FENCE(Bn[j][c][q]);
-        // one column block's decisions at a time (bounds the live temporaries)
-        __builtin_amdgcn_sched_barrier(0);
+    for (int g = 0; g < (RPW + 1) / 2; ++g) {
+      const int j0 = 2 * g;
+      if (j0 >= rw) break;  // uniform
+      const int mt0 = wave + kWaves * j0;
+      if (j0 + 1 < rw) {
+        v16i acc[2][kCB];
+        big_rows<2>(gA, sB, lane_off, mt0, nt, acc);
+        big_decide<HAS_H>(acc[0], sB, sH, tab, mt0, lane_off, half, ctr_half, ctr_trial, tg, stream, k0, k1,
+                          Bn[j0], ep);
+        if (j0 + 1 < RPW)
+          big_decide<HAS_H>(acc[1], sB, sH, tab, mt0 + kWaves, lane_off, half, ctr_half, ctr_trial, tg, stream,
+                            k0, k1, Bn[j0 + 1 < RPW ? j0 + 1 : j0], ep);
+      } else {
+        v16i acc[1][kCB];
+        big_rows<1>(gA, sB, lane_off, mt0, nt, acc);
+        big_decide<HAS_H>(acc[0], sB, sH, tab, mt0, lane_off, half, ctr_half, ctr_trial, tg, stream, k0, k1,
+                          Bn[j0], ep);
       }
     }
     // per-trial partial energies of this wave's rows (both lane halves)
@@ -296,11 +334,15 @@ __global__ __launch_bounds__(64 * kWaves, 2) void sweep_big_kernel(SweepArgs a, 
         e_best[c] = E;
         if (writer) sStat[(0 * kCB + c) * 32 + col] = tg;
         if ((trial0 + 32 * c < a.R)) {
+          // address formed here from a fenced offset (not hoisted out of the
+          // step loop into registers for every column block)
+          size_t off = (cell0 + 32 * c) * npad + 16 * half;
+          PIM_FENCE(off);
+          int8_t* dst = a.best_s + off;
 #pragma unroll
           for (int j = 0; j < RPW; ++j) {
             const int mt = wave + kWaves * j;
-            if (mt < nt)
-              *reinterpret_cast<v4i*>(a.best_s + (cell0 + 32 * c) * npad + 32 * mt + 16 * half) = sB[sb_index(mt, c, lane)];
+            if (mt < nt) *reinterpret_cast<v4i*>(dst + 32 * mt) = sB[sb_index(mt, c, lane)];
           }
         }
       }
