@@ -76,7 +76,16 @@ __device__ __forceinline__ void mfma_row_tile(const v4i* sJl, int mt, const v4i 
 // Each wave owns CB blocks of 32 trials.  Two independent blocks give the
 // in-order issue of one wave per SIMD enough independent work to keep the
 // vector ALU busy while MFMA chains and LDS lookups are in flight.
-template <int NT, int CB, bool HAS_H, bool RECORD>
+//
+// TAIL (4, 8, 12 or 16) is how many of a lane's 16 registers of the last row
+// tile carry spins below N in the lower lane half, rounded up to 4: spins
+// 32 (NT - 1) + r for r < N - 32 (NT - 1).  Decisions and energy terms are
+// skipped for the registers past it.  Those hold padding spins only (zero
+// rows and columns of J, so their fields are 0 and they never enter another
+// spin's field); they keep their initial values.  In the upper lane half the
+// same registers hold spins 32 (NT - 1) + 16 + r, which are padding whenever
+// TAIL < 16.
+template <int NT, int CB, bool HAS_H, bool RECORD, int TAIL>
 __global__ __launch_bounds__(64 * kWaves, 3) void sweep_mfma_kernel(SweepArgs a) {
   extern __shared__ __align__(16) unsigned char lds[];
   constexpr int kFragBytes = NT * NT * 1024;
@@ -207,11 +216,13 @@ __global__ __launch_bounds__(64 * kWaves, 3) void sweep_mfma_kernel(SweepArgs a)
       if (HAS_H) PIM_FENCE(hoff);
       const v4i* sJl = sJ + lane_off;
       // (1) LDS: the field thresholds of this tile, indexed by u ^ s
+      // registers of this tile that carry decisions (all but the last tile: 16)
+      const int kRegs = (mt == NT - 1) ? TAIL : 16;  // a constant once mt is unrolled
       int th[CB][16];
 #pragma unroll
       for (int c = 0; c < CB; ++c)
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
+        for (int r = 0; r < kRegs; ++r) {
           const int sv = (int)(int8_t)(bw[c][r >> 2] >> (8 * (r & 3)));
           const int idx = (int)((xw[c][r >> 2] >> (8 * (r & 3))) & 0xFFu) ^ sv;
           th[c][r] = tab[idx];
@@ -229,6 +240,10 @@ __global__ __launch_bounds__(64 * kWaves, 3) void sweep_mfma_kernel(SweepArgs a)
       for (int c = 0; c < CB; ++c)
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
+          if (4 * q >= kRegs) {  // padding spins only: kept as they are
+            Bn[c][mt][q] = B[c][mt][q];
+            continue;
+          }
           int d[4];
 #pragma unroll
           for (int b = 0; b < 4; ++b) {
@@ -326,11 +341,11 @@ __global__ __launch_bounds__(64 * kWaves, 3) void sweep_mfma_kernel(SweepArgs a)
 
 constexpr int kBlocksPerWave = 1;  // CB: 32-trial column blocks per wave
 
-template <int NT, bool HAS_H, bool RECORD>
-hipError_t launch_nt(const SweepArgs& a, int count, hipStream_t s) {
+template <int NT, bool HAS_H, bool RECORD, int TAIL>
+hipError_t launch_tail(const SweepArgs& a, int count, hipStream_t s) {
   const int waves = a.waves;  // 1, 2 or 4 (checked by the caller)
   const size_t lds = (size_t)NT * NT * 1024 + (HAS_H ? NT * 32 * 4 : 0) + (size_t)waves * kTabBytes;
-  auto kern = sweep_mfma_kernel<NT, kBlocksPerWave, HAS_H, RECORD>;
+  auto kern = sweep_mfma_kernel<NT, kBlocksPerWave, HAS_H, RECORD, TAIL>;
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
@@ -338,6 +353,17 @@ hipError_t launch_nt(const SweepArgs& a, int count, hipStream_t s) {
   const dim3 grid((a.R + per_wg - 1) / per_wg, count);
   hipLaunchKernelGGL(kern, grid, dim3(64 * waves), lds, s, a);
   return hipGetLastError();
+}
+
+// registers of the last row tile that carry spins below N (in the lower lane
+// half), rounded up to 4; recording runs always take the full tile
+template <int NT, bool HAS_H, bool RECORD>
+hipError_t launch_nt(const SweepArgs& a, int count, hipStream_t s) {
+  const int rem = a.n - 32 * (NT - 1);  // 1 .. 32
+  if (RECORD || rem > 12) return launch_tail<NT, HAS_H, RECORD, 16>(a, count, s);
+  if (rem > 8) return launch_tail<NT, HAS_H, RECORD, 12>(a, count, s);
+  if (rem > 4) return launch_tail<NT, HAS_H, RECORD, 8>(a, count, s);
+  return launch_tail<NT, HAS_H, RECORD, 4>(a, count, s);
 }
 
 template <bool HAS_H, bool RECORD>
