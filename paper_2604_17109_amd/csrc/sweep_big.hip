@@ -57,6 +57,16 @@ __device__ __forceinline__ Ctr4 noise_block(uint32_t block, int tg, uint32_t tri
   return philox4x32_10(Ctr4{block, (uint32_t)tg, trial, (kDomainNoise << 24) | stream}, k0, k1);
 }
 
+// Workgroup barrier for data exchanged through LDS only: each wave waits for
+// its own LDS operations, not for its outstanding global loads (prefetches
+// stay in flight across it).  A plain __syncthreads() is also a fence for
+// global memory and would drain every prefetch at every step.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // LDS spin buffer: tile kt of column block c, lane l at ((kt * kCB + c) * 64 + l).
 __device__ __forceinline__ int sb_index(int kt, int c, int lane) { return (kt * kCB + c) * 64 + lane; }
 
@@ -322,7 +332,7 @@ __global__ __launch_bounds__(64 * kWaves, 2) void sweep_big_kernel(SweepArgs a, 
     }
     if (threadIdx.x == 0 && (t & 255) == 0 && t < a.T)
       sFlag[0] = __atomic_load_n(a.cancel, __ATOMIC_RELAXED) != 0 ? 1 : 0;
-    __syncthreads();  // every read of s(t) and of the table is done; energies of s(t) complete
+    lds_barrier();  // every read of s(t) and of the table is done; energies of s(t) complete
     // ---- phase 2: energies, bookkeeping, s(t+1) in place ----
 #pragma unroll
     for (int c = 0; c < kCB; ++c) {
@@ -365,7 +375,7 @@ __global__ __launch_bounds__(64 * kWaves, 2) void sweep_big_kernel(SweepArgs a, 
       for (int c = 0; c < kCB; ++c) sB[sb_index(mt, c, lane)] = Bn[j][c];
     }
     if (wave == 0) reinterpret_cast<uint4*>(sTab)[lane] = nxt;
-    __syncthreads();  // s(t+1) and the table of step t+1 are complete
+    lds_barrier();  // s(t+1) and the table of step t+1 are complete
   }
   // final state: the s(t) left in LDS
 #pragma unroll

@@ -1,10 +1,12 @@
 // Plain FP32 PIMI sweep: one instance per launch, no matrix cores.
 //
-// Workgroup = 32 trials x (N/16 spin blocks); thread (b, a) owns spins
+// Workgroup = 32 trials x (ceil(N/16) spin blocks); thread (b, a) owns spins
 // 16b..16b+15 of trial a.  Each step it forms the 16 local fields (Eq. (2))
-// with ordinary FP32 multiply-adds: J rows come from global memory as float4
-// (zero-padded to whole rows of 16 and a multiple of 4 columns) and the trial's current spins from
-// LDS as float4, one spin chunk reused across the 16 rows.  It then applies the
+// with ordinary FP32 multiply-adds over float4 chunks of J rows (zero-padded to
+// whole rows of 16 and a multiple of 4 columns) and of the trial's current
+// spins (LDS), one spin chunk reused across the 16 rows.  J is staged in LDS
+// once when its padded rows fit (up to 120 KB, N <= 172), and read from
+// global memory (L2) otherwise.  It then applies the
 // same integer-threshold form of Eq. (4) as the MFMA kernel:
 // k = #{j : I >= theta_j}, s' = +1 iff u >= umin[2k + (s<0)].  FP32 sums of
 // integers below 2^24 are exact, so both kernels produce identical
@@ -30,18 +32,30 @@ constexpr int kTrials = 32;
 constexpr int kBlocks = PIM_MAX_N_LDS / 16;  // spin blocks of 16
 constexpr int kThreads = kTrials * kBlocks;
 constexpr int kRow = PIM_MAX_N_LDS + 8;      // LDS row stride (floats) of one trial's spins
+constexpr size_t kJLdsMax = 120 * 1024;      // largest J staged in LDS (bytes)
 
-template <bool REAL>
+// bytes of J's padded rows 0 .. 16 ceil(n/16) - 1
+size_t plain_j_bytes(const PlainArgs& a) { return (size_t)16 * ((a.n + 15) / 16) * a.jstride * 4; }
+
+template <bool REAL, bool JLDS>
 __global__ __launch_bounds__(kThreads) void sweep_plain_kernel(PlainArgs a) {
   __shared__ __align__(16) float sS[kTrials][kRow];
   __shared__ int32_t sE[kTrials];
   __shared__ float sEf[kBlocks][kTrials];  // per-block partial energies (REAL)
+  extern __shared__ __align__(16) float sJ[];  // J rows (JLDS)
+  // blockDim = 32 x nb: every thread owns a spin block
   const int b = threadIdx.x / kTrials;
   const int al = threadIdx.x % kTrials;
   const int trial = blockIdx.x * kTrials + al;
   const bool live = trial < a.R;
   const int nb = (a.n + 15) / 16;
   const bool owner = b < nb;
+  if (JLDS) {
+    const float4* src = reinterpret_cast<const float4*>(a.jf32);
+    float4* dst = reinterpret_cast<float4*>(sJ);
+    const int n4 = 16 * nb * a.jstride / 4;
+    for (int i = threadIdx.x; i < n4; i += blockDim.x) dst[i] = src[i];
+  }
   const size_t cell = (size_t)trial;
   const int L = a.levels;
   const int w = (L - 1) + 2 * L;
@@ -83,7 +97,7 @@ __global__ __launch_bounds__(kThreads) void sweep_plain_kernel(PlainArgs a) {
       const float4* S4 = reinterpret_cast<const float4*>(&sS[al][0]);
       // rows are zero-padded to a multiple of 32 and columns to jstride, so
       // every row of the block exists and padded columns add 0
-      const float* Jb = a.jf32 + (size_t)(16 * b) * n4;
+      const float* Jb = (JLDS ? sJ : a.jf32) + (size_t)(16 * b) * n4;
       for (int j4 = 0; j4 < n4 / 4; ++j4) {
         const float4 sv = S4[j4];
 #pragma unroll
@@ -120,7 +134,9 @@ __global__ __launch_bounds__(kThreads) void sweep_plain_kernel(PlainArgs a) {
     bool improved;
     if (REAL) {
       float tot = 0.0f;
-      for (int k = 0; k < kBlocks; ++k) tot += sEf[k][al];  // fixed order
+      for (int k = 0; k < nb; ++k) tot += sEf[k][al];  // fixed order
+      // the blocks past nb contributed +0.0 (turns a -0.0 sum into +0.0)
+      if (nb < kBlocks) tot += 0.0f;
       const float E = -0.5f * tot;
       improved = E < ef_best;
       if (improved) ef_best = E;
@@ -186,12 +202,25 @@ __global__ __launch_bounds__(kThreads) void sweep_plain_kernel(PlainArgs a) {
 
 }  // namespace
 
-hipError_t launch_sweep_plain(const PlainArgs& a, bool real, hipStream_t s) {
-  if (a.n > PIM_MAX_N_LDS) return hipErrorInvalidValue;
+template <bool REAL, bool JLDS>
+hipError_t launch_plain(const PlainArgs& a, hipStream_t s) {
+  const size_t lds = JLDS ? plain_j_bytes(a) : 0;
+  auto kern = sweep_plain_kernel<REAL, JLDS>;
+  if (JLDS) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)kJLdsMax);
+    if (e != hipSuccess) return e;
+  }
   const dim3 grid((a.R + kTrials - 1) / kTrials);
-  if (real) hipLaunchKernelGGL(sweep_plain_kernel<true>, grid, dim3(kThreads), 0, s, a);
-  else hipLaunchKernelGGL(sweep_plain_kernel<false>, grid, dim3(kThreads), 0, s, a);
+  hipLaunchKernelGGL(kern, grid, dim3(kTrials * ((a.n + 15) / 16)), lds, s, a);
   return hipGetLastError();
+}
+
+hipError_t launch_sweep_plain(const PlainArgs& a, bool real, hipStream_t s) {
+  if (a.n > PIM_MAX_N_LDS || a.n < 1) return hipErrorInvalidValue;
+  const bool jlds = plain_j_bytes(a) <= kJLdsMax;
+  if (real) return jlds ? launch_plain<true, true>(a, s) : launch_plain<true, false>(a, s);
+  return jlds ? launch_plain<false, true>(a, s) : launch_plain<false, false>(a, s);
 }
 
 }  // namespace pim

@@ -53,6 +53,16 @@ static_assert(kRealTabBytes == 64 * 32, "two 16-byte chunks per lane");
 
 #define PIM_FENCE(v) asm volatile("" : "+v"(v))
 
+// Workgroup barrier for data exchanged through LDS only: each wave waits for
+// its own LDS operations, not for its outstanding global loads (prefetches
+// stay in flight across it).  A plain __syncthreads() is also a fence for
+// global memory and would drain every prefetch at every step.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // v4i words per row tile per lane: 16 spins of 1 (FP8) or 2 (BF16) bytes.
 template <int PREC> constexpr int words() { return PREC == PIM_PREC_FP8 ? 1 : 2; }
 
@@ -119,6 +129,71 @@ __device__ __forceinline__ void real_row_tile(const unsigned char* sJ, int lane,
                                                       acc, 0, 0, 0);
       }
   }
+}
+
+// Field thresholds of one row tile's 16 spins of a lane: tab[u ^ m] with u the
+// noise byte and m the spin's sign mask.
+template <int PREC>
+__device__ __forceinline__ void real_tile_thresholds(const float* tab, const uint32_t (&xw)[4],
+                                                     const uint32_t (&sw)[4 * words<PREC>()], float (&th)[16],
+                                                     int (&sm)[16]) {
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    sm[r] = spin_mask<PREC>(sw, r);
+    const int idx = (int)((xw[r >> 2] >> (8 * (r & 3))) & 0xFFu) ^ sm[r];
+    th[r] = tab[idx];
+  }
+}
+
+// Decisions (Eq. (4)) and energy terms (Eq. (1)) of one row tile's 16 spins
+// of a lane: I = scale * acc + h, new spins into bn (operand encoding), and
+// the tile's energy sum pt = sum_r s_r (I_r + h_r), added from zero in r order.
+template <int PREC, bool HAS_H>
+__device__ __forceinline__ float real_tile_apply(const v16f& acc, float scale, const float* sH, int hoff,
+                                                 const float (&th)[16], const int (&sm)[16],
+                                                 v4i (&bn)[words<PREC>()]) {
+  float pt = 0.0f;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    float d[4];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int r = 4 * q + b;
+      float I, v;
+      if (HAS_H) {
+        const float hv = sH[hoff + r];
+        I = fmaf(scale, acc[r], hv);
+        v = I + hv;
+      } else {
+        I = scale * acc[r];
+        v = I;
+      }
+      pt += __uint_as_float(__float_as_uint(v) ^ ((uint32_t)sm[r] & 0x80000000u));  // s * v
+      d[b] = I - th[r];  // sign bit set <=> s(t+1) = -1
+    }
+    const uint32_t d0 = __float_as_uint(d[0]), d1 = __float_as_uint(d[1]);
+    const uint32_t d2 = __float_as_uint(d[2]), d3 = __float_as_uint(d[3]);
+    if (PREC == PIM_PREC_FP8) {
+      const uint32_t sgn = perm(d1, d0, 0x0C0C0B09u) | perm(d3, d2, 0x0B090C0Cu);
+      bn[0][q] = (int)((sgn & 0x80808080u) | 0x38383838u);
+    } else {
+      bn[q >> 1][2 * (q & 1)] = (int)((perm(d1, d0, 0x0B0C090Cu) & 0x80008000u) | 0x3F803F80u);
+      bn[q >> 1][2 * (q & 1) + 1] = (int)((perm(d3, d2, 0x0B0C090Cu) & 0x80008000u) | 0x3F803F80u);
+    }
+  }
+  return pt;
+}
+
+// int8 spin bytes of one row tile's 16 spins of a lane from operand words
+template <int PREC>
+__device__ __forceinline__ v4i real_tile_i8(const v4i (&w)[words<PREC>()]) {
+  v4i o;
+  if (PREC == PIM_PREC_FP8) {
+    for (int q = 0; q < 4; ++q) o[q] = (int)i8_from_fp8((uint32_t)w[0][q]);
+  } else {
+    for (int q = 0; q < 4; ++q) o[q] = (int)i8_from_bf16((uint32_t)w[q >> 1][2 * (q & 1)], (uint32_t)w[q >> 1][2 * (q & 1) + 1]);
+  }
+  return o;
 }
 
 template <int NT, int PREC, bool HAS_H>
@@ -248,45 +323,14 @@ __global__ __launch_bounds__(64 * kMaxWaves) void sweep_real_kernel(SweepRealArg
       // (1) LDS: the field thresholds of this tile
       float th[16];
       int sm[16];
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        sm[r] = spin_mask<PREC>(sw, r);
-        const int idx = (int)((xw[r >> 2] >> (8 * (r & 3))) & 0xFFu) ^ sm[r];
-        th[r] = tab[idx];
-      }
+      real_tile_thresholds<PREC>(tab, xw, sw, th, sm);
       // (2) the next tile's MFMA chain and noise block
       if (mt + 1 < NT) real_row_tile<NT, PREC>(sJ, lane_off, mt + 1, B, acc_next);
       if (mt + 1 < NT) x_next = noise_block(2u * (mt + 1) + ctr_half, tg, ctr_trial, stream, k0, k1);
       else x_next = noise_block(ctr_half, tg + 1, ctr_trial, stream, k0, k1);
-      // (3) energy of s(t) and the decisions of this tile
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        float d[4];
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-          const int r = 4 * q + b;
-          float I, v;
-          if (HAS_H) {
-            const float hv = sH[hoff + r];
-            I = fmaf(scale, acc[r], hv);
-            v = I + hv;
-          } else {
-            I = scale * acc[r];
-            v = I;
-          }
-          ep += __uint_as_float(__float_as_uint(v) ^ ((uint32_t)sm[r] & 0x80000000u));  // s * v
-          d[b] = I - th[r];  // sign bit set <=> s(t+1) = -1
-        }
-        const uint32_t d0 = __float_as_uint(d[0]), d1 = __float_as_uint(d[1]);
-        const uint32_t d2 = __float_as_uint(d[2]), d3 = __float_as_uint(d[3]);
-        if (PREC == PIM_PREC_FP8) {
-          const uint32_t sgn = perm(d1, d0, 0x0C0C0B09u) | perm(d3, d2, 0x0B090C0Cu);
-          Bn[mt][0][q] = (int)((sgn & 0x80808080u) | 0x38383838u);
-        } else {
-          Bn[mt][q >> 1][2 * (q & 1)] = (int)((perm(d1, d0, 0x0B0C090Cu) & 0x80008000u) | 0x3F803F80u);
-          Bn[mt][q >> 1][2 * (q & 1) + 1] = (int)((perm(d3, d2, 0x0B0C090Cu) & 0x80008000u) | 0x3F803F80u);
-        }
-      }
+      // (3) energy of s(t) and the decisions of this tile; tile sums are
+      //     added in tile order (the order the split kernel reproduces)
+      ep += real_tile_apply<PREC, HAS_H>(acc, scale, sH, hoff, th, sm, Bn[mt]);
       PIM_FENCE(ep);
 #pragma unroll
       for (int j = 0; j < KW; ++j)
@@ -303,16 +347,7 @@ __global__ __launch_bounds__(64 * kMaxWaves) void sweep_real_kernel(SweepRealArg
         PIM_FENCE(off);
         int8_t* dst = a.best_s + off;
 #pragma unroll
-        for (int mt = 0; mt < NT; ++mt) {
-          v4i o;
-          if (PREC == PIM_PREC_FP8) {
-            for (int q = 0; q < 4; ++q) o[q] = (int)i8_from_fp8((uint32_t)B[mt][0][q]);
-          } else {
-            for (int q = 0; q < 4; ++q)
-              o[q] = (int)i8_from_bf16((uint32_t)B[mt][q >> 1][2 * (q & 1)], (uint32_t)B[mt][q >> 1][2 * (q & 1) + 1]);
-          }
-          *reinterpret_cast<v4i*>(dst + 32 * mt) = o;
-        }
+        for (int mt = 0; mt < NT; ++mt) *reinterpret_cast<v4i*>(dst + 32 * mt) = real_tile_i8<PREC>(B[mt]);
       }
     }
     if (first_hit < 0 && E <= target) first_hit = tg;
@@ -337,16 +372,8 @@ __global__ __launch_bounds__(64 * kMaxWaves) void sweep_real_kernel(SweepRealArg
 
   if (!live) return;
 #pragma unroll
-  for (int mt = 0; mt < NT; ++mt) {
-    v4i o;
-    if (PREC == PIM_PREC_FP8) {
-      for (int q = 0; q < 4; ++q) o[q] = (int)i8_from_fp8((uint32_t)B[mt][0][q]);
-    } else {
-      for (int q = 0; q < 4; ++q)
-        o[q] = (int)i8_from_bf16((uint32_t)B[mt][q >> 1][2 * (q & 1)], (uint32_t)B[mt][q >> 1][2 * (q & 1) + 1]);
-    }
-    *reinterpret_cast<v4i*>(a.final_s + cell * kNpad + 32 * mt + 16 * half) = o;
-  }
+  for (int mt = 0; mt < NT; ++mt)
+    *reinterpret_cast<v4i*>(a.final_s + cell * kNpad + 32 * mt + 16 * half) = real_tile_i8<PREC>(B[mt]);
   if (half == 0) {
     a.e_best[cell] = e_best;
     a.t_best[cell] = t_best;
@@ -356,8 +383,238 @@ __global__ __launch_bounds__(64 * kMaxWaves) void sweep_real_kernel(SweepRealArg
   }
 }
 
+// Latency form of the sweep for launches with few 32-trial blocks (a single
+// request, a small chunk): W waves share one 32-trial block and split its row
+// tiles (wave w owns mt = w, w + W, ...), so a step's decisions run on W SIMDs
+// at once instead of one after another.  The spins of s(t) are exchanged
+// through a double-buffered LDS copy of the B-operand words (each wave writes
+// the words of its own tiles for s(t+1)); the step table is shared and
+// double-buffered; the tile energy sums go to LDS and every lane adds them in
+// tile order after the step's single barrier, which gives exactly the
+// one-wave kernel's energies.  A buffer is rewritten two steps after it was
+// read, and every wave has passed the barrier in between.
+template <int NT, int PREC, bool HAS_H, int W>
+__global__ __launch_bounds__(64 * W) void sweep_real_split_kernel(SweepRealArgs a) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  constexpr int KW = words<PREC>();
+  constexpr int kFragBytes = (int)frag_bytes(PREC, NT);
+  constexpr int kNpad = NT * 32;
+  constexpr int kHBytes = HAS_H ? kNpad * 4 : 0;
+  constexpr int RPW = (NT + W - 1) / W;
+  // LDS: fragments | h | spin words [2][NT][KW][64] v4i | tables [2][kTabEntries]
+  // | tile energy sums [2][NT][64] | cancel flag
+  v4i* sS = reinterpret_cast<v4i*>(lds + kFragBytes + kHBytes);
+  float* sTab = reinterpret_cast<float*>(sS + 2 * NT * KW * 64);
+  float* sP = sTab + 2 * kTabEntries;
+  int32_t* sFlag = reinterpret_cast<int32_t*>(sP + 2 * NT * 64);
+  const int inst = blockIdx.y;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  const int col = lane & 31;
+  const int half = lane >> 5;
+  {  // stage the instance: quantised couplings and h
+    const uint4* src = reinterpret_cast<const uint4*>(a.jfrag + (size_t)inst * kFragBytes);
+    uint4* dst = reinterpret_cast<uint4*>(lds);
+    for (int i = threadIdx.x; i < kFragBytes / 16; i += blockDim.x) dst[i] = src[i];
+    if (HAS_H) {
+      float* sh = reinterpret_cast<float*>(lds + kFragBytes);
+      for (int i = threadIdx.x; i < kNpad; i += blockDim.x) sh[i] = a.h[(size_t)inst * kNpad + i];
+    }
+  }
+  const unsigned char* sJ = lds;
+  const float* sH = reinterpret_cast<const float*>(lds + kFragBytes);
+  const int trial = blockIdx.x * 32 + col;
+  const bool live = trial < a.R;
+  const size_t cell = (size_t)inst * a.R + trial;
+  const uint32_t stream = a.inst_stream[inst];
+  const int cls = a.inst_class[inst];
+  const uint4* gTab4 = reinterpret_cast<const uint4*>(a.thtab + (size_t)cls * a.T * kTabEntries);
+  const float target = a.target ? a.target[inst] : -INFINITY;
+  const float scale = a.scale[inst];
+  const uint32_t k0 = a.k0, k1 = a.k1;
+  auto word = [&](int buf, int mt, int j) -> v4i& { return sS[((buf * NT + mt) * KW + j) * 64 + lane]; };
+
+  // ---- s(0): each wave its own row tiles ----
+#pragma unroll
+  for (int jj = 0; jj < RPW; ++jj) {
+    const int mt = wave + W * jj;
+    if (mt >= NT) break;  // uniform
+    uint32_t w[4];
+    if (a.init) {
+      const v4i v = live ? *reinterpret_cast<const v4i*>(a.init + cell * kNpad + 32 * mt + 16 * half)
+                         : v4i{0x01010101, 0x01010101, 0x01010101, 0x01010101};
+      for (int q = 0; q < 4; ++q) w[q] = (uint32_t)v[q];
+    } else {
+      const Ctr4 x = philox4x32_10(Ctr4{(uint32_t)(2 * mt + half), 0u, (uint32_t)trial,
+                                        (kDomainInit << 24) | stream}, k0, k1);
+      w[0] = spins_from_bits(x.x);
+      w[1] = spins_from_bits(x.y);
+      w[2] = spins_from_bits(x.z);
+      w[3] = spins_from_bits(x.w);
+    }
+    v4i b[KW];
+    if (PREC == PIM_PREC_FP8) {
+      for (int q = 0; q < 4; ++q) b[0][q] = (int)fp8_from_i8(w[q]);
+    } else {
+      for (int q = 0; q < 4; ++q) {
+        b[q >> 1][2 * (q & 1)] = (int)bf16_lo_from_i8(w[q]);
+        b[q >> 1][2 * (q & 1) + 1] = (int)bf16_hi_from_i8(w[q]);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < KW; ++j) word(0, mt, j) = b[j];
+  }
+  if (wave == 0) {
+    reinterpret_cast<uint4*>(sTab)[lane] = gTab4[lane];
+    reinterpret_cast<uint4*>(sTab)[64 + lane] = gTab4[64 + lane];
+  }
+  if (threadIdx.x == 0) sFlag[0] = 0;
+  __syncthreads();
+
+  float e_best = INFINITY, e_cur = 0.0f;
+  int32_t t_best = -1, first_hit = -1;
+  int done = a.T;
+  // wave 0 holds the next table in registers: loaded one step before it is
+  // stored to LDS (a step before it is used), in place, so the load has a
+  // whole step to arrive and no register copy waits on it (clamped index:
+  // in bounds)
+  uint4 tr0 = uint4{0, 0, 0, 0}, tr1 = uint4{0, 0, 0, 0};
+  if (wave == 0) {
+    const size_t row = (size_t)min(1, a.T - 1) * 128;
+    tr0 = gTab4[row + lane];
+    tr1 = gTab4[row + 64 + lane];
+  }
+  for (int t = 0;; ++t) {
+    const int tg = a.start_step + t;
+    const int cur = t & 1, nxt = cur ^ 1;
+    // the table of step t+1 into the other buffer (last read in step t-1,
+    // before the barrier every wave has passed since), then the load of the
+    // table of step t+2 into the same registers
+    if (wave == 0) {
+      reinterpret_cast<uint4*>(sTab + nxt * kTabEntries)[lane] = tr0;
+      reinterpret_cast<uint4*>(sTab + nxt * kTabEntries)[64 + lane] = tr1;
+      const size_t row = (size_t)min(t + 2, a.T - 1) * 128;
+      tr0 = gTab4[row + lane];
+      tr1 = gTab4[row + 64 + lane];
+    }
+    uint32_t ctr_trial = (uint32_t)trial, ctr_half = (uint32_t)half;
+    PIM_FENCE(ctr_trial);
+    PIM_FENCE(ctr_half);
+    // noise blocks of the wave's tiles first: independent of the spins, they
+    // cover the latency of the spin-word reads and the MFMAs
+    Ctr4 xs[RPW];
+#pragma unroll
+    for (int jj = 0; jj < RPW; ++jj) {
+      const int mt = wave + W * jj;
+      if (mt < NT) xs[jj] = noise_block(2u * mt + ctr_half, tg, ctr_trial, stream, k0, k1);
+    }
+    v4i B[NT][KW];  // s(t), all tiles
+#pragma unroll
+    for (int mt = 0; mt < NT; ++mt)
+#pragma unroll
+      for (int j = 0; j < KW; ++j) B[mt][j] = word(cur, mt, j);
+    const float* tab = sTab + cur * kTabEntries + kNoiseVals;
+#pragma unroll
+    for (int jj = 0; jj < RPW; ++jj) {
+      const int mt = wave + W * jj;
+      if (mt >= NT) break;  // uniform
+      v16f acc;
+      real_row_tile<NT, PREC>(sJ, lane, mt, B, acc);
+      uint32_t xw[4] = {xs[jj].x, xs[jj].y, xs[jj].z, xs[jj].w};
+      uint32_t sw[4 * KW];
+#pragma unroll
+      for (int q = 0; q < 4 * KW; ++q) sw[q] = (uint32_t)B[mt][q >> 2][q & 3];
+      float th[16];
+      int sm[16];
+      real_tile_thresholds<PREC>(tab, xw, sw, th, sm);
+      v4i bn[KW];
+      const float pt = real_tile_apply<PREC, HAS_H>(acc, scale, sH, 32 * mt + 16 * half, th, sm, bn);
+      sP[(cur * NT + mt) * 64 + lane] = pt;
+#pragma unroll
+      for (int j = 0; j < KW; ++j) word(nxt, mt, j) = bn[j];
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    if (threadIdx.x == 0 && (t & 255) == 0 && t < a.T)
+      sFlag[0] = __atomic_load_n(a.cancel, __ATOMIC_RELAXED) != 0 ? 1 : 0;
+    lds_barrier();  // s(t+1), the tile energy sums of s(t) and the next table are complete
+    float ep = 0.0f;
+#pragma unroll
+    for (int mt = 0; mt < NT; ++mt) ep += sP[(cur * NT + mt) * 64 + lane];  // tile order
+    const float E = -0.5f * (ep + __shfl_xor(ep, 32));
+    if (E < e_best) {
+      e_best = E;
+      t_best = tg;
+      if (live) {
+        size_t off = cell * kNpad + 16 * half;
+        PIM_FENCE(off);
+        int8_t* dst = a.best_s + off;
+#pragma unroll
+        for (int jj = 0; jj < RPW; ++jj) {
+          const int mt = wave + W * jj;
+          if (mt < NT) *reinterpret_cast<v4i*>(dst + 32 * mt) = real_tile_i8<PREC>(B[mt]);
+        }
+      }
+    }
+    if (first_hit < 0 && E <= target) first_hit = tg;
+    e_cur = E;
+    if (t == a.T) break;  // uniform: s(T) is in B
+    const bool stop = (t & 255) == 0 && sFlag[0] != 0;  // uniform: written before the barrier
+    if (stop) {
+      done = t;  // s(t) stays the final state
+      break;
+    }
+  }
+  // the final state s(t) is in B (every wave holds all tiles; each writes its own)
+  if (!live) return;
+  {
+    v4i B[NT][KW];
+    const int last = (done == a.T ? a.T : done) & 1;
+#pragma unroll
+    for (int mt = 0; mt < NT; ++mt)
+#pragma unroll
+      for (int j = 0; j < KW; ++j) B[mt][j] = word(last, mt, j);
+#pragma unroll
+    for (int jj = 0; jj < RPW; ++jj) {
+      const int mt = wave + W * jj;
+      if (mt < NT) *reinterpret_cast<v4i*>(a.final_s + cell * kNpad + 32 * mt + 16 * half) = real_tile_i8<PREC>(B[mt]);
+    }
+  }
+  if (wave == 0 && half == 0) {
+    a.e_best[cell] = e_best;
+    a.t_best[cell] = t_best;
+    a.first_hit[cell] = first_hit;
+    a.e_final[cell] = e_cur;
+    a.steps_done[cell] = done;
+  }
+}
+
+constexpr int kSplitMaxBlocks = 128;  // 32-trial blocks per launch up to which the split form runs
+
+template <int NT, int PREC, bool HAS_H>
+constexpr size_t split_lds_bytes() {
+  return frag_bytes(PREC, NT) + (HAS_H ? NT * 32 * 4 : 0) + (size_t)2 * NT * words<PREC>() * 1024 +
+         (size_t)2 * kTabEntries * 4 + (size_t)2 * NT * 64 * 4 + 16;
+}
+
+template <int NT, int PREC, bool HAS_H>
+hipError_t launch_split(const SweepRealArgs& a, int count, hipStream_t s) {
+  constexpr int W = NT < 4 ? NT : 4;
+  constexpr size_t lds = split_lds_bytes<NT, PREC, HAS_H>();
+  auto kern = sweep_real_split_kernel<NT, PREC, HAS_H, W>;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  const dim3 grid((a.R + 31) / 32, count);
+  hipLaunchKernelGGL(kern, grid, dim3(64 * W), lds, s, a);
+  return hipGetLastError();
+}
+
 template <int NT, int PREC, bool HAS_H>
 hipError_t launch_nt(const SweepRealArgs& a, int count, hipStream_t s) {
+  // few trial blocks: the latency form (when its LDS fits)
+  if (NT > 1 && (size_t)count * ((a.R + 31) / 32) <= (size_t)kSplitMaxBlocks &&
+      split_lds_bytes<NT, PREC, HAS_H>() <= (size_t)160 * 1024)
+    return launch_split<NT, PREC, HAS_H>(a, count, s);
   const int nw = std::min(kMaxWaves, (a.R + 31) / 32);
   const size_t lds = frag_bytes(PREC, NT) + (HAS_H ? NT * 32 * 4 : 0) + (size_t)nw * kRealTabBytes;
   auto kern = sweep_real_kernel<NT, PREC, HAS_H>;

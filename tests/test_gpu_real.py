@@ -184,3 +184,26 @@ def test_mimo_detection_matches_oracle_statistically(gpu_lib, prec, kernel):
     sd = np.sqrt(2 * max(ser_orc, 0.01) * (1 - max(ser_orc, 0.01)) / total)
     assert abs(ser_gpu - ser_orc) <= 4 * sd + 0.01
     batch.close()
+
+
+@pytest.mark.parametrize("prec,nt", [("fp8", 16), ("bf16", 16), ("fp8", 32), ("fp8", 48), ("bf16", 48)])
+def test_latency_and_batched_forms_agree(gpu_lib, prec, nt):
+    """A launch with few 32-trial blocks runs the latency form (the block's row
+    tiles split over several waves, spins exchanged through LDS); a launch
+    with many runs one wave per block.  The same MIMO instances (arbitrary
+    reals) run both ways give identical trajectories, best states, steps and
+    binary32 energies."""
+    _say(f"latency vs batched forms prec={prec} Nt={nt}")
+    pim = gpu_lib
+    count, trials, steps = 40, 128, 48  # 160 blocks together: the batched form
+    probs, insts, maps = _mimo_instances(pim, nt, 16, 18.0, count, prec, seed=8)
+    beta, eta = w.constant(steps, 1.0), w.mimo_eta(steps, 0.05, 1.0)
+    big = pim.Batch(insts, trials).run(beta, eta, seed=9)
+    for k0 in range(0, count, 8):  # 8 instances x 4 blocks = 32 blocks: the latency form
+        small = pim.Batch(insts[k0:k0 + 8], trials).run(beta, eta, seed=9)
+        for j in range(8):
+            a, b = big.trials_of(k0 + j), small.trials_of(j)
+            for key in ("final", "best_state", "e_best", "t_best", "e_final"):
+                np.testing.assert_array_equal(a[key], b[key], err_msg=f"{key} instance {k0 + j}")
+        small.close()
+    big.close()
