@@ -42,6 +42,7 @@ double fp8_e4m3_value(uint8_t c) {
 uint16_t bf16_rne(double x) {
   if (x == 0.0 || std::isnan(x)) return 0;
   const uint16_t sign = x < 0.0 ? 0x8000 : 0x0000;
+  if (std::isinf(x)) return sign | 0x7F80;
   const double a = std::fabs(x);
   int e;
   (void)std::frexp(a, &e);

@@ -664,6 +664,7 @@ __device__ uint8_t d_fp8(double x) {
 __device__ uint16_t d_bf16(double x) {
   if (x == 0.0 || isnan(x)) return 0;
   const uint16_t sign = x < 0.0 ? 0x8000 : 0x0000;
+  if (isinf(x)) return sign | 0x7F80;
   const double a = fabs(x);
   int e;
   (void)frexp(a, &e);
