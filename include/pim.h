@@ -348,7 +348,9 @@ pim_status pim_server_create(const pim_server_config* cfg, pim_server** out);
  * and h[r] (NULL for zeros).  Validates them and copies them into pinned
  * staging (quantisation happens on the device at launch); *admitted is how
  * many were taken (fewer when no slot or budget is free: poll, then submit
- * the rest).  No device work. */
+ * the rest).  An invalid request returns PIM_ERR_INVALID; the requests before
+ * it are admitted and counted in *admitted.  Large submissions are validated
+ * and staged by the server's host worker threads.  No device work. */
 pim_status pim_server_submit(pim_server* server, int32_t count, const uint32_t* ids, const int32_t* ns,
                              const double* const* J, const double* const* h, int32_t* admitted);
 

@@ -539,7 +539,9 @@ class Server:
         _check(lib.pim_server_create(ctypes.byref(c), ctypes.byref(self._handle)))
 
     def submit(self, ids, Js, hs=None):
-        """Stages requests (ids, J arrays, h arrays); returns how many were admitted."""
+        """Stages requests (ids, J arrays, h arrays); returns how many were
+        admitted.  A rejected request raises PimError whose `admitted` is the
+        number of requests before it that were admitted."""
         k = len(ids)
         if k == 0:
             return 0
@@ -550,8 +552,13 @@ class Server:
         jp = (ctypes.POINTER(ctypes.c_double) * k)(*[_ptr(J, ctypes.c_double) for J in Js])
         hp = None if hs is None else (ctypes.POINTER(ctypes.c_double) * k)(*[_ptr(h, ctypes.c_double) for h in hs])
         adm = ctypes.c_int32()
-        _check(lib.pim_server_submit(self._handle, k, _ptr(idarr, ctypes.c_uint32), _ptr(ns, ctypes.c_int32), jp,
-                                     hp, ctypes.byref(adm)))
+        st = lib.pim_server_submit(self._handle, k, _ptr(idarr, ctypes.c_uint32), _ptr(ns, ctypes.c_int32), jp, hp,
+                                   ctypes.byref(adm))
+        if st != PIM_OK:
+            # the requests before the rejected one are admitted; the error says how many
+            err = PimError(st, lib.pim_last_error().decode(errors="replace"))
+            err.admitted = adm.value
+            raise err
         return adm.value
 
     def flush(self):

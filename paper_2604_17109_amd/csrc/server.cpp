@@ -19,11 +19,17 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
+#include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <functional>
+#include <memory>
+#include <mutex>
 #include <new>
+#include <thread>
 #include <vector>
 
 #include "internal.hpp"
@@ -81,6 +87,121 @@ struct Klass {
   int open = -1;                 // chunk accepting requests, or -1
 };
 
+// Persistent host workers for the per-request parts of pim_server_submit
+// (validation and staging copies of large binary64 couplings).  run() hands
+// out item indices through an atomic counter; the calling thread works too
+// and returns when every item is done.
+class Pool {
+ public:
+  explicit Pool(int workers) {
+    for (int i = 0; i < workers; ++i) threads_.emplace_back([this] { loop(); });
+  }
+  ~Pool() {
+    {
+      std::lock_guard<std::mutex> g(m_);
+      stop_ = true;
+    }
+    cv_.notify_all();
+    for (auto& t : threads_) t.join();
+  }
+  void run(int count, const std::function<void(int)>& f) {
+    if (count <= 0) return;
+    {
+      std::lock_guard<std::mutex> g(m_);
+      fn_ = &f;
+      total_ = count;
+      next_.store(0);
+      active_ = (int)threads_.size();
+      ++gen_;
+    }
+    cv_.notify_all();
+    for (int i; (i = next_.fetch_add(1)) < count;) f(i);
+    std::unique_lock<std::mutex> g(m_);
+    done_cv_.wait(g, [this] { return active_ == 0; });
+    fn_ = nullptr;
+  }
+
+ private:
+  void loop() {
+    uint64_t seen = 0;
+    for (;;) {
+      const std::function<void(int)>* f;
+      int total;
+      {
+        std::unique_lock<std::mutex> g(m_);
+        cv_.wait(g, [&] { return stop_ || gen_ != seen; });
+        if (stop_) return;
+        seen = gen_;
+        f = fn_;
+        total = total_;
+      }
+      for (int i; (i = next_.fetch_add(1)) < total;) (*f)(i);
+      std::lock_guard<std::mutex> g(m_);
+      if (--active_ == 0) done_cv_.notify_one();
+    }
+  }
+  std::vector<std::thread> threads_;
+  std::mutex m_;
+  std::condition_variable cv_, done_cv_;
+  const std::function<void(int)>* fn_ = nullptr;
+  int total_ = 0, active_ = 0;
+  std::atomic<int> next_{0};
+  uint64_t gen_ = 0;
+  bool stop_ = false;
+};
+
+// J finite, symmetric with a zero diagonal, h finite.  The symmetry check
+// walks 16 x 16 tiles against their transposes, so both stay in cache.
+bool valid_request(const double* J, const double* h, int n) {
+  for (int i = 0; i < n; ++i)
+    if (J[(size_t)i * n + i] != 0.0 || (h && !std::isfinite(h[i]))) return false;
+  constexpr int kTile = 16;
+  for (int ib = 0; ib < n; ib += kTile)
+    for (int jb = ib; jb < n; jb += kTile) {
+      const int ie = std::min(ib + kTile, n), je = std::min(jb + kTile, n);
+      for (int i = ib; i < ie; ++i)
+        for (int j = std::max(jb, i + 1); j < je; ++j) {
+          const double a = J[(size_t)i * n + j];
+          if (!std::isfinite(a) || a != J[(size_t)j * n + i]) return false;
+        }
+    }
+  return true;
+}
+
+// valid_request and the staging copy in one pass: J (n x n) into j64 (np x np,
+// zero-padded) and h into h64 (np, zero-padded), tile by tile with each tile
+// and its transpose checked and copied together, so J is read once.  Returns
+// false (staging then incomplete) if the request is invalid.
+bool validate_and_stage(const double* J, const double* h, int n, size_t np, double* j64, double* h64) {
+  for (int i = 0; i < n; ++i)
+    if (J[(size_t)i * n + i] != 0.0 || (h && !std::isfinite(h[i]))) return false;
+  if (h) std::memcpy(h64, h, n * sizeof(double));
+  else std::fill(h64, h64 + n, 0.0);
+  std::fill(h64 + n, h64 + np, 0.0);
+  constexpr int kTile = 16;
+  for (int ib = 0; ib < n; ib += kTile)
+    for (int jb = ib; jb < n; jb += kTile) {
+      const int ie = std::min(ib + kTile, n), je = std::min(jb + kTile, n);
+      for (int i = ib; i < ie; ++i)
+        for (int j = std::max(jb, i + 1); j < je; ++j) {
+          const double a = J[(size_t)i * n + j];
+          if (!std::isfinite(a) || a != J[(size_t)j * n + i]) return false;
+          j64[(size_t)i * np + j] = a;
+          j64[(size_t)j * np + i] = a;
+        }
+    }
+  for (int i = 0; i < n; ++i) {
+    j64[(size_t)i * np + i] = 0.0;
+    std::fill(j64 + (size_t)i * np + n, j64 + (size_t)(i + 1) * np, 0.0);
+  }
+  std::fill(j64 + (size_t)n * np, j64 + np * np, 0.0);
+  return true;
+}
+
+// Submissions whose couplings total fewer elements than this run on the
+// calling thread alone (waking the workers would cost more than it saves).
+constexpr size_t kParallelElems = (size_t)1 << 17;
+
 }  // namespace
 }  // namespace pim
 
@@ -96,6 +217,7 @@ struct pim_server {
   int next_stream = 0;
   std::deque<pim::Chunk*> inflight;  // launch order
   size_t bytes = 0;                  // device bytes held by slots
+  std::unique_ptr<pim::Pool> pool;   // submit workers
 };
 
 using namespace pim;
@@ -386,6 +508,11 @@ pim_status pim_server_create(const pim_server_config* cfg, pim_server** out) {
       pim_server_destroy(s);
       return fail(PIM_ERR_NOMEM, "server set-up failed");
     }
+    // submit workers: up to 15 besides the caller (a GPU's share of host
+    // cores), none on a single-core host
+    const int hw = (int)std::thread::hardware_concurrency();
+    const int workers = std::min(hw, 16) - 1;
+    if (workers > 0) s->pool.reset(new Pool(workers));
     *out = s;
     return PIM_OK;
   } catch (...) {
@@ -399,46 +526,68 @@ pim_status pim_server_submit(pim_server* s, int32_t count, const uint32_t* ids, 
     if (!s || !ids || !ns || !J || !admitted) return fail(PIM_ERR_INVALID, "NULL argument");
     *admitted = 0;
     if (count <= 0) return PIM_OK;
-    // validation, then slots in order until none is free, then staging of the
-    // binary64 couplings (quantisation and packing happen on the device)
-    int took = 0;
-    for (; took < count; ++took) {
-      const int r = took;
-      const int n = ns[r];
-      if (n < 1 || n > s->cfg.max_n || ids[r] >= (1u << 24) || !J[r])
-        return fail(PIM_ERR_INVALID, "request %d (id %u): n outside [1, max_n], id >= 2^24 or J NULL", r, ids[r]);
-      const double* Jr = J[r];
-      const double* hr = h ? h[r] : nullptr;
-      for (int i = 0; i < n; ++i) {
-        const double* row = Jr + (size_t)i * n;
-        bool ok = row[i] == 0.0 && (!hr || std::isfinite(hr[i]));
-        for (int j = i + 1; j < n && ok; ++j) ok = std::isfinite(row[j]) && row[j] == Jr[(size_t)j * n + i];
-        if (!ok)
-          return fail(PIM_ERR_INVALID, "request %d (id %u): J must be finite and symmetric with a zero diagonal, "
-                      "h finite", r, ids[r]);
+    // (1) argument checks, in order up to the first failure
+    int f = 0;
+    size_t elems = 0;
+    for (; f < count; ++f) {
+      const int n = ns[f];
+      if (n < 1 || n > s->cfg.max_n || ids[f] >= (1u << 24) || !J[f]) break;
+      elems += (size_t)n * n;
+    }
+    const bool par = s->pool && elems >= kParallelElems;
+    auto run = [&](int items, const std::function<void(int)>& fn) {
+      if (par) {
+        s->pool->run(items, fn);
+      } else {
+        for (int i = 0; i < items; ++i) fn(i);
       }
+    };
+    // (2) slots in order until none is free (allocation may happen here)
+    std::vector<std::pair<Chunk*, size_t>> place;
+    place.reserve(f);
+    int took = 0;
+    for (; took < f; ++took) {
+      const int n = ns[took];
       const int cls = (n + 31) / 32 - 1;
       Chunk* c = chunk_for(s, cls);
       if (!c) break;  // no slot: the caller polls and submits the rest later
-      const size_t np = s->classes[cls].npad, sl = c->count;
+      const size_t sl = c->count;
       if (c->count == 0) c->first = std::chrono::steady_clock::now();
-      double* h64 = c->h_h64 + sl * np;
-      double* j64 = c->h_j64 + sl * np * np;
-      if (hr) std::memcpy(h64, hr, n * sizeof(double));
-      else std::fill(h64, h64 + n, 0.0);
-      std::fill(h64 + n, h64 + np, 0.0);
-      if ((size_t)n == np) {
-        std::memcpy(j64, Jr, (size_t)n * n * sizeof(double));
-      } else {
-        std::fill(j64, j64 + np * np, 0.0);
-        for (int i = 0; i < n; ++i) std::memcpy(j64 + (size_t)i * np, Jr + (size_t)i * n, n * sizeof(double));
-      }
-      c->h_sid[sl] = ids[r];
-      c->ids.push_back(ids[r]);
+      c->h_sid[sl] = ids[took];
+      c->ids.push_back(ids[took]);
       c->ns.push_back(n);
       ++c->count;
+      place.emplace_back(c, sl);
     }
+    // (3) content checks and staging copies of the binary64 couplings in one
+    //     pass per request (quantisation and packing happen on the device at
+    //     launch)
+    std::vector<uint8_t> ok(took);
+    run(took, [&](int r) {
+      Chunk* c = place[r].first;
+      const size_t sl = place[r].second, np = s->classes[c->cls].npad;
+      ok[r] = validate_and_stage(J[r], h ? h[r] : nullptr, ns[r], np, c->h_j64 + sl * np * np, c->h_h64 + sl * np)
+                  ? 1 : 0;
+    });
+    int g = 0;
+    while (g < took && ok[g]) ++g;
+    if (g < took) {
+      // an invalid request: it and the ones after it give their slots back
+      // (the last ones taken in each chunk, so in reverse order)
+      for (int r = took - 1; r >= g; --r) {
+        Chunk* c = place[r].first;
+        --c->count;
+        c->ids.pop_back();
+        c->ns.pop_back();
+      }
+      *admitted = g;
+      return fail(PIM_ERR_INVALID, "request %d (id %u): J must be finite and symmetric with a zero diagonal, "
+                  "h finite", g, ids[g]);
+    }
+    // requests before an invalid one are admitted (and counted) as usual
     *admitted = took;
+    if (took == f && f < count)
+      return fail(PIM_ERR_INVALID, "request %d (id %u): n outside [1, max_n], id >= 2^24 or J NULL", f, ids[f]);
     return PIM_OK;
   } catch (const std::bad_alloc&) {
     return fail(PIM_ERR_NOMEM, "host allocation failed");

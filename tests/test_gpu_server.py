@@ -97,3 +97,38 @@ def test_server_admission_limits(gpu_lib):
     tiny = _server(pim, hbm_budget=1024)
     assert tiny.submit([1], [J], [h]) == 0               # a chunk needs more than the budget
     tiny.close()
+
+
+def test_server_parallel_staging_and_rejection(gpu_lib):
+    """Large submissions are validated and staged by the server's host workers:
+    their results equal the same requests submitted one at a time.  An
+    invalid request is rejected; the requests before it are admitted, counted
+    in the error, and finish normally."""
+    _say("server: parallel staging, rejection with partial admission")
+    pim = gpu_lib
+    shapes = [(64, 16), (32, 16), (8, 4), (64, 4), (16, 16)]   # N = 256, 128, 16, 128, 64
+    reqs = [(900 + k, *_request(pim, 40 + k, *shapes[k % len(shapes)])) for k in range(12)]
+    one = _server(pim, max_n=256)
+    for rid, J, h in reqs:                      # one at a time: the calling thread alone
+        assert one.submit([rid], [J], [h]) == 1
+        one.flush()
+    ref = _drain(one, len(reqs))
+    one.close()
+    many = _server(pim, max_n=256)
+    assert many.submit([r[0] for r in reqs], [r[1] for r in reqs], [r[2] for r in reqs]) == len(reqs)
+    many.flush()
+    got = _drain(many, len(reqs))
+    for rid, J, _ in reqs:
+        n = J.shape[0]
+        assert np.array_equal(got[rid][0][:n], ref[rid][0][:n]) and got[rid][1] == ref[rid][1], rid
+    # rejection: the third request is not symmetric
+    J0, h0 = reqs[0][1], reqs[0][2]
+    bad = J0.copy()
+    bad[3, 5] += 1e-9
+    with pytest.raises(pim.PimError) as ei:
+        many.submit([1, 2, 3, 4], [J0, reqs[1][1], bad, J0], [h0, reqs[1][2], h0, h0])
+    assert ei.value.admitted == 2 and "symmetric" in str(ei.value)
+    assert many.pending() == (2, 0)
+    many.flush()
+    assert set(_drain(many, 2)) == {1, 2}
+    many.close()
