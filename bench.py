@@ -25,7 +25,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 INT8_MFMA_PEAK = 5.0e15            # dense int8 MFMA, ops/s (MI355X)
-VALU_PEAK = 256 * 4 * 16 * 2.4e9   # 32-bit VALU lane-ops/s: CUs x SIMDs x lanes x clock
+# 32-bit VALU lane-ops/s: CUs x SIMDs x 32 lanes per clock x clock, i.e. the published FP32 vector
+# rate (157.3 TFLOP/s) with a fused multiply-add counted as one lane-op
+VALU_PEAK = 256 * 4 * 32 * 2.4e9
 HBM_PEAK = 8.0e12
 
 
