@@ -29,6 +29,7 @@ INT8_MFMA_PEAK = 5.0e15            # dense int8 MFMA, ops/s (MI355X)
 # rate (157.3 TFLOP/s) with a fused multiply-add counted as one lane-op
 VALU_PEAK = 256 * 4 * 32 * 2.4e9
 HBM_PEAK = 8.0e12
+LDS_PEAK = 256 * 256 * 2.4e9       # LDS read bytes/s: CUs x 256 B/clk (128-bit reads) x clock
 
 
 def parse():
@@ -470,6 +471,14 @@ def main():
     alu_per_update = 6.5
     alu_ops = alu_per_update * updates
     kernel_s = kernel_ms / 1000.0
+    # LDS traffic of the int8 kernel per wave (32 trials) and step: the J
+    # fragments (Npad^2 bytes), 2-byte threshold lookups of the spins that carry
+    # decisions, and the 1 KB table written for the next step
+    nt = (n + 31) // 32
+    rem = n - 32 * (nt - 1)
+    tail = 16 if rem > 12 else 12 if rem > 8 else 8 if rem > 4 else 4
+    lds_per_wave_step = nt * nt * 1024 + ((nt - 1) * 16 + tail) * 64 * 2 + 1024
+    lds_bytes = lds_per_wave_step * float(I) * ((R + 31) // 32) * (T + 1)
     line = {
         "metric": "spin-updates/s (batched SK-1 N=200)",
         "value": value,
@@ -495,6 +504,9 @@ def main():
                      "algorithmic_per_update": alu_per_update},
         "roofline_mfma": {"bound": "mfma", "achieved": mfma_ops / kernel_s / 1e12, "peak": INT8_MFMA_PEAK / 1e12,
                           "unit": "TOP/s", "frac": mfma_ops / kernel_s / INT8_MFMA_PEAK},
+        "lds": ({"achieved": lds_bytes / kernel_s / 1e9, "peak": LDS_PEAK / 1e9, "unit": "GB/s",
+                 "frac": lds_bytes / kernel_s / LDS_PEAK, "bytes_per_wave_step": lds_per_wave_step}
+                if args.kernel == "mfma" and n <= 256 else None),
     }
     if args.plain_instances > 0 and args.kernel == "mfma":
         # the plain FP32 per-instance kernel on the first instances of the same
