@@ -104,6 +104,8 @@ class Pool {
     cv_.notify_all();
     for (auto& t : threads_) t.join();
   }
+  // f(i) for i in [0, count) on the workers and the calling thread; returns
+  // when every call has returned.  f must not throw.
   void run(int count, const std::function<void(int)>& f) {
     if (count <= 0) return;
     {
@@ -150,28 +152,11 @@ class Pool {
   bool stop_ = false;
 };
 
-// J finite, symmetric with a zero diagonal, h finite.  The symmetry check
-// walks 16 x 16 tiles against their transposes, so both stay in cache.
-bool valid_request(const double* J, const double* h, int n) {
-  for (int i = 0; i < n; ++i)
-    if (J[(size_t)i * n + i] != 0.0 || (h && !std::isfinite(h[i]))) return false;
-  constexpr int kTile = 16;
-  for (int ib = 0; ib < n; ib += kTile)
-    for (int jb = ib; jb < n; jb += kTile) {
-      const int ie = std::min(ib + kTile, n), je = std::min(jb + kTile, n);
-      for (int i = ib; i < ie; ++i)
-        for (int j = std::max(jb, i + 1); j < je; ++j) {
-          const double a = J[(size_t)i * n + j];
-          if (!std::isfinite(a) || a != J[(size_t)j * n + i]) return false;
-        }
-    }
-  return true;
-}
-
-// valid_request and the staging copy in one pass: J (n x n) into j64 (np x np,
-// zero-padded) and h into h64 (np, zero-padded), tile by tile with each tile
-// and its transpose checked and copied together, so J is read once.  Returns
-// false (staging then incomplete) if the request is invalid.
+// Checks a request (J finite, symmetric with a zero diagonal; h finite) while
+// staging it: J (n x n) into j64 (np x np, zero-padded) and h into h64 (np,
+// zero-padded).  J is walked in 16 x 16 tiles, each compared with and copied
+// together with its transpose, so both stay in cache and J is read once.
+// Returns false (staging then incomplete) if the request is invalid.
 bool validate_and_stage(const double* J, const double* h, int n, size_t np, double* j64, double* h64) {
   for (int i = 0; i < n; ++i)
     if (J[(size_t)i * n + i] != 0.0 || (h && !std::isfinite(h[i]))) return false;
