@@ -464,7 +464,10 @@ pim_status run_prepare(pim_batch* b, const pim_schedule* sc, hipStream_t s, RunC
                          hipMemcpyHostToDevice, s);
     // the host tables must stay alive until the copies are done
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess) return device_fail(e, "schedule upload");
+    if (e != hipSuccess) {
+      (void)hipStreamSynchronize(s);  // copies already queued still read the host tables
+      return device_fail(e, "schedule upload");
+    }
     __atomic_store_n(b->h_cancel, 0, __ATOMIC_SEQ_CST);
     ctx.T = T;
     ctx.L = L;
@@ -760,6 +763,7 @@ pim_status pim_create_real(const double* J, const double* h, const pim_params* p
     if (e == hipSuccess) e = hipMemcpyAsync(inst->d_h64, h64.data(), (size_t)n * 8, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
+      (void)hipStreamSynchronize(s);  // copies already queued still read the host buffers
       pim_destroy(inst);
       return fail(PIM_ERR_DEVICE, "copying the instance to the device failed: %s", hipGetErrorString(e));
     }
@@ -814,6 +818,7 @@ pim_status pim_create(const int8_t* J, const int32_t* h, const pim_params* param
     if (e == hipSuccess) e = hipMemcpyAsync(inst->d_j8, J, (size_t)n * n, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);  // host staging buffers go out of scope
     if (e != hipSuccess) {
+      (void)hipStreamSynchronize(s);  // copies already queued still read the host buffers
       pim_destroy(inst);
       return fail(PIM_ERR_DEVICE, "copying the instance to the device failed: %s", hipGetErrorString(e));
     }
@@ -954,6 +959,7 @@ pim_status pim_batch_create(pim_instance* const* insts, int32_t count, int32_t t
     }
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
+      (void)hipStreamSynchronize(s);  // copies already queued still read the host buffers
       free_batch_buffers(b);
       delete b;
       return fail(PIM_ERR_DEVICE, "batch setup failed: %s", hipGetErrorString(e));
@@ -1190,6 +1196,7 @@ pim_status pim_energy(const pim_instance* inst, const int8_t* spins, int32_t cou
     if (e == hipSuccess) e = launch_energy_f64(ea, s);
     if (e == hipSuccess) e = hipMemcpyAsync(out, d_o, (size_t)count * sizeof(double), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
+    else (void)hipStreamSynchronize(s);  // a queued copy may still read the caller's spins
     dev_free(d_s, s);
     dev_free(d_o, s);
     if (e != hipSuccess) return fail(PIM_ERR_DEVICE, "pim_energy failed: %s", hipGetErrorString(e));
