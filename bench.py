@@ -13,6 +13,7 @@ Prints one JSON line.  Workload defaults: 128 SK-1 instances of N = 200
 Gaussian noise.
 """
 import argparse
+import gc
 import json
 import math
 import os
@@ -305,16 +306,18 @@ def serving_leg(args):
             srv.flush()
             left -= len(srv.poll(states=False)[0])
         rng = np.random.default_rng(29)
-        for lam in rates:
-            arrive = np.cumsum(rng.exponential(1.0 / lam, size=M))
-            done_t = np.full(M, np.nan)
+
+        def stream(arrive, count):
+            # Poisson arrivals of requests 0..count-1: submit as they arrive,
+            # launch, collect; returns completion times and final states
+            done_t = np.full(count, np.nan)
             states = {}
             nxt = finished = 0
             t0 = time.perf_counter()
-            while finished < M:
+            while finished < count:
                 now = time.perf_counter() - t0
-                if nxt < M and arrive[nxt] <= now:
-                    k = int(np.searchsorted(arrive, now, side="right"))
+                if nxt < count and arrive[nxt] <= now:
+                    k = int(np.searchsorted(arrive[:count], now, side="right"))
                     nxt += srv.submit(list(range(nxt, k)), Js[nxt:k], hs[nxt:k])
                 srv.flush()
                 ids, st, _ = srv.poll()
@@ -323,6 +326,20 @@ def serving_leg(args):
                     for i, sv in zip(ids, st):
                         states[int(i)] = sv
                     finished += len(ids)
+            return done_t, states
+
+        # steady state first: a short unmeasured stream at the highest rate
+        # lets the server grow its slot chunks to what the load needs
+        warm = min(M, 1000)
+        stream(np.cumsum(rng.exponential(1.0 / max(rates), size=warm)), warm)
+        for lam in rates:
+            arrive = np.cumsum(rng.exponential(1.0 / lam, size=M))
+            gc.collect()
+            gc.disable()  # no collector pauses inside the measured stream
+            try:
+                done_t, states = stream(arrive, M)
+            finally:
+                gc.enable()
             lat = (done_t - arrive) * 1e6
             se = 0
             for k in range(M):

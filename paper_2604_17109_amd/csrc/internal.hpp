@@ -291,6 +291,11 @@ struct pim_batch {
   size_t h_thtab_bytes = 0;
   int32_t* d_steptab = nullptr;
   size_t steptab_bytes = 0;
+  // schedule the (u, s) step tables in d_thtab were compiled from: a run with
+  // the same beta and eta (bit for bit) reuses them without compiling or
+  // uploading again
+  bool tab_valid = false;
+  std::vector<double> tab_beta, tab_eta;
   int32_t* h_cancel = nullptr;    // pinned, host-mapped
   int32_t* d_cancel = nullptr;    // device view of h_cancel
   hipEvent_t ev0 = nullptr, ev1 = nullptr;

@@ -362,8 +362,16 @@ pim_status run_prepare(pim_batch* b, const pim_schedule* sc, hipStream_t s, RunC
     const bool seq = sc->kernel == PIM_KERNEL_SEQ_I8;
     const bool mfma = sc->kernel == PIM_KERNEL_MFMA_I8 || seq;  // both read the (u, s) tables
     const size_t entry = real ? 4 : 2;  // bytes per table entry
-    if (mfma) {
-      const size_t need = (size_t)ncls * T * kTabEntries * entry;
+    const size_t thtab_need = mfma ? (size_t)ncls * T * kTabEntries * entry : 0;
+    // the tables on the device already hold this schedule: nothing to compile
+    // or upload (they depend only on beta, eta and the batch's fixed rules)
+    const bool tab_cached = mfma && b->tab_valid && b->d_thtab && b->thtab_bytes >= thtab_need &&
+                            b->tab_beta.size() == (size_t)T &&
+                            std::memcmp(b->tab_beta.data(), sc->beta, (size_t)T * sizeof(double)) == 0 &&
+                            std::memcmp(b->tab_eta.data(), sc->eta, (size_t)T * sizeof(double)) == 0;
+    if (mfma && !tab_cached) {
+      b->tab_valid = false;
+      const size_t need = thtab_need;
       if (need > b->h_thtab_bytes) {
         if (b->h_thtab) (void)hipHostFree(b->h_thtab);
         b->h_thtab = nullptr;
@@ -410,7 +418,6 @@ pim_status run_prepare(pim_batch* b, const pim_schedule* sc, hipStream_t s, RunC
       }
     }
     // ---- upload ----
-    const size_t thtab_need = mfma ? (size_t)ncls * T * kTabEntries * entry : 0;
     if (mfma && thtab_need > b->thtab_bytes) {
       dev_free(b->d_thtab, s);
       b->d_thtab = nullptr;
@@ -457,8 +464,8 @@ pim_status run_prepare(pim_batch* b, const pim_schedule* sc, hipStream_t s, RunC
                              hipMemcpyDeviceToDevice, s);
       if (e != hipSuccess) return device_fail(e, "sequential coupling layout");
     }
-    if (mfma) e = hipMemcpyAsync(b->d_thtab, b->h_thtab, thtab_need, hipMemcpyHostToDevice, s);
-    else e = hipMemcpyAsync(b->d_steptab, steptab.data(), steptab.size() * 4, hipMemcpyHostToDevice, s);
+    if (mfma && !tab_cached) e = hipMemcpyAsync(b->d_thtab, b->h_thtab, thtab_need, hipMemcpyHostToDevice, s);
+    else if (!mfma) e = hipMemcpyAsync(b->d_steptab, steptab.data(), steptab.size() * 4, hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
       e = hipMemcpyAsync(b->d_target, real ? (const void*)tgtf.data() : (const void*)tgt.data(), b->count * 4,
                          hipMemcpyHostToDevice, s);
@@ -467,6 +474,11 @@ pim_status run_prepare(pim_batch* b, const pim_schedule* sc, hipStream_t s, RunC
     if (e != hipSuccess) {
       (void)hipStreamSynchronize(s);  // copies already queued still read the host tables
       return device_fail(e, "schedule upload");
+    }
+    if (mfma && !tab_cached) {
+      b->tab_beta.assign(sc->beta, sc->beta + T);
+      b->tab_eta.assign(sc->eta, sc->eta + T);
+      b->tab_valid = true;
     }
     __atomic_store_n(b->h_cancel, 0, __ATOMIC_SEQ_CST);
     ctx.T = T;

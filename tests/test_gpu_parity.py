@@ -271,6 +271,42 @@ def test_recorded_states_and_flip_rate(gpu_lib, xi):
     batch.close()
 
 
+def test_schedule_changes_between_runs(gpu_lib):
+    """Runs of one batch with changing schedules: the same one twice, one that
+    differs only in its last beta, one that differs only in its first eta, a
+    shorter one, then the first again.  Every run is bit-exact against the
+    oracle, on a single-N batch and on an uneven-N (graph) batch, so step tables
+    kept on the device are reused only for an identical schedule."""
+    pim = gpu_lib
+    ztab = w.gauss_table(8)
+    beta_a = w.linear_beta(120, 0.1, 3.0)
+    eta_a = w.eta_sqrt_beta_over_5(beta_a)
+    beta_b = beta_a.copy()
+    beta_b[-1] += 0.25
+    eta_d = eta_a.copy()
+    eta_d[0] *= 0.5
+    scheds = [("A", beta_a, eta_a), ("A again", beta_a, eta_a), ("last beta changed", beta_b, eta_a),
+              ("A", beta_a, eta_a), ("first eta changed", beta_a, eta_d),
+              ("shorter", beta_a[:60].copy(), eta_a[:60].copy()), ("A", beta_a, eta_a)]
+    for ns in ([40, 40], [20, 64]):
+        trials = 48
+        probs, insts = [], []
+        for k, n in enumerate(ns):
+            J, h = w.random_int8(n, seed=61, index=k, jmax=2, hmax=2)
+            c = 1.0 / np.sqrt(n)
+            probs.append((J, h, c))
+            insts.append(pim.Instance(J, h, j_scale=c, xi=0.5, noise_table=ztab, rng_stream=70 + k))
+        batch = pim.Batch(insts, trials)
+        targets = [float(pimi.energy(J, h, np.ones(len(h), dtype=np.int64))) - 1 for (J, h, c) in probs]
+        for name, beta, eta in scheds:
+            _say(f"schedule change, N {ns}: {name}")
+            batch.run(beta, eta, seed=5, target=targets)
+            for k, (J, h, c) in enumerate(probs):
+                ref = _oracle(J, h, c, 0.5, 4, ztab, beta, eta, 5, 70 + k, np.arange(trials), target=targets[k])
+                _compare(batch, k, ref, np.arange(trials), len(h))
+        batch.close()
+
+
 def test_uneven_n_batch_one_graph(gpu_lib):
     """Instances of different N in one batch (one graph launch per run): every
     instance bit-exact against the oracle, with caller initial spins for some
