@@ -307,6 +307,31 @@ def test_schedule_changes_between_runs(gpu_lib):
         batch.close()
 
 
+def test_kernel_changes_between_runs(gpu_lib):
+    """One batch, one schedule, alternating kernels: int8 MFMA, plain FP32,
+    sequential (which reads the same cached step tables as the MFMA kernel),
+    then int8 MFMA again.  The parallel runs match the oracle's parallel
+    dynamics and the sequential run its sequential dynamics, bit for bit."""
+    pim = gpu_lib
+    n, trials = 40, 48
+    ztab = w.gauss_table(8)
+    J, h = w.random_int8(n, seed=62, index=0, jmax=2, hmax=2)
+    c = 1.0 / np.sqrt(n)
+    beta = w.linear_beta(100, 0.1, 3.0)
+    eta = w.eta_sqrt_beta_over_5(beta)
+    inst = pim.Instance(J, h, j_scale=c, xi=0.5, noise_table=ztab, rng_stream=9)
+    batch = pim.Batch([inst], trials)
+    target = int(pimi.energy(J, h, np.ones(n, dtype=np.int64))) - 1
+    par = _oracle(J, h, c, 0.5, 4, ztab, beta, eta, 6, 9, np.arange(trials), target=target)
+    prob = pimi.Problem(J, h, c=c, xi=0.5, levels=4, ztab=ztab)
+    seq = pimi.run_sequential(prob, beta, eta, 6, 9, np.arange(trials), target=target)
+    for kernel, ref in (("mfma", par), ("plain", par), ("seq", seq), ("mfma", par), ("seq", seq)):
+        _say(f"kernel change: {kernel}")
+        batch.run(beta, eta, seed=6, kernel=kernel, target=[target])
+        _compare(batch, 0, ref, np.arange(trials), n)
+    batch.close()
+
+
 def test_uneven_n_batch_one_graph(gpu_lib):
     """Instances of different N in one batch (one graph launch per run): every
     instance bit-exact against the oracle, with caller initial spins for some
