@@ -176,6 +176,29 @@ def mimo_leg(args):
             kus.append(b_)
         lat[name] = {"e2e_p50_us": float(np.percentile(e2e, 50)), "e2e_p99_us": float(np.percentile(e2e, 99)),
                      "kernel_p50_us": float(np.percentile(kus, 50)), "kernel_p99_us": float(np.percentile(kus, 99))}
+    # the same requests one at a time through the request server (FP8), which
+    # keeps its device buffers and step tables between requests: submit ->
+    # launch at once (no batching wait) -> poll until the result is readable
+    srv = pim.Server(max_n=n, trials=R, beta=beta, eta=eta, xi=cfg["xi"], noise_table=ztab, prec="fp8",
+                     slots_per_class=4, max_batch=1, streams=1, seed=11, max_wait_us=0.0, prealloc_chunks=1)
+    e2e, same = [], 0
+    for k in range(-5, min(args.mimo_latency, M)):  # the first 5 are a warm-up
+        kk = max(k, 0)
+        J, h, xm = maps[kk]
+        t0 = time.perf_counter()
+        srv.submit([kk], [J], [h])
+        srv.flush()
+        got = []
+        while not len(got):
+            got, st, _ = srv.poll()
+        dt = time.perf_counter() - t0
+        if k >= 0:
+            e2e.append(dt * 1e6)
+            x = pim.mimo_decode(xm, st[0][:n], qam, cfg["mapping"])
+            same += int(np.array_equal(x, one_request(kk, "fp8", "mfma")[2]))
+    srv.close()
+    lat["server_fp8"] = {"e2e_p50_us": float(np.percentile(e2e, 50)), "e2e_p99_us": float(np.percentile(e2e, 99)),
+                         "same_detection_as_one_shot": same / len(e2e)}
     lat["kernel_p99_speedup_fp8_vs_plain"] = lat["plain_f32"]["kernel_p99_us"] / lat["fp8_mfma"]["kernel_p99_us"]
     lat["e2e_p99_speedup_fp8_vs_plain"] = lat["plain_f32"]["e2e_p99_us"] / lat["fp8_mfma"]["e2e_p99_us"]
     out["latency"] = lat
