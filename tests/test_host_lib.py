@@ -167,3 +167,60 @@ def test_valid_arguments_pass_validation(pim):
     # row bound sum |J| + |h| stays below the field limit for n = 40
     assert pim.validate(J, h, j_scale=0.1, xi=0.3, levels=5) is None
     assert pim.validate(w.sk1(256)[0], j_scale=1 / 16, xi=0.5) is None
+
+
+def _server_config(pim, keep, **over):
+    import ctypes
+    T = over.pop("steps", 16)
+    beta = np.ascontiguousarray(over.pop("beta", np.full(T, 1.0)), dtype=np.float64)
+    eta = np.ascontiguousarray(over.pop("eta", np.full(T, 0.3)), dtype=np.float64)
+    keep += [beta, eta]
+    c = pim.ServerConfig()
+    c.max_n, c.slots_per_class, c.max_batch, c.trials, c.steps = 64, 64, 16, 32, T
+    c.beta = beta.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    c.eta = eta.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    c.j_scale, c.xi, c.levels, c.noise, c.prec, c.streams = 1.0, 2.0, 4, 0, pim.PREC_FP8, 2
+    for k, v in over.items():
+        if k == "null_beta":
+            c.beta = None
+        else:
+            setattr(c, k, v)
+    return c
+
+
+@pytest.mark.parametrize("over,frag", [
+    ({"max_n": 0}, "max_n"), ({"max_n": 257}, "max_n"), ({"trials": 0}, "trials and steps"),
+    ({"steps": 0}, "trials and steps"), ({"null_beta": 1}, "beta and eta"), ({"prec": 7}, "precision"),
+    ({"streams": 0}, "streams"), ({"streams": 9}, "streams"), ({"max_batch": 0}, "max_batch"),
+    ({"max_batch": 65536, "slots_per_class": 70000}, "max_batch"), ({"slots_per_class": 8}, "slots_per_class"),
+    ({"beta": np.r_[np.ones(15), -1.0]}, "beta[15]"), ({"eta": np.r_[np.nan, np.ones(15)]}, "beta[0]"),
+    ({"levels": 1}, "levels"),
+])
+def test_server_create_rejects_invalid_config(pim, over, frag):
+    """Configuration errors are reported before any device work (no GPU here),
+    and the handle stays NULL."""
+    import ctypes
+    keep = []
+    c = _server_config(pim, keep, **over)
+    handle = ctypes.c_void_p(1234)
+    st = pim.lib.pim_server_create(ctypes.byref(c), ctypes.byref(handle))
+    assert st == pim.PIM_ERR_INVALID
+    assert frag in pim.lib.pim_last_error().decode()
+    assert not handle.value
+
+
+def test_server_calls_reject_null_handle(pim):
+    import ctypes
+    one = ctypes.c_int32()
+    ids = np.zeros(1, np.uint32)
+    ns = np.ones(1, np.int32)
+    J = np.zeros((1, 1))
+    jp = (ctypes.POINTER(ctypes.c_double) * 1)(J.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    assert pim.lib.pim_server_submit(None, 1, ids.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)),
+                                     ns.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), jp, None,
+                                     ctypes.byref(one)) == pim.PIM_ERR_INVALID
+    assert pim.lib.pim_server_flush(None, ctypes.byref(one)) == pim.PIM_ERR_INVALID
+    assert pim.lib.pim_server_poll(None, 1, ids.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)), None, None,
+                                   ctypes.byref(one)) == pim.PIM_ERR_INVALID
+    assert pim.lib.pim_server_pending(None, ctypes.byref(one), ctypes.byref(one)) == pim.PIM_ERR_INVALID
+    pim.lib.pim_server_destroy(None)  # no-op
