@@ -456,7 +456,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the sweep shards by "
-              "instance and trial with no exchange, see DESIGN.md", file=sys.stderr)
+              "instance and trial with no exchange between GPUs", file=sys.stderr)
         sys.exit(2)
     import torch
     import paper_2604_17109_amd as pim

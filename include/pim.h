@@ -82,7 +82,7 @@ extern "C" {
 typedef enum {
   PIM_OK = 0,
   PIM_ERR_INVALID = 1,     /* argument fails validation (message says which)   */
-  PIM_ERR_UNSUPPORTED = 2, /* valid request this build does not implement       */
+  PIM_ERR_UNSUPPORTED = 2, /* valid request the library does not implement      */
   PIM_ERR_NOMEM = 3,       /* the allocator returned NULL                       */
   PIM_ERR_DEVICE = 4,      /* a HIP call failed; sticky on the batch            */
   PIM_ERR_STATE = 5,       /* call out of order (e.g. results before a run)     */

@@ -9,7 +9,7 @@ CPU-baseline leg of ``bench.py`` do.
 For each spin i of each trial at step t: spin i has a flipping neighbour when
 some j with J_ij != 0 flips between s(t) and s(t+1); P_NT(t) is the
 probability that i itself flips given that, averaged over spins and trials.
-Reading (also listed in the design doc): the average is the pooled ratio
+Reading where the paper is silent: the average is the pooled ratio
     P_NT(t) = #{(i, a): i flips and a neighbour flips} / #{(i, a): a neighbour flips},
 undefined (NaN) when no spin of any trial has a flipping neighbour.
 """

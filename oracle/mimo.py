@@ -18,7 +18,7 @@ Everything is NumPy binary64, written from the paper's definitions:
 * reconstruction x = slice(x_m + T s) and the bit / symbol error rates (Suppl.
   "Performance metric: bit-error rate (BER)").
 
-Readings (also listed in the design doc):
+Readings where the paper is silent:
 * The Ising instance handed to the solver uses the Eq. (1) convention
   H(s) = -sum_{i<j} J_ij s_i s_j - sum_i h_i s_i, so its couplings are
   J = 2 J_DI (every pair appears once in Eq. (1) but twice in s^T J_DI s) and

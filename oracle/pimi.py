@@ -22,7 +22,7 @@ time, in the paper's order and notation:
   Max-Cut and SK-1 paragraph).  The argument of tanh is (beta(t) * c) * I with the
   product beta(t) * c rounded first.
 
-Readings where the paper is silent (also listed in the design doc):
+Readings where the paper is silent:
 * sign(0): a tie keeps the current spin s_i(t).
 * The LUT input x = 1 maps to the top level (half-open bins leave it unassigned).
 * Noise: a B-bit uniform integer u from Philox4x32-10 keyed on (seed, trial,
