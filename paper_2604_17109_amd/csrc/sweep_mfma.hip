@@ -203,7 +203,6 @@ __global__ __launch_bounds__(64 * kWaves, 3) void sweep_mfma_kernel(SweepArgs a)
         for (int q = 0; q < 4; ++q) {
           bw[c][q] = (uint32_t)B[c][mt][q];
           PIM_FENCE(xw[c][q]);
-          PIM_FENCE(bw[c][q]);
         }
       }
       // fence an integer lane offset, not the pointer: a pointer through the
