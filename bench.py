@@ -320,7 +320,7 @@ def serving_leg(args):
         res = {"workload": f"{M} requests uniform over Nt = Nr in {list(nts)} x {{4,16}}-QAM, 20 dB, "
                            f"N = {min(ns)}..{max(ns)}, {cfg['trials']} trials x {T} steps, fp8", "rates": {}}
         srv = pim.Server(max_n=max(ns), trials=cfg["trials"], beta=beta, eta=eta, xi=cfg["xi"],
-                         noise_table=w.gauss_table(8), prec="fp8", slots_per_class=4096, max_batch=256, streams=4,
+                         noise_table=w.gauss_table(8), prec="fp8", slots_per_class=4096, max_batch=256, streams=16,
                          seed=11, max_wait_us=150.0, prealloc_chunks=4)
         for k in range(len(pairs)):  # warm-up: every size class once
             srv.submit([k], [Js[k]], [hs[k]])

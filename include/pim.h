@@ -332,7 +332,7 @@ typedef struct {
   int32_t noise;             /* pim_noise                                              */
   const double* noise_table; /* host [256] or NULL (copied)                            */
   int32_t prec;              /* pim_prec                                               */
-  int32_t streams;           /* concurrent launch streams, 1..8                        */
+  int32_t streams;           /* concurrent launch streams, 1..16                       */
   uint64_t seed;
   size_t hbm_budget;         /* bytes, 0 = no limit                                    */
   double max_wait_us;        /* pim_server_flush holds a partly filled chunk until its

@@ -6,8 +6,9 @@
 // of slots split into chunks of `max_batch` slots.  A request is admitted into
 // the open chunk of its class when a chunk and the device-memory budget allow;
 // its binary64 couplings are copied into the chunk's pinned staging area and
-// quantised and packed into MFMA fragments on the device at launch.  pim_server_flush launches every open chunk on the next of
-// several streams: upload, the persistent FP8/BF16 sweep over the chunk's
+// quantised and packed into MFMA fragments on the device at launch.
+// pim_server_flush launches every due chunk on one of several streams (one
+// whose last launch has finished, if any): upload, the FP8/BF16 sweep over the chunk's
 // requests (32-trial waves), the binary64 re-rank and selection, and the
 // readback of the selected states into pinned memory, all asynchronous.  New
 // arrivals keep being admitted into fresh chunks and launched on other
@@ -199,6 +200,7 @@ struct pim_server {
   int32_t* d_zero = nullptr;         // class ids (all 0) for max_batch instances
   int32_t* d_cancel = nullptr;
   std::vector<hipStream_t> streams;
+  std::vector<hipEvent_t> stream_idle;  // recorded after the last launch on each stream
   int next_stream = 0;
   std::deque<pim::Chunk*> inflight;  // launch order
   size_t bytes = 0;                  // device bytes held by slots
@@ -411,7 +413,7 @@ pim_status pim_server_create(const pim_server_config* cfg, pim_server** out) {
     if (cfg->trials < 1 || cfg->steps < 1) return fail(PIM_ERR_INVALID, "trials and steps must be >= 1");
     if (!cfg->beta || !cfg->eta) return fail(PIM_ERR_INVALID, "beta and eta must be non-NULL");
     if (cfg->prec != PIM_PREC_FP8 && cfg->prec != PIM_PREC_BF16) return fail(PIM_ERR_INVALID, "unknown precision");
-    if (cfg->streams < 1 || cfg->streams > 8) return fail(PIM_ERR_INVALID, "streams must be in [1, 8]");
+    if (cfg->streams < 1 || cfg->streams > 16) return fail(PIM_ERR_INVALID, "streams must be in [1, 16]");
     if (cfg->max_batch < 1 || cfg->max_batch > 65535) return fail(PIM_ERR_INVALID, "max_batch outside [1, 65535]");
     if (cfg->slots_per_class < cfg->max_batch)
       return fail(PIM_ERR_INVALID, "slots_per_class must be >= max_batch");
@@ -466,8 +468,11 @@ pim_status pim_server_create(const pim_server_config* cfg, pim_server** out) {
     }
     for (int i = 0; ok && i < cfg->streams; ++i) {
       hipStream_t q = nullptr;
+      hipEvent_t ev = nullptr;
       ok = hipStreamCreateWithFlags(&q, hipStreamNonBlocking) == hipSuccess;
       if (ok) s->streams.push_back(q);
+      ok = ok && hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess;
+      if (ok) s->stream_idle.push_back(ev);
     }
     s->classes.resize((PIM_MAX_N_LDS + 31) / 32);
     for (size_t c = 0; c < s->classes.size(); ++c) {
@@ -595,9 +600,21 @@ pim_status pim_server_flush(pim_server* s, int32_t* launched) {
       const double age = std::chrono::duration<double, std::micro>(now - c->first).count();
       if (c->count < s->cfg.max_batch && wait > 0.0 && age < wait) continue;
       if (k.open == (int)ci) k.open = -1;
-      hipStream_t st = s->streams[s->next_stream];
-      s->next_stream = (s->next_stream + 1) % (int)s->streams.size();
+      // an idle stream if there is one, so a small chunk does not queue
+      // behind a long one; otherwise the next stream in turn
+      const int ns = (int)s->streams.size();
+      int si = s->next_stream;
+      for (int i = 0; i < ns; ++i) {
+        const int cand = (s->next_stream + i) % ns;
+        if (hipEventQuery(s->stream_idle[cand]) == hipSuccess) {
+          si = cand;
+          break;
+        }
+      }
+      s->next_stream = (si + 1) % ns;
+      hipStream_t st = s->streams[si];
       hipError_t e = launch_chunk(s, c, st);
+      if (e == hipSuccess) e = hipEventRecord(s->stream_idle[si], st);
       if (e != hipSuccess) return fail(PIM_ERR_DEVICE, "server launch failed: %s", hipGetErrorString(e));
       c->launched = true;
       s->inflight.push_back(c);
@@ -666,6 +683,7 @@ void pim_server_destroy(pim_server* s) {
   for (hipStream_t q : s->streams) (void)hipStreamSynchronize(q);
   for (Klass& k : s->classes)
     for (Chunk* c : k.chunks) free_chunk(c);
+  for (hipEvent_t ev : s->stream_idle) (void)hipEventDestroy(ev);
   for (hipStream_t q : s->streams) (void)hipStreamDestroy(q);
   dev_free(s->d_thtab, nullptr);
   dev_free(s->d_zero, nullptr);

@@ -191,7 +191,7 @@ def _server_config(pim, keep, **over):
 @pytest.mark.parametrize("over,frag", [
     ({"max_n": 0}, "max_n"), ({"max_n": 257}, "max_n"), ({"trials": 0}, "trials and steps"),
     ({"steps": 0}, "trials and steps"), ({"null_beta": 1}, "beta and eta"), ({"prec": 7}, "precision"),
-    ({"streams": 0}, "streams"), ({"streams": 9}, "streams"), ({"max_batch": 0}, "max_batch"),
+    ({"streams": 0}, "streams"), ({"streams": 17}, "streams"), ({"max_batch": 0}, "max_batch"),
     ({"max_batch": 65536, "slots_per_class": 70000}, "max_batch"), ({"slots_per_class": 8}, "slots_per_class"),
     ({"beta": np.r_[np.ones(15), -1.0]}, "beta[15]"), ({"eta": np.r_[np.nan, np.ones(15)]}, "beta[0]"),
     ({"levels": 1}, "levels"),
