@@ -241,6 +241,7 @@ struct pim_instance {
   int jstride = 0;                // row stride of d_jf32: n rounded up to 4
   size_t frag_bytes = 0;
   bool has_h = false;
+  uint8_t* d_arena = nullptr;     // one allocation holding every buffer below
   int8_t* d_jfrag = nullptr;      // int8, FP8 or BF16 MFMA fragments
   float* d_jf32 = nullptr;        // [npad][jstride] FP32 J, zero-padded
   int8_t* d_j8 = nullptr;         // row-major int8 J (re-rank; integer instances)
@@ -258,7 +259,9 @@ struct pim_batch {
   size_t frag_bytes = 0;          // per instance
   bool has_h = false;
   hipStream_t stream = nullptr;
-  // device buffers
+  // device buffers: d_arena holds the fixed-size ones (fragments .. selection
+  // outputs); the step tables, trajectories and padded int8 J are separate
+  uint8_t* d_arena = nullptr;
   int8_t* d_jfrag = nullptr;      // concatenated fragments of all instances
   int8_t* d_j8pad = nullptr;      // [count][npad][npad] row-major int8 J (sequential kernel)
   int8_t* d_trace = nullptr;      // [count][R][T+1][npad] recorded states (diagnostics)
@@ -287,8 +290,6 @@ struct pim_batch {
   std::vector<int32_t> h_sel_i;
   void* d_thtab = nullptr;        // int16 (integer) or float (real) step tables
   size_t thtab_bytes = 0;
-  void* h_thtab = nullptr;        // pinned staging of the step tables
-  size_t h_thtab_bytes = 0;
   int32_t* d_steptab = nullptr;
   size_t steptab_bytes = 0;
   // schedule the (u, s) step tables in d_thtab were compiled from: a run with
@@ -296,7 +297,7 @@ struct pim_batch {
   // uploading again
   bool tab_valid = false;
   std::vector<double> tab_beta, tab_eta;
-  int32_t* h_cancel = nullptr;    // pinned, host-mapped
+  int32_t* h_cancel = nullptr;    // pinned, host-mapped (a slot of a shared slab)
   int32_t* d_cancel = nullptr;    // device view of h_cancel
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   // host-side class bookkeeping

@@ -8,6 +8,8 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <functional>
+#include <mutex>
 #include <new>
 #include <string>
 #include <thread>
@@ -75,6 +77,78 @@ pim_status alloc_dev(T** p, size_t count, hipStream_t s) {
   if (!*p) return fail(PIM_ERR_NOMEM, "device allocation of %zu bytes failed", count * sizeof(T));
   return PIM_OK;
 }
+
+// Several device buffers carved out of one allocation (256-byte aligned
+// sub-buffers): one allocator call instead of one per buffer, which matters
+// when the allocator is a callback into the caller's runtime.
+class Carver {
+ public:
+  template <typename T>
+  void add(T** p, size_t count) {
+    const size_t off = total_;
+    total_ += (std::max<size_t>(count * sizeof(T), 1) + 255) & ~(size_t)255;
+    set_.push_back([p, off](uint8_t* base) { *p = reinterpret_cast<T*>(base + off); });
+  }
+  pim_status commit(uint8_t** arena, hipStream_t s) {
+    *arena = static_cast<uint8_t*>(dev_alloc(total_, s));
+    if (!*arena) return fail(PIM_ERR_NOMEM, "device allocation of %zu bytes failed", total_);
+    for (auto& f : set_) f(*arena);
+    return PIM_OK;
+  }
+  // the offset the next add() will get
+  size_t mark() const { return total_; }
+
+ private:
+  std::vector<std::function<void(uint8_t*)>> set_;
+  size_t total_ = 0;
+};
+
+// Cancel flags of all batches live in pinned, device-mapped slabs of 1024
+// flags that stay allocated for the life of the process: a pinned allocation
+// per batch would cost tens of microseconds at every batch creation.
+class CancelFlags {
+ public:
+  bool acquire(int32_t** h, int32_t** d) {
+    std::lock_guard<std::mutex> g(m_);
+    if (free_.empty()) {
+      int32_t* hs = nullptr;
+      int32_t* ds = nullptr;
+      if (hipHostMalloc((void**)&hs, kSlab * sizeof(int32_t), hipHostMallocMapped | hipHostMallocCoherent) !=
+          hipSuccess)
+        return false;
+      if (hipHostGetDevicePointer((void**)&ds, hs, 0) != hipSuccess) {
+        (void)hipHostFree(hs);
+        return false;
+      }
+      for (int i = kSlab - 1; i >= 0; --i) free_.push_back({hs + i, ds + i});
+    }
+    *h = free_.back().first;
+    *d = free_.back().second;
+    free_.pop_back();
+    __atomic_store_n(*h, 0, __ATOMIC_SEQ_CST);
+    return true;
+  }
+  void release(int32_t* h, int32_t* d) {
+    std::lock_guard<std::mutex> g(m_);
+    free_.push_back({h, d});
+  }
+
+ private:
+  static constexpr int kSlab = 1024;
+  std::mutex m_;
+  std::vector<std::pair<int32_t*, int32_t*>> free_;
+};
+CancelFlags g_cancel_flags;
+
+// Pinned staging of the step tables, shared by every batch: held (locked)
+// from compilation until the upload has completed, grown on demand and kept
+// for the life of the process.
+struct TableStaging {
+  std::mutex m;
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+TableStaging g_tab_staging;
 
 bool finite_nonneg(double v) { return std::isfinite(v) && v >= 0.0; }
 
@@ -148,30 +222,12 @@ void free_batch_buffers(pim_batch* b) {
   if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   hipStream_t s = b->stream;
-  dev_free(b->d_jfrag, s);
+  dev_free(b->d_arena, s);  // the fixed-size buffers, carved at creation
   dev_free(b->d_j8pad, s);
   dev_free(b->d_trace, s);
-  dev_free(b->d_h, s);
-  dev_free(b->d_init, s);
-  dev_free(b->d_final, s);
-  dev_free(b->d_best, s);
-  dev_free(b->d_stats, s);
-  dev_free(b->d_class, s);
-  dev_free(b->d_stream_ids, s);
-  dev_free(b->d_target, s);
-  dev_free(b->d_rerank, s);
   dev_free(b->d_thtab, s);
   dev_free(b->d_steptab, s);
-  dev_free((void*)b->d_jptrs, s);
-  dev_free((void*)b->d_hptrs, s);
-  dev_free((void*)b->d_j64ptrs, s);
-  dev_free((void*)b->d_h64ptrs, s);
-  dev_free(b->d_scale, s);
-  dev_free(b->d_sel_spins, s);
-  dev_free(b->d_sel_e, s);
-  dev_free(b->d_sel_i, s);
-  if (b->h_cancel) (void)hipHostFree(b->h_cancel);
-  if (b->h_thtab) (void)hipHostFree(b->h_thtab);
+  if (b->h_cancel) g_cancel_flags.release(b->h_cancel, b->d_cancel);
   if (b->ev0) (void)hipEventDestroy(b->ev0);
   if (b->ev1) (void)hipEventDestroy(b->ev1);
 }
@@ -205,12 +261,17 @@ pim_status ensure_selection(pim_batch* b) {
   b->h_sel_spins.resize((size_t)b->count * b->npad);
   b->h_sel_e.resize(b->count);
   b->h_sel_i.resize((size_t)3 * b->count);
-  HIP_TRY(hipMemcpyAsync(b->h_sel_spins.data(), b->d_sel_spins, b->h_sel_spins.size(), hipMemcpyDeviceToHost,
-                         b->stream));
-  HIP_TRY(hipMemcpyAsync(b->h_sel_e.data(), b->d_sel_e, b->count * sizeof(double), hipMemcpyDeviceToHost, b->stream));
-  HIP_TRY(hipMemcpyAsync(b->h_sel_i.data(), b->d_sel_i, 3 * b->count * sizeof(int32_t), hipMemcpyDeviceToHost,
-                         b->stream));
+  // the three outputs are adjacent in the arena: one readback of the span
+  const uint8_t* lo = reinterpret_cast<const uint8_t*>(b->d_sel_spins);
+  const uint8_t* hi = reinterpret_cast<const uint8_t*>(b->d_sel_i + 3 * b->count);
+  std::vector<uint8_t> span(hi - lo);
+  HIP_TRY(hipMemcpyAsync(span.data(), lo, span.size(), hipMemcpyDeviceToHost, b->stream));
   HIP_TRY(hipStreamSynchronize(b->stream));
+  std::memcpy(b->h_sel_spins.data(), span.data(), b->h_sel_spins.size());
+  std::memcpy(b->h_sel_e.data(), span.data() + (reinterpret_cast<const uint8_t*>(b->d_sel_e) - lo),
+              b->count * sizeof(double));
+  std::memcpy(b->h_sel_i.data(), span.data() + (reinterpret_cast<const uint8_t*>(b->d_sel_i) - lo),
+              3 * b->count * sizeof(int32_t));
   b->reranked = true;
   return PIM_OK;
 }
@@ -369,18 +430,20 @@ pim_status run_prepare(pim_batch* b, const pim_schedule* sc, hipStream_t s, RunC
                             b->tab_beta.size() == (size_t)T &&
                             std::memcmp(b->tab_beta.data(), sc->beta, (size_t)T * sizeof(double)) == 0 &&
                             std::memcmp(b->tab_eta.data(), sc->eta, (size_t)T * sizeof(double)) == 0;
+    std::unique_lock<std::mutex> staging_lock(g_tab_staging.m, std::defer_lock);
     if (mfma && !tab_cached) {
       b->tab_valid = false;
       const size_t need = thtab_need;
-      if (need > b->h_thtab_bytes) {
-        if (b->h_thtab) (void)hipHostFree(b->h_thtab);
-        b->h_thtab = nullptr;
-        b->h_thtab_bytes = 0;
-        if (hipHostMalloc(&b->h_thtab, need, hipHostMallocDefault) != hipSuccess)
+      staging_lock.lock();  // held until the upload below has completed
+      if (need > g_tab_staging.bytes) {
+        if (g_tab_staging.p) (void)hipHostFree(g_tab_staging.p);
+        g_tab_staging.p = nullptr;
+        g_tab_staging.bytes = 0;
+        if (hipHostMalloc(&g_tab_staging.p, need, hipHostMallocDefault) != hipSuccess)
           return fail(PIM_ERR_NOMEM, "pinned staging allocation of %zu bytes failed", need);
-        b->h_thtab_bytes = need;
+        g_tab_staging.bytes = need;
       }
-      void* out = b->h_thtab;
+      void* out = g_tab_staging.p;
       parallel_for(T * ncls, [&](int lo, int hi) {
         int32_t th[kMaxLevels], um[2 * kMaxLevels];
         float thf[kMaxLevels];
@@ -464,7 +527,7 @@ pim_status run_prepare(pim_batch* b, const pim_schedule* sc, hipStream_t s, RunC
                              hipMemcpyDeviceToDevice, s);
       if (e != hipSuccess) return device_fail(e, "sequential coupling layout");
     }
-    if (mfma && !tab_cached) e = hipMemcpyAsync(b->d_thtab, b->h_thtab, thtab_need, hipMemcpyHostToDevice, s);
+    if (mfma && !tab_cached) e = hipMemcpyAsync(b->d_thtab, g_tab_staging.p, thtab_need, hipMemcpyHostToDevice, s);
     else if (!mfma) e = hipMemcpyAsync(b->d_steptab, steptab.data(), steptab.size() * 4, hipMemcpyHostToDevice, s);
     if (e == hipSuccess)
       e = hipMemcpyAsync(b->d_target, real ? (const void*)tgtf.data() : (const void*)tgt.data(), b->count * 4,
@@ -747,32 +810,39 @@ pim_status pim_create_real(const double* J, const double* h, const pim_params* p
       for (int i = 0; i < n; ++i) inst->has_h |= (h[i] != 0.0);
     inst->scale = real_scale(J, (size_t)n * n, prec);
     inst->frag_bytes = real_frag_bytes(prec, inst->nt);
-    std::vector<uint8_t> frag(inst->frag_bytes);
-    pack_real_fragments(J, n, inst->nt, prec, inst->scale, frag.data());
-    std::vector<float> jf((size_t)inst->npad * inst->jstride, 0.0f);
+    // device arena: fragments, FP32 J, fl32(h), binary64 h (built on the
+    // host in one block of the same layout and uploaded by one copy), then
+    // the binary64 J (copied straight from the caller's array)
+    Carver cv;
+    const size_t o_frag = cv.mark();
+    cv.add(&inst->d_jfrag, inst->frag_bytes);
+    const size_t o_jf = cv.mark();
+    cv.add(&inst->d_jf32, (size_t)inst->npad * inst->jstride);
+    const size_t o_hf = cv.mark();
+    cv.add(&inst->d_hf, (size_t)inst->npad);
+    const size_t o_h64 = cv.mark();
+    cv.add(&inst->d_h64, (size_t)n);
+    const size_t staged = cv.mark();
+    cv.add(&inst->d_j64, (size_t)n * n);
+    std::vector<uint8_t> host(staged, 0);
+    pack_real_fragments(J, n, inst->nt, prec, inst->scale, host.data() + o_frag);
+    float* jf = reinterpret_cast<float*>(host.data() + o_jf);
     for (int i = 0; i < n; ++i)
       for (int j = 0; j < n; ++j) jf[(size_t)i * inst->jstride + j] = (float)J[(size_t)i * n + j];
-    std::vector<float> hf(inst->npad, 0.0f);
-    std::vector<double> h64(n, 0.0);
+    float* hf = reinterpret_cast<float*>(host.data() + o_hf);
+    double* h64 = reinterpret_cast<double*>(host.data() + o_h64);
     if (h)
       for (int i = 0; i < n; ++i) {
         hf[i] = (float)h[i];
         h64[i] = h[i];
       }
-    st = alloc_dev(&inst->d_jfrag, frag.size(), s);
-    if (st == PIM_OK) st = alloc_dev(&inst->d_jf32, jf.size(), s);
-    if (st == PIM_OK) st = alloc_dev(&inst->d_hf, hf.size(), s);
-    if (st == PIM_OK) st = alloc_dev(&inst->d_j64, (size_t)n * n, s);
-    if (st == PIM_OK) st = alloc_dev(&inst->d_h64, (size_t)n, s);
+    st = cv.commit(&inst->d_arena, s);
     if (st != PIM_OK) {
       pim_destroy(inst);
       return st;
     }
-    hipError_t e = hipMemcpyAsync(inst->d_jfrag, frag.data(), frag.size(), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(inst->d_jf32, jf.data(), jf.size() * 4, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(inst->d_hf, hf.data(), hf.size() * 4, hipMemcpyHostToDevice, s);
+    hipError_t e = hipMemcpyAsync(inst->d_arena, host.data(), staged, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(inst->d_j64, J, (size_t)n * n * 8, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(inst->d_h64, h64.data(), (size_t)n * 8, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
       (void)hipStreamSynchronize(s);  // copies already queued still read the host buffers
@@ -808,25 +878,31 @@ pim_status pim_create(const int8_t* J, const int32_t* h, const pim_params* param
     if (h)
       for (int i = 0; i < n; ++i) inst->has_h |= (h[i] != 0);
     inst->frag_bytes = (size_t)inst->nt * inst->nt * 1024;
-    std::vector<int8_t> frag(inst->frag_bytes);
-    pack_mfma_fragments(J, n, inst->nt, frag.data());
     inst->jstride = (n + 3) & ~3;
-    std::vector<float> jf((size_t)inst->npad * inst->jstride, 0.0f);
+    // device arena: fragments, FP32 J, h (built on the host in one block of
+    // the same layout and uploaded by one copy), then the int8 J (copied
+    // straight from the caller's array)
+    Carver cv;
+    const size_t o_frag = cv.mark();
+    cv.add(&inst->d_jfrag, inst->frag_bytes);
+    const size_t o_jf = cv.mark();
+    cv.add(&inst->d_jf32, (size_t)inst->npad * inst->jstride);
+    const size_t o_h = cv.mark();
+    cv.add(&inst->d_h, (size_t)inst->npad);
+    const size_t staged = cv.mark();
+    cv.add(&inst->d_j8, (size_t)n * n);
+    std::vector<uint8_t> host(staged, 0);
+    pack_mfma_fragments(J, n, inst->nt, reinterpret_cast<int8_t*>(host.data() + o_frag));
+    float* jf = reinterpret_cast<float*>(host.data() + o_jf);
     for (int i = 0; i < n; ++i)
       for (int j = 0; j < n; ++j) jf[(size_t)i * inst->jstride + j] = (float)J[(size_t)i * n + j];
-    std::vector<int32_t> hp(inst->npad, 0);
-    if (h) std::copy(h, h + n, hp.begin());
-    st = alloc_dev(&inst->d_jfrag, frag.size(), s);
-    if (st == PIM_OK) st = alloc_dev(&inst->d_jf32, jf.size(), s);
-    if (st == PIM_OK) st = alloc_dev(&inst->d_h, hp.size(), s);
-    if (st == PIM_OK) st = alloc_dev(&inst->d_j8, (size_t)n * n, s);
+    if (h) std::memcpy(host.data() + o_h, h, (size_t)n * sizeof(int32_t));
+    st = cv.commit(&inst->d_arena, s);
     if (st != PIM_OK) {
       pim_destroy(inst);
       return st;
     }
-    hipError_t e = hipMemcpyAsync(inst->d_jfrag, frag.data(), frag.size(), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(inst->d_jf32, jf.data(), jf.size() * 4, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(inst->d_h, hp.data(), hp.size() * 4, hipMemcpyHostToDevice, s);
+    hipError_t e = hipMemcpyAsync(inst->d_arena, host.data(), staged, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(inst->d_j8, J, (size_t)n * n, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);  // host staging buffers go out of scope
     if (e != hipSuccess) {
@@ -845,13 +921,7 @@ pim_status pim_create(const int8_t* J, const int32_t* h, const pim_params* param
 
 void pim_destroy(pim_instance* inst) {
   if (!inst) return;
-  dev_free(inst->d_jfrag, nullptr);
-  dev_free(inst->d_jf32, nullptr);
-  dev_free(inst->d_h, nullptr);
-  dev_free(inst->d_j8, nullptr);
-  dev_free(inst->d_hf, nullptr);
-  dev_free(inst->d_j64, nullptr);
-  dev_free(inst->d_h64, nullptr);
+  dev_free(inst->d_arena, nullptr);  // every device buffer of the instance
   delete inst;
 }
 
@@ -903,41 +973,53 @@ pim_status pim_batch_create(pim_instance* const* insts, int32_t count, int32_t t
     }
     const size_t frag = b->frag_bytes;
     const size_t cells = (size_t)count * trials;
-    pim_status st = alloc_dev(&b->d_jfrag, frag * count, s);
-    if (st == PIM_OK) st = alloc_dev(&b->d_h, (size_t)count * b->npad, s);
-    if (st == PIM_OK) st = alloc_dev(&b->d_final, cells * b->npad, s);
-    if (st == PIM_OK) st = alloc_dev(&b->d_best, cells * b->npad, s);
-    if (st == PIM_OK) st = alloc_dev(&b->d_stats, cells * 5, s);
-    if (st == PIM_OK) st = alloc_dev(&b->d_class, (size_t)count, s);
-    if (st == PIM_OK) st = alloc_dev(&b->d_stream_ids, (size_t)count, s);
-    if (st == PIM_OK) st = alloc_dev(&b->d_target, (size_t)count, s);
-    if (st == PIM_OK) st = alloc_dev(&b->d_rerank, cells, s);
-    if (st == PIM_OK && init_spins) st = alloc_dev(&b->d_init, cells * b->npad, s);
-    if (st == PIM_OK) st = alloc_dev(&b->d_jptrs, (size_t)count, s);
-    if (st == PIM_OK) st = alloc_dev(&b->d_hptrs, (size_t)count, s);
-    if (st == PIM_OK) st = alloc_dev(&b->d_j64ptrs, (size_t)count, s);
-    if (st == PIM_OK) st = alloc_dev(&b->d_h64ptrs, (size_t)count, s);
-    if (st == PIM_OK) st = alloc_dev(&b->d_scale, (size_t)count, s);
-    if (st == PIM_OK) st = alloc_dev(&b->d_sel_spins, (size_t)count * b->npad, s);
-    if (st == PIM_OK) st = alloc_dev(&b->d_sel_e, (size_t)count, s);
-    if (st == PIM_OK) st = alloc_dev(&b->d_sel_i, (size_t)3 * count, s);
+    // the arena starts with the per-instance tables filled on the host (one
+    // upload), then the device-only buffers; the three selection outputs are
+    // last and adjacent (one readback)
+    Carver cv;
+    const size_t o_class = cv.mark();
+    cv.add(&b->d_class, (size_t)count);
+    const size_t o_sid = cv.mark();
+    cv.add(&b->d_stream_ids, (size_t)count);
+    const size_t o_jp = cv.mark();
+    cv.add(&b->d_jptrs, (size_t)count);
+    const size_t o_hp = cv.mark();
+    cv.add(&b->d_hptrs, (size_t)count);
+    const size_t o_jp64 = cv.mark();
+    cv.add(&b->d_j64ptrs, (size_t)count);
+    const size_t o_hp64 = cv.mark();
+    cv.add(&b->d_h64ptrs, (size_t)count);
+    const size_t o_scale = cv.mark();
+    cv.add(&b->d_scale, (size_t)count);
+    const size_t tables = cv.mark();
+    cv.add(&b->d_jfrag, frag * count);
+    cv.add(&b->d_h, (size_t)count * b->npad);
+    cv.add(&b->d_final, cells * b->npad);
+    cv.add(&b->d_best, cells * b->npad);
+    cv.add(&b->d_stats, cells * 5);
+    cv.add(&b->d_target, (size_t)count);
+    cv.add(&b->d_rerank, cells);
+    if (init_spins) cv.add(&b->d_init, cells * b->npad);
+    cv.add(&b->d_sel_spins, (size_t)count * b->npad);
+    cv.add(&b->d_sel_e, (size_t)count);
+    cv.add(&b->d_sel_i, (size_t)3 * count);
+    pim_status st = cv.commit(&b->d_arena, s);
     if (st != PIM_OK) {
       free_batch_buffers(b);
       delete b;
       return st;
     }
-    hipError_t e = hipHostMalloc((void**)&b->h_cancel, sizeof(int32_t), hipHostMallocMapped | hipHostMallocCoherent);
-    if (e == hipSuccess) {
-      *b->h_cancel = 0;
-      e = hipHostGetDevicePointer((void**)&b->d_cancel, b->h_cancel, 0);
-    }
+    hipError_t e = g_cancel_flags.acquire(&b->h_cancel, &b->d_cancel) ? hipSuccess : hipErrorOutOfMemory;
     if (e == hipSuccess) e = hipEventCreate(&b->ev0);
     if (e == hipSuccess) e = hipEventCreate(&b->ev1);
-    std::vector<uint32_t> sid(count);
-    std::vector<const int8_t*> jp(count);
-    std::vector<const int32_t*> hp(count);
-    std::vector<const double*> jp64(count), hp64(count);
-    std::vector<float> scales(count);
+    std::vector<uint8_t> host(tables, 0);
+    auto* sid = reinterpret_cast<uint32_t*>(host.data() + o_sid);
+    auto* jp = reinterpret_cast<const int8_t**>(host.data() + o_jp);
+    auto* hp = reinterpret_cast<const int32_t**>(host.data() + o_hp);
+    auto* jp64 = reinterpret_cast<const double**>(host.data() + o_jp64);
+    auto* hp64 = reinterpret_cast<const double**>(host.data() + o_hp64);
+    auto* scales = reinterpret_cast<float*>(host.data() + o_scale);
+    std::memcpy(host.data() + o_class, b->inst_class.data(), (size_t)count * sizeof(int32_t));
     for (int k = 0; k < count; ++k) {
       sid[k] = insts[k]->rule.stream;
       jp[k] = insts[k]->d_j8;
@@ -952,17 +1034,7 @@ pim_status pim_batch_create(pim_instance* const* insts, int32_t count, int32_t t
       if (e == hipSuccess)
         e = hipMemcpyAsync(b->d_h + (size_t)k * b->npad, hsrc, b->npad * 4, hipMemcpyDeviceToDevice, s);
     }
-    if (e == hipSuccess)
-      e = hipMemcpyAsync((void*)b->d_j64ptrs, jp64.data(), count * sizeof(void*), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess)
-      e = hipMemcpyAsync((void*)b->d_h64ptrs, hp64.data(), count * sizeof(void*), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(b->d_scale, scales.data(), count * 4, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(b->d_class, b->inst_class.data(), count * 4, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(b->d_stream_ids, sid.data(), count * 4, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess)
-      e = hipMemcpyAsync((void*)b->d_jptrs, jp.data(), count * sizeof(void*), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess)
-      e = hipMemcpyAsync((void*)b->d_hptrs, hp.data(), count * sizeof(void*), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(b->d_arena, host.data(), tables, hipMemcpyHostToDevice, s);
     std::vector<int8_t> init_pad;
     if (e == hipSuccess && init_spins) {
       init_pad.assign(cells * b->npad, (int8_t)1);
