@@ -6,10 +6,39 @@
 // rounding through binary32), and FP8 saturates at +-448.
 #include <cmath>
 #include <cstdint>
+#include <cstring>
 
 #include "internal.hpp"
 
 namespace pim {
+namespace {
+
+// Exponent field of a binary64 value minus its bias: E with x in [2^E, 2^(E+1))
+// for normal x (-1023 for zero and subnormals).
+int exponent_of(double x) {
+  uint64_t u;
+  std::memcpy(&u, &x, sizeof u);
+  return (int)((u >> 52) & 0x7FF) - 1023;
+}
+
+// 2^k as a binary64 value, -1022 <= k <= 1023 (exact).
+double pow2(int k) {
+  const uint64_t u = (uint64_t)(k + 1023) << 52;
+  double x;
+  std::memcpy(&x, &u, sizeof x);
+  return x;
+}
+
+// Round to the nearest integer, ties to even, for 0 <= v <= 2^52: adding 2^52
+// leaves no fraction bits, so the addition itself rounds (binary64, default
+// rounding mode) and the subtraction is exact.
+double rint_small(double v) {
+  const double big = 4503599627370496.0;  // 2^52
+  volatile double t = v + big;            // kept as written: not folded to v
+  return t - big;
+}
+
+}  // namespace
 
 uint8_t fp8_e4m3_rne(double x) {
   if (x == 0.0 || std::isnan(x)) return 0;
@@ -17,13 +46,11 @@ uint8_t fp8_e4m3_rne(double x) {
   const double a = std::fabs(x);
   if (a >= 448.0) return sign | 0x7E;
   if (a < 0.015625) {                               // below 2^-6: subnormal steps of 2^-9
-    const double q = std::nearbyint(a * 512.0);     // exact scaling, ties to even; q in [0, 8]
+    const double q = rint_small(a * 512.0);         // exact scaling, ties to even; q in [0, 8]
     return sign | (uint8_t)q;                       // q = 8 is the smallest normal, code 0x08
   }
-  int e;
-  (void)std::frexp(a, &e);
-  int E = e - 1;                                     // a in [2^E, 2^(E+1))
-  double q = std::nearbyint(std::ldexp(a, 3 - E));   // significand x 8, in [8, 16]
+  int E = exponent_of(a);                           // a in [2^E, 2^(E+1)), -6 <= E <= 8
+  double q = rint_small(a * pow2(3 - E));           // significand x 8, in [8, 16]
   if (q == 16.0) {
     q = 8.0;
     ++E;
@@ -35,8 +62,8 @@ uint8_t fp8_e4m3_rne(double x) {
 double fp8_e4m3_value(uint8_t c) {
   const double sign = (c & 0x80) ? -1.0 : 1.0;
   const int ex = (c >> 3) & 0xF, m = c & 7;
-  if (ex == 0) return sign * std::ldexp((double)m, -9);
-  return sign * std::ldexp(8.0 + m, ex - 10);
+  if (ex == 0) return sign * (double)m * pow2(-9);
+  return sign * (8.0 + m) * pow2(ex - 10);
 }
 
 uint16_t bf16_rne(double x) {
@@ -44,14 +71,12 @@ uint16_t bf16_rne(double x) {
   const uint16_t sign = x < 0.0 ? 0x8000 : 0x0000;
   if (std::isinf(x)) return sign | 0x7F80;
   const double a = std::fabs(x);
-  int e;
-  (void)std::frexp(a, &e);
-  int E = e - 1;
+  int E = exponent_of(a);                            // a in [2^E, 2^(E+1)) (-1023: subnormal a)
   if (E < -126) {                                    // subnormal: steps of 2^-133
-    const double q = std::nearbyint(std::ldexp(a, 133));
+    const double q = rint_small(a * pow2(133));      // a < 2^-126: exact, q in [0, 128]
     return sign | (uint16_t)q;                       // q = 128 is the smallest normal
   }
-  double q = std::nearbyint(std::ldexp(a, 7 - E));   // significand x 128, in [128, 256]
+  double q = rint_small(a * pow2(7 - E));            // significand x 128, in [128, 256]
   if (q == 256.0) {
     q = 128.0;
     ++E;
@@ -63,9 +88,9 @@ uint16_t bf16_rne(double x) {
 double bf16_value(uint16_t c) {
   const double sign = (c & 0x8000) ? -1.0 : 1.0;
   const int ex = (c >> 7) & 0xFF, m = c & 0x7F;
-  if (ex == 0) return sign * std::ldexp((double)m, -133);
+  if (ex == 0) return sign * (double)m * pow2(-133);
   if (ex == 0xFF) return sign * INFINITY;
-  return sign * std::ldexp(128.0 + m, ex - 134);
+  return sign * (128.0 + m) * pow2(ex - 134);
 }
 
 float real_scale(const double* J, size_t count, int prec) {
