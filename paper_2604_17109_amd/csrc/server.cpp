@@ -155,17 +155,23 @@ class Pool {
 
 // Checks a request (J finite, symmetric with a zero diagonal; h finite) while
 // staging it: J (n x n) into j64 (np x np, zero-padded) and h into h64 (np,
-// zero-padded).  J is walked in 16 x 16 tiles, each compared with and copied
-// together with its transpose, so both stay in cache and J is read once.
-// Returns false (staging then incomplete) if the request is invalid.
-bool validate_and_stage(const double* J, const double* h, int n, size_t np, double* j64, double* h64) {
-  for (int i = 0; i < n; ++i)
+// zero-padded).  J is walked in kTile x kTile tiles, each compared with and
+// copied together with its transpose, so both stay in cache and J is read
+// once.  This call handles the tile rows that start in [i0, i1): their tiles
+// on and right of the diagonal (and the transposes, which land in other rows
+// but in columns below i1, so no element is written by two calls), and the
+// diagonal, padding columns and h of rows i0 .. i1 - 1; the call whose range
+// ends at n also clears the padding rows.  Returns false (staging then
+// incomplete) if the request is invalid in that part.
+constexpr int kTile = 16;
+
+bool validate_and_stage_rows(const double* J, const double* h, int n, size_t np, double* j64, double* h64, int i0,
+                             int i1) {
+  for (int i = i0; i < i1; ++i) {
     if (J[(size_t)i * n + i] != 0.0 || (h && !std::isfinite(h[i]))) return false;
-  if (h) std::memcpy(h64, h, n * sizeof(double));
-  else std::fill(h64, h64 + n, 0.0);
-  std::fill(h64 + n, h64 + np, 0.0);
-  constexpr int kTile = 16;
-  for (int ib = 0; ib < n; ib += kTile)
+    h64[i] = h ? h[i] : 0.0;
+  }
+  for (int ib = i0; ib < i1; ib += kTile)
     for (int jb = ib; jb < n; jb += kTile) {
       const int ie = std::min(ib + kTile, n), je = std::min(jb + kTile, n);
       for (int i = ib; i < ie; ++i)
@@ -176,17 +182,28 @@ bool validate_and_stage(const double* J, const double* h, int n, size_t np, doub
           j64[(size_t)j * np + i] = a;
         }
     }
-  for (int i = 0; i < n; ++i) {
+  for (int i = i0; i < i1; ++i) {
     j64[(size_t)i * np + i] = 0.0;
     std::fill(j64 + (size_t)i * np + n, j64 + (size_t)(i + 1) * np, 0.0);
   }
-  std::fill(j64 + (size_t)n * np, j64 + np * np, 0.0);
+  if (i1 == n) {
+    std::fill(h64 + n, h64 + np, 0.0);
+    std::fill(j64 + (size_t)n * np, j64 + np * np, 0.0);
+  }
   return true;
 }
 
-// Submissions whose couplings total fewer elements than this run on the
-// calling thread alone (waking the workers would cost more than it saves).
+// Submissions whose couplings total fewer elements than kParallelElems run on
+// the calling thread alone (waking the workers would cost more than it
+// saves), with one exception: a submission of fewer than kFewRequests
+// requests that still holds kSplitElems elements splits its requests of at
+// least kSplitN spins into strips of kTile rows, so that one large request is
+// staged by several threads.  Large submissions keep whole requests as work
+// items, which keeps each request's reads in one thread's cache.
 constexpr size_t kParallelElems = (size_t)1 << 17;
+constexpr size_t kSplitElems = (size_t)1 << 15;
+constexpr int kFewRequests = 8;
+constexpr int kSplitN = 96;
 
 }  // namespace
 }  // namespace pim
@@ -524,7 +541,8 @@ pim_status pim_server_submit(pim_server* s, int32_t count, const uint32_t* ids, 
       if (n < 1 || n > s->cfg.max_n || ids[f] >= (1u << 24) || !J[f]) break;
       elems += (size_t)n * n;
     }
-    const bool par = s->pool && elems >= kParallelElems;
+    const bool few = f < kFewRequests;
+    const bool par = s->pool && (elems >= kParallelElems || (few && elems >= kSplitElems));
     auto run = [&](int items, const std::function<void(int)>& fn) {
       if (par) {
         s->pool->run(items, fn);
@@ -552,15 +570,32 @@ pim_status pim_server_submit(pim_server* s, int32_t count, const uint32_t* ids, 
     // (3) content checks and staging copies of the binary64 couplings in one
     //     pass per request (quantisation and packing happen on the device at
     //     launch)
-    std::vector<uint8_t> ok(took);
-    run(took, [&](int r) {
-      Chunk* c = place[r].first;
-      const size_t sl = place[r].second, np = s->classes[c->cls].npad;
-      ok[r] = validate_and_stage(J[r], h ? h[r] : nullptr, ns[r], np, c->h_j64 + sl * np * np, c->h_h64 + sl * np)
-                  ? 1 : 0;
+    //     work items: whole requests, or strips of kTile rows of the large
+    //     ones when the pool is in use; a failed item clears its request's flag
+    struct Item {
+      int r, i0, i1;
+    };
+    std::vector<Item> items;
+    items.reserve(took);
+    for (int r = 0; r < took; ++r) {
+      const int n = ns[r];
+      if (par && few && n >= kSplitN)
+        for (int i0 = 0; i0 < n; i0 += kTile) items.push_back({r, i0, std::min(i0 + kTile, n)});
+      else
+        items.push_back({r, 0, n});
+    }
+    std::unique_ptr<std::atomic<uint8_t>[]> ok(new std::atomic<uint8_t>[took]);
+    for (int r = 0; r < took; ++r) ok[r].store(1, std::memory_order_relaxed);
+    run((int)items.size(), [&](int k) {
+      const Item& it = items[k];
+      Chunk* c = place[it.r].first;
+      const size_t sl = place[it.r].second, np = s->classes[c->cls].npad;
+      if (!validate_and_stage_rows(J[it.r], h ? h[it.r] : nullptr, ns[it.r], np, c->h_j64 + sl * np * np,
+                                   c->h_h64 + sl * np, it.i0, it.i1))
+        ok[it.r].store(0, std::memory_order_relaxed);
     });
     int g = 0;
-    while (g < took && ok[g]) ++g;
+    while (g < took && ok[g].load(std::memory_order_relaxed)) ++g;
     if (g < took) {
       // an invalid request: it and the ones after it give their slots back
       // (the last ones taken in each chunk, so in reverse order)
