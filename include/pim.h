@@ -204,7 +204,11 @@ pim_status pim_batch_create(pim_instance* const* insts, int32_t count, int32_t t
  * is this rule with xi = 0 and uniform noise),
  * asynchronously on `stream`.  Compiles the schedule on the host, uploads the
  * tables and launches the sweep (PIM_KERNEL_MFMA_I8: one launch for the whole
- * batch; PIM_KERNEL_PLAIN_F32: one launch per instance).  Tracks, over the
+ * batch; PIM_KERNEL_PLAIN_F32: one launch per instance).  The MFMA and
+ * sequential kernels' tables stay on the device: a run whose beta and eta
+ * equal (bit for bit, same T) those of the batch's previous such run reuses
+ * them without compiling or uploading.  The host waits for the table upload
+ * before returning; the sweep itself runs asynchronously.  Tracks, over the
  * energies E(t) of s(t) for t = 0..T (counter steps start_step..start_step+T):
  * the lowest energy and its earliest step, the state there, and the first step
  * with E <= target.  Resuming: pass the previous final spins as init_spins of a
