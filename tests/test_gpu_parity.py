@@ -332,6 +332,56 @@ def test_kernel_changes_between_runs(gpu_lib):
     batch.close()
 
 
+def test_concurrent_runs_on_distinct_batches(gpu_lib):
+    """Two threads run two batches at once, each on its own stream, switching
+    schedules every run so that every run compiles and uploads its step tables
+    through the library's shared staging buffer.  Every run equals the result
+    of the same run done alone, bit for bit."""
+    import threading
+    import torch
+    _say("concurrent runs on distinct batches")
+    pim = gpu_lib
+    ztab = w.gauss_table(8)
+    jobs = []
+    for k, (n, T) in enumerate(((40, 90), (72, 60))):
+        J, h = w.random_int8(n, seed=71, index=k, jmax=2, hmax=2)
+        inst = pim.Instance(J, h, j_scale=1 / np.sqrt(n), xi=0.5, noise_table=ztab, rng_stream=80 + k)
+        b1 = w.linear_beta(T, 0.1, 3.0)
+        b2 = w.linear_beta(T, 0.2, 2.5)
+        scheds = [(b1, w.eta_sqrt_beta_over_5(b1)), (b2, w.eta_sqrt_beta_over_5(b2))]
+        refs = []
+        for beta, eta in scheds:
+            alone = pim.Batch([inst], 48).run(beta, eta, seed=13)
+            refs.append(alone.trials_of(0))
+            alone.close()
+        jobs.append((inst, scheds, refs))
+    errors = []
+
+    def worker(inst, scheds, refs):
+        try:
+            stream = torch.cuda.Stream()
+            with torch.cuda.stream(stream):
+                batch = pim.Batch([inst], 48)
+                for it in range(8):
+                    beta, eta = scheds[it % 2]
+                    batch.run(beta, eta, seed=13)
+                    got = batch.trials_of(0)
+                    for key in ("final", "e_best", "t_best", "best_state"):
+                        if not np.array_equal(got[key], refs[it % 2][key]):
+                            errors.append((inst.n, it, key))
+                batch.close()
+        except Exception as e:  # noqa: BLE001 - reported by the main thread
+            errors.append(repr(e))
+
+    threads = [threading.Thread(target=worker, args=job) for job in jobs]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    torch.cuda.synchronize()
+    assert not errors, errors
+
+
 def test_uneven_n_batch_one_graph(gpu_lib):
     """Instances of different N in one batch (one graph launch per run): every
     instance bit-exact against the oracle, with caller initial spins for some
