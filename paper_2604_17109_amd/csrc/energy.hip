@@ -124,33 +124,86 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void rerank_kernel(RerankArgs 
   }
 }
 
-// Re-rank for N > PIM_MAX_N_LDS (couplings too large for LDS): one wave per
-// candidate; lane l covers columns l, l + 64, ...; every row's exact integer
-// sum is accumulated in binary64 as in rerank_kernel.
+// Re-rank for N > PIM_MAX_N_LDS (couplings too large for LDS): one block per
+// (instance, 64 candidates), 16 candidates per wave.  J streams through LDS in
+// tiles of kBigRows rows (row stride PIM_MAX_N, columns >= n cleared), so every
+// row read from L2 serves all 64 candidates.  Lane l keeps columns 16l ..
+// 16l + 15 of its wave's candidates in registers (int8; columns >= n are 0 in
+// the LDS rows, so their spins add nothing); a row costs one 16-byte LDS read
+// and four v_dot4 per candidate, and the row's own spin s_i comes from the lane
+// that holds column i.  Every sum is an exact integer (|s^T J s| <= N^2 * 127
+// < 2^31), so the energies equal the binary64 evaluation of Eq. (1) exactly.
+constexpr int kBigCand = 16;  // candidates per wave
+constexpr int kBigRows = 16;  // J rows per LDS tile
+
 __global__ __launch_bounds__(64 * kWavesPerBlock) void rerank_big_kernel(RerankArgs a) {
-  __shared__ __align__(16) int8_t sS[kWavesPerBlock][PIM_MAX_N];
+  __shared__ __align__(16) int8_t sJ[kBigRows][PIM_MAX_N];
   const int inst = blockIdx.y;
+  const int n = a.n, npad = a.npad;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int trial = blockIdx.x * kWavesPerBlock + wave;
-  if (trial >= a.R) return;  // wave-uniform; no block barrier follows
-  const int n = a.n;
-  const size_t cell = (size_t)inst * a.R + trial;
-  const int8_t* s = a.best_s + cell * a.npad;
-  for (int i = lane; i < n; i += 64) sS[wave][i] = s[i];
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  const int cand0 = (blockIdx.x * kWavesPerBlock + wave) * kBigCand;
+  // this lane's 16 columns of each candidate's state (zero past npad or R)
+  const bool has_cols = 16 * lane < npad;
+  int4 sv[kBigCand];
+#pragma unroll
+  for (int c = 0; c < kBigCand; ++c) {
+    sv[c] = int4{0, 0, 0, 0};
+    const int trial = cand0 + c;
+    if (has_cols && trial < a.R)
+      sv[c] = *reinterpret_cast<const int4*>(a.best_s + ((size_t)inst * a.R + trial) * npad + 16 * lane);
+  }
+  for (int i = threadIdx.x; i < kBigRows * PIM_MAX_N / 16; i += 64 * kWavesPerBlock)
+    reinterpret_cast<int4*>(&sJ[0][0])[i] = int4{0, 0, 0, 0};
   const int8_t* J = a.j8[inst];
-  double acc = 0.0;
-  for (int i = 0; i < n; ++i) {
-    int row = 0;
-    for (int j = lane; j < n; j += 64) row += (int)J[(size_t)i * n + j] * (int)sS[wave][j];
-    acc += (double)(sS[wave][i] * row);
+  int acc[kBigCand];
+#pragma unroll
+  for (int c = 0; c < kBigCand; ++c) acc[c] = 0;
+  for (int t0 = 0; t0 < n; t0 += kBigRows) {
+    const int rows = min(kBigRows, n - t0);
+    __syncthreads();  // the previous tile has been read (and the clearing done)
+    // rows t0 .. t0 + rows - 1 are rows * n contiguous bytes of J
+    const int8_t* src = J + (size_t)t0 * n;
+    for (int k = threadIdx.x; k < rows * n; k += 64 * kWavesPerBlock) {
+      const int r = k / n;
+      sJ[r][k - r * n] = src[k];
+    }
+    __syncthreads();
+    const int owner = t0 >> 4;  // the lane holding columns t0 .. t0 + 15
+#pragma unroll
+    for (int r = 0; r < kBigRows; ++r) {
+      if (r < rows) {  // uniform
+        const int4 jr = has_cols ? *reinterpret_cast<const int4*>(&sJ[r][16 * lane]) : int4{0, 0, 0, 0};
+#pragma unroll
+        for (int c = 0; c < kBigCand; ++c) {
+          int part = __builtin_amdgcn_sdot4(jr.x, sv[c].x, 0, false);
+          part = __builtin_amdgcn_sdot4(jr.y, sv[c].y, part, false);
+          part = __builtin_amdgcn_sdot4(jr.z, sv[c].z, part, false);
+          part = __builtin_amdgcn_sdot4(jr.w, sv[c].w, part, false);
+          // s_i of candidate c, i = t0 + r: byte r of the owner lane's columns
+          const int w = (r < 4) ? sv[c].x : (r < 8) ? sv[c].y : (r < 12) ? sv[c].z : sv[c].w;
+          const int si = (int)(int8_t)(__builtin_amdgcn_readlane(w, owner) >> (8 * (r & 3)));
+          acc[c] += si * part;
+        }
+      }
+    }
   }
   const int32_t* hp = a.h ? a.h[inst] : nullptr;
-  if (hp)
-    for (int j = lane; j < n; j += 64) acc += 2.0 * (double)hp[j] * (double)sS[wave][j];
-  const double e = -0.5 * wave_sum(acc);
-  if (lane == 0) a.energy[cell] = e;
+#pragma unroll
+  for (int c = 0; c < kBigCand; ++c) {
+    const int trial = cand0 + c;
+    // the field term 2 sum_j h_j s_j over this lane's columns, in binary64
+    double hs = 0.0;
+    if (hp && has_cols) {
+      const int q[4] = {sv[c].x, sv[c].y, sv[c].z, sv[c].w};
+#pragma unroll
+      for (int b = 0; b < 16; ++b) {
+        const int j = 16 * lane + b;
+        if (j < n) hs += 2.0 * (double)hp[j] * (double)(int8_t)(q[b >> 2] >> (8 * (b & 3)));
+      }
+    }
+    const double e = -0.5 * wave_sum((double)acc[c] + hs);
+    if (lane == 0 && trial < a.R) a.energy[(size_t)inst * a.R + trial] = e;
+  }
 }
 
 // One block per instance: lowest binary64 energy, ties to the lowest trial;
@@ -208,7 +261,9 @@ hipError_t launch_rerank_select(const RerankArgs& a, hipStream_t s) {
     const dim3 grid((a.R + kWavesPerBlock - 1) / kWavesPerBlock, a.count);
     hipLaunchKernelGGL(rerank_real_kernel, grid, dim3(64 * kWavesPerBlock), 0, s, a);
   } else if (a.n > PIM_MAX_N_LDS) {
-    const dim3 grid((a.R + kWavesPerBlock - 1) / kWavesPerBlock, a.count);
+    if (a.npad > PIM_MAX_N || a.npad % 16) return hipErrorInvalidValue;
+    const int per_block = kWavesPerBlock * kBigCand;
+    const dim3 grid((a.R + per_block - 1) / per_block, a.count);
     hipLaunchKernelGGL(rerank_big_kernel, grid, dim3(64 * kWavesPerBlock), 0, s, a);
   } else {
     const dim3 grid((a.R + kRerankTrialsPerBlock - 1) / kRerankTrialsPerBlock, a.count);

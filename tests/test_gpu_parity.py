@@ -458,7 +458,18 @@ def test_streamed_large_n_parity(gpu_lib, case):
     partial trial blocks, fields); bit-exact against the oracle."""
     n, trials, steps, jmax, hmax = case
     _say(f"large N streamed n={n} trials={trials} steps={steps}")
-    _run_case(gpu_lib, "int", n, trials, steps, "mfma", seed=13, count=2, jmax=jmax, hmax=hmax)
+    batch = _run_case(gpu_lib, "int", n, trials, steps, "mfma", seed=13, count=2, jmax=jmax, hmax=hmax)
+    # the re-rank: pim_best returns the trial whose best state has the lowest
+    # Eq. (1) energy (ties to the lowest trial), with that energy and state
+    for k in range(2):
+        J, h = w.random_int8(n, seed=13, index=k, jmax=jmax, hmax=hmax)
+        got = batch.trials_of(k)
+        e_all = pimi.energy(J, h, got["best_state"].T.astype(np.int64))
+        spins, e, trial, step = batch.best(k)
+        assert e == float(e_all.min())
+        assert trial == int(np.argmin(e_all))
+        np.testing.assert_array_equal(spins, got["best_state"][trial])
+        assert step == got["t_best"][trial]
 
 
 def test_mixed_small_and_large_n_graph(gpu_lib):
