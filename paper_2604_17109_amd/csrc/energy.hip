@@ -58,21 +58,88 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void energy_f64_kernel(EnergyA
   if (lane == 0) a.out[cfg] = e;
 }
 
-// Re-rank for real-valued instances: one wave per candidate, binary64 J rows
-// read from global memory (too large for LDS at N = 256), lanes over columns.
+// Re-rank for real-valued instances (N <= PIM_MAX_N_LDS): one block per
+// (instance, 4 CAND candidates), CAND candidates per wave.  The binary64 J
+// streams through LDS in tiles of kRealRows rows, so each row read from L2
+// serves all of the block's candidates.  CAND = 8 when that still gives every
+// CU a block (large chunks: least L2 traffic), else CAND = 1 (a few requests:
+// their candidates spread over more CUs).  Per candidate the arithmetic is config_energy_real's, in the
+// same order: lane l sums the columns l, l + 64, ... of each row times the
+// spins, then adds s_i times that row sum (binary64, separate multiply and
+// add), and the lanes are reduced by wave_sum.  The row's own spin s_i comes
+// from the lane holding column i.
+constexpr int kRealRows = 8;   // J rows per LDS tile
+
+template <int kRealCand>
 __global__ __launch_bounds__(64 * kWavesPerBlock) void rerank_real_kernel(RerankArgs a) {
-  __shared__ __align__(16) int8_t sS[kWavesPerBlock][PIM_MAX_N_LDS];
+  __shared__ double sJ[kRealRows][PIM_MAX_N_LDS];
   const int inst = blockIdx.y;
+  const int n = a.n, npad = a.npad;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int trial = blockIdx.x * kWavesPerBlock + wave;
-  if (trial >= a.R) return;  // wave-uniform; no block barrier follows
-  const size_t cell = (size_t)inst * a.R + trial;
-  const int8_t* s = a.best_s + cell * a.npad;
-  for (int i = lane; i < a.n; i += 64) sS[wave][i] = s[i];
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-  const double e = config_energy_real(a.j64[inst], a.h64 ? a.h64[inst] : nullptr, sS[wave], a.n, lane);
-  if (lane == 0) a.energy[cell] = e;
+  const int cand0 = (blockIdx.x * kWavesPerBlock + wave) * kRealCand;
+  // spins of columns lane + 64 m (m < 4) of each candidate: packed bytes
+  // (for the s_i broadcast) and as binary64 values
+  uint32_t packed[kRealCand];
+  double sd[kRealCand][4];
+#pragma unroll
+  for (int c = 0; c < kRealCand; ++c) {
+    const int trial = cand0 + c;
+    const int8_t* s = a.best_s + ((size_t)inst * a.R + (trial < a.R ? trial : 0)) * npad;
+    packed[c] = 0;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int j = lane + 64 * m;
+      const int8_t v = (trial < a.R && j < n) ? s[j] : (int8_t)0;
+      packed[c] |= (uint32_t)(uint8_t)v << (8 * m);
+      sd[c][m] = (double)v;
+    }
+  }
+  const double* J = a.j64[inst];
+  double acc[kRealCand];
+#pragma unroll
+  for (int c = 0; c < kRealCand; ++c) acc[c] = 0.0;
+  for (int t0 = 0; t0 < n; t0 += kRealRows) {
+    const int rows = min(kRealRows, n - t0);
+    __syncthreads();  // the previous tile has been read
+    const double* src = J + (size_t)t0 * n;
+    for (int k = threadIdx.x; k < rows * n; k += 64 * kWavesPerBlock) {
+      const int r = k / n;
+      sJ[r][k - r * n] = src[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kRealRows; ++r) {
+      if (r < rows) {  // uniform
+        const int i = t0 + r;
+        const int owner = i & 63, shift = 8 * (i >> 6);
+#pragma unroll
+        for (int c = 0; c < kRealCand; ++c) {
+          double row = 0.0;
+#pragma unroll
+          for (int m = 0; m < 4; ++m) {
+            const int j = lane + 64 * m;
+            if (j < n) row += sJ[r][j] * sd[c][m];
+          }
+          const int si = (int)(int8_t)((uint32_t)__builtin_amdgcn_readlane((int)packed[c], owner) >> shift);
+          acc[c] += (double)si * row;
+        }
+      }
+    }
+  }
+  const double* h = a.h64 ? a.h64[inst] : nullptr;
+#pragma unroll
+  for (int c = 0; c < kRealCand; ++c) {
+    double v = acc[c];
+    if (h)
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const int j = lane + 64 * m;
+        if (j < n) v += 2.0 * h[j] * sd[c][m];
+      }
+    const double e = -0.5 * wave_sum(v);
+    const int trial = cand0 + c;
+    if (lane == 0 && trial < a.R) a.energy[(size_t)inst * a.R + trial] = e;
+  }
 }
 
 // Batch re-rank of every trial's best state.  One block per (instance, 16
@@ -258,8 +325,16 @@ hipError_t launch_energy_f64(const EnergyArgs& a, hipStream_t s) {
 hipError_t launch_rerank_select(const RerankArgs& a, hipStream_t s) {
   if (a.n > PIM_MAX_N) return hipErrorInvalidValue;
   if (a.j64) {
-    const dim3 grid((a.R + kWavesPerBlock - 1) / kWavesPerBlock, a.count);
-    hipLaunchKernelGGL(rerank_real_kernel, grid, dim3(64 * kWavesPerBlock), 0, s, a);
+    if (a.n > PIM_MAX_N_LDS) return hipErrorInvalidValue;
+    constexpr int kWide = 8, kCus = 256;
+    const size_t wide_blocks = (size_t)a.count * ((a.R + kWavesPerBlock * kWide - 1) / (kWavesPerBlock * kWide));
+    if (wide_blocks >= kCus) {
+      const dim3 grid((a.R + kWavesPerBlock * kWide - 1) / (kWavesPerBlock * kWide), a.count);
+      hipLaunchKernelGGL(rerank_real_kernel<kWide>, grid, dim3(64 * kWavesPerBlock), 0, s, a);
+    } else {
+      const dim3 grid((a.R + kWavesPerBlock - 1) / kWavesPerBlock, a.count);
+      hipLaunchKernelGGL(rerank_real_kernel<1>, grid, dim3(64 * kWavesPerBlock), 0, s, a);
+    }
   } else if (a.n > PIM_MAX_N_LDS) {
     if (a.npad > PIM_MAX_N || a.npad % 16) return hipErrorInvalidValue;
     const int per_block = kWavesPerBlock * kBigCand;
