@@ -1059,7 +1059,9 @@ pim_status pim_batch_create(pim_instance* const* insts, int32_t count, int32_t t
 
 void pim_batch_destroy(pim_batch* b) {
   if (!b) return;
-  if (b->stream || true) (void)hipStreamSynchronize(b->stream);
+  // the last run's work (on the stream it was issued on) has finished before
+  // its buffers and its cancel flag slot are released
+  (void)hipStreamSynchronize(b->stream);
   free_batch_buffers(b);
   delete b;
 }
