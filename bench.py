@@ -57,6 +57,7 @@ def parse():
     ap.add_argument("--serving-requests", type=int, default=4000)
     ap.add_argument("--uneven-steps", type=int, default=2000,
                     help="steps of the uneven-N batched leg (the workload states 10^4; shortened to bound the run)")
+    ap.add_argument("--no-tts-scan", action="store_true", help="skip the TTS99 scan over the anneal length")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the parallel-vs-sequential comparison and the flip-rate diagnostic")
     ap.add_argument("--mimo-requests", type=int, default=512,
@@ -450,6 +451,7 @@ def main():
     args = parse()
     if args.core_only:
         args.no_mimo = args.no_serving = args.no_uneven = args.no_compare = args.no_cpu_baseline = True
+        args.no_tts_scan = True
         args.plain_instances = 0
     if args.copy_probe:
         copy_probe(args.copy_probe)
@@ -502,6 +504,25 @@ def main():
     tau = (kernel_ms / 1000.0) / (I * R * T)  # seconds per trial-step on the full batch
     tts99 = n99 * T * tau if n99 != math.inf else None
 
+    # TTS99 over the anneal length: the same batch and success threshold, a
+    # linear 0.1 -> 3.0 schedule over each T (after the timed region)
+    def tts_row(Ts, p, kms):
+        n = 1 if p >= 1 else (math.inf if p <= 0 else math.ceil(math.log(0.01) / math.log(1 - p)))
+        t = (kms / 1000.0) / (I * R * Ts) if kms > 0 else 0.0
+        return {"steps": Ts, "p_bar": p, "n99": n if n != math.inf else None,
+                "tts99_s": n * Ts * t if n != math.inf else None}
+
+    scan = []
+    if args.kernel == "mfma" and not args.no_tts_scan:
+        for Ts in sorted({t for t in (250, 500, 1000, 2000, 5000) if t < T}):
+            bs = w.linear_beta(Ts, 0.1, 3.0)
+            batch.run(bs, w.eta_sqrt_beta_over_5(bs), seed=1, kernel=args.kernel, target=target)
+            hs = [batch.trials_of(k, spins=False)["first_hit"] for k in range(I)]
+            scan.append(tts_row(Ts, float(np.mean([(fh >= 0).mean() for fh in hs])), batch.kernel_ms()))
+    scan.append(tts_row(T, p_bar, kernel_ms))
+    finite = [r for r in scan if r["tts99_s"] is not None]
+    tts_best = min(finite, key=lambda r: r["tts99_s"]) if finite else None
+
     # roofline of the sweep kernel (algorithmic counts per launch)
     contractions = float(I) * R * (T + 1)
     mfma_ops = 2.0 * n * n * contractions
@@ -536,7 +557,8 @@ def main():
                    "instances": I, "trials": R, "steps_per_trial": T, "n": n, "parallelism": "single GPU"},
         "kernel_ms": kernel_ms,
         "tts99": {"p_bar": p_bar, "n99": n99 if n99 != math.inf else None, "tts99_s": tts99,
-                  "criterion": "E <= floor(0.999 * best energy of the warmup run)", "steps": T},
+                  "criterion": "E <= floor(0.999 * best energy of the warmup run)", "steps": T,
+                  "over_steps": scan, "min_over_steps": tts_best},
         "roofline": {"bound": "alu", "achieved": alu_ops / kernel_s, "peak": VALU_PEAK, "unit": "lane-op/s",
                      "frac": alu_ops / kernel_s / VALU_PEAK,
                      "traffic": measured_traffic() if (args.n, args.trials, args.instances, args.sweeps)
