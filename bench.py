@@ -273,14 +273,22 @@ def uneven_leg(args):
     batch.close()
     for n in sizes:
         sub = [i for i, m in zip(insts, ns) if m == n]
+        sub_tgt = [t for t, m in zip(tgt, ns) if m == n]
         b = pim.Batch(sub, R)
         b.run(beta, eta, seed=2)
-        b.run(beta, eta, seed=2)
+        b.run(beta, eta, seed=2, target=sub_tgt)
         k = b.kernel_ms()
         u = float(len(sub)) * n * R * T
         o = 2.0 * n * n * len(sub) * R * (T + 1)
+        # success against the same thresholds (0.999 of the best found by
+        # the batch's warm-up run): p_bar, n99 and TTS99 with all trials in
+        # flight, tau = this bucket's kernel time per trial-step
+        p = float(np.mean([(b.trials_of(q, spins=False)["first_hit"] >= 0).mean() for q in range(len(sub))]))
+        n99 = 1 if p >= 1 else (None if p <= 0 else math.ceil(math.log(0.01) / math.log(1 - p)))
+        tau = (k / 1e3) / (len(sub) * R * T)
         out["per_n"][str(n)] = {"instances": len(sub), "kernel_ms": k, "spin_updates_per_s": u / (k / 1e3),
-                                "int8_mfma_frac": o / (k / 1e3) / INT8_MFMA_PEAK}
+                                "int8_mfma_frac": o / (k / 1e3) / INT8_MFMA_PEAK, "p_bar_relaxed": p,
+                                "n99": n99, "tts99_s": n99 * T * tau if n99 else None}
         b.close()
     for i in insts:
         i.close()
