@@ -78,7 +78,7 @@ def test_sk20_config_parity(gpu_lib, kernel):
 
 
 @pytest.mark.parametrize("kernel", KERNELS)
-@pytest.mark.parametrize("n,trials", [(1, 8), (31, 40), (32, 64), (33, 33), (200, 70), (256, 32)])
+@pytest.mark.parametrize("n,trials", [(1, 8), (31, 40), (32, 64), (33, 33), (200, 70), (256, 32), (50, 1), (2, 1)])
 def test_sizes_and_ragged_tails(gpu_lib, kernel, n, trials):
     _say(f"sizes n={n} trials={trials} kernel={kernel}")
     _run_case(gpu_lib, "maxcut" if n > 2 else "sk", n, trials, 120, kernel, seed=n, count=2)
@@ -448,6 +448,7 @@ BIG_CASES = [
     (777, 64, 30, 1, 0),
     (1000, 32, 30, 1, 0),
     (1024, 70, 24, 30, 40),
+    (300, 1, 20, 2, 1),     # a single trial: one column block with 31 empty lanes, 3 empty blocks
 ]
 
 

@@ -64,6 +64,8 @@ CASES = [
     ("bf16", "mfma", 256, 32, 30, False, "mimo"),
     ("fp8", "plain", 33, 40, 60, True, "anneal"),
     ("bf16", "plain", 128, 64, 40, True, "mimo"),
+    ("fp8", "mfma", 64, 1, 30, True, "mimo"),      # a single trial
+    ("bf16", "plain", 40, 1, 30, False, "anneal"),
 ]
 
 
