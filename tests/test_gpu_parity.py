@@ -201,6 +201,7 @@ SEQ_CASES = [
     # n, trials, steps, hmax, jmax, xi, noise
     (20, 64, 2000, 0, 1, 0.0, "uniform"),
     (1, 8, 12, 0, 1, 0.0, "uniform"),
+    (33, 40, 1, 2, 2, 0.5, "gauss"),     # a single step
     (33, 70, 700, 5, 3, 0.5, "gauss"),
     (64, 64, 640, 0, 1, 0.0, "uniform"),
     (200, 16, 600, 0, 1, 0.0, "uniform"),
@@ -269,6 +270,13 @@ def test_recorded_states_and_flip_rate(gpu_lib, xi):
     np.testing.assert_array_equal(num, rnum)
     np.testing.assert_array_equal(den, rden)
     batch.close()
+
+
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_single_step_runs(gpu_lib, kernel):
+    """T = 1: one update and the energies of s(0) and s(1), bit-exact."""
+    _say(f"single step {kernel}")
+    _run_case(gpu_lib, "int", 40, 33, 1, kernel, seed=21, count=2, jmax=2, hmax=2)
 
 
 def test_schedule_changes_between_runs(gpu_lib):
@@ -449,6 +457,7 @@ BIG_CASES = [
     (1000, 32, 30, 1, 0),
     (1024, 70, 24, 30, 40),
     (300, 1, 20, 2, 1),     # a single trial: one column block with 31 empty lanes, 3 empty blocks
+    (400, 64, 1, 2, 0),     # a single step
 ]
 
 

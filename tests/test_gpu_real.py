@@ -65,6 +65,7 @@ CASES = [
     ("fp8", "plain", 33, 40, 60, True, "anneal"),
     ("bf16", "plain", 128, 64, 40, True, "mimo"),
     ("fp8", "mfma", 64, 1, 30, True, "mimo"),      # a single trial
+    ("bf16", "mfma", 96, 40, 1, True, "mimo"),     # a single step
     ("bf16", "plain", 40, 1, 30, False, "anneal"),
 ]
 
