@@ -114,8 +114,14 @@ def cpu_baseline(n, trials, steps, xi, c):
     t0 = time.perf_counter()
     pimi.run_parallel(prob, beta, eta, 1, 0, np.arange(trials))
     dt = time.perf_counter() - t0
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": trials * steps * n / dt, "unit": "spin-updates/s", "cores": int(threads),
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": model, "nproc": os.cpu_count(),
             "sample": f"SK-1 N={n} instance 0, {trials} trials x first {steps} of the 10^4 steps "
                       f"({dt:.1f} s, NumPy binary64 on the host)"}
 
