@@ -208,7 +208,9 @@ pim_status pim_batch_create(pim_instance* const* insts, int32_t count, int32_t t
  * sequential kernels' tables stay on the device: a run whose beta and eta
  * equal (bit for bit, same T) those of the batch's previous such run reuses
  * them without compiling or uploading.  The host waits for the table upload
- * before returning; the sweep itself runs asynchronously.  Tracks, over the
+ * before returning; the sweep itself runs asynchronously.  A run on another
+ * stream than the batch's previous call first waits on the host for the work
+ * on that stream, since the two runs share the batch's buffers.  Tracks, over the
  * energies E(t) of s(t) for t = 0..T (counter steps start_step..start_step+T):
  * the lowest energy and its earliest step, the state there, and the first step
  * with E <= target.  Resuming: pass the previous final spins as init_spins of a

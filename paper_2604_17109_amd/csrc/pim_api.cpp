@@ -368,6 +368,16 @@ pim_status create_composite(pim_instance* const* insts, int32_t count, int32_t t
   return PIM_OK;
 }
 
+// Every run of a batch reuses its buffers.  A call on another stream than the
+// batch's previous one first waits for the work left on that stream, since
+// the two streams are not otherwise ordered.
+hipError_t settle_stream(pim_batch* b, hipStream_t s) {
+  if (b->stream == s) return hipSuccess;
+  hipError_t e = hipStreamSynchronize(b->stream);
+  if (e == hipSuccess) b->stream = s;
+  return e;
+}
+
 struct RunCtx {
   int T = 0, L = 0;
   bool real = false, mfma = false, seq = false;
@@ -414,7 +424,10 @@ pim_status run_prepare(pim_batch* b, const pim_schedule* sc, hipStream_t s, RunC
         if ((double)tf > sc->target[k]) tf = std::nextafter(tf, -INFINITY);
         tgtf[k] = tf;
       }
-    b->stream = s;
+    if (hipError_t e0 = settle_stream(b, s); e0 != hipSuccess) {
+      b->sticky_error = true;
+      return fail(PIM_ERR_DEVICE, "waiting for the previous stream failed: %s", hipGetErrorString(e0));
+    }
     const int L = b->insts[0]->rule.levels;
     const int ncls = (int)b->class_rep.size();
     const bool real = b->real;
@@ -1104,13 +1117,16 @@ pim_status pim_run(pim_batch* b, const pim_schedule* sc, uint64_t seed, void* st
     std::vector<pim_schedule> psc(P, *sc);
     if (sc->use_target)
       for (int k = 0; k < b->count; ++k) tg[b->part_of[k]].push_back(sc->target[k]);
+    if (hipError_t e0 = settle_stream(b, s); e0 != hipSuccess) {
+      b->sticky_error = true;
+      return fail(PIM_ERR_DEVICE, "waiting for the previous stream failed: %s", hipGetErrorString(e0));
+    }
     std::vector<RunCtx> ctx(P);
     for (size_t p = 0; p < P; ++p) {
       if (sc->use_target) psc[p].target = tg[p].data();
       pim_status st = run_prepare(b->parts[p], &psc[p], s, ctx[p]);
       if (st != PIM_OK) return st;
     }
-    b->stream = s;
     if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     b->gexec = nullptr;

@@ -340,6 +340,33 @@ def test_kernel_changes_between_runs(gpu_lib):
     batch.close()
 
 
+def test_run_on_another_stream(gpu_lib):
+    """A long run of a batch on one stream, then at once a run with another
+    schedule on a second stream: the second waits for the first and equals
+    the same run done alone, bit for bit."""
+    import ctypes
+    import torch
+    _say("runs of one batch on two streams")
+    pim = gpu_lib
+    n = 64
+    J, h = w.random_int8(n, seed=72, index=0, jmax=2, hmax=2)
+    inst = pim.Instance(J, h, j_scale=1 / np.sqrt(n), xi=0.5, noise_table=w.gauss_table(8), rng_stream=90)
+    b1 = w.linear_beta(20000, 0.1, 3.0)
+    b2 = w.linear_beta(3000, 0.2, 2.5)
+    e1, e2 = w.eta_sqrt_beta_over_5(b1), w.eta_sqrt_beta_over_5(b2)
+    alone = pim.Batch([inst], 256).run(b2, e2, seed=14)
+    ref = alone.trials_of(0)
+    alone.close()
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    batch = pim.Batch([inst], 256)
+    batch.run(b1, e1, seed=14, stream=ctypes.c_void_p(s1.cuda_stream))
+    batch.run(b2, e2, seed=14, stream=ctypes.c_void_p(s2.cuda_stream))
+    got = batch.trials_of(0)
+    for key in ("final", "e_best", "t_best", "best_state", "first_hit"):
+        assert np.array_equal(got[key], ref[key]), key
+    batch.close()
+
+
 def test_concurrent_runs_on_distinct_batches(gpu_lib):
     """Two threads run two batches at once, each on its own stream, switching
     schedules every run so that every run compiles and uploads its step tables
