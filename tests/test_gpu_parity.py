@@ -197,6 +197,41 @@ def test_full_size_maxcut200_sampled_trials(gpu_lib):
     np.testing.assert_array_equal(e_final, got["e_final"])
 
 
+def test_full_size_sk200_batched_sampled(gpu_lib):
+    """Batched SK-1 N=200, 128 instances x 1024 trials x 10^4 steps with a
+    first-hit target: the benchmark's headline workload in its launch
+    configuration.  The oracle recomputes sampled (instance, trial) pairs in
+    full; every trial's tracked best and final energies equal the energies of
+    the states returned, and each instance's best is the lowest trial."""
+    _say("sk200 128x1024x10000 mfma, sampled oracle trials")
+    pim = gpu_lib
+    n, R, T, I = 200, 1024, 10000, 128
+    c, xi, ztab = 1.0 / np.sqrt(n), 0.5, w.gauss_table(8)
+    target = -2000.0
+    probs = [w.sk1(n, seed=1, index=k) for k in range(I)]
+    insts = [pim.Instance(J, h, j_scale=c, xi=xi, levels=4, noise_table=ztab, rng_stream=k)
+             for k, (J, h) in enumerate(probs)]
+    beta = w.linear_beta(T, 0.1, 3.0)
+    eta = w.eta_sqrt_beta_over_5(beta)
+    batch = pim.Batch(insts, R)
+    batch.run(beta, eta, seed=1, kernel="mfma", target=[target] * I)
+    for k, trials in ((0, [0, 1023]), (63, [5, 700]), (127, [511])):
+        J, h = probs[k]
+        ref = _oracle(J, h, c, xi, 4, ztab, beta, eta, 1, k, trials, target=target)
+        _compare(batch, k, ref, trials, n)
+    for k in range(I):
+        J, h = probs[k]
+        got = batch.trials_of(k)
+        for key, ek in (("best_state", "e_best"), ("final", "e_final")):
+            S = got[key].T.astype(np.int64)
+            np.testing.assert_array_equal(pimi.energy_from_field(pimi.local_field(J, h, S), h, S), got[ek])
+        hit = got["first_hit"]
+        assert np.all((hit == -1) == (got["e_best"] > target))
+        spins, e, trial, _ = batch.best(k)
+        assert e == got["e_best"].min() and trial == int(np.argmin(got["e_best"]))
+    batch.close()
+
+
 SEQ_CASES = [
     # n, trials, steps, hmax, jmax, xi, noise
     (20, 64, 2000, 0, 1, 0.0, "uniform"),
