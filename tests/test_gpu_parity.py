@@ -232,6 +232,40 @@ def test_full_size_sk200_batched_sampled(gpu_lib):
     batch.close()
 
 
+def test_full_size_uneven_batch_sampled(gpu_lib):
+    """The benchmark's uneven-N workload as it is launched there: 128 SK-1
+    instances with N_k = [100, 200, 400, 800, 1000][k mod 5], 1024 trials x
+    2000 steps, tuned, one graph launch, with first-hit targets.  The oracle
+    recomputes a sampled trial of six instances (every N) in full; every
+    trial's tracked best energy equals the energy of its returned state."""
+    _say("uneven N 128x1024x2000 graph, sampled oracle trials")
+    pim = gpu_lib
+    sizes = [100, 200, 400, 800, 1000]
+    count, R, T = 128, 1024, 2000
+    ns = [sizes[k % 5] for k in range(count)]
+    ztab = w.gauss_table(8)
+    probs = [w.sk1(ns[k], seed=9, index=k) for k in range(count)]
+    insts = [pim.Instance(J, h, j_scale=1 / np.sqrt(ns[k]), xi=0.5, noise_table=ztab, rng_stream=k)
+             for k, (J, h) in enumerate(probs)]
+    beta = w.linear_beta(T, 0.1, 3.0)
+    eta = w.eta_sqrt_beta_over_5(beta)
+    tgt = [float(np.floor(-0.7 * n ** 1.5)) for n in ns]
+    batch = pim.Batch(insts, R)
+    batch.tune(steps=100)
+    batch.run(beta, eta, seed=2, target=tgt)
+    for k, trials in ((0, [0]), (1, [1023]), (2, [300]), (3, [511]), (4, [1000]), (124, [7])):
+        J, h = probs[k]
+        ref = _oracle(J, h, 1 / np.sqrt(ns[k]), 0.5, 4, ztab, beta, eta, 2, k, trials, target=tgt[k])
+        _compare(batch, k, ref, trials, ns[k])
+    for k in range(count):
+        J, h = probs[k]
+        got = batch.trials_of(k)
+        S = got["best_state"].T.astype(np.int64)
+        np.testing.assert_array_equal(pimi.energy_from_field(pimi.local_field(J, h, S), h, S), got["e_best"])
+        assert np.all((got["first_hit"] == -1) == (got["e_best"] > tgt[k]))
+    batch.close()
+
+
 SEQ_CASES = [
     # n, trials, steps, hmax, jmax, xi, noise
     (20, 64, 2000, 0, 1, 0.0, "uniform"),
