@@ -140,7 +140,8 @@ def _load():
         "pim_flip_counts": (I32, [VP, I32, P(ctypes.c_int64), P(ctypes.c_int64)]),
         "pim_tune": (I32, [VP, I32, VP, P(I32)]),
         "pim_server_create": (I32, [P(ServerConfig), P(VP)]),
-        "pim_server_submit": (I32, [VP, I32, P(ctypes.c_uint32), P(I32), P(P(F64)), P(P(F64)), P(I32)]),
+        # ids, ns and the two pointer tables go as raw addresses of numpy arrays
+        "pim_server_submit": (I32, [VP, I32, VP, VP, VP, VP, P(I32)]),
         "pim_server_flush": (I32, [VP, P(I32)]),
         "pim_server_poll": (I32, [VP, I32, P(ctypes.c_uint32), P(ctypes.c_int8), P(F64), P(I32)]),
         "pim_server_pending": (I32, [VP, P(I32), P(I32)]),
@@ -548,12 +549,22 @@ class Server:
         Js = [np.ascontiguousarray(J, dtype=np.float64) for J in Js]
         hs = None if hs is None else [np.ascontiguousarray(h, dtype=np.float64) for h in hs]
         idarr = np.ascontiguousarray(ids, dtype=np.uint32)
-        ns = np.array([J.shape[0] for J in Js], dtype=np.int32)
-        jp = (ctypes.POINTER(ctypes.c_double) * k)(*[_ptr(J, ctypes.c_double) for J in Js])
-        hp = None if hs is None else (ctypes.POINTER(ctypes.c_double) * k)(*[_ptr(h, ctypes.c_double) for h in hs])
+        if len(Js) != k or idarr.shape != (k,) or (hs is not None and len(hs) != k):
+            raise ValueError("ids, Js and hs must have one entry per request")
+        for J in Js:
+            if J.ndim != 2 or J.shape[0] != J.shape[1]:
+                raise ValueError("each J must be a square matrix")
+        if hs is not None:
+            for J, h in zip(Js, hs):
+                if h.shape != (J.shape[0],):
+                    raise ValueError("each h must have one entry per spin")
+        # the library reads the arrays through these addresses during the call
+        ns = np.fromiter((J.shape[0] for J in Js), dtype=np.int32, count=k)
+        jp = np.fromiter((J.ctypes.data for J in Js), dtype=np.uintp, count=k)
+        hp = None if hs is None else np.fromiter((h.ctypes.data for h in hs), dtype=np.uintp, count=k)
         adm = ctypes.c_int32()
-        st = lib.pim_server_submit(self._handle, k, _ptr(idarr, ctypes.c_uint32), _ptr(ns, ctypes.c_int32), jp, hp,
-                                   ctypes.byref(adm))
+        st = lib.pim_server_submit(self._handle, k, idarr.ctypes.data, ns.ctypes.data, jp.ctypes.data,
+                                   None if hp is None else hp.ctypes.data, ctypes.byref(adm))
         if st != PIM_OK:
             # the requests before the rejected one are admitted; the error says how many
             err = PimError(st, lib.pim_last_error().decode(errors="replace"))
