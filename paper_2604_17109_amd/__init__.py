@@ -352,10 +352,19 @@ class Instance:
     def __init__(self, J, h=None, *, j_scale, xi, levels=4, noise="gauss", noise_table=None,
                  rng_stream=0, prec=None, stream=None):
         self.real = prec is not None
-        J = np.ascontiguousarray(J, dtype=np.float64 if self.real else np.int8)
+        Jin = np.asarray(J)
+        J = np.ascontiguousarray(Jin, dtype=np.float64 if self.real else np.int8)
         if J.ndim != 2 or J.shape[0] != J.shape[1]:
             raise ValueError("J must be square")
+        if not self.real and not np.array_equal(J, Jin):
+            raise ValueError("integer couplings must be whole numbers in [-128, 127]")
         self.n = J.shape[0]
+        if h is not None:
+            hin = np.asarray(h)
+            if hin.shape != (self.n,):
+                raise ValueError("h must have one entry per spin")
+            if not self.real and not np.array_equal(hin.astype(np.int32), hin):
+                raise ValueError("integer fields must be whole numbers in the int32 range")
         p, keep = make_params(self.n, j_scale, xi, levels, noise, noise_table, rng_stream)
         self._handle = ctypes.c_void_p()
         _device_ready()

@@ -224,3 +224,18 @@ def test_server_calls_reject_null_handle(pim):
                                    ctypes.byref(one)) == pim.PIM_ERR_INVALID
     assert pim.lib.pim_server_pending(None, ctypes.byref(one), ctypes.byref(one)) == pim.PIM_ERR_INVALID
     pim.lib.pim_server_destroy(None)  # no-op
+
+
+@pytest.mark.parametrize("J, h, what", [
+    (np.array([[0, 200], [200, 0]]), None, "whole numbers"),      # would wrap in int8
+    (np.array([[0, 0.5], [0.5, 0]]), None, "whole numbers"),
+    (np.zeros((2, 3)), None, "square"),
+    (np.zeros((3, 3)), np.zeros(2), "one entry per spin"),
+    (np.zeros((2, 2)), np.array([2 ** 40, 0]), "int32 range"),
+])
+def test_instance_rejects_malformed_input_before_the_library(pim, J, h, what):
+    """The binding refuses arrays that it could not hand over faithfully
+    (values that a cast would change, shapes the library would read past)
+    before any device call, so this runs without a GPU."""
+    with pytest.raises(ValueError, match=what):
+        pim.Instance(J, h, j_scale=1.0, xi=0.5)
