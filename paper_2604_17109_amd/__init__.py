@@ -342,6 +342,15 @@ def mimo_decode(xm, spins, qam, mapping="di"):
     return x[:, 0] + 1j * x[:, 1]
 
 
+def _spins_int8(a):
+    """a as contiguous int8, refusing values that the cast would change."""
+    a_in = np.asarray(a)
+    s = np.ascontiguousarray(a_in, dtype=np.int8)
+    if not np.array_equal(s, a_in):
+        raise ValueError("spins must be +1 or -1")
+    return s
+
+
 class Instance:
     """One Ising instance with its update-rule constants, copied to the device.
 
@@ -385,7 +394,9 @@ class Instance:
 
     def energy(self, spins, stream=None):
         """Binary64 energies (Eq. (1)) of configurations spins[count, n]."""
-        s = np.ascontiguousarray(np.atleast_2d(spins), dtype=np.int8)
+        s = _spins_int8(np.atleast_2d(spins))
+        if s.ndim != 2 or s.shape[1] != self.n:
+            raise ValueError("spins must be [count, n]")
         out = np.zeros(s.shape[0], dtype=np.float64)
         _check(lib.pim_energy(self._handle, _ptr(s, ctypes.c_int8), s.shape[0], _ptr(out, ctypes.c_double),
                               stream if stream is not None else current_stream()))
@@ -418,10 +429,15 @@ class Batch:
         init = None
         if init_spins is not None:
             if self.n is not None:
-                init = np.ascontiguousarray(init_spins, dtype=np.int8).reshape(self.count, self.trials, self.n)
+                init = _spins_int8(init_spins).reshape(self.count, self.trials, self.n)
             else:  # a sequence of [trials, n_k] arrays
-                init = np.ascontiguousarray(np.concatenate(
-                    [np.asarray(a, dtype=np.int8).reshape(-1) for a in init_spins]))
+                parts = list(init_spins)
+                if len(parts) != self.count:
+                    raise ValueError("init_spins needs one [trials, n_k] array per instance")
+                for a, n in zip(parts, self.ns):
+                    if np.shape(a) != (self.trials, n):
+                        raise ValueError("init_spins needs one [trials, n_k] array per instance")
+                init = np.ascontiguousarray(np.concatenate([_spins_int8(a).reshape(-1) for a in parts]))
         self._handle = ctypes.c_void_p()
         self.stream = stream if stream is not None else current_stream()
         _check(lib.pim_batch_create(arr, self.count, self.trials, _ptr(init, ctypes.c_int8), self.stream,

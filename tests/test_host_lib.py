@@ -239,3 +239,11 @@ def test_instance_rejects_malformed_input_before_the_library(pim, J, h, what):
     before any device call, so this runs without a GPU."""
     with pytest.raises(ValueError, match=what):
         pim.Instance(J, h, j_scale=1.0, xi=0.5)
+
+
+def test_spin_arrays_refuse_values_the_cast_would_change(pim):
+    """255 would become -1 in int8: the binding refuses it instead."""
+    from paper_2604_17109_amd import _spins_int8
+    assert _spins_int8(np.array([1, -1, 1.0])).dtype == np.int8
+    with pytest.raises(ValueError, match="spins"):
+        _spins_int8(np.array([1, 255]))
