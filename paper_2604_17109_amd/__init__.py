@@ -301,6 +301,8 @@ def quantize(J, prec):
     """Host-only: (couplings scale * q as float64, scale) that the batched kernel
     uses for a real-valued J in precision "fp8" or "bf16"."""
     J = np.ascontiguousarray(J, dtype=np.float64)
+    if J.ndim != 2 or J.shape[0] != J.shape[1]:
+        raise ValueError("J must be square")
     out = np.zeros_like(J)
     scale = ctypes.c_double()
     _check(lib.pim_quantize(_ptr(J, ctypes.c_double), J.shape[0], _PRECS[prec], _ptr(out, ctypes.c_double),
@@ -318,6 +320,8 @@ def mimo_ising(H, y, qam, mapping="di", esn0=1.0):
     [nr, nt], y [nr]): returns (J [n, n], h [n], x_m [2 nt]), all float64."""
     Hc = _complex_interleaved(H)
     yc = _complex_interleaved(y)
+    if Hc.ndim != 3 or yc.shape != (Hc.shape[0], 2):
+        raise ValueError("H must be [nr, nt] and y [nr]")
     nr, nt = Hc.shape[0], Hc.shape[1]
     J = np.zeros((4 * nt, 4 * nt), np.float64)
     h = np.zeros(4 * nt, np.float64)
@@ -334,8 +338,11 @@ def mimo_ising(H, y, qam, mapping="di", esn0=1.0):
 def mimo_decode(xm, spins, qam, mapping="di"):
     """Detected complex symbols [nt] of a spin vector under the same mapping."""
     xm = np.ascontiguousarray(xm, dtype=np.float64)
-    s = np.ascontiguousarray(spins, dtype=np.int8)
+    s = _spins_int8(spins)
     nt = xm.size // 2
+    n = 2 * nt if (mapping == "ml" and int(qam) == 4) else 4 * nt
+    if xm.size != 2 * nt or int(qam) not in (4, 16) or s.size != n:
+        raise ValueError("x_m must be [2 nt] and spins [2 nt] (ML, 4-QAM) or [4 nt]")
     x = np.zeros((nt, 2), np.float64)
     _check(lib.pim_mimo_decode(_ptr(xm, ctypes.c_double), _ptr(s, ctypes.c_int8), nt, int(qam), _MAPS[mapping],
                                _ptr(x, ctypes.c_double)))

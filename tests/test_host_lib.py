@@ -247,3 +247,15 @@ def test_spin_arrays_refuse_values_the_cast_would_change(pim):
     assert _spins_int8(np.array([1, -1, 1.0])).dtype == np.int8
     with pytest.raises(ValueError, match="spins"):
         _spins_int8(np.array([1, 255]))
+
+
+def test_mimo_helpers_check_shapes(pim):
+    """Shapes that the library would read past are refused in the binding."""
+    with pytest.raises(ValueError, match="square"):
+        pim.quantize(np.zeros((2, 3)), "fp8")
+    with pytest.raises(ValueError, match="H must be"):
+        pim.mimo_ising(np.zeros((4, 2), complex), np.zeros(3, complex), 4, "ml")
+    with pytest.raises(ValueError, match="spins"):
+        pim.mimo_decode(np.zeros(4), np.ones(3), 4, "ml")       # 2 nt = 4 spins expected
+    with pytest.raises(ValueError, match="spins"):
+        pim.mimo_decode(np.zeros(4), np.ones(4), 16, "di")      # 4 nt = 8 spins expected
