@@ -360,9 +360,10 @@ pim_status pim_server_create(const pim_server_config* cfg, pim_server** out);
 pim_status pim_server_submit(pim_server* server, int32_t count, const uint32_t* ids, const int32_t* ns,
                              const double* const* J, const double* const* h, int32_t* admitted);
 
-/* Launches staged requests, one launch per chunk, round-robin over the
- * server's streams (upload, sweep, re-rank and readback are asynchronous),
- * and returns: full chunks always, partly filled ones once their first request
+/* Launches staged requests, one launch per chunk, on a server stream whose
+ * previous launch has finished if there is one, else on the next stream in
+ * turn (upload, sweep, re-rank and readback are asynchronous), and returns:
+ * full chunks always, partly filled ones once their first request
  * has waited max_wait_us.  *launched: requests launched. */
 pim_status pim_server_flush(pim_server* server, int32_t* launched);
 
