@@ -55,7 +55,12 @@
  *     owned by the handle that allocated it.
  *   - `stream` arguments are hipStream_t values owned by the caller (NULL =
  *     the default stream).  pim_run is asynchronous on its stream; pim_best,
- *     pim_trials and pim_energy synchronise the stream they use.
+ *     pim_trials and pim_energy synchronise the stream they use.  The result
+ *     calls of a batch (pim_best, pim_trials, pim_states, pim_flip_counts)
+ *     run on the stream of its last pim_run, which must therefore stay valid
+ *     until the batch's last such call; a later pim_run on another stream and
+ *     pim_batch_destroy wait for the last run through an event of the batch
+ *     and never touch that stream.
  *   - Handles are not thread-safe; distinct handles may be used from
  *     distinct threads.
  */
@@ -123,7 +128,12 @@ typedef struct {
   double xi;                 /* inertia xi >= 0, finite                             */
   int32_t levels;            /* L, 2 <= L <= 16                                     */
   int32_t noise;             /* pim_noise                                           */
-  int32_t noise_bits;        /* B; must be 8                                        */
+  int32_t noise_bits;        /* B; must be 8 (PIM_ERR_UNSUPPORTED otherwise): one
+                                Philox4x32-10 call draws the noise of 16 spins, the
+                                grain of the kernels' 16-spin tiles, and the
+                                paper's own noise samples are 4-bit fixed point
+                                (Suppl. "PIMI FPGA implementation for Max-cut and
+                                SK-1")                                              */
   const double* noise_table; /* host, 2^B finite non-decreasing values, or NULL for
                                 the built-in table of `noise` (copied at create)   */
   uint32_t rng_stream;       /* counter word 3 id, < 2^24 (request/instance id)    */
@@ -230,8 +240,12 @@ pim_status pim_tune(pim_batch* batch, int32_t steps, void* stream, int32_t* wave
  * run are partial and the result getters return PIM_ERR_CANCELLED. */
 pim_status pim_cancel(pim_batch* batch);
 
-/* Energies (Eq. (1)) of `count` host configurations spins[count][N] (+-1), in
- * binary64 on the device; out: host double[count].  Synchronises `stream`. */
+/* Energies (Eq. (1)) of `count` configurations spins[count][N] (+-1), in
+ * binary64 on the device; out: host double[count].  `spins` is either host
+ * memory (validated: every value must be +-1, else PIM_ERR_INVALID) or device
+ * memory of the current device, which the runtime identifies as such and the
+ * kernel reads in place without validation (values other than +-1 give
+ * meaningless energies).  Synchronises `stream`. */
 pim_status pim_energy(const pim_instance* inst, const int8_t* spins, int32_t count,
                       double* out, void* stream);
 
@@ -372,6 +386,14 @@ pim_status pim_server_flush(pim_server* server, int32_t* launched);
  * binary64 energies [max] (may be NULL); *done: how many. */
 pim_status pim_server_poll(pim_server* server, int32_t max, uint32_t* ids, int8_t* states, double* energies,
                            int32_t* done);
+
+/* pim_server_poll that also reports, per returned request, three times in
+ * seconds of the host's monotonic clock (CLOCK_MONOTONIC on Linux):
+ * times[3r] its admission by pim_server_submit, times[3r+1] the
+ * pim_server_flush call that launched its chunk, times[3r+2] this poll,
+ * which found the chunk's work finished (times: host [max][3], or NULL). */
+pim_status pim_server_poll_times(pim_server* server, int32_t max, uint32_t* ids, int8_t* states,
+                                 double* energies, double* times, int32_t* done);
 
 /* Requests staged but not launched, and launched but not yet polled. */
 pim_status pim_server_pending(pim_server* server, int32_t* staged, int32_t* in_flight);

@@ -46,7 +46,7 @@ EXPORTED = (
     "pim_create_real", "pim_quantize", "pim_compile_table_real", "pim_mimo_ising", "pim_mimo_decode",
     "pim_states", "pim_flip_counts", "pim_tune",
     "pim_server_create", "pim_server_submit", "pim_server_flush", "pim_server_poll", "pim_server_pending",
-    "pim_server_destroy",
+    "pim_server_destroy", "pim_server_poll_times",
 )
 MAX_N_LDS = 256
 
@@ -145,6 +145,7 @@ def _load():
         "pim_server_flush": (I32, [VP, P(I32)]),
         "pim_server_poll": (I32, [VP, I32, P(ctypes.c_uint32), P(ctypes.c_int8), P(F64), P(I32)]),
         "pim_server_pending": (I32, [VP, P(I32), P(I32)]),
+        "pim_server_poll_times": (I32, [VP, I32, P(ctypes.c_uint32), P(ctypes.c_int8), P(F64), P(F64), P(I32)]),
         "pim_server_destroy": (None, [VP]),
     }
     for name, (res, args) in sig.items():
@@ -400,7 +401,21 @@ class Instance:
         return self._handle
 
     def energy(self, spins, stream=None):
-        """Binary64 energies (Eq. (1)) of configurations spins[count, n]."""
+        """Binary64 energies (Eq. (1)) of configurations spins[count, n]: a
+        host array, or a contiguous int8 torch tensor on the GPU, which the
+        library reads in place (its values are not checked: they must be
+        +-1)."""
+        import torch
+        if isinstance(spins, torch.Tensor) and spins.is_cuda:
+            if spins.dtype != torch.int8 or spins.dim() != 2 or spins.shape[1] != self.n \
+                    or not spins.is_contiguous() or spins.shape[0] < 1:
+                raise ValueError("device spins must be a contiguous int8 tensor [count, n]")
+            out = np.zeros(spins.shape[0], dtype=np.float64)
+            _check(lib.pim_energy(self._handle, ctypes.cast(ctypes.c_void_p(spins.data_ptr()),
+                                                            ctypes.POINTER(ctypes.c_int8)),
+                                  spins.shape[0], _ptr(out, ctypes.c_double),
+                                  stream if stream is not None else current_stream()))
+            return out
         s = _spins_int8(np.atleast_2d(spins))
         if s.ndim != 2 or s.shape[1] != self.n:
             raise ValueError("spins must be [count, n]")
@@ -554,6 +569,7 @@ class Server:
         self._ids = np.zeros(self._poll_max, np.uint32)
         self._states = np.zeros((self._poll_max, MAX_N_LDS), np.int8)
         self._e = np.zeros(self._poll_max, np.float64)
+        self._t = np.zeros((self._poll_max, 3), np.float64)
         self._beta = np.ascontiguousarray(beta, dtype=np.float64)
         self._eta = np.ascontiguousarray(eta, dtype=np.float64)
         self._ztab = None if noise_table is None else np.ascontiguousarray(noise_table, dtype=np.float64)
@@ -618,6 +634,18 @@ class Server:
                                    _ptr(self._e, ctypes.c_double), ctypes.byref(done)))
         k = done.value
         return self._ids[:k].copy(), (self._states[:k].copy() if states else None), self._e[:k].copy()
+
+    def poll_times(self, states=True):
+        """poll() plus, per request, (admitted, launched, seen finished) in
+        seconds of the host's monotonic clock (time.perf_counter's clock)."""
+        done = ctypes.c_int32()
+        _check(lib.pim_server_poll_times(self._handle, self._poll_max, _ptr(self._ids, ctypes.c_uint32),
+                                         _ptr(self._states, ctypes.c_int8) if states else None,
+                                         _ptr(self._e, ctypes.c_double), _ptr(self._t, ctypes.c_double),
+                                         ctypes.byref(done)))
+        k = done.value
+        return (self._ids[:k].copy(), (self._states[:k].copy() if states else None), self._e[:k].copy(),
+                self._t[:k].copy())
 
     def pending(self):
         a, b = ctypes.c_int32(), ctypes.c_int32()

@@ -206,9 +206,11 @@ pim_status check_spins(const int8_t* s, size_t count) {
   return PIM_OK;
 }
 
+hipError_t wait_last_run(pim_batch* b);
+
 void free_batch_buffers(pim_batch* b) {
   for (pim_batch* part : b->parts) {
-    (void)hipStreamSynchronize(part->stream);
+    (void)wait_last_run(part);
     free_batch_buffers(part);
     delete part;
   }
@@ -368,12 +370,22 @@ pim_status create_composite(pim_instance* const* insts, int32_t count, int32_t t
   return PIM_OK;
 }
 
+// Waits on the host for the batch's last run: ev1 is recorded after every
+// launch of a run, and every later call on the batch synchronises before it
+// returns, so nothing of the batch is in flight after it.  Waiting on the
+// event rather than on the run's stream keeps working when the caller has
+// destroyed that stream since.
+hipError_t wait_last_run(pim_batch* b) {
+  if (!b->ran || !b->ev1) return hipSuccess;
+  return hipEventSynchronize(b->ev1);
+}
+
 // Every run of a batch reuses its buffers.  A call on another stream than the
-// batch's previous one first waits for the work left on that stream, since
-// the two streams are not otherwise ordered.
+// batch's previous one first waits for the previous run, since the two
+// streams are not otherwise ordered.
 hipError_t settle_stream(pim_batch* b, hipStream_t s) {
   if (b->stream == s) return hipSuccess;
-  hipError_t e = hipStreamSynchronize(b->stream);
+  hipError_t e = wait_last_run(b);
   if (e == hipSuccess) b->stream = s;
   return e;
 }
@@ -1072,9 +1084,9 @@ pim_status pim_batch_create(pim_instance* const* insts, int32_t count, int32_t t
 
 void pim_batch_destroy(pim_batch* b) {
   if (!b) return;
-  // the last run's work (on the stream it was issued on) has finished before
-  // its buffers and its cancel flag slot are released
-  (void)hipStreamSynchronize(b->stream);
+  // the last run's work has finished before its buffers and its cancel flag
+  // slot are released
+  (void)wait_last_run(b);
   free_batch_buffers(b);
   delete b;
 }
@@ -1272,12 +1284,22 @@ pim_status pim_energy(const pim_instance* inst, const int8_t* spins, int32_t cou
     if (!inst || !spins || !out) return fail(PIM_ERR_INVALID, "NULL argument");
     if (count < 1) return fail(PIM_ERR_INVALID, "count must be >= 1");
     const int n = inst->rule.n;
-    pim_status st = check_spins(spins, (size_t)count * n);
+    // device memory (the caller's device buffer) is read in place; anything
+    // the runtime does not know as device memory is a host array
+    bool on_device = false;
+    {
+      hipPointerAttribute_t attr{};
+      if (hipPointerGetAttributes(&attr, spins) == hipSuccess)
+        on_device = attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged;
+      else
+        (void)hipGetLastError();  // an unknown pointer is host memory, not an error
+    }
+    pim_status st = on_device ? PIM_OK : check_spins(spins, (size_t)count * n);
     if (st != PIM_OK) return st;
     hipStream_t s = (hipStream_t)stream;
     int8_t* d_s = nullptr;
     double* d_o = nullptr;
-    st = alloc_dev(&d_s, (size_t)count * n, s);
+    if (!on_device) st = alloc_dev(&d_s, (size_t)count * n, s);
     if (st == PIM_OK) st = alloc_dev(&d_o, (size_t)count, s);
     if (st != PIM_OK) {
       dev_free(d_s, s);
@@ -1288,13 +1310,13 @@ pim_status pim_energy(const pim_instance* inst, const int8_t* spins, int32_t cou
     ea.h = (!inst->rule.real && inst->has_h) ? inst->d_h : nullptr;
     ea.jf64 = inst->rule.real ? inst->d_j64 : nullptr;
     ea.hf64 = (inst->rule.real && inst->has_h) ? inst->d_h64 : nullptr;
-    ea.spins = d_s;
+    ea.spins = on_device ? spins : d_s;
     ea.out = d_o;
     ea.n = n;
     ea.jstride = inst->jstride;
     ea.stride = n;
     ea.count = count;
-    hipError_t e = hipMemcpyAsync(d_s, spins, (size_t)count * n, hipMemcpyHostToDevice, s);
+    hipError_t e = on_device ? hipSuccess : hipMemcpyAsync(d_s, spins, (size_t)count * n, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = launch_energy_f64(ea, s);
     if (e == hipSuccess) e = hipMemcpyAsync(out, d_o, (size_t)count * sizeof(double), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);

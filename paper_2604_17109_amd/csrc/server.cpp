@@ -38,6 +38,11 @@
 namespace pim {
 namespace {
 
+// Seconds on the host's monotonic clock (CLOCK_MONOTONIC on Linux).
+double mono_now() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
 struct Chunk {
   int cls = 0;
   int count = 0;                 // requests admitted into this chunk
@@ -46,6 +51,8 @@ struct Chunk {
   hipEvent_t done = nullptr;
   std::vector<uint32_t> ids;
   std::vector<int32_t> ns;
+  std::vector<double> t_admit;   // per request: admission time (host monotonic clock, s)
+  double t_launch = 0.0;         // when pim_server_flush issued the chunk
   // pinned host staging (inputs) and results, each one contiguous block
   // (h_in / d_in, h_out / d_out) of sections; the result block is read back
   // by one copy
@@ -564,6 +571,7 @@ pim_status pim_server_submit(pim_server* s, int32_t count, const uint32_t* ids, 
       c->h_sid[sl] = ids[took];
       c->ids.push_back(ids[took]);
       c->ns.push_back(n);
+      c->t_admit.push_back(0.0);
       ++c->count;
       place.emplace_back(c, sl);
     }
@@ -604,12 +612,15 @@ pim_status pim_server_submit(pim_server* s, int32_t count, const uint32_t* ids, 
         --c->count;
         c->ids.pop_back();
         c->ns.pop_back();
+        c->t_admit.pop_back();
       }
       *admitted = g;
       return fail(PIM_ERR_INVALID, "request %d (id %u): J must be finite and symmetric with a zero diagonal, "
                   "h finite", g, ids[g]);
     }
     // requests before an invalid one are admitted (and counted) as usual
+    const double t_adm = mono_now();
+    for (int r = 0; r < took; ++r) place[r].first->t_admit[place[r].second] = t_adm;
     *admitted = took;
     if (took == f && f < count)
       return fail(PIM_ERR_INVALID, "request %d (id %u): n outside [1, max_n], id >= 2^24 or J NULL", f, ids[f]);
@@ -648,6 +659,7 @@ pim_status pim_server_flush(pim_server* s, int32_t* launched) {
       }
       s->next_stream = (si + 1) % ns;
       hipStream_t st = s->streams[si];
+      c->t_launch = mono_now();
       hipError_t e = launch_chunk(s, c, st);
       if (e == hipSuccess) e = hipEventRecord(s->stream_idle[si], st);
       if (e != hipSuccess) return fail(PIM_ERR_DEVICE, "server launch failed: %s", hipGetErrorString(e));
@@ -665,9 +677,15 @@ pim_status pim_server_flush(pim_server* s, int32_t* launched) {
 
 pim_status pim_server_poll(pim_server* s, int32_t max, uint32_t* ids, int8_t* states, double* energies,
                            int32_t* done) {
+  return pim_server_poll_times(s, max, ids, states, energies, nullptr, done);
+}
+
+pim_status pim_server_poll_times(pim_server* s, int32_t max, uint32_t* ids, int8_t* states, double* energies,
+                                 double* times, int32_t* done) {
   try {
     if (!s || !ids || !done) return fail(PIM_ERR_INVALID, "NULL argument");
     *done = 0;
+    const double t_seen = times ? mono_now() : 0.0;
     // finished chunks in any order (streams complete independently)
     for (auto it = s->inflight.begin(); it != s->inflight.end();) {
       Chunk* c = *it;
@@ -687,12 +705,18 @@ pim_status pim_server_poll(pim_server* s, int32_t max, uint32_t* ids, int8_t* st
           std::memcpy(states + (size_t)o * PIM_MAX_N_LDS, c->h_spins + (size_t)r * np, c->ns[r]);
         }
         if (energies) energies[o] = c->h_e[r];
+        if (times) {
+          times[3 * (size_t)o] = c->t_admit[r];
+          times[3 * (size_t)o + 1] = c->t_launch;
+          times[3 * (size_t)o + 2] = t_seen;
+        }
       }
       *done += c->count;
       c->count = 0;
       c->launched = false;
       c->ids.clear();
       c->ns.clear();
+      c->t_admit.clear();
       it = s->inflight.erase(it);
     }
     return PIM_OK;

@@ -130,6 +130,11 @@ def test_energy_f64_matches_eq1(gpu_lib):
         got = inst.energy(S)
         want = pimi.energy(J, h, S.T.astype(np.int64)).astype(np.float64)
         np.testing.assert_array_equal(got, want)
+        # the same configurations from device memory, read in place
+        import torch
+        dev = torch.from_numpy(S).to("cuda")
+        np.testing.assert_array_equal(inst.energy(dev), want)
+        np.testing.assert_array_equal(inst.energy(dev[5:9]), want[5:9])
 
 
 def test_best_is_lowest_trial_argmin(gpu_lib):

@@ -105,6 +105,54 @@ def test_dyadic_trajectories_bit_exact(gpu_lib, case):
     batch.close()
 
 
+# (prec, n, instances, trials, steps, with_h): instances x ceil(trials / 32)
+# trial blocks > 128, so the launch takes the batched form (one wave per
+# 32-trial block, every row tile of the block in that wave)
+BATCHED = [
+    ("fp8", 64, 5, 1024, 40, True),      # 2 row tiles: one K step of the FP8 MFMA
+    ("fp8", 200, 5, 1000, 30, True),     # 7 tiles, ragged N and a ragged last block
+    ("fp8", 96, 9, 500, 30, False),      # 3 tiles (odd), 16 blocks per instance
+    ("bf16", 128, 5, 1024, 30, True),    # 4 tiles
+    ("bf16", 256, 5, 1024, 24, False),   # 8 tiles, the largest N
+    ("bf16", 33, 5, 1000, 40, True),     # 2 tiles, 1 spin in the second
+]
+
+
+@pytest.mark.parametrize("case", BATCHED, ids=lambda c: "-".join(map(str, c)))
+def test_dyadic_batched_form_bit_exact(gpu_lib, case):
+    """The batched one-wave-per-block form, the one that large batches and
+    large server chunks run, against the binary64 oracle bit for bit."""
+    prec, n, count, trials, steps, with_h = case
+    assert count * ((trials + 31) // 32) > 128
+    _say(f"real dyadic batched form prec={prec} n={n} instances={count} trials={trials} steps={steps}")
+    pim = gpu_lib
+    ztab = w.gauss_table(8)
+    beta, eta, c, xi = _schedule("anneal", steps)
+    insts, refs = [], []
+    for k in range(count):
+        J, h = _dyadic(n, prec, seed=40 + k, with_h=with_h)
+        insts.append(pim.Instance(J, h, j_scale=c, xi=xi, levels=4, noise_table=ztab, rng_stream=60 + k,
+                                  prec=prec))
+        refs.append((J, h))
+    batch = pim.Batch(insts, trials)
+    targets = [float(pimi.energy_f64(J, h, np.ones(n))) - 1.0 for (J, h) in refs]
+    batch.run(beta, eta, seed=31, target=targets)
+    for k, (J, h) in enumerate(refs):
+        prob = pimi.RealProblem(J, h, c, xi, 4, ztab)
+        ref = pimi.run_parallel(prob, beta, eta, 31, 60 + k, np.arange(trials), target=targets[k])
+        got = batch.trials_of(k)
+        np.testing.assert_array_equal(got["final"], ref["final"].T.astype(np.int8))
+        np.testing.assert_array_equal(got["t_best"], ref["t_best"])
+        np.testing.assert_array_equal(got["e_best"], ref["e_best"])
+        np.testing.assert_array_equal(got["best_state"], ref["best_state"].T.astype(np.int8))
+        np.testing.assert_array_equal(got["first_hit"], ref["first_hit"])
+        spins, e, trial, step = batch.best(k)
+        e_ref = pimi.energy_f64(J, h, ref["best_state"].astype(np.float64))
+        assert e == float(e_ref.min()) and trial == int(np.argmin(e_ref))
+        np.testing.assert_array_equal(spins, ref["best_state"][:, trial].astype(np.int8))
+    batch.close()
+
+
 @pytest.mark.parametrize("prec", ["fp8", "bf16"])
 def test_real_resume_equals_uninterrupted(gpu_lib, prec):
     _say(f"real resume prec={prec}")
@@ -159,13 +207,16 @@ def test_mimo_energies_are_binary64(gpu_lib, prec):
 
 @pytest.mark.parametrize("prec,kernel", [("fp8", "mfma"), ("bf16", "mfma"), ("fp8", "plain")])
 def test_mimo_detection_matches_oracle_statistically(gpu_lib, prec, kernel):
-    """8x8 16-QAM at 15 dB, DI mapping, 32 trials x 32 steps: the symbol error
-    rate of the GPU kernels is within sampling error of the binary64 oracle's
-    dynamics on the same channels (different arithmetic, so different noise
-    realisations of the same law in effect)."""
+    """8x8 16-QAM at 15 dB, DI mapping, 32 trials x 32 steps, 256 channels
+    (2048 symbols): the symbol error rate of the GPU kernels is within three
+    standard deviations of the binary64 oracle's dynamics on the same channels
+    (different arithmetic, so in effect different noise realisations of the
+    same law).  The deviation is that of the difference of two independent
+    binomial rates at the pooled rate, which overstates the spread of these
+    correlated runs; there is no additive allowance."""
     _say(f"mimo SER prec={prec} kernel={kernel}")
     pim = gpu_lib
-    count, nt, qam = 48, 8, 16
+    count, nt, qam = 256, 8, 16
     probs, insts, maps = _mimo_instances(pim, nt, qam, 15.0, count, prec, seed=2)
     steps = 32
     beta, eta = w.constant(steps, 1.0), w.mimo_eta(steps, 0.05, 1.0)
@@ -182,10 +233,12 @@ def test_mimo_detection_matches_oracle_statistically(gpu_lib, prec, kernel):
         s_ref = ref["best_state"][:, int(np.argmin(e_ref))]
         err_orc += mimo.symbol_errors(p["x"], mimo.decode(d["xm"], d["T"], s_ref, qam))
     total = count * nt
+    assert total >= 2000
     ser_gpu, ser_orc = err_gpu / total, err_orc / total
-    print(f"SER gpu {ser_gpu:.4f} oracle {ser_orc:.4f} over {total} symbols", flush=True)
-    sd = np.sqrt(2 * max(ser_orc, 0.01) * (1 - max(ser_orc, 0.01)) / total)
-    assert abs(ser_gpu - ser_orc) <= 4 * sd + 0.01
+    pooled = (err_gpu + err_orc) / (2 * total)
+    sd = np.sqrt(2 * pooled * (1 - pooled) / total)
+    print(f"SER gpu {ser_gpu:.4f} oracle {ser_orc:.4f} over {total} symbols, 3 sd = {3 * sd:.4f}", flush=True)
+    assert abs(ser_gpu - ser_orc) <= 3 * sd
     batch.close()
 
 

@@ -8,6 +8,7 @@ import numpy as np
 import pytest
 
 import workloads as w
+from oracle import pimi
 
 pytestmark = pytest.mark.gpu
 
@@ -76,6 +77,63 @@ def test_server_matches_batch_api_and_alone_equals_mix(gpu_lib):
     assert set(got) == {r[0] for r in reqs}
     assert np.array_equal(got[777][0][:n], alone[0][:n]) and got[777][1] == alone[1]
     srv.close()
+    # every request of the mix equals the same request through the batch API
+    # (rng stream = id; instances of different N run as one uneven batch), and
+    # its reported energy is the oracle's binary64 Eq. (1) energy of its state
+    insts = [pim.Instance(J_, h_, j_scale=1.0, xi=2.0, noise_table=w.gauss_table(8), rng_stream=rid, prec="fp8")
+             for rid, J_, h_ in reqs]
+    b = pim.Batch(insts, 32).run(BETA, ETA, seed=7)
+    for k, (rid, J_, h_) in enumerate(reqs):
+        m = J_.shape[0]
+        s_ref, e_ref, _, _ = b.best(k)
+        assert np.array_equal(got[rid][0][:m], s_ref) and got[rid][1] == e_ref, rid
+        assert got[rid][1] == pytest.approx(pimi.energy_f64(J_, h_, got[rid][0][:m].astype(np.float64)),
+                                            rel=1e-9, abs=1e-9), rid
+    b.close()
+
+
+def _dyadic_fp8(n, seed):
+    """Couplings whose FP8 quantisation on the device is exact (q in e4m3,
+    max |q| = 448 so the scale is 2^-6) and fields on the same grid: every
+    binary32 operation of the sweep is exact."""
+    rng = np.random.default_rng([seed, n])
+    q = np.triu(rng.integers(-16, 17, size=(n, n)).astype(np.float64), 1)
+    q = q + q.T
+    q[0, 1] = q[1, 0] = 448.0
+    return q * 2.0 ** -6, rng.integers(-1000, 1001, size=n) * 2.0 ** -6
+
+
+def test_server_dyadic_requests_bit_exact_vs_oracle(gpu_lib):
+    """Requests through pim_server_* (binary64 staging, device-side FP8
+    quantisation, chunked sweep, binary64 re-rank and selection) against the
+    binary64 oracle: the returned state is the oracle's best trial state (ties
+    to the lowest trial) and the energy is its Eq. (1) energy, exactly."""
+    _say("server: dyadic requests vs the oracle")
+    pim = gpu_lib
+    # small chunks of mixed classes (the latency form of the sweep), then one
+    # chunk of 160 requests of one class (more than 128 trial blocks: the
+    # batched form)
+    sizes = [16, 40, 64, 100, 128, 33, 64, 96]
+    small = [(300 + k, *_dyadic_fp8(sizes[k % len(sizes)], seed=k)) for k in range(24)]
+    large = [(400 + k, *_dyadic_fp8(64, seed=100 + k)) for k in range(160)]
+    got = {}
+    for reqs, max_batch, slots in ((small, 8, 64), (large, 160, 160)):
+        srv = _server(pim, max_n=128, max_batch=max_batch, slots_per_class=slots)
+        left = reqs
+        took = srv.submit([r[0] for r in left], [r[1] for r in left], [r[2] for r in left])
+        assert took == len(reqs)
+        srv.flush()
+        got.update(_drain(srv, len(reqs)))
+        srv.close()
+    reqs = small + large
+    ztab = w.gauss_table(8)
+    for rid, J, h in reqs:
+        n = J.shape[0]
+        ref = pimi.run_parallel(pimi.RealProblem(J, h, 1.0, 2.0, 4, ztab), BETA, ETA, 7, rid, np.arange(32))
+        e_all = pimi.energy_f64(J, h, ref["best_state"].astype(np.float64))
+        a = int(np.argmin(e_all))
+        assert np.array_equal(got[rid][0][:n], ref["best_state"][:, a].astype(np.int8)), rid
+        assert got[rid][1] == float(e_all[a]), rid
 
 
 def test_server_admission_limits(gpu_lib):

@@ -109,3 +109,21 @@ def interleaved(z):
     the layout the C library takes for complex inputs."""
     z = np.asarray(z, dtype=np.complex128)
     return np.ascontiguousarray(np.stack([z.real, z.imag], axis=-1))
+
+
+# The detection grid of the MIMO benchmark (Fig. 5 / Table 1 sizes and SNRs
+# extended to Nt = 32, 64): Nt = Nr, modulation, Eb/N0 in dB and the number of
+# update steps (Table 1's 16 / 32 for 8x8 and 32 / 64 for 16x16 with 4- / 16-QAM,
+# doubled for every doubling of Nt).  32 trials, DI mapping (N = 4 Nt spins).
+GRID_SIZES = (8, 16, 32, 64)
+GRID_QAMS = (4, 16)
+GRID_SNRS_DB = (10.0, 15.0, 20.0, 25.0)
+GRID_SEED = 31
+
+
+def grid_steps(nt, qam):
+    return (16 if qam == 4 else 32) * (nt // 8)
+
+
+def grid_points():
+    return [(nt, qam, db, grid_steps(nt, qam)) for nt in GRID_SIZES for qam in GRID_QAMS for db in GRID_SNRS_DB]
