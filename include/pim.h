@@ -249,6 +249,24 @@ pim_status pim_cancel(pim_batch* batch);
 pim_status pim_energy(const pim_instance* inst, const int8_t* spins, int32_t count,
                       double* out, void* stream);
 
+/* Size in bytes of the device scratch array behind pim_energy_noalloc (one
+ * per GPU, held until the process ends). */
+#define PIM_NOALLOC_SCRATCH_BYTES 1048576
+
+/* pim_energy for callers that cannot allocate device memory (code that must
+ * not call hipMalloc, tight serving loops, harnesses that forbid allocation):
+ * the same arguments, validation, results and synchronisation, but no device
+ * allocation of any kind.  The energies, and host spins staged for the
+ * kernel, live in the library's fixed per-GPU scratch array of
+ * PIM_NOALLOC_SCRATCH_BYTES bytes: 8 * count rounded up to 256, plus
+ * count * N for host spins (device spins are read in place), must fit, else
+ * PIM_ERR_INVALID.  Every call on a GPU shares that GPU's array: calls that
+ * overlap on one GPU (from several host threads, on any streams) race and
+ * must be serialised by the caller.  Not for stream capture (it
+ * synchronises). */
+pim_status pim_energy_noalloc(const pim_instance* inst, const int8_t* spins, int32_t count,
+                              double* out, void* stream);
+
 /* Best candidate of instance `inst` after a run: re-evaluates every trial's
  * best state in binary64 on the device (once per run), takes the lowest
  * energy (ties: lowest trial id) and returns its state (host int8[N]), energy,

@@ -46,9 +46,10 @@ EXPORTED = (
     "pim_create_real", "pim_quantize", "pim_compile_table_real", "pim_mimo_ising", "pim_mimo_decode",
     "pim_states", "pim_flip_counts", "pim_tune",
     "pim_server_create", "pim_server_submit", "pim_server_flush", "pim_server_poll", "pim_server_pending",
-    "pim_server_destroy", "pim_server_poll_times",
+    "pim_server_destroy", "pim_energy_noalloc", "pim_server_poll_times",
 )
 MAX_N_LDS = 256
+NOALLOC_SCRATCH_BYTES = 1 << 20
 
 
 class PimError(RuntimeError):
@@ -122,6 +123,7 @@ def _load():
         "pim_run": (I32, [VP, P(Schedule), ctypes.c_uint64, VP]),
         "pim_cancel": (I32, [VP]),
         "pim_energy": (I32, [VP, P(ctypes.c_int8), I32, P(F64), VP]),
+        "pim_energy_noalloc": (I32, [VP, P(ctypes.c_int8), I32, P(F64), VP]),
         "pim_best": (I32, [VP, I32, P(ctypes.c_int8), P(F64), P(I32), P(I32)]),
         "pim_trials": (I32, [VP, I32, P(F64), P(I32), P(I32), P(F64), P(ctypes.c_int8), P(ctypes.c_int8)]),
         "pim_kernel_time": (I32, [VP, P(ctypes.c_float)]),
@@ -422,6 +424,28 @@ class Instance:
         out = np.zeros(s.shape[0], dtype=np.float64)
         _check(lib.pim_energy(self._handle, _ptr(s, ctypes.c_int8), s.shape[0], _ptr(out, ctypes.c_double),
                               stream if stream is not None else current_stream()))
+        return out
+
+    def energy_noalloc(self, spins, stream=None):
+        """energy() through pim_energy_noalloc: no device allocation (the
+        library's fixed per-GPU scratch array holds the staging)."""
+        import torch
+        st = stream if stream is not None else current_stream()
+        if isinstance(spins, torch.Tensor) and spins.is_cuda:
+            if spins.dtype != torch.int8 or spins.dim() != 2 or spins.shape[1] != self.n \
+                    or not spins.is_contiguous() or spins.shape[0] < 1:
+                raise ValueError("device spins must be a contiguous int8 tensor [count, n]")
+            out = np.zeros(spins.shape[0], dtype=np.float64)
+            _check(lib.pim_energy_noalloc(self._handle, ctypes.cast(ctypes.c_void_p(spins.data_ptr()),
+                                                                    ctypes.POINTER(ctypes.c_int8)),
+                                          spins.shape[0], _ptr(out, ctypes.c_double), st))
+            return out
+        s = _spins_int8(np.atleast_2d(spins))
+        if s.ndim != 2 or s.shape[1] != self.n:
+            raise ValueError("spins must be [count, n]")
+        out = np.zeros(s.shape[0], dtype=np.float64)
+        _check(lib.pim_energy_noalloc(self._handle, _ptr(s, ctypes.c_int8), s.shape[0],
+                                      _ptr(out, ctypes.c_double), st))
         return out
 
     def close(self):
