@@ -337,6 +337,15 @@ pim_status pim_compile_table_real(const pim_params* params, double beta, double 
 pim_status pim_mimo_ising(const double* H, const double* y, int32_t nr, int32_t nt, int32_t qam, int32_t map,
                           double esn0, double* J, double* h, double* xm, int32_t* n_out);
 
+/* pim_mimo_ising computed on the device (the request server's mapping
+ * kernel, one workgroup, binary64): same arguments and outputs, plus the
+ * stream it runs on (synchronised before returning).  nr <= PIM_MAX_N_LDS / 2.
+ * The sums run in the host function's order, so the results are expected to
+ * be identical to it. */
+pim_status pim_mimo_ising_device(const double* H, const double* y, int32_t nr, int32_t nt, int32_t qam,
+                                 int32_t map, double esn0, double* J, double* h, double* xm, int32_t* n_out,
+                                 void* stream);
+
 /* Detected symbols of a spin vector s (host int8 [n] of +-1) under the same
  * mapping: x = slice(x_m + T s), each real component sliced to the nearest
  * odd-integer level (2 floor(v/2) + 1, clipped).  x: host complex [nt] as
@@ -412,6 +421,37 @@ pim_status pim_server_poll(pim_server* server, int32_t max, uint32_t* ids, int8_
  * which found the chunk's work finished (times: host [max][3], or NULL). */
 pim_status pim_server_poll_times(pim_server* server, int32_t max, uint32_t* ids, int8_t* states,
                                  double* energies, double* times, int32_t* done);
+
+/* A server for MIMO detection requests given as the detection problem
+ * itself (Suppl. "Throughput requirement for LTE/5G systems": one instance
+ * per data-bearing OFDM symbol): each request is (H, y, modulation, mapping,
+ * Es/N0), and the Ising instance of pim_mimo_ising (J, h and x_m in binary64)
+ * is built on the device at launch, so the host stages only H and y.  Same
+ * configuration, slots, launches and results as pim_server_create; such a
+ * server takes pim_server_submit_mimo only (pim_server_submit returns
+ * PIM_ERR_STATE), and pim_server_poll_mimo also returns each request's x_m. */
+pim_status pim_server_create_mimo(const pim_server_config* cfg, pim_server** out);
+
+/* Admits up to `count` MIMO requests in order: ids[r] < 2^24 (also the noise
+ * stream); dims[4r .. 4r+3] = (nr, nt, qam, map) with qam 4 or 16, map a
+ * pim_mimo_map, 1 <= nt <= PIM_MAX_N_LDS / 4, N = 2 nt (ML, 4-QAM) or 4 nt
+ * <= max_n, and 1 <= 2 nr <= N rounded up to 32; esn0[r] (linear Es/N0, > 0
+ * for the DI mapping); H[r]: host complex [nr][nt] and y[r]: complex [nr],
+ * interleaved (re, im) binary64, finite.  Copies H and y into pinned staging;
+ * *admitted: how many were taken (fewer when no slot or budget is free).  An
+ * invalid request returns PIM_ERR_INVALID with the ones before it admitted.
+ * No device work.  A request whose MMSE system is not positive definite in
+ * binary64 finishes with energy NaN. */
+pim_status pim_server_submit_mimo(pim_server* server, int32_t count, const uint32_t* ids, const int32_t* dims,
+                                  const double* esn0, const double* const* H, const double* const* y,
+                                  int32_t* admitted);
+
+/* pim_server_poll_times that also returns, for MIMO requests, x_m (host
+ * [max][PIM_MAX_N_LDS / 2] binary64, first 2 nt entries used: real parts then
+ * imaginary parts; may be NULL): the detected symbols are
+ * pim_mimo_decode(x_m, state, nt, qam, map). */
+pim_status pim_server_poll_mimo(pim_server* server, int32_t max, uint32_t* ids, int8_t* states, double* energies,
+                                double* xm, double* times, int32_t* done);
 
 /* Requests staged but not launched, and launched but not yet polled. */
 pim_status pim_server_pending(pim_server* server, int32_t* staged, int32_t* in_flight);

@@ -47,6 +47,7 @@ EXPORTED = (
     "pim_states", "pim_flip_counts", "pim_tune",
     "pim_server_create", "pim_server_submit", "pim_server_flush", "pim_server_poll", "pim_server_pending",
     "pim_server_destroy", "pim_energy_noalloc", "pim_server_poll_times",
+    "pim_mimo_ising_device", "pim_server_create_mimo", "pim_server_submit_mimo", "pim_server_poll_mimo",
 )
 MAX_N_LDS = 256
 NOALLOC_SCRATCH_BYTES = 1 << 20
@@ -148,6 +149,13 @@ def _load():
         "pim_server_poll": (I32, [VP, I32, P(ctypes.c_uint32), P(ctypes.c_int8), P(F64), P(I32)]),
         "pim_server_pending": (I32, [VP, P(I32), P(I32)]),
         "pim_server_poll_times": (I32, [VP, I32, P(ctypes.c_uint32), P(ctypes.c_int8), P(F64), P(F64), P(I32)]),
+        "pim_mimo_ising_device": (I32, [P(F64), P(F64), I32, I32, I32, I32, F64, P(F64), P(F64), P(F64), P(I32),
+                                        VP]),
+        "pim_server_create_mimo": (I32, [P(ServerConfig), P(VP)]),
+        # ids, dims, esn0 and the two pointer tables go as raw addresses of numpy arrays
+        "pim_server_submit_mimo": (I32, [VP, I32, VP, VP, VP, VP, VP, P(I32)]),
+        "pim_server_poll_mimo": (I32, [VP, I32, P(ctypes.c_uint32), P(ctypes.c_int8), P(F64), P(F64), P(F64),
+                                       P(I32)]),
         "pim_server_destroy": (None, [VP]),
     }
     for name, (res, args) in sig.items():
@@ -335,6 +343,26 @@ def mimo_ising(H, y, qam, mapping="di", esn0=1.0):
                               _ptr(xm, ctypes.c_double), ctypes.byref(n)))
     k = n.value
     # the library writes J as a dense k x k block at the start of the buffer
+    return np.ascontiguousarray(J.reshape(-1)[: k * k].reshape(k, k)), h[:k].copy(), xm
+
+
+def mimo_ising_device(H, y, qam, mapping="di", esn0=1.0, stream=None):
+    """mimo_ising computed by the device mapping kernel (binary64)."""
+    Hc = _complex_interleaved(H)
+    yc = _complex_interleaved(y)
+    if Hc.ndim != 3 or yc.shape != (Hc.shape[0], 2):
+        raise ValueError("H must be [nr, nt] and y [nr]")
+    nr, nt = Hc.shape[0], Hc.shape[1]
+    J = np.zeros((4 * nt, 4 * nt), np.float64)
+    h = np.zeros(4 * nt, np.float64)
+    xm = np.zeros(2 * nt, np.float64)
+    n = ctypes.c_int32()
+    _device_ready()
+    _check(lib.pim_mimo_ising_device(_ptr(Hc, ctypes.c_double), _ptr(yc, ctypes.c_double), nr, nt, int(qam),
+                                     _MAPS[mapping], float(esn0), _ptr(J, ctypes.c_double), _ptr(h, ctypes.c_double),
+                                     _ptr(xm, ctypes.c_double), ctypes.byref(n),
+                                     stream if stream is not None else current_stream()))
+    k = n.value
     return np.ascontiguousarray(J.reshape(-1)[: k * k].reshape(k, k)), h[:k].copy(), xm
 
 
@@ -587,13 +615,15 @@ class Server:
 
     def __init__(self, *, max_n, trials, beta, eta, j_scale=1.0, xi=2.0, levels=4, noise="gauss",
                  noise_table=None, prec="fp8", slots_per_class=4096, max_batch=256, streams=4, seed=1,
-                 hbm_budget=0, poll_max=4096, max_wait_us=0.0, prealloc_chunks=0):
+                 hbm_budget=0, poll_max=4096, max_wait_us=0.0, prealloc_chunks=0, mimo=False):
         _device_ready()
+        self.mimo = bool(mimo)
         self._poll_max = max(int(poll_max), int(max_batch))
         self._ids = np.zeros(self._poll_max, np.uint32)
         self._states = np.zeros((self._poll_max, MAX_N_LDS), np.int8)
         self._e = np.zeros(self._poll_max, np.float64)
         self._t = np.zeros((self._poll_max, 3), np.float64)
+        self._xm = np.zeros((self._poll_max, MAX_N_LDS // 2), np.float64)
         self._beta = np.ascontiguousarray(beta, dtype=np.float64)
         self._eta = np.ascontiguousarray(eta, dtype=np.float64)
         self._ztab = None if noise_table is None else np.ascontiguousarray(noise_table, dtype=np.float64)
@@ -609,7 +639,8 @@ class Server:
         c.max_wait_us = float(max_wait_us)
         c.prealloc_chunks = int(prealloc_chunks)
         self._handle = ctypes.c_void_p()
-        _check(lib.pim_server_create(ctypes.byref(c), ctypes.byref(self._handle)))
+        create = lib.pim_server_create_mimo if self.mimo else lib.pim_server_create
+        _check(create(ctypes.byref(c), ctypes.byref(self._handle)))
 
     def submit(self, ids, Js, hs=None):
         """Stages requests (ids, J arrays, h arrays); returns how many were
@@ -643,6 +674,63 @@ class Server:
             err.admitted = adm.value
             raise err
         return adm.value
+
+    def submit_mimo(self, ids, Hs, ys, qams, mappings="di", esn0s=1.0):
+        """Stages MIMO requests (server created with mimo=True): complex H
+        [nr, nt] and y [nr] per request, its modulation, mapping and Es/N0;
+        returns how many were admitted."""
+        k = len(ids)
+        if k == 0:
+            return 0
+        Hc = [_complex_interleaved(H) for H in Hs]
+        yc = [_complex_interleaved(y) for y in ys]
+        qams = np.broadcast_to(np.asarray(qams), (k,))
+        maps = np.broadcast_to(np.asarray(mappings), (k,))
+        dims = np.zeros((k, 4), np.int32)
+        for r in range(k):
+            if Hc[r].ndim != 3 or yc[r].shape != (Hc[r].shape[0], 2):
+                raise ValueError("each H must be [nr, nt] and y [nr]")
+            dims[r] = (Hc[r].shape[0], Hc[r].shape[1], int(qams[r]), _MAPS[str(maps[r])])
+        esn0 = np.ascontiguousarray(np.broadcast_to(np.asarray(esn0s, np.float64), (k,)))
+        hp = np.fromiter((a.ctypes.data for a in Hc), dtype=np.uintp, count=k)
+        yp = np.fromiter((a.ctypes.data for a in yc), dtype=np.uintp, count=k)
+        return self.submit_mimo_raw(np.asarray(ids, np.uint32), dims, esn0, hp, yp)
+
+    def submit_mimo_raw(self, ids, dims, esn0, hptrs, yptrs):
+        """submit_mimo on prepared arrays: ids uint32 [k], dims int32 [k, 4]
+        (nr, nt, qam, mapping code), esn0 float64 [k], and the addresses of
+        each request's interleaved H and y (uintp [k]), which must stay valid
+        during the call."""
+        k = len(ids)
+        if k == 0:
+            return 0
+        ids = np.ascontiguousarray(ids, np.uint32)
+        dims = np.ascontiguousarray(dims, np.int32)
+        esn0 = np.ascontiguousarray(esn0, np.float64)
+        hptrs = np.ascontiguousarray(hptrs, np.uintp)
+        yptrs = np.ascontiguousarray(yptrs, np.uintp)
+        if dims.shape != (k, 4) or esn0.shape != (k,) or hptrs.shape != (k,) or yptrs.shape != (k,):
+            raise ValueError("ids, dims, esn0 and the pointer arrays must have one entry per request")
+        adm = ctypes.c_int32()
+        st = lib.pim_server_submit_mimo(self._handle, k, ids.ctypes.data, dims.ctypes.data, esn0.ctypes.data,
+                                        hptrs.ctypes.data, yptrs.ctypes.data, ctypes.byref(adm))
+        if st != PIM_OK:
+            err = PimError(st, lib.pim_last_error().decode(errors="replace"))
+            err.admitted = adm.value
+            raise err
+        return adm.value
+
+    def poll_mimo(self, states=True):
+        """poll_times() plus x_m [k, MAX_N_LDS // 2] per request (first 2 nt
+        entries used)."""
+        done = ctypes.c_int32()
+        _check(lib.pim_server_poll_mimo(self._handle, self._poll_max, _ptr(self._ids, ctypes.c_uint32),
+                                        _ptr(self._states, ctypes.c_int8) if states else None,
+                                        _ptr(self._e, ctypes.c_double), _ptr(self._xm, ctypes.c_double),
+                                        _ptr(self._t, ctypes.c_double), ctypes.byref(done)))
+        k = done.value
+        return (self._ids[:k].copy(), (self._states[:k].copy() if states else None), self._e[:k].copy(),
+                self._xm[:k].copy(), self._t[:k].copy())
 
     def flush(self):
         n = ctypes.c_int32()

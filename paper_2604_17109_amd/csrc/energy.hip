@@ -68,7 +68,7 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void energy_f64_kernel(EnergyA
 // spins, then adds s_i times that row sum (binary64, separate multiply and
 // add), and the lanes are reduced by wave_sum.  The row's own spin s_i comes
 // from the lane holding column i.
-constexpr int kRealRows = 8;   // J rows per LDS tile
+constexpr int kRealRows = 16;  // J rows per LDS tile
 
 template <int kRealCand>
 __global__ __launch_bounds__(64 * kWavesPerBlock) void rerank_real_kernel(RerankArgs a) {
@@ -98,15 +98,29 @@ __global__ __launch_bounds__(64 * kWavesPerBlock) void rerank_real_kernel(Rerank
   double acc[kRealCand];
 #pragma unroll
   for (int c = 0; c < kRealCand; ++c) acc[c] = 0.0;
+  // thread t stages column t of each tile row (J is row-major n x n, n <= 256
+  // = the block size); the next tile's loads are issued before the current
+  // tile's arithmetic
+  static_assert(64 * kWavesPerBlock == PIM_MAX_N_LDS, "one tile column per thread");
+  // (two tiles ahead: the loads of tiles t+1 and t+2 are in flight while
+  // tile t is used)
+  double nxt[2][kRealRows];
+  auto load_tile = [&](int t0, double (&dst)[kRealRows]) {
+#pragma unroll
+    for (int r = 0; r < kRealRows; ++r)
+      dst[r] = (t0 + r < n && (int)threadIdx.x < n) ? J[(size_t)(t0 + r) * n + threadIdx.x] : 0.0;
+  };
+  load_tile(0, nxt[0]);
+  load_tile(kRealRows, nxt[1]);
   for (int t0 = 0; t0 < n; t0 += kRealRows) {
     const int rows = min(kRealRows, n - t0);
     __syncthreads();  // the previous tile has been read
-    const double* src = J + (size_t)t0 * n;
-    for (int k = threadIdx.x; k < rows * n; k += 64 * kWavesPerBlock) {
-      const int r = k / n;
-      sJ[r][k - r * n] = src[k];
-    }
+#pragma unroll
+    for (int r = 0; r < kRealRows; ++r) sJ[r][threadIdx.x] = nxt[0][r];
     __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kRealRows; ++r) nxt[0][r] = nxt[1][r];
+    if (t0 + 2 * kRealRows < n) load_tile(t0 + 2 * kRealRows, nxt[1]);
 #pragma unroll
     for (int r = 0; r < kRealRows; ++r) {
       if (r < rows) {  // uniform

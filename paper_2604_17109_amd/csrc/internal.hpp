@@ -202,10 +202,29 @@ struct RealPackArgs {
   uint8_t* frag;       // [count][frag_bytes]
   float* hf;           // [count][npad]
   float* scale;        // [count]
+  double* pmax;        // [count][kPackSlices] scratch: max |J| of each slice of J
   size_t frag_bytes;
   int32_t npad, count;
 };
+constexpr int kPackSlices = 16;
 hipError_t launch_pack_real(const RealPackArgs& a, int prec, hipStream_t s);
+// Device-side MIMO mapping (mimo_map.hip): per request the Ising instance of
+// pim_mimo_ising, written zero-padded into j64 / h64, and x_m.
+struct MimoSlot {
+  int32_t nr, nt, qam, map;  // map: pim_mimo_map
+  double esn0;               // Es/N0 (linear), used by the DI mapping
+  int64_t hy_off;            // offset (doubles) of the request's H then y in hy
+};
+struct MimoMapArgs {
+  const MimoSlot* slots;     // [count]
+  const double* hy;          // H (nr x nt complex, interleaved, row-major) then y (nr complex)
+  double* j64;               // [count][npad][npad]
+  double* h64;               // [count][npad]
+  double* xm;                // [count][xm_stride]
+  int32_t npad, xm_stride, count;
+};
+hipError_t launch_mimo_map(const MimoMapArgs& a, size_t max_work, size_t max_hy, hipStream_t s);
+size_t mimo_map_work_doubles(int nr, int nt);
 hipError_t launch_energy_f64(const EnergyArgs& a, hipStream_t s);
 
 // Neighbour-triggered flip counts of one instance's recorded states.

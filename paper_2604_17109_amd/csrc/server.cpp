@@ -67,6 +67,11 @@ struct Chunk {
   double* h_j64 = nullptr;
   double* h_h64 = nullptr;
   uint32_t* h_sid = nullptr;
+  MimoSlot* h_slots = nullptr;   // MIMO requests: per slot dimensions and H / y offset
+  double* h_hy = nullptr;        // MIMO requests: H then y of each request, packed
+  size_t hy_used = 0;            // doubles of h_hy in use
+  size_t max_work = 0, max_hy = 0;  // largest mapping workspace / H + y among its MIMO requests
+  double* h_xm = nullptr;        // results: x_m per slot
   int8_t* h_spins = nullptr;
   double* h_e = nullptr;
   int32_t* h_sel = nullptr;
@@ -77,6 +82,9 @@ struct Chunk {
   double* d_j64 = nullptr;
   double* d_h64 = nullptr;
   uint32_t* d_sid = nullptr;
+  MimoSlot* d_slots = nullptr;
+  double* d_hy = nullptr;
+  double* d_xm = nullptr;
   const double** d_j64p = nullptr;
   const double** d_h64p = nullptr;
   int8_t* d_final = nullptr;
@@ -217,6 +225,7 @@ constexpr int kSplitN = 96;
 
 struct pim_server {
   pim_server_config cfg{};
+  bool mimo = false;                 // requests are MIMO problems (H, y), mapped on the device
   pim::Rule rule;
   std::vector<double> beta, eta;
   std::vector<pim::Klass> classes;   // index nt - 1
@@ -258,27 +267,50 @@ bool dev_alloc_n(T** p, size_t count) {
   return *p != nullptr;
 }
 
-// Offsets of the input block: frag | hf | scale | j64 | h64 | sid (each 256-B
-// aligned), and of the result block: spins | energies | (trial, step, tracked).
+// Offsets (each 256-B aligned) of the input block and of the result block
+// (spins | energies | (trial, step, tracked) | x_m of MIMO requests).  Couplings
+// staged on the host: frag | hf | scale | j64 | h64 | sid, all uploaded from the
+// host copy.  MIMO requests: sid | slots | hy first (the part uploaded from the
+// host, host_in_bytes), then the device-only frag | hf | scale | j64 | h64.
 struct Layout {
-  size_t frag, hf, scale, j64, h64, sid, in_bytes;
-  size_t spins, e, sel, out_bytes;
+  size_t frag, hf, scale, j64, h64, pmax, sid, slots, hy, in_bytes, host_in_bytes;
+  size_t spins, e, sel, xm, out_bytes;
 };
 size_t al(size_t x) { return (x + 255) & ~size_t(255); }
+// Doubles of H (Nr x Nt complex) and y (Nr complex) a MIMO request of class
+// npad can bring: Nr <= npad / 2 and Nt <= npad / 2.
+size_t hy_slot_doubles(size_t np) { return np * np / 2 + np; }
+// x_m values returned per MIMO request: 2 Nt <= min(npad, PIM_MAX_N_LDS / 2).
+size_t xm_stride(size_t np) { return std::min<size_t>(np, PIM_MAX_N_LDS / 2); }
 Layout layout(const pim_server* s, const Klass& k) {
   const size_t B = s->cfg.max_batch, np = k.npad;
   Layout L{};
-  L.frag = 0;
+  if (s->mimo) {
+    L.sid = 0;
+    L.slots = al(B * 4);
+    L.hy = al(L.slots + B * sizeof(MimoSlot));
+    L.host_in_bytes = al(L.hy + B * hy_slot_doubles(np) * 8);
+    L.frag = L.host_in_bytes;
+  } else {
+    L.frag = 0;
+  }
   L.hf = al(L.frag + B * k.frag);
   L.scale = al(L.hf + B * np * 4);
   L.j64 = al(L.scale + B * 4);
   L.h64 = al(L.j64 + B * np * np * 8);
-  L.sid = al(L.h64 + B * np * 8);
-  L.in_bytes = al(L.sid + B * 4);
+  L.pmax = al(L.h64 + B * np * 8);
+  if (s->mimo) {
+    L.in_bytes = al(L.pmax + B * kPackSlices * 8);
+  } else {
+    L.sid = al(L.pmax + B * kPackSlices * 8);
+    L.in_bytes = al(L.sid + B * 4);
+    L.host_in_bytes = L.in_bytes;
+  }
   L.spins = 0;
   L.e = al(B * np);
   L.sel = al(L.e + B * 8);
-  L.out_bytes = al(L.sel + 3 * B * 4);
+  L.xm = al(L.sel + 3 * B * 4);
+  L.out_bytes = s->mimo ? al(L.xm + B * xm_stride(np) * 8) : L.xm;
   return L;
 }
 
@@ -291,17 +323,26 @@ Chunk* new_chunk(pim_server* s, int cls) {
   c->in_bytes = L.in_bytes;
   c->out_bytes = L.out_bytes;
   bool ok = hipEventCreateWithFlags(&c->done, hipEventDisableTiming) == hipSuccess;
-  ok = ok && host_alloc(&c->h_in, L.in_bytes) && host_alloc(&c->h_out, L.out_bytes) &&
+  ok = ok && host_alloc(&c->h_in, L.host_in_bytes) && host_alloc(&c->h_out, L.out_bytes) &&
        dev_alloc_n(&c->d_in, L.in_bytes) && dev_alloc_n(&c->d_out, L.out_bytes);
   ok = ok && dev_alloc_n(&c->d_j64p, B) && dev_alloc_n(&c->d_h64p, B) && dev_alloc_n(&c->d_final, B * R * np) &&
        dev_alloc_n(&c->d_best, B * R * np) && dev_alloc_n(&c->d_stats, 5 * B * R) &&
        dev_alloc_n(&c->d_rerank, B * R);
   if (ok) {
-    c->h_frag = c->h_in + L.frag;
-    c->h_hf = reinterpret_cast<float*>(c->h_in + L.hf);
-    c->h_scale = reinterpret_cast<float*>(c->h_in + L.scale);
-    c->h_j64 = reinterpret_cast<double*>(c->h_in + L.j64);
-    c->h_h64 = reinterpret_cast<double*>(c->h_in + L.h64);
+    if (s->mimo) {
+      c->h_slots = reinterpret_cast<MimoSlot*>(c->h_in + L.slots);
+      c->h_hy = reinterpret_cast<double*>(c->h_in + L.hy);
+      c->d_slots = reinterpret_cast<MimoSlot*>(c->d_in + L.slots);
+      c->d_hy = reinterpret_cast<double*>(c->d_in + L.hy);
+      c->h_xm = reinterpret_cast<double*>(c->h_out + L.xm);
+      c->d_xm = reinterpret_cast<double*>(c->d_out + L.xm);
+    } else {
+      c->h_frag = c->h_in + L.frag;
+      c->h_hf = reinterpret_cast<float*>(c->h_in + L.hf);
+      c->h_scale = reinterpret_cast<float*>(c->h_in + L.scale);
+      c->h_j64 = reinterpret_cast<double*>(c->h_in + L.j64);
+      c->h_h64 = reinterpret_cast<double*>(c->h_in + L.h64);
+    }
     c->h_sid = reinterpret_cast<uint32_t*>(c->h_in + L.sid);
     c->d_frag = c->d_in + L.frag;
     c->d_hf = reinterpret_cast<float*>(c->d_in + L.hf);
@@ -361,9 +402,28 @@ hipError_t launch_chunk(pim_server* s, Chunk* c, hipStream_t st) {
   const size_t B = c->count, R = s->cfg.trials, np = k.npad;
   // the used part of each input section (the result block is small and read
   // back whole)
-  hipError_t e = hipMemcpyAsync(c->d_j64, c->h_j64, B * np * np * 8, hipMemcpyHostToDevice, st);
-  if (e == hipSuccess) e = hipMemcpyAsync(c->d_h64, c->h_h64, B * np * 8, hipMemcpyHostToDevice, st);
-  if (e == hipSuccess) e = hipMemcpyAsync(c->d_sid, c->h_sid, B * 4, hipMemcpyHostToDevice, st);
+  hipError_t e = hipSuccess;
+  if (s->mimo) {
+    // ids, slot records and the packed (H, y) are one contiguous prefix of
+    // the block: one upload, then the Ising instances are built on the device
+    const Layout L = layout(s, k);
+    e = hipMemcpyAsync(c->d_in, c->h_in, L.hy + c->hy_used * 8, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return e;
+    MimoMapArgs ma{};
+    ma.slots = c->d_slots;
+    ma.hy = c->d_hy;
+    ma.j64 = c->d_j64;
+    ma.h64 = c->d_h64;
+    ma.xm = c->d_xm;
+    ma.npad = (int)np;
+    ma.xm_stride = (int)xm_stride(np);
+    ma.count = (int)B;
+    e = launch_mimo_map(ma, c->max_work, c->max_hy, st);
+  } else {
+    e = hipMemcpyAsync(c->d_j64, c->h_j64, B * np * np * 8, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->d_h64, c->h_h64, B * np * 8, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->d_sid, c->h_sid, B * 4, hipMemcpyHostToDevice, st);
+  }
   if (e != hipSuccess) return e;
   RealPackArgs pa{};
   pa.j64 = c->d_j64;
@@ -371,6 +431,7 @@ hipError_t launch_chunk(pim_server* s, Chunk* c, hipStream_t st) {
   pa.frag = c->d_frag;
   pa.hf = c->d_hf;
   pa.scale = c->d_scale;
+  pa.pmax = reinterpret_cast<double*>(c->d_in + layout(s, k).pmax);
   pa.frag_bytes = k.frag;
   pa.npad = (int)np;
   pa.count = (int)B;
@@ -426,9 +487,9 @@ hipError_t launch_chunk(pim_server* s, Chunk* c, hipStream_t st) {
 
 }  // namespace
 
-extern "C" {
+namespace {
 
-pim_status pim_server_create(const pim_server_config* cfg, pim_server** out) {
+pim_status server_create(const pim_server_config* cfg, bool mimo, pim_server** out) {
   try {
     if (!cfg || !out) return fail(PIM_ERR_INVALID, "NULL argument");
     *out = nullptr;
@@ -457,6 +518,7 @@ pim_status pim_server_create(const pim_server_config* cfg, pim_server** out) {
     if (st != PIM_OK) return st;
     auto* s = new pim_server();
     s->cfg = *cfg;
+    s->mimo = mimo;
     s->beta.assign(cfg->beta, cfg->beta + cfg->steps);
     s->eta.assign(cfg->eta, cfg->eta + cfg->steps);
     s->cfg.beta = s->beta.data();
@@ -534,11 +596,75 @@ pim_status pim_server_create(const pim_server_config* cfg, pim_server** out) {
   }
 }
 
+}  // namespace
+
+extern "C" {
+
+pim_status pim_server_create(const pim_server_config* cfg, pim_server** out) {
+  return server_create(cfg, false, out);
+}
+
+pim_status pim_server_create_mimo(const pim_server_config* cfg, pim_server** out) {
+  return server_create(cfg, true, out);
+}
+
+pim_status pim_server_submit_mimo(pim_server* s, int32_t count, const uint32_t* ids, const int32_t* dims,
+                                  const double* esn0, const double* const* H, const double* const* y,
+                                  int32_t* admitted) {
+  try {
+    if (!s || !ids || !dims || !esn0 || !H || !y || !admitted) return fail(PIM_ERR_INVALID, "NULL argument");
+    *admitted = 0;
+    if (!s->mimo) return fail(PIM_ERR_STATE, "this server takes (J, h) requests (pim_server_submit)");
+    for (int r = 0; r < count; ++r) {
+      const int nr = dims[4 * r], nt = dims[4 * r + 1], qam = dims[4 * r + 2], map = dims[4 * r + 3];
+      const bool known = (qam == 4 || qam == 16) && (map == PIM_MIMO_ML || map == PIM_MIMO_DI);
+      const int n = (map == PIM_MIMO_ML && qam == 4) ? 2 * nt : 4 * nt;
+      const int np = 32 * ((n + 31) / 32);
+      if (!known || nt < 1 || nt > PIM_MAX_N_LDS / 4 || n > s->cfg.max_n || nr < 1 || 2 * nr > np ||
+          ids[r] >= (1u << 24) || !H[r] || !y[r] || (map == PIM_MIMO_DI && !(std::isfinite(esn0[r]) && esn0[r] > 0.0)))
+        return fail(PIM_ERR_INVALID, "request %d (id %u): need qam 4 or 16, a known mapping, 1 <= nt <= %d, "
+                    "N <= max_n, 1 <= 2 nr <= N rounded up to 32, id < 2^24, esn0 > 0 finite (DI)",
+                    r, ids[r], PIM_MAX_N_LDS / 4);
+      const size_t nh = 2 * (size_t)nr * nt, ny = 2 * (size_t)nr;
+      for (size_t i = 0; i < nh; ++i)
+        if (!std::isfinite(H[r][i])) return fail(PIM_ERR_INVALID, "request %d (id %u): H is not finite", r, ids[r]);
+      for (size_t i = 0; i < ny; ++i)
+        if (!std::isfinite(y[r][i])) return fail(PIM_ERR_INVALID, "request %d (id %u): y is not finite", r, ids[r]);
+      Chunk* c = chunk_for(s, np / 32 - 1);
+      if (!c) return PIM_OK;  // no slot: the caller polls and submits the rest later
+      const size_t sl = c->count;
+      if (c->count == 0) {
+        c->first = std::chrono::steady_clock::now();
+        c->hy_used = 0;
+        c->max_work = c->max_hy = 0;
+      }
+      std::memcpy(c->h_hy + c->hy_used, H[r], nh * 8);
+      std::memcpy(c->h_hy + c->hy_used + nh, y[r], ny * 8);
+      c->h_slots[sl] = MimoSlot{nr, nt, qam, map, esn0[r], (int64_t)c->hy_used};
+      c->hy_used += nh + ny;
+      c->max_work = std::max(c->max_work, mimo_map_work_doubles(nr, nt));
+      c->max_hy = std::max(c->max_hy, nh + ny);
+      c->h_sid[sl] = ids[r];
+      c->ids.push_back(ids[r]);
+      c->ns.push_back(n);
+      c->t_admit.push_back(mono_now());
+      ++c->count;
+      ++*admitted;
+    }
+    return PIM_OK;
+  } catch (const std::bad_alloc&) {
+    return fail(PIM_ERR_NOMEM, "host allocation failed");
+  } catch (...) {
+    return fail(PIM_ERR_INVALID, "internal error in pim_server_submit_mimo");
+  }
+}
+
 pim_status pim_server_submit(pim_server* s, int32_t count, const uint32_t* ids, const int32_t* ns,
                              const double* const* J, const double* const* h, int32_t* admitted) {
   try {
     if (!s || !ids || !ns || !J || !admitted) return fail(PIM_ERR_INVALID, "NULL argument");
     *admitted = 0;
+    if (s->mimo) return fail(PIM_ERR_STATE, "this server takes MIMO requests (pim_server_submit_mimo)");
     if (count <= 0) return PIM_OK;
     // (1) argument checks, in order up to the first failure
     int f = 0;
@@ -677,11 +803,16 @@ pim_status pim_server_flush(pim_server* s, int32_t* launched) {
 
 pim_status pim_server_poll(pim_server* s, int32_t max, uint32_t* ids, int8_t* states, double* energies,
                            int32_t* done) {
-  return pim_server_poll_times(s, max, ids, states, energies, nullptr, done);
+  return pim_server_poll_mimo(s, max, ids, states, energies, nullptr, nullptr, done);
 }
 
 pim_status pim_server_poll_times(pim_server* s, int32_t max, uint32_t* ids, int8_t* states, double* energies,
                                  double* times, int32_t* done) {
+  return pim_server_poll_mimo(s, max, ids, states, energies, nullptr, times, done);
+}
+
+pim_status pim_server_poll_mimo(pim_server* s, int32_t max, uint32_t* ids, int8_t* states, double* energies,
+                                double* xm, double* times, int32_t* done) {
   try {
     if (!s || !ids || !done) return fail(PIM_ERR_INVALID, "NULL argument");
     *done = 0;
@@ -705,6 +836,11 @@ pim_status pim_server_poll_times(pim_server* s, int32_t max, uint32_t* ids, int8
           std::memcpy(states + (size_t)o * PIM_MAX_N_LDS, c->h_spins + (size_t)r * np, c->ns[r]);
         }
         if (energies) energies[o] = c->h_e[r];
+        if (xm) {
+          double* row = xm + (size_t)o * (PIM_MAX_N_LDS / 2);
+          std::fill(row, row + PIM_MAX_N_LDS / 2, 0.0);
+          if (s->mimo) std::memcpy(row, c->h_xm + (size_t)r * xm_stride(np), 2 * c->h_slots[r].nt * sizeof(double));
+        }
         if (times) {
           times[3 * (size_t)o] = c->t_admit[r];
           times[3 * (size_t)o + 1] = c->t_launch;
@@ -717,6 +853,8 @@ pim_status pim_server_poll_times(pim_server* s, int32_t max, uint32_t* ids, int8
       c->ids.clear();
       c->ns.clear();
       c->t_admit.clear();
+      c->hy_used = 0;
+      c->max_work = c->max_hy = 0;
       it = s->inflight.erase(it);
     }
     return PIM_OK;

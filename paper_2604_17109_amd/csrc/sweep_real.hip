@@ -679,25 +679,38 @@ __device__ uint16_t d_bf16(double x) {
   return sign | (uint16_t)(((E + 127) << 7) | ((int)q - 128));
 }
 
-// One block per instance: scale = max|J| / 448 (FP8, rounded to binary32) or
-// the power of two with max|J| / scale in [1, 2) (BF16); J / scale quantised
-// into the fragment order of pack_real_fragments; h converted to binary32.
-// J and h are the instance's binary64 values, zero-padded to npad.
-template <int PREC>
-__global__ __launch_bounds__(256) void pack_real_kernel(RealPackArgs a) {
+// Blocks (slice, inst): max |J| over one of kPackSlices equal slices of the
+// instance's binary64 J (npad^2 is a multiple of kPackSlices).
+__global__ __launch_bounds__(256) void max_slices_kernel(RealPackArgs a) {
   __shared__ double red[256];
-  const int inst = blockIdx.x;
-  const int np = a.npad, nt = np / 32;
-  const double* J = a.j64 + (size_t)inst * np * np;
+  const int inst = blockIdx.y, np = a.npad;
+  const int per = np * np / kPackSlices;
+  const double* J = a.j64 + (size_t)inst * np * np + (size_t)blockIdx.x * per;
   double m = 0.0;
-  for (int i = threadIdx.x; i < np * np; i += 256) m = fmax(m, fabs(J[i]));
+  for (int i = threadIdx.x; i < per; i += 256) m = fmax(m, fabs(J[i]));
   red[threadIdx.x] = m;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
     if (threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
     __syncthreads();
   }
-  m = red[0];
+  if (threadIdx.x == 0) a.pmax[(size_t)inst * kPackSlices + blockIdx.x] = red[0];
+}
+
+// Blocks (x, inst): scale = max|J| / 448 (FP8, rounded to binary32) or the
+// power of two with max|J| / scale in [1, 2) (BF16), formed by every block of
+// the instance alike from the slice maxima; J / scale quantised into the
+// fragment order of pack_real_fragments, each block taking every
+// gridDim.x-th group of 256 outputs; h converted to binary32.  J and h are
+// the instance's binary64 values, zero-padded to npad.
+template <int PREC>
+__global__ __launch_bounds__(256) void pack_real_kernel(RealPackArgs a) {
+  const int inst = blockIdx.y;
+  const int first = blockIdx.x * 256 + threadIdx.x, step = gridDim.x * 256;
+  const int np = a.npad, nt = np / 32;
+  const double* J = a.j64 + (size_t)inst * np * np;
+  double m = 0.0;
+  for (int q = 0; q < kPackSlices; ++q) m = fmax(m, a.pmax[(size_t)inst * kPackSlices + q]);
   float scale = 1.0f;
   if (m > 0.0) {
     if (PREC == PIM_PREC_FP8) {
@@ -708,13 +721,13 @@ __global__ __launch_bounds__(256) void pack_real_kernel(RealPackArgs a) {
       scale = (float)ldexp(1.0, e - 1);
     }
   }
-  if (threadIdx.x == 0) a.scale[inst] = scale;
+  if (blockIdx.x == 0 && threadIdx.x == 0) a.scale[inst] = scale;
   auto row_of = [](int mt, int r) { return 32 * mt + 16 * ((r >> 2) & 1) + 4 * (r >> 3) + (r & 3); };
   uint8_t* out = a.frag + (size_t)inst * a.frag_bytes;
   if (PREC == PIM_PREC_FP8) {
     const int nk = (nt + 1) / 2;
     const int total = nt * nk * 64 * 32;
-    for (int b = threadIdx.x; b < total; b += 256) {
+    for (int b = first; b < total; b += step) {
       const int p = b & 31, l = (b >> 5) & 63, blk = b >> 11;  // blk = mt * nk + kk
       const int mt = blk / nk, kk = blk % nk;
       const int row = row_of(mt, l & 31);
@@ -725,7 +738,7 @@ __global__ __launch_bounds__(256) void pack_real_kernel(RealPackArgs a) {
   } else {
     uint16_t* o16 = reinterpret_cast<uint16_t*>(out);
     const int total = nt * nt * 2 * 64 * 8;
-    for (int b = threadIdx.x; b < total; b += 256) {
+    for (int b = first; b < total; b += step) {
       const int p = b & 7, l = (b >> 3) & 63, blk = b >> 9;  // blk = (mt * nt + kt) * 2 + j
       const int j = blk & 1, kt = (blk >> 1) % nt, mt = (blk >> 1) / nt;
       const int row = row_of(mt, l & 31);
@@ -733,7 +746,7 @@ __global__ __launch_bounds__(256) void pack_real_kernel(RealPackArgs a) {
       o16[b] = d_bf16(J[(size_t)row * np + colj] / (double)scale);
     }
   }
-  for (int i = threadIdx.x; i < np; i += 256) a.hf[(size_t)inst * np + i] = (float)a.h64[(size_t)inst * np + i];
+  for (int i = first; i < np; i += step) a.hf[(size_t)inst * np + i] = (float)a.h64[(size_t)inst * np + i];
 }
 
 }  // namespace
@@ -743,8 +756,13 @@ size_t real_frag_bytes(int prec, int nt) { return frag_bytes(prec, nt); }
 hipError_t launch_pack_real(const RealPackArgs& a, int prec, hipStream_t s) {
   if (a.count < 1) return hipSuccess;
   if (a.npad < 32 || a.npad > PIM_MAX_N_LDS || a.npad % 32) return hipErrorInvalidValue;
-  if (prec == PIM_PREC_FP8) hipLaunchKernelGGL(pack_real_kernel<PIM_PREC_FP8>, dim3(a.count), dim3(256), 0, s, a);
-  else if (prec == PIM_PREC_BF16) hipLaunchKernelGGL(pack_real_kernel<PIM_PREC_BF16>, dim3(a.count), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(max_slices_kernel, dim3(kPackSlices, a.count), dim3(256), 0, s, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  // blocks per instance: one per 4096 coupling elements (1 at N = 32, 16 at N = 256)
+  const dim3 grid(std::max(1, a.npad * a.npad / 4096), a.count);
+  if (prec == PIM_PREC_FP8) hipLaunchKernelGGL(pack_real_kernel<PIM_PREC_FP8>, grid, dim3(256), 0, s, a);
+  else if (prec == PIM_PREC_BF16) hipLaunchKernelGGL(pack_real_kernel<PIM_PREC_BF16>, grid, dim3(256), 0, s, a);
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }

@@ -190,3 +190,101 @@ def test_server_parallel_staging_and_rejection(gpu_lib):
     many.flush()
     assert set(_drain(many, 2)) == {1, 2}
     many.close()
+
+
+MIMO_SHAPES = [(8, 8, 4, "di"), (8, 8, 16, "di"), (16, 16, 16, "di"), (16, 16, 4, "ml"), (12, 8, 16, "di"),
+               (32, 32, 4, "di"), (8, 6, 16, "ml"), (64, 64, 16, "di"), (16, 12, 4, "di"), (64, 64, 4, "ml")]
+
+
+def _mimo_problem(k, nr, nt, qam, db=15.0):
+    return w.mimo.mimo_problem(nt, nr, qam, db, seed=12, index=k)
+
+
+def test_device_mimo_mapping_matches_host_and_oracle(gpu_lib):
+    """The server's device mapping kernel (binary64 Gram, Cholesky MMSE,
+    slicing, J and h) against the host library's mapping (same operation
+    order: identical) and the oracle's (Suppl. "Delta-Ising MIMO"; 1e-12)."""
+    from oracle import mimo
+    pim = gpu_lib
+    for k, (nr, nt, qam, mapping) in enumerate(MIMO_SHAPES * 2):
+        _say(f"device MIMO mapping nr={nr} nt={nt} qam={qam} {mapping}")
+        p = _mimo_problem(k, nr, nt, qam)
+        Jd, hd, xd = pim.mimo_ising_device(p["H"], p["y"], qam, mapping, p["esn0"])
+        Jh, hh, xh = pim.mimo_ising(p["H"], p["y"], qam, mapping, p["esn0"])
+        d = mimo.detector_instance(p, mapping)
+        assert np.array_equal(xd, d["xm"]) and np.array_equal(xd, xh)
+        scale = np.abs(d["J"]).max()
+        np.testing.assert_allclose(Jd, d["J"], rtol=0, atol=1e-12 * scale)
+        np.testing.assert_allclose(hd, d["h"], rtol=0, atol=1e-12 * max(np.abs(d["h"]).max(), 1.0))
+        print(f"  host identical: J {np.array_equal(Jd, Jh)} h {np.array_equal(hd, hh)}", flush=True)
+
+
+def test_mimo_server_matches_host_staged_server(gpu_lib):
+    """The same detection problems through the MIMO server ((H, y) staged,
+    Ising instance built on the device) and through the (J, h) server (host
+    mapping): the same states, binary64 energies within 1e-12 (equal when the
+    two mappings are bit-identical), x_m equal; every energy equals the
+    oracle's Eq. (1) energy of the returned state on the oracle's own
+    instance within 1e-9 (P14)."""
+    from oracle import mimo
+    pim = gpu_lib
+    reqs = []
+    for k in range(60):
+        nr, nt, qam, mapping = MIMO_SHAPES[k % len(MIMO_SHAPES)]
+        reqs.append((2000 + k, nr, nt, qam, mapping, _mimo_problem(100 + k, nr, nt, qam)))
+    kw = dict(max_n=256, max_batch=16, slots_per_class=64)
+    dev = _server(pim, mimo=True, **kw)
+    host = _server(pim, **kw)
+    _say("MIMO server: device mapping vs host-staged requests")
+    assert dev.submit_mimo([r[0] for r in reqs], [r[5]["H"] for r in reqs], [r[5]["y"] for r in reqs],
+                           [r[3] for r in reqs], [r[4] for r in reqs], [r[5]["esn0"] for r in reqs]) == len(reqs)
+    dev.flush()
+    maps = [pim.mimo_ising(r[5]["H"], r[5]["y"], r[3], r[4], r[5]["esn0"]) for r in reqs]
+    assert host.submit([r[0] for r in reqs], [m[0] for m in maps], [m[1] for m in maps]) == len(reqs)
+    host.flush()
+    got_d, xms = {}, {}
+    t0 = time.time()
+    while len(got_d) < len(reqs):
+        ids, st, e, xm, tm = dev.poll_mimo()
+        for i, sv, ev, xv, tv in zip(ids, st, e, xm, tm):
+            got_d[int(i)] = (sv.copy(), float(ev))
+            xms[int(i)] = xv.copy()
+            assert tv[0] <= tv[1] <= tv[2]
+        assert time.time() - t0 < 60
+    got_h = _drain(host, len(reqs))
+    dev.close()
+    host.close()
+    for (rid, nr, nt, qam, mapping, p), (J, h, xm) in zip(reqs, maps):
+        n = J.shape[0]
+        assert np.array_equal(xms[rid][:2 * nt], xm) and not xms[rid][2 * nt:].any(), rid
+        assert np.array_equal(got_d[rid][0][:n], got_h[rid][0][:n]), rid
+        assert got_d[rid][1] == pytest.approx(got_h[rid][1], rel=1e-12, abs=1e-9), rid
+        d = mimo.detector_instance(p, mapping)
+        e_orc = pimi.energy_f64(d["J"], d["h"], got_d[rid][0][:n].astype(np.float64))
+        assert got_d[rid][1] == pytest.approx(e_orc, rel=1e-9, abs=1e-9), rid
+        x = pim.mimo_decode(xms[rid][:2 * nt], got_d[rid][0][:n], qam, mapping)
+        assert np.array_equal(x, mimo.decode(d["xm"], d["T"], got_d[rid][0][:n], qam)), rid
+
+
+def test_mimo_server_rejects_invalid_requests(gpu_lib):
+    pim = gpu_lib
+    _say("MIMO server: validation")
+    srv = _server(pim, mimo=True, max_n=64)
+    p = _mimo_problem(1, 8, 8, 16)
+    J, h = pim.mimo_ising(p["H"], p["y"], 16, "di", p["esn0"])[:2]
+    with pytest.raises(pim.PimError) as ei:
+        srv.submit([1], [J], [h])
+    assert ei.value.status == pim.PIM_ERR_STATE
+    bad_H = p["H"].copy()
+    bad_H[2, 3] = np.nan
+    with pytest.raises(pim.PimError) as ei:
+        srv.submit_mimo([1, 2, 3], [p["H"], p["H"], bad_H], [p["y"]] * 3, 16, "di", p["esn0"])
+    assert ei.value.admitted == 2 and "finite" in str(ei.value)
+    big = _mimo_problem(2, 32, 32, 16)  # N = 128 > max_n
+    with pytest.raises(pim.PimError) as ei:
+        srv.submit_mimo([4], [big["H"]], [big["y"]], 16, "di", big["esn0"])
+    assert ei.value.admitted == 0
+    assert srv.pending() == (2, 0)
+    srv.flush()
+    assert set(_drain(srv, 2)) == {1, 2}
+    srv.close()
