@@ -60,13 +60,15 @@ def parse():
                     help="only the SK-1 N=200 sweep (no plain, MIMO, serving, uneven-N, comparison or CPU legs)")
     ap.add_argument("--no-mimo", action="store_true", help="skip the MIMO detection leg")
     ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-N batched leg")
+    ap.add_argument("--no-mimo-grid", action="store_true", help="skip the MIMO detection grid")
+    ap.add_argument("--grid-channels", type=int, default=256, help="channels per MIMO grid point")
     ap.add_argument("--no-serving", action="store_true", help="skip the MIMO serving leg")
     ap.add_argument("--serving-mix", default="both", choices=["5g", "full", "both"])
     ap.add_argument("--serving-streams", type=int, default=16)
     ap.add_argument("--serving-batch", type=int, default=0, help="requests per launch (0: 256 for the 5G mix, "
                     "64 for the full mix)")
     ap.add_argument("--serving-prealloc", type=int, default=0, help="chunks allocated up front per size class "
-                    "(0: 4 for the 5G mix, 16 for the full mix)")
+                    "(0: 16)")
     ap.add_argument("--serving-requests", type=int, default=100000,
                     help="requests per arrival rate (the paper's throughput protocol uses 10^5)")
     ap.add_argument("--uneven-steps", type=int, default=10000, help="steps of the uneven-N batched leg")
@@ -299,6 +301,86 @@ def mimo_leg(args):
     return out
 
 
+def mimo_grid_leg(args):
+    """Detection quality over the MIMO grid (Fig. 5 / Table 1 sizes extended to
+    Nt = 32, 64; workloads.mimo.grid_points()): Nt = Nr in {8, 16, 32, 64} x
+    {4, 16}-QAM x Eb/N0 in {10, 15, 20, 25} dB, DI mapping, 32 trials, the
+    steps of Table 1 doubled per doubling of Nt, beta = 1, xi = 2, gamma 0.05
+    -> 0.3.  Per point: `channels` seeded channels in one batched launch per
+    MFMA precision (FP8, BF16) and, on the first 64 of them, the plain FP32
+    kernel; symbol and bit error rates against the transmitted symbols, the
+    sliced MMSE estimate, and, from tests/golden/mimo_grid_ref.json (written
+    by the CPU oracle): the binary64 oracle's own PIMI dynamics on those 64
+    channels and exact ML detection where it is enumerable.  Energy gap: the
+    mean over those 64 channels of (E of the GPU's best state - E of the
+    oracle's best state) in the Eq. (1) units of the instance, and the share
+    of channels where the GPU's is not higher."""
+    import paper_2604_17109_amd as pim
+    import workloads as w
+    path = os.path.join(GOLDEN, "mimo_grid_ref.json")
+    ref = {(r["nt"], r["qam"], r["ebn0_db"]): r for r in json.load(open(path))["points"]} \
+        if os.path.exists(path) else {}
+    ztab = w.gauss_table(8)
+    C, R = args.grid_channels, 32
+    rows = []
+    t_start = time.perf_counter()
+    for nt, qam, db, T in w.mimo.grid_points():
+        beta, eta = w.constant(T, 1.0), w.mimo_eta(T, 0.05, 0.3)
+        probs = [w.mimo.mimo_problem(nt, nt, qam, db, seed=w.mimo.GRID_SEED, index=k) for k in range(C)]
+        maps = [pim.mimo_ising(p["H"], p["y"], qam, "di", p["esn0"]) for p in probs]
+        sym = sum(p["nt"] for p in probs)
+        bits = sym * w.mimo.bits_per_symbol(qam)
+
+        def rates(dets, idx):
+            se = be = 0
+            for k, s_ in zip(idx, dets):
+                x = pim.mimo_decode(maps[k][2], s_, qam, "di")
+                se += int(np.count_nonzero(x != probs[k]["x"]))
+                be += int(np.count_nonzero(w.mimo.bits_from_symbols(x, qam) != probs[k]["bits"]))
+            ns_ = len(idx) * nt
+            return se / ns_, be / (ns_ * w.mimo.bits_per_symbol(qam))
+
+        row = {"nt": nt, "qam": qam, "ebn0_db": db, "steps": T, "channels": C, "n": maps[0][0].shape[0]}
+        energies = {}
+        for name, prec, kern, cnt in (("fp8", "fp8", "mfma", C), ("bf16", "bf16", "mfma", C),
+                                      ("plain_f32", "fp8", "plain", min(C, 64))):
+            insts = [pim.Instance(maps[k][0], maps[k][1], j_scale=1.0, xi=2.0, noise_table=ztab, rng_stream=k,
+                                  prec=prec) for k in range(cnt)]
+            b = pim.Batch(insts, R).run(beta, eta, seed=11, kernel=kern)
+            best = [b.best(k) for k in range(cnt)]
+            row[f"{name}_ser"], row[f"{name}_ber"] = rates([x[0] for x in best], range(cnt))
+            if cnt > 64:  # the oracle's subset too, for a like-for-like comparison
+                row[f"{name}_ser_first64"], row[f"{name}_ber_first64"] = rates([x[0] for x in best[:64]], range(64))
+            row[f"{name}_kernel_ms"] = b.kernel_ms()
+            energies[name] = np.array([x[1] for x in best[:64]])
+            b.close()
+            for i in insts:
+                i.close()
+        se = be = 0
+        for k, p in enumerate(probs):
+            x = maps[k][2][:nt] + 1j * maps[k][2][nt:]
+            se += int(np.count_nonzero(x != p["x"]))
+            be += int(np.count_nonzero(w.mimo.bits_from_symbols(x, qam) != p["bits"]))
+        row["mmse_ser"], row["mmse_ber"] = se / sym, be / bits
+        g = ref.get((nt, qam, db))
+        if g and C >= g["channels"]:
+            m = g["channels"]
+            row["oracle_channels"] = m
+            row["oracle_ser"], row["oracle_ber"] = g["oracle_ser"], g["oracle_ber"]
+            row["ml_ser"], row["ml_ber"] = g["ml_ser"], g["ml_ber"]
+            eo = np.array(g["oracle_best_energy"][:m])
+            for name in ("fp8", "bf16", "plain_f32"):
+                d = energies[name][:m] - eo
+                row[f"{name}_energy_gap_mean"] = float(d.mean())
+                row[f"{name}_not_above_oracle"] = float(np.mean(d <= 1e-9 * np.abs(eo)))
+        rows.append(row)
+    return {"workload": "MIMO detection grid, Nt = Nr in {8, 16, 32, 64} x {4, 16}-QAM x {10, 15, 20, 25} dB, "
+                        f"DI mapping, {C} channels per point ({min(C, 64)} for the plain kernel), 32 trials",
+            "reference": "tests/golden/mimo_grid_ref.json (binary64 oracle dynamics and ML on the first 64 "
+                         "channels)" if ref else None,
+            "seconds": time.perf_counter() - t_start, "points": rows}
+
+
 def uneven_leg(args):
     """Batched SK-1 with uneven N: 128 instances, N_k = [100, 200, 400, 800,
     1000][k mod 5], J = +-1, h = 0, c = 1/sqrt(N_k), xi = 0.5, 1024 replicas
@@ -407,7 +489,7 @@ def serving_leg(args):
         # launches at high rates); 64 for the full mix, whose 64x64 requests
         # make a 256-slot chunk hold 200 MB of staging
         mb = args.serving_batch or (256 if mix == "5g" else 64)
-        pre = args.serving_prealloc or (4 if mix == "5g" else 16)
+        pre = args.serving_prealloc or 16
         srv = pim.Server(max_n=int(ns.max()), trials=cfg["trials"], beta=beta, eta=eta, xi=cfg["xi"],
                          noise_table=w.gauss_table(8), prec="fp8", slots_per_class=4096, max_batch=mb,
                          streams=args.serving_streams, seed=11, max_wait_us=150.0, prealloc_chunks=pre, mimo=True)
@@ -648,6 +730,7 @@ def main():
     args = parse()
     if args.core_only:
         args.no_mimo = args.no_serving = args.no_uneven = args.no_compare = args.no_cpu_baseline = True
+        args.no_mimo_grid = True
         args.no_tts_scan = True
         args.plain_instances = 0
     if args.copy_probe:
@@ -801,6 +884,8 @@ def main():
         pb.close()
     if not args.no_mimo:
         line["mimo"] = mimo_leg(args)
+    if not args.no_mimo_grid:
+        line["mimo_grid"] = mimo_grid_leg(args)
     if not args.no_serving:
         line["serving"] = serving_leg(args)
     if not args.no_uneven:
