@@ -31,6 +31,10 @@ import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
+# The request server runs up to 16 streams; the HIP runtime maps streams onto
+# this many hardware queues (its default is 4), read once when it starts, so
+# it is set before torch loads.  The other legs use one or two streams.
+os.environ["GPU_MAX_HW_QUEUES"] = "16"
 
 INT8_MFMA_PEAK = 5.0e15            # dense int8 MFMA, ops/s (MI355X)
 # 32-bit VALU lane-ops/s: CUs x SIMDs x 32 lanes per clock x clock, i.e. the published FP32 vector
@@ -494,7 +498,7 @@ def serving_leg(args):
                          noise_table=w.gauss_table(8), prec="fp8", slots_per_class=4096, max_batch=mb,
                          streams=args.serving_streams, seed=11, max_wait_us=150.0, prealloc_chunks=pre, mimo=True)
         res["server"] = {"max_batch": mb, "prealloc_chunks": pre, "streams": args.serving_streams,
-                         "max_wait_us": 150.0}
+                         "max_wait_us": 150.0, "hw_queues": int(os.environ["GPU_MAX_HW_QUEUES"])}
         srv.submit_mimo_raw(ids[:len(pairs)], dims[:len(pairs)], esn0[:len(pairs)], hp[:len(pairs)],
                             yp[:len(pairs)])  # warm-up: every size class once
         left = len(pairs)

@@ -224,6 +224,9 @@ struct MimoMapArgs {
   int32_t npad, xm_stride, count;
 };
 hipError_t launch_mimo_map(const MimoMapArgs& a, size_t max_work, size_t max_hy, hipStream_t s);
+// bytes from src to dst by a kernel on stream s (either side may be pinned,
+// device-mapped host memory given by its device address); both 16-byte aligned
+hipError_t launch_copy_bytes(void* dst, const void* src, size_t bytes, hipStream_t s);
 size_t mimo_map_work_doubles(int nr, int nt);
 hipError_t launch_energy_f64(const EnergyArgs& a, hipStream_t s);
 

@@ -55,11 +55,14 @@ struct Chunk {
   double t_launch = 0.0;         // when pim_server_flush issued the chunk
   // pinned host staging (inputs) and results, each one contiguous block
   // (h_in / d_in, h_out / d_out) of sections; the result block is read back
-  // by one copy
+  // by one copy.  MIMO chunks map their host blocks into the device's address
+  // space (dh_in / dh_out) and copy them with kernels on the chunk's stream.
   uint8_t* h_in = nullptr;
   uint8_t* d_in = nullptr;
   uint8_t* h_out = nullptr;
   uint8_t* d_out = nullptr;
+  uint8_t* dh_in = nullptr;
+  uint8_t* dh_out = nullptr;
   size_t in_bytes = 0, out_bytes = 0;
   uint8_t* h_frag = nullptr;
   float* h_hf = nullptr;
@@ -258,8 +261,8 @@ void free_chunk(Chunk* c) {
 }
 
 template <typename T>
-bool host_alloc(T** p, size_t count) {
-  return hipHostMalloc((void**)p, std::max<size_t>(count, 1) * sizeof(T), hipHostMallocDefault) == hipSuccess;
+bool host_alloc(T** p, size_t count, unsigned flags = hipHostMallocDefault) {
+  return hipHostMalloc((void**)p, std::max<size_t>(count, 1) * sizeof(T), flags) == hipSuccess;
 }
 template <typename T>
 bool dev_alloc_n(T** p, size_t count) {
@@ -323,8 +326,14 @@ Chunk* new_chunk(pim_server* s, int cls) {
   c->in_bytes = L.in_bytes;
   c->out_bytes = L.out_bytes;
   bool ok = hipEventCreateWithFlags(&c->done, hipEventDisableTiming) == hipSuccess;
-  ok = ok && host_alloc(&c->h_in, L.host_in_bytes) && host_alloc(&c->h_out, L.out_bytes) &&
+  // MIMO chunks: coherent (not cached by the device) and device-mapped, so
+  // kernels can read the staged requests and write the results directly
+  const unsigned hflags = s->mimo ? (hipHostMallocMapped | hipHostMallocCoherent) : hipHostMallocDefault;
+  ok = ok && host_alloc(&c->h_in, L.host_in_bytes, hflags) && host_alloc(&c->h_out, L.out_bytes, hflags) &&
        dev_alloc_n(&c->d_in, L.in_bytes) && dev_alloc_n(&c->d_out, L.out_bytes);
+  if (ok && s->mimo)
+    ok = hipHostGetDevicePointer((void**)&c->dh_in, c->h_in, 0) == hipSuccess &&
+         hipHostGetDevicePointer((void**)&c->dh_out, c->h_out, 0) == hipSuccess && c->dh_in && c->dh_out;
   ok = ok && dev_alloc_n(&c->d_j64p, B) && dev_alloc_n(&c->d_h64p, B) && dev_alloc_n(&c->d_final, B * R * np) &&
        dev_alloc_n(&c->d_best, B * R * np) && dev_alloc_n(&c->d_stats, 5 * B * R) &&
        dev_alloc_n(&c->d_rerank, B * R);
@@ -405,9 +414,11 @@ hipError_t launch_chunk(pim_server* s, Chunk* c, hipStream_t st) {
   hipError_t e = hipSuccess;
   if (s->mimo) {
     // ids, slot records and the packed (H, y) are one contiguous prefix of
-    // the block: one upload, then the Ising instances are built on the device
+    // the block: one upload (a copy kernel reading the mapped host block, so
+    // the chunk never waits on a copy engine), then the Ising instances are
+    // built on the device
     const Layout L = layout(s, k);
-    e = hipMemcpyAsync(c->d_in, c->h_in, L.hy + c->hy_used * 8, hipMemcpyHostToDevice, st);
+    e = launch_copy_bytes(c->d_in, c->dh_in, L.hy + c->hy_used * 8, st);
     if (e != hipSuccess) return e;
     MimoMapArgs ma{};
     ma.slots = c->d_slots;
@@ -480,7 +491,9 @@ hipError_t launch_chunk(pim_server* s, Chunk* c, hipStream_t st) {
   ra.R = (int)R;
   ra.count = (int)B;
   e = launch_rerank_select(ra, st);
-  if (e == hipSuccess) e = hipMemcpyAsync(c->h_out, c->d_out, c->out_bytes, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess)
+    e = s->mimo ? launch_copy_bytes(c->dh_out, c->d_out, c->out_bytes, st)
+                : hipMemcpyAsync(c->h_out, c->d_out, c->out_bytes, hipMemcpyDeviceToHost, st);
   if (e == hipSuccess) e = hipEventRecord(c->done, st);
   return e;
 }
