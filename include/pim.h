@@ -363,7 +363,14 @@ pim_status pim_mimo_decode(const double* xm, const int8_t* s, int32_t nt, int32_
  *
  * Device memory: per N class (N rounded up to 32) up to slots_per_class slots,
  * allocated in chunks of max_batch as requests arrive, while the total stays
- * within hbm_budget bytes (0 = unbounded).  A chunk is one launch. */
+ * within hbm_budget bytes (0 = unbounded).  A chunk is one launch.  Its
+ * host staging and result blocks are pinned, coherent and mapped into the
+ * device's address space, and copy kernels on the chunk's stream move them, so
+ * a chunk's whole sequence (upload, quantisation, sweep, re-rank, readback)
+ * runs in order on one compute queue and never waits on a copy engine.  The
+ * HIP runtime multiplexes the server's streams onto GPU_MAX_HW_QUEUES hardware
+ * queues (4 unless the environment sets it before the runtime starts); mixes
+ * with long requests need as many queues as streams to overlap chunks. */
 typedef struct pim_server pim_server;
 typedef struct {
   int32_t max_n;             /* largest request N, <= PIM_MAX_N_LDS                  */
@@ -429,14 +436,7 @@ pim_status pim_server_poll_times(pim_server* server, int32_t max, uint32_t* ids,
  * is built on the device at launch, so the host stages only H and y.  Same
  * configuration, slots, launches and results as pim_server_create; such a
  * server takes pim_server_submit_mimo only (pim_server_submit returns
- * PIM_ERR_STATE), and pim_server_poll_mimo also returns each request's x_m.
- * Its staging and result blocks are pinned, coherent and mapped into the
- * device's address space; copy kernels on the chunk's stream move them, so a
- * chunk's whole sequence (upload, mapping, sweep, re-rank, readback) runs in
- * order on one compute queue and never waits on a copy engine.  The HIP
- * runtime multiplexes the server's streams onto GPU_MAX_HW_QUEUES hardware
- * queues (4 unless the environment sets it before the runtime starts); mixes
- * with long requests need as many queues as streams to overlap chunks. */
+ * PIM_ERR_STATE), and pim_server_poll_mimo also returns each request's x_m. */
 pim_status pim_server_create_mimo(const pim_server_config* cfg, pim_server** out);
 
 /* Admits up to `count` MIMO requests in order: ids[r] < 2^24 (also the noise

@@ -66,30 +66,37 @@ void real_model(const double* Hc, const double* yc, int nr, int nt, std::vector<
   }
 }
 
-// Solves A z = b for symmetric positive definite A (n x n) by Cholesky.
-bool spd_solve(std::vector<double> A, const std::vector<double>& b, int n, std::vector<double>& z) {
+// Solves A z = b for symmetric positive definite A (n x n) by an LDL^T
+// factorization (unit lower L, diagonal D, no square roots):
+//   W_ij = A_ij - sum_{l<j} W_il L_jl (l ascending, i >= j),  D_j = W_jj,
+//   L_ij = W_ij / D_j (i > j),
+// then L w = b, y = w / D and L^T z = y, each row's subtractions taken in
+// ascending k going forward and from the last row's term back going back.
+// The device mapping (mimo_map.hip) performs the same operations in the same
+// order, so both give the same z bit for bit.
+bool spd_solve(const std::vector<double>& A, const std::vector<double>& b, int n, std::vector<double>& z) {
+  std::vector<double> W((size_t)n * n, 0.0), L((size_t)n * n, 0.0), D(n);
   for (int j = 0; j < n; ++j) {
-    double d = A[(size_t)j * n + j];
-    for (int k = 0; k < j; ++k) d -= A[(size_t)j * n + k] * A[(size_t)j * n + k];
-    if (!(d > 0.0)) return false;
-    d = std::sqrt(d);
-    A[(size_t)j * n + j] = d;
-    for (int i = j + 1; i < n; ++i) {
+    for (int i = j; i < n; ++i) {
       double v = A[(size_t)i * n + j];
-      for (int k = 0; k < j; ++k) v -= A[(size_t)i * n + k] * A[(size_t)j * n + k];
-      A[(size_t)i * n + j] = v / d;
+      for (int l = 0; l < j; ++l) v -= W[(size_t)i * n + l] * L[(size_t)j * n + l];
+      W[(size_t)i * n + j] = v;
     }
+    D[j] = W[(size_t)j * n + j];
+    if (!(D[j] > 0.0)) return false;
+    for (int i = j + 1; i < n; ++i) L[(size_t)i * n + j] = W[(size_t)i * n + j] / D[j];
   }
   z = b;
   for (int i = 0; i < n; ++i) {  // L w = b
     double v = z[i];
-    for (int k = 0; k < i; ++k) v -= A[(size_t)i * n + k] * z[k];
-    z[i] = v / A[(size_t)i * n + i];
+    for (int k = 0; k < i; ++k) v -= L[(size_t)i * n + k] * z[k];
+    z[i] = v;
   }
-  for (int i = n - 1; i >= 0; --i) {  // L^T z = w
+  for (int i = 0; i < n; ++i) z[i] = z[i] / D[i];
+  for (int i = n - 1; i >= 0; --i) {  // L^T z = y
     double v = z[i];
-    for (int k = i + 1; k < n; ++k) v -= A[(size_t)k * n + i] * z[k];
-    z[i] = v / A[(size_t)i * n + i];
+    for (int k = n - 1; k > i; --k) v -= L[(size_t)k * n + i] * z[k];
+    z[i] = v;
   }
   return true;
 }

@@ -6,7 +6,7 @@
 //
 //   Hr = [[Re H, -Im H], [Im H, Re H]] (2Nr x 2Nt),  yr = [Re y; Im y],
 //   G  = Hr^T Hr,
-//   x_m = 0 (ML) or slice((G + I / esn0)^-1 Hr^T yr) (DI; Cholesky),
+//   x_m = 0 (ML) or slice((G + I / esn0)^-1 Hr^T yr) (DI; LDL^T solve),
 //   r  = yr - Hr x_m,  c = Hr^T r,
 //   J  = -2 w_a w_b G_ij off the diagonal (spin a*2Nt + i carries weight w_a
 //        on real component i),  h = 2 w_a c_i.
@@ -14,15 +14,17 @@
 // Hr is never formed: its entries are read from the complex H (interleaved
 // (re, im), row-major Nr x Nt), which is staged in LDS when it fits beside the
 // lower triangle of G.  Every sum runs over its index in ascending order with
-// separate multiplies and adds, as the host function does; the Cholesky
-// factor is formed right-looking, which applies each element's subtractions in
-// that same order, so G, J and the factor equal the host's bit for bit.  The
-// triangular solves run in one wave (lane l owns rows l and l + 64).
+// separate multiplies and adds, as the host function does; the LDL^T factor
+// is formed right-looking, which applies each element's subtractions in that
+// same order, and the solves take the host's order too, so G, J, the factor
+// and the unsliced MMSE estimate equal the host's bit for bit.  The triangular
+// solves run in one wave (lane l owns rows l and l + 64).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <type_traits>
 #include <vector>
 
 #include "internal.hpp"
@@ -55,6 +57,16 @@ __device__ __forceinline__ double slice_level(double v, int qam) {
 // packed lower triangle: (i, j), j <= i
 __device__ __forceinline__ int tri(int i, int j) { return i * (i + 1) / 2 + j; }
 
+// v of lane `lane` (the same in every lane of the wave) in every lane
+__device__ __forceinline__ double bcast(double v, int lane) {
+  const uint64_t b = (uint64_t)__double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, lane);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), lane);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+constexpr int kPanel = 8;  // LDL^T columns factored per panel
+
 // Column i of Hr as (offset of its re/im value in H, sign) for the rows
 // k < nr (first) and k >= nr (second); the row stride in H is 2 nt.
 struct HrCol {
@@ -86,13 +98,15 @@ __global__ __launch_bounds__(kThreads) void mimo_map_kernel(MimoMapArgs a) {
   double* hv = a.h64 + (size_t)slot * a.npad;
   double* xm_out = a.xm + (size_t)slot * a.xm_stride;
 
-  // LDS: [H, y (staged)] | G lower triangle | z [n2] | x_m [n2] | r [m] | c [n2]
+  // LDS: [H, y (staged)] | G lower triangle | z [n2] | x_m [n2] | r [m] | c [n2] |
+  //      W of the factor's current panel [n2][kPanel] (DI)
   const int hy_len = STAGE_H ? 2 * nr * nt + 2 * nr : 0;
   double* G = smem + hy_len;
   double* z = G + n2 * (n2 + 1) / 2;
   double* xm = z + n2;
   double* r = xm + n2;
   double* c = r + m;
+  double* Wp = c + n2;
   if (STAGE_H)
     for (int i = tid; i < hy_len; i += kThreads) smem[i] = Hg[i];
   if (tid == 0) bad = 0;
@@ -100,130 +114,276 @@ __global__ __launch_bounds__(kThreads) void mimo_map_kernel(MimoMapArgs a) {
   const double* Hs = STAGE_H ? smem : Hg;
   const double* ys = Hs + 2 * nr * nt;
 
-  // ---- G = Hr^T Hr, lower triangle: each thread a 4 x 4 block of entries
-  //      (rows 4 bi.., columns 4 bj.., bi >= bj), every entry summed over k in
-  //      ascending order as above ----
+  // ---- G = Hr^T Hr, lower triangle: thread (bi, bj) of an nb4 x nb4 grid
+  //      takes rows i = bi + nb4 a and columns j = bj + nb4 b (a, b < 4), the
+  //      entries with a >= b (the others lie above the diagonal), so that the
+  //      lanes of a wave read consecutive columns of H; every entry summed
+  //      over k in ascending order as above ----
   {
     const int nb4 = (n2 + 3) / 4;
     for (int t = tid; t < nb4 * nb4; t += kThreads) {
-      const int bi = t / nb4, bj = t % nb4;
-      if (bj > bi) continue;
+      const int bi = t / nb4, bj = t - bi * nb4;
       HrCol ci[4], cj[4];
+#pragma unroll
       for (int q = 0; q < 4; ++q) {
-        ci[q] = hr_col(nt, min(4 * bi + q, n2 - 1));
-        cj[q] = hr_col(nt, min(4 * bj + q, n2 - 1));
+        ci[q] = hr_col(nt, min(bi + nb4 * q, n2 - 1));
+        cj[q] = hr_col(nt, min(bj + nb4 * q, n2 - 1));
       }
       double acc[4][4];
+#pragma unroll
       for (int a = 0; a < 4; ++a)
-        for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+#pragma unroll
+        for (int b = 0; b <= a; ++b) acc[a][b] = 0.0;
       for (int k = 0; k < nr; ++k) {  // rows k < nr of Hr
         const double* row = Hs + 2 * k * nt;
         double x[4], y[4];
+#pragma unroll
         for (int q = 0; q < 4; ++q) {
           x[q] = ci[q].sg_lo * row[ci[q].off_lo];
           y[q] = cj[q].sg_lo * row[cj[q].off_lo];
         }
+#pragma unroll
         for (int a = 0; a < 4; ++a)
-          for (int b = 0; b < 4; ++b) acc[a][b] += x[a] * y[b];
+#pragma unroll
+          for (int b = 0; b <= a; ++b) acc[a][b] += x[a] * y[b];
       }
       for (int k = 0; k < nr; ++k) {  // rows k >= nr
         const double* row = Hs + 2 * k * nt;
         double x[4], y[4];
+#pragma unroll
         for (int q = 0; q < 4; ++q) {
           x[q] = ci[q].sg_hi * row[ci[q].off_hi];
           y[q] = cj[q].sg_hi * row[cj[q].off_hi];
         }
+#pragma unroll
         for (int a = 0; a < 4; ++a)
-          for (int b = 0; b < 4; ++b) acc[a][b] += x[a] * y[b];
+#pragma unroll
+          for (int b = 0; b <= a; ++b) acc[a][b] += x[a] * y[b];
       }
+#pragma unroll
       for (int a = 0; a < 4; ++a)
-        for (int b = 0; b < 4; ++b) {
-          const int i = 4 * bi + a, j = 4 * bj + b;
+#pragma unroll
+        for (int b = 0; b <= a; ++b) {
+          const int i = bi + nb4 * a, j = bj + nb4 * b;
           if (i < n2 && j <= i) G[tri(i, j)] = acc[a][b];
         }
     }
   }
   __syncthreads();
-  // ---- J from G (zero diagonal, zero padding to npad x npad) ----
-  for (int e = tid; e < a.npad * a.npad; e += kThreads) {
-    const int p = e / a.npad, q = e % a.npad;
-    double v = 0.0;
-    if (p < n && q < n && p != q) {
-      const int pa = p / n2, i = p % n2, qb = q / n2, j = q % n2;
-      v = -2.0 * (pa ? w1 : w0) * (qb ? w1 : w0) * G[i >= j ? tri(i, j) : tri(j, i)];
+  // ---- J from G (zero diagonal, zero padding to npad x npad): a wave per
+  //      row; spin p is component p - n2 of block 1 when p >= n2 (n <= 2 n2) ----
+  for (int p = tid >> 6; p < a.npad; p += kThreads / 64) {
+    const int pa = p >= n2 ? 1 : 0, i = p - pa * n2;
+    double* Jrow = J + (size_t)p * a.npad;
+    for (int q = tid & 63; q < a.npad; q += 64) {
+      double v = 0.0;
+      if (p < n && q < n && p != q) {
+        const int qb = q >= n2 ? 1 : 0, j = q - qb * n2;
+        v = -2.0 * (pa ? w1 : w0) * (qb ? w1 : w0) * G[i >= j ? tri(i, j) : tri(j, i)];
+      }
+      Jrow[q] = v;
     }
-    J[e] = v;
   }
   // ---- x_m ----
   if (map == PIM_MIMO_DI) {
     for (int i = tid; i < n2; i += kThreads) {  // b = Hr^T yr
       const HrCol a = hr_col(nt, i);
       double v = 0.0;
+#pragma unroll 8
       for (int k = 0; k < nr; ++k) v += (a.sg_lo * Hs[2 * k * nt + a.off_lo]) * ys[2 * k];
+#pragma unroll 8
       for (int k = 0; k < nr; ++k) v += (a.sg_hi * Hs[2 * k * nt + a.off_hi]) * ys[2 * k + 1];
       z[i] = v;
     }
     __syncthreads();  // J has read G: it becomes A = G + I / esn0, factored in place
     for (int i = tid; i < n2; i += kThreads) G[tri(i, i)] += 1.0 / rec.esn0;
     __syncthreads();
-    // Cholesky A = L L^T, right-looking, two phases per column: (1) every
-    // thread forms the pivot sqrt(A_jj) itself and the rows below j are
-    // divided by it; (2) the trailing update A_ik -= L_ij L_kj (j < k <= i) on
-    // a 32 x 32 thread grid.  A pivot that is not positive (A not positive
-    // definite in binary64) marks the request as failed.
+    // A = L D L^T (unit lower L, diagonal D) in panels of kPanel columns:
+    //   W_ij = A_ij - sum_{l<j} W_il L_jl,  D_j = W_jj,  L_ij = W_ij / D_j.
+    // (1) Wave 0 factors the panel: lane l holds rows j0 + l and j0 + l + 64
+    // of the panel's columns in registers; per column every lane reads D_j
+    // from its lane, the rows below are divided by it (W kept for the
+    // updates) and W_il L_jl is subtracted from the later panel columns.
+    // (2) All threads subtract W_ij L_kj of the panel's columns, in ascending
+    // order, from the trailing matrix (rows and columns past the panel).
+    // Each element thus receives its subtractions in ascending column order
+    // and then its division, as in the host's column-by-column factorization.
+    // The triangle ends with L below the diagonal and D on it.  A pivot that
+    // is not positive (A not positive definite in binary64) marks the request
+    // as failed.
     const int tr = tid >> 5, tc = tid & 31;
-    for (int j = 0; j < n2; ++j) {
-      double d = G[tri(j, j)];
-      if (!(d > 0.0)) {
-        if (tid == 0) bad = 1;
-        d = 1.0;
+    for (int j0 = 0; j0 < n2; j0 += kPanel) {
+      const int w = min(kPanel, n2 - j0);
+      // fully unrolled over the panel's columns (register arrays indexed by
+      // constants); FULL: w == kPanel, TWO: rows past j0 + 64 exist (both
+      // uniform), so the common panels run without branches
+      auto panel = [&](auto full_c, auto two_c) __attribute__((always_inline)) {
+        constexpr bool FULL = decltype(full_c)::value, TWO = decltype(two_c)::value;
+        constexpr int NQ = TWO ? 2 : 1;
+        double P[NQ][kPanel];
+        bool not_pd = false;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+          const int r = tid + 64 * q, i = j0 + r;
+#pragma unroll
+          for (int c = 0; c < kPanel; ++c)
+            P[q][c] = (i < n2 && (FULL || c < w) && c <= r) ? G[tri(i, j0 + c)] : 0.0;
+        }
+#pragma unroll
+        for (int c = 0; c < kPanel; ++c) {
+          if (FULL || c < w) {
+            double d = bcast(P[0][c], c);  // row j0 + c is lane c
+            not_pd = not_pd || !(d > 0.0);
+            d = d > 0.0 ? d : 1.0;
+            double Wv[NQ];
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+              const int r = tid + 64 * q;
+              Wv[q] = P[q][c];
+              const double l = Wv[q] / d;
+              P[q][c] = (r > c) ? l : Wv[q];
+              if (j0 + r < n2) Wp[(j0 + r) * kPanel + c] = Wv[q];
+            }
+#pragma unroll
+            for (int c2 = c + 1; c2 < kPanel; ++c2) {
+              if (FULL || c2 < w) {
+                const double lk = bcast(P[0][c], c2);  // L of row j0 + c2, column j0 + c
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) {
+                  const int r = tid + 64 * q;
+                  const double u = P[q][c2] - Wv[q] * lk;
+                  P[q][c2] = (r >= c2) ? u : P[q][c2];
+                }
+              }
+            }
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+          const int r = tid + 64 * q, i = j0 + r;
+#pragma unroll
+          for (int c = 0; c < kPanel; ++c)
+            if (i < n2 && (FULL || c < w) && c <= r) G[tri(i, j0 + c)] = P[q][c];
+        }
+        if (not_pd && tid == 0) bad = 1;
+      };
+      if (tid < 64) {
+        using T = std::true_type;
+        using F = std::false_type;
+        const bool two = j0 + 64 < n2;
+        if (w == kPanel) {
+          if (two) panel(T{}, T{});
+          else panel(T{}, F{});
+        } else {
+          if (two) panel(F{}, T{});
+          else panel(F{}, F{});
+        }
       }
-      const double djj = sqrt(d);
-      for (int i = j + 1 + tid; i < n2; i += kThreads) G[tri(i, j)] = G[tri(i, j)] / djj;
       __syncthreads();
-      if (tid == 0) G[tri(j, j)] = djj;
-      // this thread's rows i = j+1+tr+32a and columns k = j+1+tc+32b (k <= i):
-      // operands loaded first, so the reads overlap, then updated
-      double lik[4], lkj[4], aik[4][4];
-      for (int q = 0; q < 4; ++q) {
-        const int i = j + 1 + tr + 32 * q, k = j + 1 + tc + 32 * q;
-        lik[q] = i < n2 ? G[tri(i, j)] : 0.0;
-        lkj[q] = k < n2 ? G[tri(k, j)] : 0.0;
+      const int b0 = j0 + w;  // trailing matrix: rows and columns >= b0 (fewer than 128)
+      if (b0 < n2) {
+        // this thread's rows i = b0 + tr + 32 qa and columns k = b0 + tc + 32 qb (k <= i)
+        double lk[4][kPanel];
+#pragma unroll
+        for (int qb = 0; qb < 4; ++qb) {
+          const int k = b0 + tc + 32 * qb;
+#pragma unroll
+          for (int c = 0; c < kPanel; ++c) lk[qb][c] = (k < n2 && c < w) ? G[tri(k, j0 + c)] : 0.0;
+        }
+#pragma unroll
+        for (int qa = 0; qa < 4; ++qa) {
+          const int i = b0 + tr + 32 * qa;
+          if (i < n2) {
+            double wi[kPanel];
+#pragma unroll
+            for (int c = 0; c < kPanel; ++c) wi[c] = c < w ? Wp[i * kPanel + c] : 0.0;
+#pragma unroll
+            for (int qb = 0; qb <= qa; ++qb) {
+              const int k = b0 + tc + 32 * qb;
+              if (k <= i) {
+                double v = G[tri(i, k)];
+#pragma unroll
+                for (int c = 0; c < kPanel; ++c)
+                  if (c < w) v = v - wi[c] * lk[qb][c];
+                G[tri(i, k)] = v;
+              }
+            }
+          }
+        }
       }
-      for (int qa = 0; qa < 4; ++qa)
-        for (int qb = 0; qb <= qa; ++qb) {
-          const int i = j + 1 + tr + 32 * qa, k = j + 1 + tc + 32 * qb;
-          aik[qa][qb] = (i < n2 && k <= i) ? G[tri(i, k)] : 0.0;
-        }
-      for (int qa = 0; qa < 4; ++qa)
-        for (int qb = 0; qb <= qa; ++qb) {
-          const int i = j + 1 + tr + 32 * qa, k = j + 1 + tc + 32 * qb;
-          if (i < n2 && k <= i) G[tri(i, k)] = aik[qa][qb] - lik[qa] * lkj[qb];
-        }
       __syncthreads();
     }
-    // L w = b, then L^T z = w, in wave 0: lane l owns rows l and l + 64
+    // L w = b, y = w / D, then L^T z = y, in wave 0: lane l owns rows l and
+    // l + 64.  Step k broadcasts the final value of row k from its lane, the
+    // owner keeps it, and every lane subtracts its row's term; rows that are
+    // already final, or past n2, take a don't-care term (they are never read
+    // again), and the step count is rounded up to a multiple of kAhead with
+    // such don't-care steps, which keeps the steps free of branches.  The
+    // factor entries are loaded kAhead steps before they are used.  Row i
+    // takes its subtractions in ascending k going forward and descending k
+    // going back, as the host's solve does.
     if (tid < 64) {
-      double zr[2];
-      for (int q = 0; q < 2; ++q) zr[q] = (tid + 64 * q < n2) ? z[tid + 64 * q] : 0.0;
-      for (int k = 0; k < n2; ++k) {  // forward: z_k is final once divided; the rows below subtract it
-        const double zk = __shfl(zr[k >> 6], k & 63) / G[tri(k, k)];
-        for (int q = 0; q < 2; ++q) {
-          const int i = tid + 64 * q;
-          if (i == k) zr[q] = zk;
-          else if (i > k && i < n2) zr[q] = zr[q] - G[tri(i, k)] * zk;
+      constexpr int kAhead = 4;
+      const int last = n2 - 1, steps = (n2 + kAhead - 1) / kAhead * kAhead;
+      // L_ik for i > k, and some finite entry of the triangle otherwise
+      auto l_row = [&](int i, int k) {
+        const int ii = max(min(i, last), 0), kk = max(min(k, ii), 0);
+        return G[tri(ii, kk)];
+      };
+      double zr[2], zf[2], dg[2], lb[kAhead][2];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int i = tid + 64 * q;
+        zr[q] = i < n2 ? z[i] : 0.0;
+        zf[q] = 0.0;
+        dg[q] = i < n2 ? G[tri(i, i)] : 1.0;
+      }
+#pragma unroll
+      for (int s = 0; s < kAhead; ++s)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) lb[s][q] = l_row(tid + 64 * q, s);
+      for (int k0 = 0; k0 < steps; k0 += kAhead) {  // forward
+#pragma unroll
+        for (int s = 0; s < kAhead; ++s) {
+          const int k = k0 + s;
+          const double z0 = bcast(zr[0], k & 63), z1 = bcast(zr[1], k & 63);
+          const double zk = k < 64 ? z0 : z1;
+#pragma unroll
+          for (int q = 0; q < 2; ++q) {
+            zf[q] = tid + 64 * q == k ? zk : zf[q];
+            zr[q] = zr[q] - lb[s][q] * zk;
+            lb[s][q] = l_row(tid + 64 * q, k + kAhead);
+          }
+          __builtin_amdgcn_sched_barrier(0);  // keeps the loads in this step, kAhead steps before their use
         }
       }
-      for (int k = n2 - 1; k >= 0; --k) {  // backward
-        const double zk = __shfl(zr[k >> 6], k & 63) / G[tri(k, k)];
-        for (int q = 0; q < 2; ++q) {
-          const int i = tid + 64 * q;
-          if (i == k) zr[q] = zk;
-          else if (i < k) zr[q] = zr[q] - G[tri(k, i)] * zk;
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        zr[q] = zf[q] / dg[q];
+        zf[q] = 0.0;
+      }
+#pragma unroll
+      for (int s = 0; s < kAhead; ++s)
+#pragma unroll
+        for (int q = 0; q < 2; ++q) lb[s][q] = l_row(last - s, tid + 64 * q);
+      for (int k0 = last; k0 > last - steps; k0 -= kAhead) {  // backward: L_ki for i < k
+#pragma unroll
+        for (int s = 0; s < kAhead; ++s) {
+          const int k = k0 - s;
+          const double z0 = bcast(zr[0], k & 63), z1 = bcast(zr[1], k & 63);
+          const double zk = k < 64 ? z0 : z1;
+#pragma unroll
+          for (int q = 0; q < 2; ++q) {
+            zf[q] = tid + 64 * q == k ? zk : zf[q];
+            zr[q] = zr[q] - lb[s][q] * zk;
+            lb[s][q] = l_row(k - kAhead, tid + 64 * q);
+          }
+          __builtin_amdgcn_sched_barrier(0);
         }
       }
+#pragma unroll
       for (int q = 0; q < 2; ++q)
-        if (tid + 64 * q < n2) z[tid + 64 * q] = zr[q];
+        if (tid + 64 * q < n2) z[tid + 64 * q] = zf[q];
     }
     __syncthreads();
     // a failed request: x_m and h are NaN, so its binary64 energy is NaN
@@ -235,6 +395,7 @@ __global__ __launch_bounds__(kThreads) void mimo_map_kernel(MimoMapArgs a) {
   // ---- r = yr - Hr x_m, c = Hr^T r, h ----
   for (int k = tid; k < m; k += kThreads) {
     double v = yr_at(ys, nr, k);
+#pragma unroll 8
     for (int j = 0; j < n2; ++j) v -= hr_at(Hs, nr, nt, k, j) * xm[j];
     r[k] = v;
   }
@@ -242,7 +403,9 @@ __global__ __launch_bounds__(kThreads) void mimo_map_kernel(MimoMapArgs a) {
   for (int i = tid; i < n2; i += kThreads) {
     const HrCol a = hr_col(nt, i);
     double v = 0.0;
+#pragma unroll 8
     for (int k = 0; k < nr; ++k) v += (a.sg_lo * Hs[2 * k * nt + a.off_lo]) * r[k];
+#pragma unroll 8
     for (int k = 0; k < nr; ++k) v += (a.sg_hi * Hs[2 * k * nt + a.off_hi]) * r[nr + k];
     c[i] = v;
   }
@@ -254,9 +417,10 @@ __global__ __launch_bounds__(kThreads) void mimo_map_kernel(MimoMapArgs a) {
 }  // namespace
 
 size_t mimo_map_work_doubles(int nr, int nt) {
-  // LDS doubles of one request besides its staged H and y: G triangle, z, x_m, r, c
+  // LDS doubles of one request besides its staged H and y: G triangle, z, x_m,
+  // r, c and the factor's panel W
   const size_t n2 = 2 * (size_t)nt, m = 2 * (size_t)nr;
-  return n2 * (n2 + 1) / 2 + 3 * n2 + m;
+  return n2 * (n2 + 1) / 2 + 3 * n2 + m + n2 * kPanel;
 }
 
 hipError_t launch_mimo_map(const MimoMapArgs& a, size_t max_work, size_t max_hy, hipStream_t s) {

@@ -55,8 +55,8 @@ struct Chunk {
   double t_launch = 0.0;         // when pim_server_flush issued the chunk
   // pinned host staging (inputs) and results, each one contiguous block
   // (h_in / d_in, h_out / d_out) of sections; the result block is read back
-  // by one copy.  MIMO chunks map their host blocks into the device's address
-  // space (dh_in / dh_out) and copy them with kernels on the chunk's stream.
+  // by one copy.  Both host blocks are mapped into the device's address space
+  // (dh_in / dh_out) and copied by kernels on the chunk's stream.
   uint8_t* h_in = nullptr;
   uint8_t* d_in = nullptr;
   uint8_t* h_out = nullptr;
@@ -326,12 +326,12 @@ Chunk* new_chunk(pim_server* s, int cls) {
   c->in_bytes = L.in_bytes;
   c->out_bytes = L.out_bytes;
   bool ok = hipEventCreateWithFlags(&c->done, hipEventDisableTiming) == hipSuccess;
-  // MIMO chunks: coherent (not cached by the device) and device-mapped, so
-  // kernels can read the staged requests and write the results directly
-  const unsigned hflags = s->mimo ? (hipHostMallocMapped | hipHostMallocCoherent) : hipHostMallocDefault;
+  // coherent (not cached by the device) and device-mapped, so copy kernels
+  // can read the staged requests and write the results directly
+  const unsigned hflags = hipHostMallocMapped | hipHostMallocCoherent;
   ok = ok && host_alloc(&c->h_in, L.host_in_bytes, hflags) && host_alloc(&c->h_out, L.out_bytes, hflags) &&
        dev_alloc_n(&c->d_in, L.in_bytes) && dev_alloc_n(&c->d_out, L.out_bytes);
-  if (ok && s->mimo)
+  if (ok)
     ok = hipHostGetDevicePointer((void**)&c->dh_in, c->h_in, 0) == hipSuccess &&
          hipHostGetDevicePointer((void**)&c->dh_out, c->h_out, 0) == hipSuccess && c->dh_in && c->dh_out;
   ok = ok && dev_alloc_n(&c->d_j64p, B) && dev_alloc_n(&c->d_h64p, B) && dev_alloc_n(&c->d_final, B * R * np) &&
@@ -431,9 +431,12 @@ hipError_t launch_chunk(pim_server* s, Chunk* c, hipStream_t st) {
     ma.count = (int)B;
     e = launch_mimo_map(ma, c->max_work, c->max_hy, st);
   } else {
-    e = hipMemcpyAsync(c->d_j64, c->h_j64, B * np * np * 8, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(c->d_h64, c->h_h64, B * np * 8, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(c->d_sid, c->h_sid, B * 4, hipMemcpyHostToDevice, st);
+    // the used part of each staged section, by copy kernels (see above)
+    const size_t off_j = (uint8_t*)c->h_j64 - c->h_in, off_h = (uint8_t*)c->h_h64 - c->h_in,
+                 off_s = (uint8_t*)c->h_sid - c->h_in;
+    e = launch_copy_bytes(c->d_j64, c->dh_in + off_j, B * np * np * 8, st);
+    if (e == hipSuccess) e = launch_copy_bytes(c->d_h64, c->dh_in + off_h, B * np * 8, st);
+    if (e == hipSuccess) e = launch_copy_bytes(c->d_sid, c->dh_in + off_s, B * 4, st);
   }
   if (e != hipSuccess) return e;
   RealPackArgs pa{};
@@ -491,9 +494,7 @@ hipError_t launch_chunk(pim_server* s, Chunk* c, hipStream_t st) {
   ra.R = (int)R;
   ra.count = (int)B;
   e = launch_rerank_select(ra, st);
-  if (e == hipSuccess)
-    e = s->mimo ? launch_copy_bytes(c->dh_out, c->d_out, c->out_bytes, st)
-                : hipMemcpyAsync(c->h_out, c->d_out, c->out_bytes, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = launch_copy_bytes(c->dh_out, c->d_out, c->out_bytes, st);
   if (e == hipSuccess) e = hipEventRecord(c->done, st);
   return e;
 }
