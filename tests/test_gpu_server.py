@@ -201,7 +201,7 @@ def _mimo_problem(k, nr, nt, qam, db=15.0):
 
 
 def test_device_mimo_mapping_matches_host_and_oracle(gpu_lib):
-    """The server's device mapping kernel (binary64 Gram, Cholesky MMSE,
+    """The server's device mapping kernel (binary64 Gram, LDL^T MMSE solve,
     slicing, J and h) against the host library's mapping (same operation
     order: identical) and the oracle's (Suppl. "Delta-Ising MIMO"; 1e-12)."""
     from oracle import mimo
@@ -217,6 +217,42 @@ def test_device_mimo_mapping_matches_host_and_oracle(gpu_lib):
         np.testing.assert_allclose(Jd, d["J"], rtol=0, atol=1e-12 * scale)
         np.testing.assert_allclose(hd, d["h"], rtol=0, atol=1e-12 * max(np.abs(d["h"]).max(), 1.0))
         print(f"  host identical: J {np.array_equal(Jd, Jh)} h {np.array_equal(hd, hh)}", flush=True)
+
+
+def test_device_mimo_mapping_singular_systems_agree_with_host(gpu_lib):
+    """Numerically singular MMSE systems (equal or proportional channel
+    columns, a regulariser 1/(Es/N0) below rounding): host and device take the
+    same LDL^T steps, so both reject the system (a pivot that is not
+    positive) or both return the same mapping bit for bit."""
+    pim = gpu_lib
+    rng = np.random.default_rng(5)
+
+    def outcome(fn, H, y, esn0):
+        try:
+            return True, fn(H, y, 16, "di", esn0)
+        except pim.PimError as e:
+            assert "positive definite" in str(e), e
+            return False, None
+
+    cases = [(np.ones((2, 2), complex), 1e300), (np.ones((2, 2), complex), 10.0)]
+    for k in range(6):
+        nt = 2 + 3 * k
+        H = (rng.standard_normal((nt + 1, nt)) + 1j * rng.standard_normal((nt + 1, nt))) / np.sqrt(2)
+        H[:, -1] = (k + 1) * H[:, 0]
+        cases.append((H, 1e300))
+    accepted = []
+    for i, (H, esn0) in enumerate(cases):
+        y = rng.standard_normal(H.shape[0]) + 1j * rng.standard_normal(H.shape[0])
+        _say(f"singular MMSE case {i}: nr={H.shape[0]} nt={H.shape[1]} esn0={esn0:g}")
+        ok_h, rh = outcome(pim.mimo_ising, H, y, esn0)
+        ok_d, rd = outcome(pim.mimo_ising_device, H, y, esn0)
+        assert ok_h == ok_d, (i, ok_h, ok_d)
+        if ok_h:
+            for a, b in zip(rh, rd):
+                assert np.array_equal(a, b), i
+        accepted.append(ok_h)
+    # two equal columns, regulariser below rounding: the second pivot is exactly 0
+    assert accepted[0] is False and accepted[1] is True
 
 
 def test_mimo_server_matches_host_staged_server(gpu_lib):

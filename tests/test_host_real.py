@@ -132,6 +132,20 @@ def test_mimo_mapping_matches_oracle(mapping, qam, nt):
             assert np.array_equal(pim.mimo_decode(xm, s, qam, mapping), mimo.decode(d["xm"], d["T"], s, qam))
 
 
+def test_mimo_mapping_rejects_a_singular_mmse_system():
+    """Two equal channel columns and a regulariser 1/(Es/N0) below rounding:
+    the LDL^T factorization's second pivot is exactly 0, which the mapping
+    rejects; with Es/N0 = 10 the same channel maps, and its sliced MMSE
+    estimate equals the oracle's (Suppl. "Baseline: linear MMSE detector")."""
+    H = np.ones((2, 2), complex)
+    y = np.array([1.0 + 1.0j, 2.0 - 1.0j])
+    with pytest.raises(pim.PimError, match="positive definite"):
+        pim.mimo_ising(H, y, 16, "di", 1e300)
+    J, h, xm = pim.mimo_ising(H, y, 16, "di", 10.0)
+    p = {"H": H, "y": y, "qam": 16, "esn0": 10.0, "nt": 2, "nr": 2}
+    assert np.array_equal(xm, mimo.detector_instance(p, "di")["xm"])
+
+
 def test_real_instance_validation():
     J = np.zeros((4, 4))
     J[0, 1] = 1.0
