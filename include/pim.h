@@ -389,7 +389,8 @@ typedef struct {
   int32_t streams;           /* concurrent launch streams, 1..16                       */
   uint64_t seed;
   size_t hbm_budget;         /* bytes, 0 = no limit                                    */
-  double max_wait_us;        /* pim_server_flush holds a partly filled chunk until its
+  double max_wait_us;        /* pim_server_flush holds a partly filled chunk, while an
+                                earlier chunk of its class is in flight, until its
                                 first request has waited this long (0 = never)      */
   int32_t prealloc_chunks;   /* chunks allocated at creation per class up to max_n
                                 (within slots_per_class and hbm_budget)             */
@@ -411,8 +412,9 @@ pim_status pim_server_submit(pim_server* server, int32_t count, const uint32_t* 
 /* Launches staged requests, one launch per chunk, on a server stream whose
  * previous launch has finished if there is one, else on the next stream in
  * turn (upload, sweep, re-rank and readback are asynchronous), and returns:
- * full chunks always, partly filled ones once their first request
- * has waited max_wait_us.  *launched: requests launched. */
+ * full chunks always; partly filled ones at once when no chunk of their class
+ * is in flight (launched and not yet collected by a poll), else once their
+ * first request has waited max_wait_us.  *launched: requests launched. */
 pim_status pim_server_flush(pim_server* server, int32_t* launched);
 
 /* Collects up to `max` finished requests without blocking: ids [max], states

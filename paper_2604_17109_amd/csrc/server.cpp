@@ -779,12 +779,17 @@ pim_status pim_server_flush(pim_server* s, int32_t* launched) {
     const auto now = std::chrono::steady_clock::now();
     const double wait = s->cfg.max_wait_us;
     for (Klass& k : s->classes) {
+      // a class with a chunk still in flight (launched, not yet collected)
+      bool busy = false;
+      for (const Chunk* c : k.chunks) busy = busy || c->launched;
       for (size_t ci = 0; ci < k.chunks.size(); ++ci) {
       Chunk* c = k.chunks[ci];
       if (c->launched || c->count == 0) continue;
-      // a partly filled chunk waits for company up to max_wait_us
+      // a partly filled chunk waits for company up to max_wait_us, but only
+      // while an earlier chunk of its class is in flight: an idle class
+      // launches at once
       const double age = std::chrono::duration<double, std::micro>(now - c->first).count();
-      if (c->count < s->cfg.max_batch && wait > 0.0 && age < wait) continue;
+      if (c->count < s->cfg.max_batch && wait > 0.0 && busy && age < wait) continue;
       if (k.open == (int)ci) k.open = -1;
       // an idle stream if there is one, so a small chunk does not queue
       // behind a long one; otherwise the next stream in turn
@@ -804,6 +809,7 @@ pim_status pim_server_flush(pim_server* s, int32_t* launched) {
       if (e == hipSuccess) e = hipEventRecord(s->stream_idle[si], st);
       if (e != hipSuccess) return fail(PIM_ERR_DEVICE, "server launch failed: %s", hipGetErrorString(e));
       c->launched = true;
+      busy = true;
       s->inflight.push_back(c);
       total += c->count;
       }
