@@ -196,6 +196,27 @@ MIMO_SHAPES = [(8, 8, 4, "di"), (8, 8, 16, "di"), (16, 16, 16, "di"), (16, 16, 4
                (32, 32, 4, "di"), (8, 6, 16, "ml"), (64, 64, 16, "di"), (16, 12, 4, "di"), (64, 64, 4, "ml")]
 
 
+def test_server_batching_wait_only_while_class_in_flight(gpu_lib):
+    """pim_server_flush launches a partly filled chunk at once when no chunk
+    of its class is in flight, and holds it (up to max_wait_us) while one is."""
+    _say("server: batching wait only under load")
+    pim = gpu_lib
+    J, h = _request(pim, 5, 8, 4)  # N = 32
+    J2, h2 = _request(pim, 6, 16, 4)  # N = 64, another class
+    srv = _server(pim, max_wait_us=1e9, slots_per_class=64, max_batch=8)
+    assert srv.submit([1], [J], [h]) == 1
+    assert srv.flush() == 1                  # idle class: launched at once
+    assert srv.submit([2, 3], [J, J], [h, h]) == 2
+    assert srv.flush() == 0                  # its class has a chunk in flight: held
+    assert srv.submit([4], [J2], [h2]) == 1
+    assert srv.flush() == 1                  # an idle class is not held by another
+    got = _drain(srv, 2)                     # collecting request 1 makes its class idle
+    assert set(got) == {1, 4}
+    assert srv.flush() == 2
+    assert set(_drain(srv, 2)) == {2, 3}
+    srv.close()
+
+
 def _mimo_problem(k, nr, nt, qam, db=15.0):
     return w.mimo.mimo_problem(nt, nr, qam, db, seed=12, index=k)
 
