@@ -31,6 +31,7 @@
 #include <climits>
 #include <cmath>
 #include <cstdint>
+#include <type_traits>
 
 #include "internal.hpp"
 #include "philox.hpp"
@@ -143,6 +144,14 @@ __device__ __forceinline__ void real_tile_thresholds(const float* tab, const uin
     const int idx = (int)((xw[r >> 2] >> (8 * (r & 3))) & 0xFFu) ^ sm[r];
     th[r] = tab[idx];
   }
+}
+
+// v of the lane plus v of the lane 32 away (the two halves of a trial
+// column): the lower half's value first, so every lane gets the same sum.
+// One VALU lane swap instead of an LDS round trip.
+__device__ __forceinline__ float half_sum(float v) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
 }
 
 // Decisions (Eq. (4)) and energy terms (Eq. (1)) of one row tile's 16 spins
@@ -338,7 +347,7 @@ __global__ __launch_bounds__(64 * kMaxWaves) void sweep_real_kernel(SweepRealArg
         for (int q = 0; q < 4; ++q) PIM_FENCE(Bn[mt][j][q]);
       __builtin_amdgcn_sched_barrier(0);
     }
-    const float E = -0.5f * (ep + __shfl_xor(ep, 32));
+    const float E = -0.5f * half_sum(ep);
     if (E < e_best) {
       e_best = E;
       t_best = tg;
@@ -464,55 +473,82 @@ __global__ __launch_bounds__(64 * W) void sweep_real_split_kernel(SweepRealArgs 
 #pragma unroll
     for (int j = 0; j < KW; ++j) word(0, mt, j) = b[j];
   }
-  if (wave == 0) {
-    reinterpret_cast<uint4*>(sTab)[lane] = gTab4[lane];
-    reinterpret_cast<uint4*>(sTab)[64 + lane] = gTab4[64 + lane];
-  }
+  // the step tables move through LDS as kTabVec 16-byte words, spread over
+  // every thread of the block (kTabPer words each; with more threads than
+  // words the last word is loaded and stored by several threads, all with the
+  // same value, so no access needs a branch)
+  constexpr int kTabVec = kTabEntries / 4;
+  constexpr int kTabPer = (kTabVec + 64 * W - 1) / (64 * W);
+  uint4* sTab4 = reinterpret_cast<uint4*>(sTab);
+  auto tab_word = [&](int i) { return min((int)threadIdx.x + 64 * W * i, kTabVec - 1); };
+#pragma unroll
+  for (int i = 0; i < kTabPer; ++i) sTab4[tab_word(i)] = gTab4[tab_word(i)];
   if (threadIdx.x == 0) sFlag[0] = 0;
   __syncthreads();
 
   float e_best = INFINITY, e_cur = 0.0f;
   int32_t t_best = -1, first_hit = -1;
   int done = a.T;
-  // wave 0 holds the next table in registers: loaded one step before it is
-  // stored to LDS (a step before it is used), in place, so the load has a
-  // whole step to arrive and no register copy waits on it (clamped index:
-  // in bounds)
-  uint4 tr0 = uint4{0, 0, 0, 0}, tr1 = uint4{0, 0, 0, 0};
-  if (wave == 0) {
-    const size_t row = (size_t)min(1, a.T - 1) * 128;
-    tr0 = gTab4[row + lane];
-    tr1 = gTab4[row + 64 + lane];
+  // The next tables are held in registers, in two sets used by alternate
+  // steps: a table is loaded two steps before it is stored to LDS (three
+  // before it is used), in place, because one step is shorter than the load's
+  // latency from a cache of another chiplet; no register copy waits on a
+  // load (clamped index: in bounds).  The best state stays in registers and
+  // is stored once after the step loop, so the loop issues no global store
+  // and the table loads are the only memory operations a wait counts.
+  uint4 trA[kTabPer], trB[kTabPer];
+#pragma unroll
+  for (int i = 0; i < kTabPer; ++i) {
+    trA[i] = gTab4[(size_t)min(1, a.T - 1) * kTabVec + tab_word(i)];
+    trB[i] = gTab4[(size_t)min(2, a.T - 1) * kTabVec + tab_word(i)];
   }
-  for (int t = 0;; ++t) {
+  v4i Bb[RPW][KW];  // s(t) of the best energy so far, own tiles
+  auto store_best = [&]() {
+    size_t off = cell * kNpad + 16 * half;
+    PIM_FENCE(off);
+    int8_t* dst = a.best_s + off;
+#pragma unroll
+    for (int jj = 0; jj < RPW; ++jj) {
+      const int mt = wave + W * jj;
+      if (mt < NT) *reinterpret_cast<v4i*>(dst + 32 * mt) = real_tile_i8<PREC>(Bb[jj]);
+    }
+  };
+  // the start of step t: the table of step t+1 into the other buffer (last
+  // read in step t-1, before the barrier every thread has passed since), then
+  // the load of the table of step t+3 into the same registers
+  auto step_tables = [&](int t, uint4 (&tr)[kTabPer]) __attribute__((always_inline)) {
+    const int nxt = (t & 1) ^ 1;
+#pragma unroll
+    for (int i = 0; i < kTabPer; ++i) sTab4[nxt * kTabVec + tab_word(i)] = tr[i];
+    const size_t row = (size_t)min(t + 3, a.T - 1) * kTabVec;
+#pragma unroll
+    for (int i = 0; i < kTabPer; ++i) tr[i] = gTab4[row + tab_word(i)];
+  };
+  // the rest of step t; true when the run ends after it.  The loop below
+  // alternates the register set, so each set is a constant in its copy of the
+  // step, and runs the next step's tables at the end of each step, so the
+  // loop header uses no loaded register.  t is even in the first copy, which
+  // alone can meet the cancel poll (every 256 steps).
+  auto step = [&](int t, auto even_c) __attribute__((always_inline)) -> bool {
+    constexpr bool EVEN = decltype(even_c)::value;
     const int tg = a.start_step + t;
     const int cur = t & 1, nxt = cur ^ 1;
-    // the table of step t+1 into the other buffer (last read in step t-1,
-    // before the barrier every wave has passed since), then the load of the
-    // table of step t+2 into the same registers
-    if (wave == 0) {
-      reinterpret_cast<uint4*>(sTab + nxt * kTabEntries)[lane] = tr0;
-      reinterpret_cast<uint4*>(sTab + nxt * kTabEntries)[64 + lane] = tr1;
-      const size_t row = (size_t)min(t + 2, a.T - 1) * 128;
-      tr0 = gTab4[row + lane];
-      tr1 = gTab4[row + 64 + lane];
-    }
     uint32_t ctr_trial = (uint32_t)trial, ctr_half = (uint32_t)half;
     PIM_FENCE(ctr_trial);
     PIM_FENCE(ctr_half);
-    // noise blocks of the wave's tiles first: independent of the spins, they
-    // cover the latency of the spin-word reads and the MFMAs
+    v4i B[NT][KW];  // s(t), all tiles
+#pragma unroll
+    for (int mt = 0; mt < NT; ++mt)
+#pragma unroll
+      for (int j = 0; j < KW; ++j) B[mt][j] = word(cur, mt, j);
+    // noise blocks of the wave's tiles, issued after the spin-word reads:
+    // independent of the spins, they cover that latency and the MFMAs'
     Ctr4 xs[RPW];
 #pragma unroll
     for (int jj = 0; jj < RPW; ++jj) {
       const int mt = wave + W * jj;
       if (mt < NT) xs[jj] = noise_block(2u * mt + ctr_half, tg, ctr_trial, stream, k0, k1);
     }
-    v4i B[NT][KW];  // s(t), all tiles
-#pragma unroll
-    for (int mt = 0; mt < NT; ++mt)
-#pragma unroll
-      for (int j = 0; j < KW; ++j) B[mt][j] = word(cur, mt, j);
     const float* tab = sTab + cur * kTabEntries + kNoiseVals;
 #pragma unroll
     for (int jj = 0; jj < RPW; ++jj) {
@@ -534,36 +570,44 @@ __global__ __launch_bounds__(64 * W) void sweep_real_split_kernel(SweepRealArgs 
       for (int j = 0; j < KW; ++j) word(nxt, mt, j) = bn[j];
       __builtin_amdgcn_sched_barrier(0);
     }
-    if (threadIdx.x == 0 && (t & 255) == 0 && t < a.T)
+    if (EVEN && threadIdx.x == 0 && (t & 255) == 0 && t < a.T)
       sFlag[0] = __atomic_load_n(a.cancel, __ATOMIC_RELAXED) != 0 ? 1 : 0;
     lds_barrier();  // s(t+1), the tile energy sums of s(t) and the next table are complete
     float ep = 0.0f;
 #pragma unroll
     for (int mt = 0; mt < NT; ++mt) ep += sP[(cur * NT + mt) * 64 + lane];  // tile order
-    const float E = -0.5f * (ep + __shfl_xor(ep, 32));
+    const float E = -0.5f * half_sum(ep);
     if (E < e_best) {
       e_best = E;
       t_best = tg;
       if (live) {
-        size_t off = cell * kNpad + 16 * half;
-        PIM_FENCE(off);
-        int8_t* dst = a.best_s + off;
 #pragma unroll
         for (int jj = 0; jj < RPW; ++jj) {
           const int mt = wave + W * jj;
-          if (mt < NT) *reinterpret_cast<v4i*>(dst + 32 * mt) = real_tile_i8<PREC>(B[mt]);
+          if (mt < NT)
+#pragma unroll
+            for (int j = 0; j < KW; ++j) Bb[jj][j] = B[mt][j];
         }
       }
     }
     if (first_hit < 0 && E <= target) first_hit = tg;
     e_cur = E;
-    if (t == a.T) break;  // uniform: s(T) is in B
-    const bool stop = (t & 255) == 0 && sFlag[0] != 0;  // uniform: written before the barrier
+    if (t == a.T) return true;  // uniform: s(T) is in B
+    const bool stop = EVEN && (t & 255) == 0 && sFlag[0] != 0;  // uniform: written before the barrier
     if (stop) {
       done = t;  // s(t) stays the final state
-      break;
+      return true;
     }
+    return false;
+  };
+  step_tables(0, trA);
+  for (int t = 0;; t += 2) {
+    if (step(t, std::true_type{})) break;
+    step_tables(t + 1, trB);
+    if (step(t + 1, std::false_type{})) break;
+    step_tables(t + 2, trA);
   }
+  if (live && t_best >= 0) store_best();
   // the final state s(t) is in B (every wave holds all tiles; each writes its own)
   if (!live) return;
   {
