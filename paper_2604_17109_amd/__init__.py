@@ -28,14 +28,15 @@ LIB_PATH = os.path.join(_HERE, "libpim.so")
 PIM_OK, PIM_ERR_INVALID, PIM_ERR_UNSUPPORTED, PIM_ERR_NOMEM = 0, 1, 2, 3
 PIM_ERR_DEVICE, PIM_ERR_STATE, PIM_ERR_CANCELLED = 4, 5, 6
 NOISE_GAUSS, NOISE_UNIFORM = 0, 1
-KERNEL_MFMA_I8, KERNEL_PLAIN_F32, KERNEL_SEQ_I8 = 0, 1, 2
+KERNEL_MFMA_I8, KERNEL_PLAIN_F32, KERNEL_SEQ_I8, KERNEL_MFMA_F4 = 0, 1, 2, 3
 PREC_FP8, PREC_BF16 = 1, 2
 MIMO_ML, MIMO_DI = 0, 1
 ABI_VERSION = 2
 _PRECS = {"fp8": PREC_FP8, "bf16": PREC_BF16}
 _MAPS = {"ml": MIMO_ML, "di": MIMO_DI}
 _KERNELS = {"mfma": KERNEL_MFMA_I8, "mfma_i8": KERNEL_MFMA_I8, "plain": KERNEL_PLAIN_F32,
-            "plain_f32": KERNEL_PLAIN_F32, "seq": KERNEL_SEQ_I8, "sequential": KERNEL_SEQ_I8}
+            "plain_f32": KERNEL_PLAIN_F32, "seq": KERNEL_SEQ_I8, "sequential": KERNEL_SEQ_I8,
+            "mfma_f4": KERNEL_MFMA_F4, "f4": KERNEL_MFMA_F4}
 _NOISES = {"gauss": NOISE_GAUSS, "uniform": NOISE_UNIFORM}
 
 # every symbol declared in include/pim.h

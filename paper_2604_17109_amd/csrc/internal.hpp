@@ -192,6 +192,12 @@ hipError_t launch_sweep_plain(const PlainArgs& a, bool real, hipStream_t s);
 // 256 < N <= 1024: couplings streamed from global memory, spins in LDS.
 hipError_t launch_sweep_big(const SweepArgs& a, int count, int nt, bool has_h, hipStream_t s);
 int big_tiles(int n);  // row tiles of the streamed kernel: ceil(n / 32)
+// The same range on e2m1 (FP4) operands, for couplings in {0, +-1, +-2, +-3,
+// +-4, +-6} (exact): a.jfrag holds pack_f4_fragments output.
+hipError_t launch_sweep_big4(const SweepArgs& a, int count, int nt, bool has_h, hipStream_t s);
+bool f4_couplings(const int8_t* J, size_t count);  // every value e2m1-exact
+size_t f4_frag_bytes(int nt);                      // per instance: nt x ceil(nt/2) fragments of 1 KB
+void pack_f4_fragments(const int8_t* J, int n, int nt, uint8_t* out);
 hipError_t launch_sweep_seq(const SeqArgs& a, int count, int nt, bool has_h, hipStream_t s);
 hipError_t launch_sweep_real(const SweepRealArgs& a, int count, int nt, int prec, bool has_h, hipStream_t s);
 size_t real_frag_bytes(int prec, int nt);
@@ -265,6 +271,8 @@ struct pim_instance {
   bool has_h = false;
   uint8_t* d_arena = nullptr;     // one allocation holding every buffer below
   int8_t* d_jfrag = nullptr;      // int8, FP8 or BF16 MFMA fragments
+  uint8_t* d_jfrag4 = nullptr;    // e2m1 fragments (integer, N > PIM_MAX_N_LDS, e2m1-exact J) or NULL
+  size_t frag4_bytes = 0;
   float* d_jf32 = nullptr;        // [npad][jstride] FP32 J, zero-padded
   int8_t* d_j8 = nullptr;         // row-major int8 J (re-rank; integer instances)
   int32_t* d_h = nullptr;         // [npad] (integer instances)
@@ -285,6 +293,8 @@ struct pim_batch {
   // outputs); the step tables, trajectories and padded int8 J are separate
   uint8_t* d_arena = nullptr;
   int8_t* d_jfrag = nullptr;      // concatenated fragments of all instances
+  uint8_t* d_jfrag4 = nullptr;    // concatenated e2m1 fragments, when every instance has them
+  size_t frag4_bytes = 0;         // per instance
   int8_t* d_j8pad = nullptr;      // [count][npad][npad] row-major int8 J (sequential kernel)
   int8_t* d_trace = nullptr;      // [count][R][T+1][npad] recorded states (diagnostics)
   size_t trace_bytes = 0;

@@ -393,6 +393,7 @@ hipError_t settle_stream(pim_batch* b, hipStream_t s) {
 struct RunCtx {
   int T = 0, L = 0;
   bool real = false, mfma = false, seq = false;
+  bool f4 = false;  // the streamed kernel on e2m1 operands
   std::vector<int32_t> tgt;
   std::vector<float> tgtf;
 };
@@ -408,15 +409,19 @@ pim_status run_prepare(pim_batch* b, const pim_schedule* sc, hipStream_t s, RunC
     if (!sc->beta || !sc->eta) return fail(PIM_ERR_INVALID, "beta and eta must be non-NULL");
     if (sc->start_step < 0 || (int64_t)sc->start_step + sc->steps >= (int64_t)1 << 31)
       return fail(PIM_ERR_INVALID, "start_step + steps must lie in [0, 2^31)");
-    if (sc->kernel != PIM_KERNEL_MFMA_I8 && sc->kernel != PIM_KERNEL_PLAIN_F32 && sc->kernel != PIM_KERNEL_SEQ_I8)
+    if (sc->kernel != PIM_KERNEL_MFMA_I8 && sc->kernel != PIM_KERNEL_PLAIN_F32 && sc->kernel != PIM_KERNEL_SEQ_I8 &&
+        sc->kernel != PIM_KERNEL_MFMA_F4)
       return fail(PIM_ERR_INVALID, "unknown kernel %d", sc->kernel);
+    if (sc->kernel == PIM_KERNEL_MFMA_F4 && b->real)
+      return fail(PIM_ERR_UNSUPPORTED, "e2m1 operands take integer instances");
     if (sc->kernel == PIM_KERNEL_SEQ_I8 && b->real)
       return fail(PIM_ERR_UNSUPPORTED, "the sequential kernel takes integer instances");
     if (sc->record_states && (sc->kernel != PIM_KERNEL_MFMA_I8 || b->real))
       return fail(PIM_ERR_UNSUPPORTED, "state recording is implemented for the int8 MFMA kernel");
-    if (b->n > PIM_MAX_N_LDS && (sc->kernel != PIM_KERNEL_MFMA_I8 || sc->record_states))
-      return fail(PIM_ERR_UNSUPPORTED, "N = %d > %d runs only the int8 MFMA kernel, without state recording", b->n,
-                  PIM_MAX_N_LDS);
+    if (b->n > PIM_MAX_N_LDS &&
+        ((sc->kernel != PIM_KERNEL_MFMA_I8 && sc->kernel != PIM_KERNEL_MFMA_F4) || sc->record_states))
+      return fail(PIM_ERR_UNSUPPORTED, "N = %d > %d runs only the matrix-core kernels, without state recording",
+                  b->n, PIM_MAX_N_LDS);
     if (sc->use_target && !sc->target) return fail(PIM_ERR_INVALID, "use_target set without target energies");
     const int T = sc->steps;
     for (int t = 0; t < T; ++t)
@@ -446,7 +451,8 @@ pim_status run_prepare(pim_batch* b, const pim_schedule* sc, hipStream_t s, RunC
     // ---- compile ----
     std::vector<int32_t> steptab;
     const bool seq = sc->kernel == PIM_KERNEL_SEQ_I8;
-    const bool mfma = sc->kernel == PIM_KERNEL_MFMA_I8 || seq;  // both read the (u, s) tables
+    // the matrix-core and sequential kernels all read the (u, s) tables
+    const bool mfma = sc->kernel == PIM_KERNEL_MFMA_I8 || sc->kernel == PIM_KERNEL_MFMA_F4 || seq;
     const size_t entry = real ? 4 : 2;  // bytes per table entry
     const size_t thtab_need = mfma ? (size_t)ncls * T * kTabEntries * entry : 0;
     // the tables on the device already hold this schedule: nothing to compile
@@ -574,6 +580,7 @@ pim_status run_prepare(pim_batch* b, const pim_schedule* sc, hipStream_t s, RunC
     ctx.real = real;
     ctx.mfma = mfma;
     ctx.seq = seq;
+    ctx.f4 = sc->kernel == PIM_KERNEL_MFMA_F4 && b->d_jfrag4 && b->nt * 32 > PIM_MAX_N_LDS;
     ctx.tgt = std::move(tgt);
     ctx.tgtf = std::move(tgtf);
     return PIM_OK;
@@ -641,8 +648,13 @@ hipError_t run_launch(pim_batch* b, const pim_schedule* sc, uint64_t seed, const
       a.k1 = k1;
       a.waves = b->waves;
       a.count = b->count;
-      e = b->nt * 32 > PIM_MAX_N_LDS ? launch_sweep_big(a, b->count, b->nt, b->has_h, s)
-                                     : launch_sweep_mfma(a, b->count, b->nt, b->has_h, s);
+      if (ctx.f4) {
+        a.jfrag = reinterpret_cast<const int8_t*>(b->d_jfrag4);
+        e = launch_sweep_big4(a, b->count, b->nt, b->has_h, s);
+      } else {
+        e = b->nt * 32 > PIM_MAX_N_LDS ? launch_sweep_big(a, b->count, b->nt, b->has_h, s)
+                                       : launch_sweep_mfma(a, b->count, b->nt, b->has_h, s);
+      }
     } else if (mfma) {
       SweepRealArgs a{};
       a.jfrag = reinterpret_cast<const uint8_t*>(b->d_jfrag);
@@ -903,6 +915,8 @@ pim_status pim_create(const int8_t* J, const int32_t* h, const pim_params* param
     if (h)
       for (int i = 0; i < n; ++i) inst->has_h |= (h[i] != 0);
     inst->frag_bytes = (size_t)inst->nt * inst->nt * 1024;
+    // the streamed range also gets e2m1 fragments when every coupling is e2m1-exact
+    if (n > PIM_MAX_N_LDS && f4_couplings(J, (size_t)n * n)) inst->frag4_bytes = f4_frag_bytes(inst->nt);
     inst->jstride = (n + 3) & ~3;
     // device arena: fragments, FP32 J, h (built on the host in one block of
     // the same layout and uploaded by one copy), then the int8 J (copied
@@ -910,6 +924,8 @@ pim_status pim_create(const int8_t* J, const int32_t* h, const pim_params* param
     Carver cv;
     const size_t o_frag = cv.mark();
     cv.add(&inst->d_jfrag, inst->frag_bytes);
+    const size_t o_frag4 = cv.mark();
+    if (inst->frag4_bytes) cv.add(&inst->d_jfrag4, inst->frag4_bytes);
     const size_t o_jf = cv.mark();
     cv.add(&inst->d_jf32, (size_t)inst->npad * inst->jstride);
     const size_t o_h = cv.mark();
@@ -918,6 +934,7 @@ pim_status pim_create(const int8_t* J, const int32_t* h, const pim_params* param
     cv.add(&inst->d_j8, (size_t)n * n);
     std::vector<uint8_t> host(staged, 0);
     pack_mfma_fragments(J, n, inst->nt, reinterpret_cast<int8_t*>(host.data() + o_frag));
+    if (inst->frag4_bytes) pack_f4_fragments(J, n, inst->nt, host.data() + o_frag4);
     float* jf = reinterpret_cast<float*>(host.data() + o_jf);
     for (int i = 0; i < n; ++i)
       for (int j = 0; j < n; ++j) jf[(size_t)i * inst->jstride + j] = (float)J[(size_t)i * n + j];
@@ -982,6 +999,9 @@ pim_status pim_batch_create(pim_instance* const* insts, int32_t count, int32_t t
     b->real = insts[0]->rule.real;
     b->prec = insts[0]->prec;
     b->frag_bytes = insts[0]->frag_bytes;
+    b->frag4_bytes = insts[0]->frag4_bytes;
+    for (int k = 0; k < count; ++k)
+      if (!insts[k]->d_jfrag4) b->frag4_bytes = 0;  // e2m1 only when every instance has it
     b->stream = s;
     for (int k = 0; k < count; ++k) b->has_h |= insts[k]->has_h;
     // table classes: instances whose compiled tables coincide share one
@@ -1018,6 +1038,7 @@ pim_status pim_batch_create(pim_instance* const* insts, int32_t count, int32_t t
     cv.add(&b->d_scale, (size_t)count);
     const size_t tables = cv.mark();
     cv.add(&b->d_jfrag, frag * count);
+    if (b->frag4_bytes) cv.add(&b->d_jfrag4, b->frag4_bytes * count);
     cv.add(&b->d_h, (size_t)count * b->npad);
     cv.add(&b->d_final, cells * b->npad);
     cv.add(&b->d_best, cells * b->npad);
@@ -1055,6 +1076,9 @@ pim_status pim_batch_create(pim_instance* const* insts, int32_t count, int32_t t
     }
     for (int k = 0; k < count && e == hipSuccess; ++k) {
       e = hipMemcpyAsync(b->d_jfrag + frag * k, insts[k]->d_jfrag, frag, hipMemcpyDeviceToDevice, s);
+      if (e == hipSuccess && b->frag4_bytes)
+        e = hipMemcpyAsync(b->d_jfrag4 + b->frag4_bytes * k, insts[k]->d_jfrag4, b->frag4_bytes,
+                           hipMemcpyDeviceToDevice, s);
       const void* hsrc = b->real ? (const void*)insts[k]->d_hf : (const void*)insts[k]->d_h;
       if (e == hipSuccess)
         e = hipMemcpyAsync(b->d_h + (size_t)k * b->npad, hsrc, b->npad * 4, hipMemcpyDeviceToDevice, s);

@@ -1,0 +1,201 @@
+"""GPU parity of the streamed sweep on e2m1 (FP4) operands (N > 256, couplings
+in {0, +-1, +-2, +-3, +-4, +-6}) against the CPU oracle, bit for bit: the
+field is the same exact integer as in the int8 kernel, so final spins, best
+energy, its step and state, and the first hit must all equal the oracle's.
+Every case prints its name before touching the GPU."""
+import numpy as np
+import pytest
+
+import workloads as w
+from oracle import pimi
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"\n[gpu-case] {msg}", flush=True)
+
+
+def _oracle(J, h, c, beta, eta, seed, stream, trials, ztab, init=None, start=0, target=None):
+    prob = pimi.Problem(J, h, c=c, xi=0.5, levels=4, ztab=ztab)
+    return pimi.run_parallel(prob, beta, eta, seed, stream, np.asarray(trials), init=init, start_step=start,
+                             target=target)
+
+
+def _compare(got, ref, trials):
+    idx = np.asarray(trials)
+    np.testing.assert_array_equal(got["final"][idx], ref["final"].T.astype(np.int8))
+    np.testing.assert_array_equal(got["e_best"][idx], ref["e_best"].astype(np.float64))
+    np.testing.assert_array_equal(got["t_best"][idx], ref["t_best"])
+    np.testing.assert_array_equal(got["best_state"][idx], ref["best_state"].T.astype(np.int8))
+    np.testing.assert_array_equal(got["first_hit"][idx], ref["first_hit"])
+
+
+def _e2m1_instance(n, seed, index, values, hmax=0):
+    """Symmetric J with entries drawn from `values`, zero diagonal."""
+    rng = np.random.default_rng([seed, index, 77])
+    J = np.zeros((n, n), np.int8)
+    iu = np.triu_indices(n, 1)
+    J[iu] = rng.choice(np.asarray(values, np.int8), size=iu[0].size)
+    J = (J + J.T).astype(np.int8)
+    h = rng.integers(-hmax, hmax + 1, size=n).astype(np.int32) if hmax else np.zeros(n, np.int32)
+    return J, h
+
+
+def _run(pim, probs, trials, steps, kernel, seed, init=None, start=0, beta1=3.0):
+    ztab = w.gauss_table(8)
+    insts = [pim.Instance(J, h, j_scale=1 / np.sqrt(len(h)), xi=0.5, levels=4, noise_table=ztab, rng_stream=3 + k)
+             for k, (J, h) in enumerate(probs)]
+    beta = w.linear_beta(steps, 0.1, beta1)
+    eta = w.eta_sqrt_beta_over_5(beta)
+    targets = [int(pimi.energy(J, h, np.ones(len(h), dtype=np.int64))) - 1 for J, h in probs]
+    batch = pim.Batch(insts, trials, init_spins=init)
+    batch.run(beta, eta, seed=seed, kernel=kernel, target=targets, start_step=start)
+    return batch, beta, eta, targets, ztab
+
+
+CASES = [
+    # n, trials, steps, values, hmax
+    (257, 64, 60, (-1, 0, 1), 0),                  # nine row tiles: odd K-step count, padded half step
+    (300, 40, 50, (-1, 1), 5),                     # fields
+    (400, 64, 1, (-2, -1, 0, 1, 2), 0),            # a single step
+    (512, 33, 40, (-3, -1, 1, 3), 0),
+    (600, 130, 30, (-4, -2, 0, 2, 4), 3),          # three row tiles per wave; a mostly idle trial block
+    (777, 64, 30, (-6, -4, -3, -2, -1, 0, 1, 2, 3, 4, 6), 0),  # every e2m1 integer
+    (1000, 32, 30, (-1, 1), 0),
+    (1024, 70, 24, (-6, 6, -1, 1), 40),
+    (300, 1, 20, (-1, 0, 1), 1),                   # a single trial
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"{c[0]}-{c[1]}-{c[2]}-{len(c[3])}v-h{c[4]}")
+def test_f4_streamed_parity(gpu_lib, case):
+    n, trials, steps, values, hmax = case
+    _say(f"f4 streamed n={n} trials={trials} steps={steps} values={values} hmax={hmax}")
+    probs = [_e2m1_instance(n, 31, k, values, hmax) for k in range(2)]
+    batch, beta, eta, targets, ztab = _run(gpu_lib, probs, trials, steps, "f4", seed=13)
+    for k, (J, h) in enumerate(probs):
+        got = batch.trials_of(k)
+        ref = _oracle(J, h, 1 / np.sqrt(n), beta, eta, 13, 3 + k, np.arange(trials), ztab, target=targets[k])
+        _compare(got, ref, np.arange(trials))
+        e_all = pimi.energy(J, h, got["best_state"].T.astype(np.int64))
+        spins, e, trial, step = batch.best(k)
+        assert e == float(e_all.min()) and trial == int(np.argmin(e_all))
+    batch.close()
+
+
+def test_f4_equals_int8_and_initial_spins(gpu_lib):
+    """The same batch through both kernels, from caller spins: identical
+    results, and both equal to the oracle on sampled trials."""
+    _say("f4 vs int8, caller initial spins, n=800")
+    pim = gpu_lib
+    n, trials, steps = 800, 96, 40
+    probs = [w.sk1(n, seed=5, index=k) for k in range(3)]
+    init = np.random.default_rng(4).choice([-1, 1], size=(3, trials, n)).astype(np.int8)
+    b4, beta, eta, targets, ztab = _run(pim, probs, trials, steps, "f4", seed=9, init=init)
+    b8, *_ = _run(pim, probs, trials, steps, "mfma", seed=9, init=init)
+    for k, (J, h) in enumerate(probs):
+        g4, g8 = b4.trials_of(k), b8.trials_of(k)
+        for key in ("final", "e_best", "t_best", "best_state", "first_hit", "e_final"):
+            np.testing.assert_array_equal(g4[key], g8[key], err_msg=key)
+        tr = [0, 95] if k != 1 else [41]
+        ref = _oracle(J, h, 1 / np.sqrt(n), beta, eta, 9, 3 + k, tr, ztab, init=init[k][tr].T.astype(np.int64),
+                      target=targets[k])
+        _compare(g4, ref, tr)
+    b4.close()
+    b8.close()
+
+
+def test_f4_resume_equals_uninterrupted(gpu_lib):
+    _say("f4 resume 2 x 40 == 80, n=448")
+    pim = gpu_lib
+    n, R = 448, 64
+    J, h = w.sk1(n, seed=6)
+    ztab = w.gauss_table(8)
+    inst = pim.Instance(J, h, j_scale=1 / np.sqrt(n), xi=0.5, noise_table=ztab, rng_stream=2)
+    beta = w.linear_beta(80)
+    eta = w.eta_sqrt_beta_over_5(beta)
+    full = pim.Batch([inst], R).run(beta, eta, seed=3, kernel="f4").trials_of(0)
+    a = pim.Batch([inst], R).run(beta[:40], eta[:40], seed=3, kernel="f4").trials_of(0)
+    b = pim.Batch([inst], R, init_spins=a["final"][None]).run(beta[40:], eta[40:], seed=3, start_step=40,
+                                                              kernel="f4").trials_of(0)
+    np.testing.assert_array_equal(b["final"], full["final"])
+    np.testing.assert_array_equal(np.minimum(a["e_best"], b["e_best"]), full["e_best"])
+
+
+def test_f4_ineligible_couplings_fall_back(gpu_lib):
+    """A coupling of 5 has no exact e2m1 code: the batch runs the int8 kernel
+    and still equals the oracle."""
+    _say("f4 request with |J| = 5: int8 kernel, n=300")
+    n, trials, steps = 300, 32, 30
+    probs = [_e2m1_instance(n, 8, k, (-5, -1, 1, 5)) for k in range(2)]
+    batch, beta, eta, targets, ztab = _run(gpu_lib, probs, trials, steps, "f4", seed=4)
+    for k, (J, h) in enumerate(probs):
+        ref = _oracle(J, h, 1 / np.sqrt(n), beta, eta, 4, 3 + k, np.arange(trials), ztab, target=targets[k])
+        _compare(batch.trials_of(k), ref, np.arange(trials))
+    batch.close()
+
+
+def test_f4_mixed_sizes_graph(gpu_lib):
+    """Uneven N in one graph launch with the e2m1 kernel: parts with N <= 256
+    run the int8 LDS kernel, the others the e2m1 streamed kernel."""
+    _say("f4 mixed small/large N graph")
+    pim = gpu_lib
+    ns = [100, 400, 200, 1000, 800]
+    trials, steps = 48, 40
+    probs = [w.sk1(n, seed=21, index=k) for k, n in enumerate(ns)]
+    ztab = w.gauss_table(8)
+    insts = [pim.Instance(J, h, j_scale=1 / np.sqrt(len(h)), xi=0.5, noise_table=ztab, rng_stream=k)
+             for k, (J, h) in enumerate(probs)]
+    beta = w.linear_beta(steps, 0.1, 3.0)
+    eta = w.eta_sqrt_beta_over_5(beta)
+    batch = pim.Batch(insts, trials).run(beta, eta, seed=2, kernel="f4")
+    for k, (J, h) in enumerate(probs):
+        ref = _oracle(J, h, 1 / np.sqrt(len(h)), beta, eta, 2, k, np.arange(trials), ztab)
+        _compare(batch.trials_of(k), ref, np.arange(trials))
+    batch.close()
+
+
+def test_f4_cancel_reports_partial_results(gpu_lib):
+    _say("f4 cancel, n=300")
+    pim = gpu_lib
+    n, R = 300, 64
+    J, h = w.sk1(n, seed=2)
+    inst = pim.Instance(J, h, j_scale=1 / np.sqrt(n), xi=0.5)
+    batch = pim.Batch([inst], R)
+    T = 100000
+    beta = np.full(T, 1.0)
+    batch.run(beta, np.full(T, 0.4), seed=1, kernel="f4")
+    batch.cancel()
+    with pytest.raises(pim.PimError) as ei:
+        batch.trials_of(0)
+    assert ei.value.status == pim.PIM_ERR_CANCELLED
+    batch.run(beta[:50], np.full(50, 0.4), seed=1, kernel="f4")
+    batch.trials_of(0)
+
+
+def test_f4_full_size_n1000_sampled(gpu_lib):
+    """N = 1000 SK-1, 32 instances x 1024 trials x 400 steps: the launch the
+    benchmark's large-N leg times.  Sampled trials of four instances are
+    recomputed by the oracle in full; every trial's tracked best energy equals
+    the Eq. (1) energy of its returned state."""
+    _say("f4 n=1000 32x1024x400, sampled oracle trials")
+    pim = gpu_lib
+    n, R, T, count = 1000, 1024, 400, 32
+    probs = [w.sk1(n, seed=3, index=k) for k in range(count)]
+    ztab = w.gauss_table(8)
+    insts = [pim.Instance(J, h, j_scale=1 / np.sqrt(n), xi=0.5, noise_table=ztab, rng_stream=k)
+             for k, (J, h) in enumerate(probs)]
+    beta = w.linear_beta(T, 0.1, 3.0)
+    eta = w.eta_sqrt_beta_over_5(beta)
+    batch = pim.Batch(insts, R).run(beta, eta, seed=8, kernel="f4")
+    for k, trials in ((0, [0]), (9, [1023]), (17, [500]), (31, [127, 128])):
+        J, h = probs[k]
+        ref = _oracle(J, h, 1 / np.sqrt(n), beta, eta, 8, k, trials, ztab)
+        _compare(batch.trials_of(k), ref, trials)
+    for k in range(0, count, 5):
+        J, h = probs[k]
+        got = batch.trials_of(k)
+        S = got["best_state"].T.astype(np.int64)
+        np.testing.assert_array_equal(pimi.energy_from_field(pimi.local_field(J, h, S), h, S), got["e_best"])
+    batch.close()
