@@ -37,6 +37,7 @@ sys.path.insert(0, ROOT)
 os.environ["GPU_MAX_HW_QUEUES"] = "16"
 
 INT8_MFMA_PEAK = 5.0e15            # dense int8 MFMA, ops/s (MI355X)
+FP4_MFMA_PEAK = 10.1e15           # dense FP4 (e2m1) MFMA, ops/s (MI355X)
 # 32-bit VALU lane-ops/s: CUs x SIMDs x 32 lanes per clock x clock, i.e. the published FP32 vector
 # rate (157.3 TFLOP/s) with a fused multiply-add counted as one lane-op
 VALU_PEAK = 256 * 4 * 32 * 2.4e9
@@ -53,7 +54,8 @@ def parse():
     ap.add_argument("--trials", type=int, default=1024)
     ap.add_argument("--sweeps", type=int, default=10000, help="update steps T per trial")
     ap.add_argument("--n", type=int, default=200)
-    ap.add_argument("--kernel", default="mfma", choices=["mfma", "plain"])
+    ap.add_argument("--kernel", default="mfma", choices=["mfma", "plain", "f4"],
+                    help="mfma: int8 operands; f4: e2m1 (FP4) operands where N > 256 (exact for J = +-1)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-trials", type=int, default=512)
     ap.add_argument("--cpu-steps", type=int, default=2000)
@@ -390,8 +392,11 @@ def uneven_leg(args):
     1000][k mod 5], J = +-1, h = 0, c = 1/sqrt(N_k), xi = 0.5, 1024 replicas
     each, beta linear 0.1 -> 3.0 with eta = sqrt(beta / 5).  All instances run
     in one batch: one part per N, launched together as one captured graph.
-    Also each N bucket alone, for per-N rates and the int8 MFMA fraction
-    (2 N^2 ops per replica-step)."""
+    Parts with N > 256 run on e2m1 (FP4) operands (J = +-1 is exact in e2m1,
+    results identical to int8); the same graph on int8 operands is timed
+    beside it and must give identical results.  Also each N bucket alone, for
+    per-N rates and MFMA fractions (2 N^2 ops per replica-step, against the
+    int8 peak and, for e2m1 buckets, the FP4 peak)."""
     import paper_2604_17109_amd as pim
     import workloads as w
     sizes = [100, 200, 400, 800, 1000]
@@ -408,14 +413,25 @@ def uneven_leg(args):
     e_sa = sa_reference_uneven(ns, 9)
     ref = [min(a, b) for a, b in zip(gpu, e_sa)] if e_sa else gpu
     tgt = [math.floor(0.999 * r) for r in ref]
-    batch.run(beta, eta, seed=2, target=tgt)
+    batch.run(beta, eta, seed=2, target=tgt, kernel="mfma")
+    k8 = batch.kernel_ms()
+    res8 = [batch.trials_of(k, spins=False) for k in range(count)]
+    batch.run(beta, eta, seed=2, target=tgt, kernel="f4")
     kms = batch.kernel_ms()
+    res4 = [batch.trials_of(k, spins=False) for k in range(count)]
+    same = all(np.array_equal(a[key], b[key]) for a, b in zip(res4, res8)
+               for key in ("e_best", "t_best", "first_hit", "e_final"))
     updates = float(sum(ns)) * R * T
     ops = float(sum(2 * n * n for n in ns)) * R * (T + 1)
-    hits = [(batch.trials_of(k, spins=False)["first_hit"] >= 0).mean() for k in range(count)]
+    hits = [(r["first_hit"] >= 0).mean() for r in res4]
     out = {"workload": f"{count} SK-1 instances, N in {sizes}, {R} replicas x {T} steps, one graph launch",
+           "kernel": "int8 MFMA for N <= 256 (couplings in LDS), e2m1 (FP4) MFMA for N > 256 (streamed)",
            "kernel_ms": kms, "spin_updates_per_s": updates / (kms / 1e3),
-           "int8_mfma_frac": ops / (kms / 1e3) / INT8_MFMA_PEAK, "waves_per_workgroup": dict(zip(map(str, sizes), waves)),
+           "int8_mfma_frac": ops / (kms / 1e3) / INT8_MFMA_PEAK,
+           "int8_operands": {"kernel_ms": k8, "spin_updates_per_s": updates / (k8 / 1e3),
+                             "int8_mfma_frac": ops / (k8 / 1e3) / INT8_MFMA_PEAK},
+           "identical_to_int8_operands": bool(same),
+           "waves_per_workgroup": dict(zip(map(str, sizes), waves)),
            "p_bar_relaxed": float(np.mean(hits)),
            "criterion": ("E <= floor(0.999 * min(simulated-annealing reference, best of the warm-up run))" if e_sa
                          else "E <= floor(0.999 * best of the warm-up run)"), "per_n": {}}
@@ -424,8 +440,13 @@ def uneven_leg(args):
         sub = [i for i, m in zip(insts, ns) if m == n]
         sub_tgt = [t for t, m in zip(tgt, ns) if m == n]
         b = pim.Batch(sub, R)
-        b.run(beta, eta, seed=2)
-        b.run(beta, eta, seed=2, target=sub_tgt)
+        big = n > 256
+        if big:
+            b.run(beta, eta, seed=2, kernel="mfma")
+            b.run(beta, eta, seed=2, target=sub_tgt, kernel="mfma")
+            k8n = b.kernel_ms()
+        b.run(beta, eta, seed=2, kernel="f4")
+        b.run(beta, eta, seed=2, target=sub_tgt, kernel="f4")
         k = b.kernel_ms()
         u = float(len(sub)) * n * R * T
         o = 2.0 * n * n * len(sub) * R * (T + 1)
@@ -436,7 +457,12 @@ def uneven_leg(args):
         tau = (k / 1e3) / (len(sub) * R * T)
         out["per_n"][str(n)] = {"instances": len(sub), "kernel_ms": k, "spin_updates_per_s": u / (k / 1e3),
                                 "int8_mfma_frac": o / (k / 1e3) / INT8_MFMA_PEAK, "p_bar_relaxed": p,
-                                "n99": n99, "tts99_s": n99 * T * tau if n99 else None}
+                                "n99": n99, "tts99_s": n99 * T * tau if n99 else None,
+                                "operands": "e2m1" if big else "int8"}
+        if big:
+            out["per_n"][str(n)]["fp4_mfma_frac"] = o / (k / 1e3) / FP4_MFMA_PEAK
+            out["per_n"][str(n)]["int8_operands"] = {"kernel_ms": k8n, "spin_updates_per_s": u / (k8n / 1e3),
+                                                     "int8_mfma_frac": o / (k8n / 1e3) / INT8_MFMA_PEAK}
         if e_sa:
             out["per_n"][str(n)]["reference"] = reference_summary([g for g, m in zip(gpu, ns) if m == n],
                                                                   [a for a, m in zip(e_sa, ns) if m == n])
@@ -845,7 +871,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "i8",
+        "dtype": "fp4" if (args.kernel == "f4" and n > 256) else "i8",
         "data": "synthetic",
         "config": {"workload": f"SK-1 N={n}, {I} instances x {R} trials x {T} steps, kernel {args.kernel}",
                    "instances": I, "trials": R, "steps_per_trial": T, "n": n, "parallelism": "single GPU"},
@@ -868,6 +894,9 @@ def main():
                      "algorithmic_per_update": alu_per_update},
         "roofline_mfma": {"bound": "mfma", "achieved": mfma_ops / kernel_s / 1e12, "peak": INT8_MFMA_PEAK / 1e12,
                           "unit": "TOP/s", "frac": mfma_ops / kernel_s / INT8_MFMA_PEAK},
+        "roofline_fp4": ({"bound": "mfma", "achieved": mfma_ops / kernel_s / 1e12, "peak": FP4_MFMA_PEAK / 1e12,
+                          "unit": "TOP/s", "frac": mfma_ops / kernel_s / FP4_MFMA_PEAK}
+                         if args.kernel == "f4" and n > 256 else None),
         "lds": ({"achieved": lds_bytes / kernel_s / 1e9, "peak": LDS_PEAK / 1e9, "unit": "GB/s",
                  "frac": lds_bytes / kernel_s / LDS_PEAK, "bytes_per_wave_step": lds_per_wave_step}
                 if args.kernel == "mfma" and n <= 256 else None),

@@ -195,6 +195,24 @@ int big_tiles(int n);  // row tiles of the streamed kernel: ceil(n / 32)
 // The same range on e2m1 (FP4) operands, for couplings in {0, +-1, +-2, +-3,
 // +-4, +-6} (exact): a.jfrag holds pack_f4_fragments output.
 hipError_t launch_sweep_big4(const SweepArgs& a, int count, int nt, bool has_h, hipStream_t s);
+// Several e2m1 batches (parts) in one launch: parts[p] holds part p's
+// arguments and row tile count; work[b] = (part, instance, trial block, 0),
+// or part -1 for an empty workgroup.  LDS is sized for the largest tile
+// count.  With has_h every part's a.h is non-null (zeros where a part has no
+// fields).
+// The run's scalars (seed words, steps, first counter step, whether targets
+// are tracked) replace those in the parts' arguments.
+struct Big4Part {
+  SweepArgs a;
+  int32_t nt, pad[3];
+};
+struct Big4Run {
+  uint32_t k0, k1;
+  int32_t T, start_step, use_target;
+};
+hipError_t launch_sweep_big4_multi(const Big4Part* d_parts, const int4* d_work, int nwork, int nt_max, bool has_h,
+                                   const Big4Run& run, hipStream_t s);
+double big4_step_cost(int nt);  // relative workgroup time per step, for ordering work
 bool f4_couplings(const int8_t* J, size_t count);  // every value e2m1-exact
 size_t f4_frag_bytes(int nt);                      // per instance: nt x ceil(nt/2) fragments of 1 KB
 void pack_f4_fragments(const int8_t* J, int n, int nt, uint8_t* out);
@@ -346,6 +364,11 @@ struct pim_batch {
   hipStream_t cap = nullptr;           // capture stream
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
+  // e2m1 parts run as one launch: part arguments then the work list on the
+  // device, and the host copy last uploaded (re-uploaded only when it changes)
+  uint8_t* d_multi = nullptr;
+  size_t multi_cap = 0;
+  std::vector<uint8_t> h_multi;
   // run state
   bool ran = false, reranked = false, sticky_error = false;
   int last_T = 0, last_start = 0;

@@ -225,6 +225,7 @@ void free_batch_buffers(pim_batch* b) {
   if (b->graph) (void)hipGraphDestroy(b->graph);
   hipStream_t s = b->stream;
   dev_free(b->d_arena, s);  // the fixed-size buffers, carved at creation
+  dev_free(b->d_multi, s);
   dev_free(b->d_j8pad, s);
   dev_free(b->d_trace, s);
   dev_free(b->d_thtab, s);
@@ -587,6 +588,37 @@ pim_status run_prepare(pim_batch* b, const pim_schedule* sc, hipStream_t s, RunC
   }
 }
 
+// Arguments of the integer matrix-core sweep of a simple batch.
+SweepArgs int_sweep_args(pim_batch* b, const pim_schedule* sc, uint64_t seed, int T) {
+  SweepArgs a{};
+  a.jfrag = b->d_jfrag;
+  a.trace = sc->record_states ? b->d_trace : nullptr;
+  a.h = b->has_h ? b->d_h : nullptr;
+  a.thtab = static_cast<const int16_t*>(b->d_thtab);
+  a.inst_class = b->d_class;
+  a.inst_stream = b->d_stream_ids;
+  a.target = sc->use_target ? b->d_target : nullptr;
+  a.init = b->d_init;
+  a.final_s = b->d_final;
+  a.best_s = b->d_best;
+  a.e_best = stat_ptr(b, 0);
+  a.t_best = stat_ptr(b, 1);
+  a.first_hit = stat_ptr(b, 2);
+  a.e_final = stat_ptr(b, 3);
+  a.steps_done = stat_ptr(b, 4);
+  a.cancel = b->d_cancel;
+  a.n = b->n;
+  a.npad = b->npad;
+  a.R = b->R;
+  a.T = T;
+  a.start_step = sc->start_step;
+  a.k0 = (uint32_t)seed;
+  a.k1 = (uint32_t)(seed >> 32);
+  a.waves = b->waves;
+  a.count = b->count;
+  return a;
+}
+
 // Launches the prepared run of a simple batch on stream s (asynchronous).
 hipError_t run_launch(pim_batch* b, const pim_schedule* sc, uint64_t seed, const RunCtx& ctx, hipStream_t s) {
   {
@@ -622,32 +654,7 @@ hipError_t run_launch(pim_batch* b, const pim_schedule* sc, uint64_t seed, const
       a.k1 = k1;
       e = launch_sweep_seq(a, b->count, b->nt, b->has_h, s);
     } else if (mfma && !real) {
-      SweepArgs a{};
-      a.jfrag = b->d_jfrag;
-      a.trace = sc->record_states ? b->d_trace : nullptr;
-      a.h = b->has_h ? b->d_h : nullptr;
-      a.thtab = static_cast<const int16_t*>(b->d_thtab);
-      a.inst_class = b->d_class;
-      a.inst_stream = b->d_stream_ids;
-      a.target = sc->use_target ? b->d_target : nullptr;
-      a.init = b->d_init;
-      a.final_s = b->d_final;
-      a.best_s = b->d_best;
-      a.e_best = stat_ptr(b, 0);
-      a.t_best = stat_ptr(b, 1);
-      a.first_hit = stat_ptr(b, 2);
-      a.e_final = stat_ptr(b, 3);
-      a.steps_done = stat_ptr(b, 4);
-      a.cancel = b->d_cancel;
-      a.n = b->n;
-      a.npad = b->npad;
-      a.R = b->R;
-      a.T = T;
-      a.start_step = sc->start_step;
-      a.k0 = k0;
-      a.k1 = k1;
-      a.waves = b->waves;
-      a.count = b->count;
+      SweepArgs a = int_sweep_args(b, sc, seed, T);
       if (ctx.f4) {
         a.jfrag = reinterpret_cast<const int8_t*>(b->d_jfrag4);
         e = launch_sweep_big4(a, b->count, b->nt, b->has_h, s);
@@ -720,6 +727,86 @@ hipError_t run_launch(pim_batch* b, const pim_schedule* sc, uint64_t seed, const
 }
 
 // Run-state bookkeeping after a successful launch.
+// Parts mp of composite b that run on e2m1 operands, as one launch: each
+// instance's trial blocks stay on one XCD (workgroups 8k + x run on XCD x),
+// instances go to the least-loaded XCD longest first, and each XCD takes its
+// workgroups longest first, so short ones fill in behind long ones instead of
+// the parts' launches sharing the CUs among themselves.  The part arguments
+// and the work list are uploaded when they differ from the last upload (after
+// the batch's previous run, which may still read them).
+pim_status stage_multi(pim_batch* b, const std::vector<pim_schedule>& psc, uint64_t seed, int T,
+                       const std::vector<size_t>& mp, hipStream_t s, const Big4Part** d_parts, const int4** d_work,
+                       int* nwork, int* nt_max, bool* has_h) {
+  constexpr int kX = 8;
+  std::vector<Big4Part> parts(mp.size());
+  struct Item {
+    int part, inst, bpi;
+    double cost;
+  };
+  std::vector<Item> items;
+  *nt_max = 0;
+  *has_h = false;
+  for (size_t i : mp) *has_h |= b->parts[i]->has_h;
+  for (size_t i = 0; i < mp.size(); ++i) {
+    pim_batch* pb = b->parts[mp[i]];
+    std::memset(&parts[i], 0, sizeof(Big4Part));
+    parts[i].a = int_sweep_args(pb, &psc[mp[i]], seed, T);
+    parts[i].a.jfrag = reinterpret_cast<const int8_t*>(pb->d_jfrag4);
+    parts[i].a.h = *has_h ? pb->d_h : nullptr;  // zeros for instances without fields
+    parts[i].a.target = pb->d_target;     // the launch drops it when targets are off
+    parts[i].a.k0 = parts[i].a.k1 = 0;    // per run: kernel arguments
+    parts[i].a.T = parts[i].a.start_step = 0;
+    parts[i].nt = pb->nt;
+    *nt_max = std::max(*nt_max, pb->nt);
+    const int bpi = (pb->R + 127) / 128;
+    const double c = big4_step_cost(pb->nt);
+    for (int k = 0; k < pb->count; ++k) items.push_back({(int)i, k, bpi, c});
+  }
+  std::stable_sort(items.begin(), items.end(), [](const Item& x, const Item& y) { return x.cost > y.cost; });
+  std::vector<std::vector<int4>> lists(kX);
+  std::vector<double> load(kX, 0.0);
+  for (const Item& it : items) {
+    const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    load[x] += it.bpi * it.cost;
+    for (int t = 0; t < it.bpi; ++t) lists[x].push_back(int4{it.part, it.inst, t, 0});
+  }
+  size_t depth = 0;
+  for (const auto& l : lists) depth = std::max(depth, l.size());
+  std::vector<int4> work(depth * kX, int4{-1, 0, 0, 0});
+  for (int x = 0; x < kX; ++x)
+    for (size_t k = 0; k < lists[x].size(); ++k) work[k * kX + x] = lists[x][k];
+  const size_t pbytes = (parts.size() * sizeof(Big4Part) + 255) & ~(size_t)255;
+  const size_t bytes = pbytes + work.size() * sizeof(int4);
+  std::vector<uint8_t> host(bytes, 0);
+  std::memcpy(host.data(), parts.data(), parts.size() * sizeof(Big4Part));
+  std::memcpy(host.data() + pbytes, work.data(), work.size() * sizeof(int4));
+  auto device_fail = [&](hipError_t e, const char* what) {
+    b->sticky_error = true;
+    return fail(PIM_ERR_DEVICE, "%s failed: %s", what, hipGetErrorString(e));
+  };
+  if (host != b->h_multi) {
+    hipError_t e = wait_last_run(b);
+    if (e != hipSuccess) return device_fail(e, "waiting for the previous run");
+    if (bytes > b->multi_cap) {
+      dev_free(b->d_multi, s);
+      b->d_multi = static_cast<uint8_t*>(dev_alloc(bytes, s));
+      b->multi_cap = b->d_multi ? bytes : 0;
+      if (!b->d_multi) return fail(PIM_ERR_NOMEM, "device allocation of %zu bytes failed", bytes);
+    }
+    e = hipMemcpyAsync(b->d_multi, host.data(), bytes, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);  // the host copy goes out of scope
+    if (e != hipSuccess) {
+      b->h_multi.clear();
+      return device_fail(e, "work list upload");
+    }
+    b->h_multi.swap(host);
+  }
+  *d_parts = reinterpret_cast<const Big4Part*>(b->d_multi);
+  *d_work = reinterpret_cast<const int4*>(b->d_multi + pbytes);
+  *nwork = (int)work.size();
+  return PIM_OK;
+}
+
 void run_mark(pim_batch* b, const pim_schedule* sc) {
   {
     const int T = sc->steps;
@@ -1163,6 +1250,21 @@ pim_status pim_run(pim_batch* b, const pim_schedule* sc, uint64_t seed, void* st
       pim_status st = run_prepare(b->parts[p], &psc[p], s, ctx[p]);
       if (st != PIM_OK) return st;
     }
+    // e2m1 parts: one launch over a longest-first work list
+    std::vector<char> in_multi(P, 0);
+    std::vector<size_t> mp;
+    for (size_t p = 0; p < P; ++p)
+      if (ctx[p].f4) mp.push_back(p);
+    const Big4Part* d_parts = nullptr;
+    const int4* d_work = nullptr;
+    int nwork = 0, nt_max = 0;
+    bool multi_h = false;
+    if (mp.size() >= 2) {
+      pim_status st = stage_multi(b, psc, seed, ctx[0].T, mp, s, &d_parts, &d_work, &nwork, &nt_max, &multi_h);
+      if (st != PIM_OK) return st;
+      for (size_t p : mp) in_multi[p] = 1;
+    }
+    const Big4Run run{(uint32_t)seed, (uint32_t)(seed >> 32), ctx[0].T, sc->start_step, sc->use_target ? 1 : 0};
     if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     b->gexec = nullptr;
@@ -1172,9 +1274,19 @@ pim_status pim_run(pim_batch* b, const pim_schedule* sc, uint64_t seed, void* st
     if (e == hipSuccess) e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
       hipError_t ce = hipEventRecord(b->fork_ev, b->cap);
-      for (size_t p = 0; p < P && ce == hipSuccess; ++p) {
+      // the one launch of the e2m1 parts first: its longest workgroups take
+      // the CUs before the small parts' launches are dispatched
+      std::vector<size_t> order;
+      if (nwork > 0) order.push_back(mp[0]);
+      for (size_t p = 0; p < P; ++p)
+        if (!in_multi[p]) order.push_back(p);
+      for (size_t i = 0; i < order.size() && ce == hipSuccess; ++i) {
+        const size_t p = order[i];
+        const bool multi_head = nwork > 0 && p == mp[0];
         ce = hipStreamWaitEvent(b->fork[p], b->fork_ev, 0);
-        if (ce == hipSuccess) ce = run_launch(b->parts[p], &psc[p], seed, ctx[p], b->fork[p]);
+        if (ce == hipSuccess)
+          ce = multi_head ? launch_sweep_big4_multi(d_parts, d_work, nwork, nt_max, multi_h, run, b->fork[p])
+                          : run_launch(b->parts[p], &psc[p], seed, ctx[p], b->fork[p]);
         if (ce == hipSuccess) ce = hipEventRecord(b->join[p], b->fork[p]);
         if (ce == hipSuccess) ce = hipStreamWaitEvent(b->cap, b->join[p], 0);
       }

@@ -236,8 +236,9 @@ __device__ __forceinline__ void stage_table(int16_t* dst, uint4 v, int lane) {
   reinterpret_cast<uint4*>(dst)[lane] = v;
 }
 
+// One workgroup's run: trial block tblk (128 trials) of instance inst.
 template <int RPW, bool HAS_H>
-__global__ __launch_bounds__(64 * kWaves, 2) void sweep_big4_kernel(SweepArgs a, int nt, int blocks_per_inst) {
+__device__ __forceinline__ void big4_body(const SweepArgs& a, int nt, int inst, int tblk) {
   extern __shared__ __align__(16) unsigned char lds[];
   const int npad = nt * 32;
   const int np = (nt + 1) >> 1;  // K steps of 64 spins
@@ -253,12 +254,6 @@ __global__ __launch_bounds__(64 * kWaves, 2) void sweep_big4_kernel(SweepArgs a,
   int32_t* sFlag = sStat + 3 * kCB * 32;
   int32_t* sH = sFlag + 4;
 
-  // workgroup -> (instance, trial block): the blocks of instance k all have
-  // linear ids congruent to k modulo the XCD count
-  const int lin = blockIdx.x;
-  const int inst = (lin % kXcds) + kXcds * ((lin / kXcds) / blocks_per_inst);
-  const int tblk = (lin / kXcds) % blocks_per_inst;
-  if (inst >= a.count) return;  // whole workgroup: before any barrier
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   const int col = lane & 31;
@@ -435,6 +430,38 @@ __global__ __launch_bounds__(64 * kWaves, 2) void sweep_big4_kernel(SweepArgs a,
   }
 }
 
+template <int RPW, bool HAS_H>
+__global__ __launch_bounds__(64 * kWaves, 2) void sweep_big4_kernel(SweepArgs a, int nt, int blocks_per_inst) {
+  // workgroup -> (instance, trial block): the blocks of instance k all have
+  // linear ids congruent to k modulo the XCD count (hardware dispatch sends
+  // consecutive workgroups to consecutive XCDs), so they share one L2
+  const int lin = blockIdx.x;
+  const int inst = (lin % kXcds) + kXcds * ((lin / kXcds) / blocks_per_inst);
+  const int tblk = (lin / kXcds) % blocks_per_inst;
+  if (inst >= a.count) return;  // whole workgroup: before any barrier
+  big4_body<RPW, HAS_H>(a, nt, inst, tblk);
+}
+
+// Several batches of different N in one launch: workgroup b runs work item
+// work[b] = (part, instance, trial block) with that part's arguments.  The
+// host orders the items so that workgroups 8k + x all run on XCD x, each
+// instance's blocks on one XCD, and each XCD's items longest first.
+template <bool HAS_H>
+__global__ __launch_bounds__(64 * kWaves, 2) void sweep_big4_multi_kernel(const Big4Part* parts, const int4* work,
+                                                                          int nwork, Big4Run run) {
+  if ((int)blockIdx.x >= nwork) return;
+  const int4 item = work[blockIdx.x];
+  if (item.x < 0) return;  // padding item: whole workgroup, before any barrier
+  SweepArgs a = parts[item.x].a;
+  const int nt = parts[item.x].nt;
+  a.k0 = run.k0;
+  a.k1 = run.k1;
+  a.T = run.T;
+  a.start_step = run.start_step;
+  if (!run.use_target) a.target = nullptr;
+  big4_body<kMaxTiles / kWaves, HAS_H>(a, nt, item.y, item.z);
+}
+
 size_t big4_lds_bytes(int nt, bool has_h) {
   const size_t np = (size_t)(nt + 1) / 2;
   return 2 * np * kCB * 1024 + 2 * kTabBytes + (size_t)(2 * kWaves + 3) * kCB * 32 * 4 + 16 +
@@ -514,6 +541,39 @@ void pack_f4_fragments(const int8_t* J, int n, int nt, uint8_t* out) {
           dst[e >> 1] |= (uint8_t)(e2m1_code(v) << (4 * (e & 1)));
         }
       }
+}
+
+template <bool HAS_H>
+hipError_t launch_multi(const Big4Part* d_parts, const int4* d_work, int nwork, int nt_max, const Big4Run& run,
+                        hipStream_t s) {
+  const size_t lds = big4_lds_bytes(nt_max, HAS_H);
+  auto kern = sweep_big4_multi_kernel<HAS_H>;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kern, dim3((unsigned)nwork), dim3(64 * kWaves), lds, s, d_parts, d_work, nwork, run);
+  return hipGetLastError();
+}
+
+hipError_t launch_sweep_big4_multi(const Big4Part* d_parts, const int4* d_work, int nwork, int nt_max, bool has_h,
+                                   const Big4Run& run, hipStream_t s) {
+  if (nwork < 1 || nt_max < kMinTiles || nt_max > kMaxTiles) return hipErrorInvalidValue;
+  return has_h ? launch_multi<true>(d_parts, d_work, nwork, nt_max, run, s)
+               : launch_multi<false>(d_parts, d_work, nwork, nt_max, run, s);
+}
+
+// Relative time of one workgroup-step at nt row tiles: the waves of a SIMD
+// (w and w + 4) run their tiles' contractions (4 MFMAs per tile and K step)
+// and decisions (4 blocks of 16 per tile) one after the other, and the
+// workgroup waits at every step for its busiest SIMD.
+double big4_step_cost(int nt) {
+  const int np = (nt + 1) / 2;
+  int simd_tiles = 0;
+  for (int w = 0; w < kWaves / 2; ++w) {
+    const int t = (nt - w + kWaves - 1) / kWaves + (nt - w - kWaves / 2 + kWaves - 1) / kWaves;
+    simd_tiles = t > simd_tiles ? t : simd_tiles;
+  }
+  return simd_tiles * (128.0 * np + 2660.0) + 3000.0;
 }
 
 hipError_t launch_sweep_big4(const SweepArgs& a, int count, int nt, bool has_h, hipStream_t s) {

@@ -199,3 +199,73 @@ def test_f4_full_size_n1000_sampled(gpu_lib):
         S = got["best_state"].T.astype(np.int64)
         np.testing.assert_array_equal(pimi.energy_from_field(pimi.local_field(J, h, S), h, S), got["e_best"])
     batch.close()
+
+
+def test_f4_one_launch_for_all_parts(gpu_lib):
+    """Several e2m1 parts of an uneven batch run as one launch over a work
+    list: partial trial blocks (200 trials), parts with and without fields,
+    odd tile counts, and repeated runs that change the seed (the list is
+    uploaded again) or keep it (reused); each result equals the oracle, and
+    the third run equals the first."""
+    _say("f4 one launch over parts, 200 trials, fields")
+    pim = gpu_lib
+    ns = [300, 520, 300, 1000, 700, 130, 520]
+    trials, steps = 200, 24
+    ztab = w.gauss_table(8)
+    probs = []
+    for k, n in enumerate(ns):
+        probs.append(_e2m1_instance(n, 17, k, (-2, -1, 0, 1, 2), hmax=3 if k % 3 == 1 else 0))
+    insts = [pim.Instance(J, h, j_scale=1 / np.sqrt(len(h)), xi=0.5, noise_table=ztab, rng_stream=40 + k)
+             for k, (J, h) in enumerate(probs)]
+    beta = w.linear_beta(steps, 0.1, 3.0)
+    eta = w.eta_sqrt_beta_over_5(beta)
+    batch = pim.Batch(insts, trials)
+    first = None
+    for run, seed in enumerate((2, 5, 2)):
+        batch.run(beta, eta, seed=seed, kernel="f4")
+        got = [batch.trials_of(k) for k in range(len(ns))]
+        if run == 0:
+            first = got
+        if run < 2:
+            for k, (J, h) in enumerate(probs):
+                tr = np.arange(trials) if ns[k] <= 520 else np.array([0, 127, 128, 199])
+                ref = _oracle(J, h, 1 / np.sqrt(len(h)), beta, eta, seed, 40 + k, tr, ztab)
+                _compare(got[k], ref, tr)
+        else:
+            for a, b in zip(first, got):
+                for key in ("final", "e_best", "t_best", "best_state"):
+                    np.testing.assert_array_equal(a[key], b[key])
+    batch.close()
+
+
+def test_f4_full_size_uneven_batch_sampled(gpu_lib):
+    """The benchmark's uneven-N workload as it times it: 128 SK-1 instances,
+    N_k = [100, 200, 400, 800, 1000][k mod 5], 1024 trials, here 2000 steps,
+    one graph launch, e2m1 operands for N > 256 (one launch over all those
+    parts), with first-hit targets.  Every trial equals the int8-operand run;
+    sampled trials of six instances (every N) equal the oracle."""
+    _say("f4 uneven N 128x1024x2000 graph, vs int8 and sampled oracle trials")
+    pim = gpu_lib
+    sizes = [100, 200, 400, 800, 1000]
+    count, R, T = 128, 1024, 2000
+    ns = [sizes[k % 5] for k in range(count)]
+    ztab = w.gauss_table(8)
+    probs = [w.sk1(ns[k], seed=9, index=k) for k in range(count)]
+    insts = [pim.Instance(J, h, j_scale=1 / np.sqrt(ns[k]), xi=0.5, noise_table=ztab, rng_stream=k)
+             for k, (J, h) in enumerate(probs)]
+    beta = w.linear_beta(T, 0.1, 3.0)
+    eta = w.eta_sqrt_beta_over_5(beta)
+    tgt = [float(np.floor(-0.7 * n ** 1.5)) for n in ns]
+    batch = pim.Batch(insts, R)
+    batch.run(beta, eta, seed=2, target=tgt, kernel="mfma")
+    i8 = [batch.trials_of(k) for k in range(count)]
+    batch.run(beta, eta, seed=2, target=tgt, kernel="f4")
+    for k in range(count):
+        got = batch.trials_of(k)
+        for key in ("final", "e_best", "t_best", "best_state", "first_hit", "e_final"):
+            np.testing.assert_array_equal(got[key], i8[k][key], err_msg=f"instance {k} {key}")
+    for k, trials in ((0, [0]), (1, [1023]), (2, [300]), (3, [511]), (4, [1000]), (122, [7])):
+        J, h = probs[k]
+        ref = _oracle(J, h, 1 / np.sqrt(ns[k]), beta, eta, 2, k, trials, ztab, target=tgt[k])
+        _compare(batch.trials_of(k), ref, trials)
+    batch.close()
