@@ -1,10 +1,12 @@
 // PIMI sweep for 256 < N <= 1024 on e2m1 (FP4) matrix cores, for integer
 // instances whose couplings all lie in {0, +-1, +-2, +-3, +-4, +-6}, the
 // integers e2m1 represents exactly (SK-1 and unweighted Max-Cut have J in
-// {0, +-1}).  Spins +-1 are e2m1 values too, so every product J_ij s_j is
-// exact and the binary32 accumulation of at most 1024 of them (|I| <= 6 * 1023
-// < 2^24) is exact in any order: the field of Eq. (2) is the same integer the
-// int8 kernel forms, and trajectories, energies and best states are identical.
+// {0, +-1}).  The spins enter as +-2 (e2m1 0x4 / 0xC), so every product is an
+// exact integer and the binary32 accumulation (|2 I| <= 2 * 32766 < 2^24, the
+// bound instances are validated against) is exact in any order: the kernel
+// holds twice the field of Eq. (2) exactly, compares it with doubled integer
+// thresholds, and its trajectories, energies and best states are the int8
+// kernel's.
 // One v_mfma_f32_32x32x64_f8f6f4 on e2m1 operands issues in the cycles of one
 // 32x32x32 int8 MFMA and covers twice the K, and J and the spins take 4 bits
 // per value in L2 and LDS.
@@ -47,10 +49,10 @@ constexpr int kWaves = 8;            // two waves per SIMD
 constexpr int kCB = 4;               // 32-trial column blocks per workgroup
 constexpr int kTrialsWG = 32 * kCB;  // trials per workgroup
 constexpr int kXcds = 8;
-constexpr int kTabBytes = kTabEntries * 2;
 constexpr int kMinTiles = PIM_MAX_N_LDS / 32 + 1;  // 9
 constexpr int kMaxTiles = PIM_MAX_N / 32;          // 32
-constexpr uint32_t kPlusOnes = 0x22222222u;        // eight e2m1 +1.0 (sign bit 3 of each nibble clear)
+constexpr uint32_t kPlusTwos = 0x44444444u;        // eight e2m1 +2.0 (sign bit 3 of each nibble clear)
+constexpr int kTab32Bytes = kTabEntries * 4;       // a step table in LDS: doubled thresholds as int32
 
 #define PIM_FENCE(v) asm volatile("" : "+v"(v))
 
@@ -64,11 +66,13 @@ __device__ __forceinline__ v16f mfma_f4(v4i a, v4i b, v16f c) {
 }
 
 // Spin encodings.  A lane holds the 16 spins r = 0..15 of a row tile (spin
-// 32 mt + 16 half + r).  As e2m1 they sit in two words q = 0, 1: byte b of word
-// q holds spin 8q + b in its low nibble and spin 8q + 4 + b in its high nibble.
-// As int8 (+-1 bytes) they sit in four words k: byte b of word k is spin 4k + b.
+// 32 mt + 16 half + r).  As e2m1 (s = +1 -> +2.0 = 0x4, s = -1 -> -2.0 = 0xC)
+// they sit in two words q = 0, 1: byte b of word q holds spin 8q + b in its
+// low nibble and spin 8q + 4 + b in its high nibble; the top two bits of a
+// nibble, read as a signed 2-bit field, are s itself.  As int8 (+-1 bytes)
+// they sit in four words k: byte b of word k is spin 4k + b.
 __device__ __forceinline__ uint32_t nib_from_i8(uint32_t lo, uint32_t hi) {
-  return ((lo >> 4) & 0x08080808u) | (hi & 0x80808080u) | kPlusOnes;
+  return ((lo >> 4) & 0x08080808u) | (hi & 0x80808080u) | kPlusTwos;
 }
 __device__ __forceinline__ uint32_t i8_from_nib(uint32_t w, int hi) {
   return 0x01010101u + 0xFEu * ((w >> (4 * hi + 3)) & 0x01010101u);
@@ -162,13 +166,12 @@ __device__ __forceinline__ void rows_f4(const v4i* __restrict__ gA, const v4i* s
 
 // Eq. (4) decisions and Eq. (1) energy terms of row tile mt for the four
 // column blocks: s(t+1) of the tile written into the next spin buffer, the
-// partial sums s_r (I_r + 2 h_r) added to ep.  The field is the exact integer
-// the accumulator holds; s = +1 / -1 appears as m = 0 / -1 (the nibble's sign
-// bit), the threshold index is u ^ m (u for +1, ~u for -1), and s v is
-// accumulated as (v ^ m) plus the count of negative spins.
+// partial sums s_r (2 I_r + 4 h_r) added to ep.  The accumulator holds 2 I
+// exactly; sH and tab hold 2 h and the doubled thresholds, indexed as in the
+// int8 kernel by u ^ s (u ^ 1 for s = +1, ~u for s = -1).
 template <bool HAS_H>
 __device__ __forceinline__ void decide_f4(const v16f (&acc)[kCB], const uint2* sCur, uint2* sNxt,
-                                          const int32_t* sH, const int16_t* tab, int mt, int lane_off, int half,
+                                          const int32_t* sH, const int32_t* tab, int mt, int lane_off, int half,
                                           uint32_t ctr_half, uint32_t ctr_trial, int tg, uint32_t stream,
                                           uint32_t k0, uint32_t k1, int32_t (&ep)[kCB]) {
   const int hoff = 32 * mt + 16 * half;
@@ -182,11 +185,11 @@ __device__ __forceinline__ void decide_f4(const v16f (&acc)[kCB], const uint2* s
     for (int q = 0; q < 4; ++q) PIM_FENCE(xw[q]);
     PIM_FENCE(sw[0]);
     PIM_FENCE(sw[1]);
-    int m[16], th[16];
+    int sv[16], th[16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-      m[r] = (int)__builtin_amdgcn_sbfe(sw[r >> 3], 8 * (r & 3) + 4 * ((r >> 2) & 1) + 3, 1);
-      th[r] = tab[(int)((xw[r >> 2] >> (8 * (r & 3))) & 0xFFu) ^ m[r]];
+      sv[r] = (int)__builtin_amdgcn_sbfe(sw[r >> 3], 8 * (r & 3) + 4 * ((r >> 2) & 1) + 2, 2);  // +1 / -1
+      th[r] = tab[(int)((xw[r >> 2] >> (8 * (r & 3))) & 0xFFu) ^ sv[r]];
     }
     int hoff_c = hoff;
     if (HAS_H) PIM_FENCE(hoff_c);
@@ -194,17 +197,17 @@ __device__ __forceinline__ void decide_f4(const v16f (&acc)[kCB], const uint2* s
     int32_t e = ep[c];
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-      int I = (int)acc[c][r];  // exact integer
+      int I = (int)acc[c][r];  // 2 I, exact
       int v = I;
       if (HAS_H) {
         const int hv = sH[hoff_c + r];
         I += hv;
         v = I + hv;
       }
-      e += v ^ m[r];  // s v - (s < 0)
-      d[r] = I - th[r];  // >= 0  <=>  s(t+1) = +1
+      e += __mul24(sv[r], v);  // |v| <= 4 * 32766 < 2^23
+      PIM_FENCE(e);            // one multiply-add per term, not a multiply and an add tree
+      d[r] = I - th[r];        // >= 0  <=>  s(t+1) = +1
     }
-    e += __builtin_popcount(sw[0] & 0x88888888u) + __builtin_popcount(sw[1] & 0x88888888u);
     ep[c] = e;
     uint32_t w[2];
 #pragma unroll
@@ -214,7 +217,7 @@ __device__ __forceinline__ void decide_f4(const v16f (&acc)[kCB], const uint2* s
                           __builtin_amdgcn_perm((uint32_t)d[8 * q + 3], (uint32_t)d[8 * q + 2], 0x0B090C0Cu);
       const uint32_t hi = __builtin_amdgcn_perm((uint32_t)d[8 * q + 5], (uint32_t)d[8 * q + 4], 0x0C0C0B09u) |
                           __builtin_amdgcn_perm((uint32_t)d[8 * q + 7], (uint32_t)d[8 * q + 6], 0x0B090C0Cu);
-      w[q] = (lo & 0x08080808u) | (hi & 0x80808080u) | kPlusOnes;
+      w[q] = (lo & 0x08080808u) | (hi & 0x80808080u) | kPlusTwos;
     }
     sNxt[sb_half(mt, c, lane_off)] = uint2{w[0], w[1]};
     PIM_FENCE(ep[c]);
@@ -223,17 +226,18 @@ __device__ __forceinline__ void decide_f4(const v16f (&acc)[kCB], const uint2* s
   }
 }
 
-// Step table into LDS for this kernel's index u ^ m: the entries of s = -1
-// (index ~u, lanes 0..31) are where the host table has them; those of s = +1
-// sit at u instead of u ^ 1, i.e. the two 16-bit entries of each word swap.
-__device__ __forceinline__ void stage_table(int16_t* dst, uint4 v, int lane) {
-  if (lane >= 32) {
-    v.x = __builtin_amdgcn_alignbit(v.x, v.x, 16);
-    v.y = __builtin_amdgcn_alignbit(v.y, v.y, 16);
-    v.z = __builtin_amdgcn_alignbit(v.z, v.z, 16);
-    v.w = __builtin_amdgcn_alignbit(v.w, v.w, 16);
+// Step table into LDS as doubled thresholds: lane l holds host entries
+// 8l .. 8l + 7 (16-bit), written as eight int32 2 * theta.
+__device__ __forceinline__ void stage_table(int32_t* dst, uint4 v, int lane) {
+  const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+  int32_t o[8];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    o[2 * q] = (int32_t)(w[q] << 16) >> 15;               // 2 * sign-extended low half
+    o[2 * q + 1] = (int32_t)(w[q] & 0xFFFF0000u) >> 15;   // 2 * sign-extended high half
   }
-  reinterpret_cast<uint4*>(dst)[lane] = v;
+  reinterpret_cast<int4*>(dst)[2 * lane] = int4{o[0], o[1], o[2], o[3]};
+  reinterpret_cast<int4*>(dst)[2 * lane + 1] = int4{o[4], o[5], o[6], o[7]};
 }
 
 // One workgroup's run: trial block tblk (128 trials) of instance inst.
@@ -243,13 +247,13 @@ __device__ __forceinline__ void big4_body(const SweepArgs& a, int nt, int inst, 
   const int npad = nt * 32;
   const int np = (nt + 1) >> 1;  // K steps of 64 spins
   const int buf = np * kCB * 64;  // 16-byte slots per spin buffer
-  // LDS: spins [2][np][kCB][64] x 16 B | tables [2] x 1 KB | energy partials
+  // LDS: spins [2][np][kCB][64] x 16 B | tables [2] x 2 KB | energy partials
   // [2][kWaves][kCB][32] | per-trial t_best, first_hit, e_cur [3][kCB][32] |
-  // cancel flag | h
+  // cancel flag | 2 h
   v4i* sB = reinterpret_cast<v4i*>(lds);
   unsigned char* rest = lds + (size_t)2 * buf * 16;
-  int16_t* sTab = reinterpret_cast<int16_t*>(rest);
-  int32_t* sE = reinterpret_cast<int32_t*>(rest + 2 * kTabBytes);
+  int32_t* sTab = reinterpret_cast<int32_t*>(rest);
+  int32_t* sE = reinterpret_cast<int32_t*>(rest + 2 * kTab32Bytes);
   int32_t* sStat = sE + 2 * kWaves * kCB * 32;
   int32_t* sFlag = sStat + 3 * kCB * 32;
   int32_t* sH = sFlag + 4;
@@ -271,7 +275,7 @@ __device__ __forceinline__ void big4_body(const SweepArgs& a, int nt, int inst, 
   const v4i* gA = reinterpret_cast<const v4i*>(a.jfrag + (size_t)inst * nt * np * 1024);
 
   if (HAS_H)
-    for (int i = threadIdx.x; i < npad; i += 64 * kWaves) sH[i] = a.h[(size_t)inst * npad + i];
+    for (int i = threadIdx.x; i < npad; i += 64 * kWaves) sH[i] = 2 * a.h[(size_t)inst * npad + i];
   // s(0) into buffer 0: each wave its own row tiles
   uint2* sB2 = reinterpret_cast<uint2*>(sB);
 #pragma unroll
@@ -301,8 +305,8 @@ __device__ __forceinline__ void big4_body(const SweepArgs& a, int nt, int inst, 
   if ((nt & 1) && wave == kWaves - 1)
 #pragma unroll
     for (int c = 0; c < kCB; ++c) {
-      sB2[sb_half(nt, c, lane)] = uint2{kPlusOnes, kPlusOnes};
-      sB2[2 * buf + sb_half(nt, c, lane)] = uint2{kPlusOnes, kPlusOnes};
+      sB2[sb_half(nt, c, lane)] = uint2{kPlusTwos, kPlusTwos};
+      sB2[2 * buf + sb_half(nt, c, lane)] = uint2{kPlusTwos, kPlusTwos};
     }
   // table of step 0 into table buffer 0; the next one waits in registers
   uint4 nxt = uint4{0, 0, 0, 0};
@@ -335,7 +339,7 @@ __device__ __forceinline__ void big4_body(const SweepArgs& a, int nt, int inst, 
       stage_table(sTab + (cur ^ 1) * kTabEntries, nxt, lane);
       nxt = gTab4[(size_t)min(t + 2, a.T - 1) * 64 + lane];
     }
-    const int16_t* tab = sTab + cur * kTabEntries + kNoiseVals;
+    const int32_t* tab = sTab + cur * kTabEntries + kNoiseVals;
     const v4i* sCur = sB + cur * buf;
     const uint2* sCur2 = reinterpret_cast<const uint2*>(sCur);
     uint2* sNxt2 = sB2 + (cur ^ 1) * 2 * buf;
@@ -382,7 +386,7 @@ __device__ __forceinline__ void big4_body(const SweepArgs& a, int nt, int inst, 
       int32_t tot = 0;
 #pragma unroll
       for (int w = 0; w < kWaves; ++w) tot += sE[((cur * kWaves + w) * kCB + c) * 32 + col];
-      const int32_t E = -(tot / 2);
+      const int32_t E = -(tot / 4);  // tot = 2 sum_i s_i (I_i + 2 h_i)
       if (E < e_best[c]) {
         e_best[c] = E;
         if (writer) sStat[(0 * kCB + c) * 32 + col] = tg;
@@ -464,7 +468,7 @@ __global__ __launch_bounds__(64 * kWaves, 2) void sweep_big4_multi_kernel(const 
 
 size_t big4_lds_bytes(int nt, bool has_h) {
   const size_t np = (size_t)(nt + 1) / 2;
-  return 2 * np * kCB * 1024 + 2 * kTabBytes + (size_t)(2 * kWaves + 3) * kCB * 32 * 4 + 16 +
+  return 2 * np * kCB * 1024 + 2 * kTab32Bytes + (size_t)(2 * kWaves + 3) * kCB * 32 * 4 + 16 +
          (has_h ? (size_t)nt * 32 * 4 : 0);
 }
 

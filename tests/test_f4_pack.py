@@ -1,6 +1,6 @@
 """Host logic of the e2m1 (FP4) streamed kernel, no GPU: the library's
-fragment packer, combined with the kernel's spin encoding, reproduces the
-exact field J.s of Eq. (2).
+fragment packer, combined with the kernel's spin encoding, reproduces twice
+the exact field J.s of Eq. (2).
 
 The C++ program below decodes e2m1 from the format's definition (sign bit 3,
 exponent bits 2..1 with bias 1, mantissa bit 0; subnormal 0 and 0.5) and
@@ -9,7 +9,8 @@ C[i][j] = sum over lane groups g and elements e of A(lane i + 32 g, e) *
 B(lane j + 32 g, e), element e being nibble e % 8 of word e / 8, and C's
 register v of lane l holding row 8 (v / 4) + 4 (l / 32) + v % 4.  The B slots
 are built as the kernel packs decided spins (word q, byte b: spin 8q + b in
-the low nibble, 8q + 4 + b in the high one; +1 = 0x2, -1 = 0xA)."""
+the low nibble, 8q + 4 + b in the high one; s = +1 as 2.0 = 0x4, s = -1 as
+-2.0 = 0xC), so the product is 2 J.s."""
 import os
 import shutil
 import subprocess
@@ -55,7 +56,7 @@ int main() {
       for (int g = 0; g < 2; ++g)
         for (int h = 0; h < 2; ++h)
           for (int q = 0; q < 2; ++q) {
-            uint32_t w = 0x22222222u;
+            uint32_t w = 0x44444444u;
             for (int b = 0; b < 4; ++b)
               for (int hi = 0; hi < 2; ++hi)
                 if (s[32 * (2 * p + h) + 16 * g + 8 * q + 4 * hi + b] < 0) w |= 8u << (8 * b + 4 * hi);
@@ -76,7 +77,7 @@ int main() {
           const int i = 32 * mt + 16 * g + v;  // the spin register v of lane group g decides
           long ref = 0;
           if (i < n)
-            for (int j = 0; j < n; ++j) ref += (long)J[(size_t)i * n + j] * s[j];
+            for (int j = 0; j < n; ++j) ref += 2L * J[(size_t)i * n + j] * s[j];
           ++checked;
           if ((double)ref != acc) ++bad;
         }
