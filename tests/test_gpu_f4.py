@@ -269,3 +269,43 @@ def test_f4_full_size_uneven_batch_sampled(gpu_lib):
         ref = _oracle(J, h, 1 / np.sqrt(ns[k]), beta, eta, 2, k, trials, ztab, target=tgt[k])
         _compare(batch.trials_of(k), ref, trials)
     batch.close()
+
+
+def test_f4_one_launch_cancel_and_target_toggle(gpu_lib):
+    """The one launch over e2m1 parts: a run with first-hit targets, then the
+    same schedule without them (the uploaded work list is reused, the target
+    flag is a kernel argument), then a long run cancelled from the host, then
+    a short run that completes; results equal the oracle where they are
+    defined."""
+    _say("f4 one launch: targets on/off, cancel")
+    pim = gpu_lib
+    ns = [300, 600, 1000]
+    trials, steps = 64, 30
+    ztab = w.gauss_table(8)
+    probs = [w.sk1(n, seed=23, index=k) for k, n in enumerate(ns)]
+    insts = [pim.Instance(J, h, j_scale=1 / np.sqrt(len(h)), xi=0.5, noise_table=ztab, rng_stream=60 + k)
+             for k, (J, h) in enumerate(probs)]
+    beta = w.linear_beta(steps, 0.1, 3.0)
+    eta = w.eta_sqrt_beta_over_5(beta)
+    tgt = [float(np.floor(-0.6 * n ** 1.5)) for n in ns]
+    batch = pim.Batch(insts, trials)
+    for use_target in (True, False):
+        batch.run(beta, eta, seed=4, kernel="f4", target=tgt if use_target else None)
+        for k, (J, h) in enumerate(probs):
+            got = batch.trials_of(k)
+            ref = _oracle(J, h, 1 / np.sqrt(len(h)), beta, eta, 4, 60 + k, np.arange(trials), ztab,
+                          target=tgt[k] if use_target else None)
+            _compare(got, ref, np.arange(trials))
+            if not use_target:
+                assert np.all(got["first_hit"] == -1)
+    T = 60000
+    batch.run(np.full(T, 1.0), np.full(T, 0.4), seed=1, kernel="f4")
+    batch.cancel()
+    with pytest.raises(pim.PimError) as ei:
+        batch.trials_of(0)
+    assert ei.value.status == pim.PIM_ERR_CANCELLED
+    batch.run(beta, eta, seed=4, kernel="f4")
+    for k, (J, h) in enumerate(probs):
+        ref = _oracle(J, h, 1 / np.sqrt(len(h)), beta, eta, 4, 60 + k, [0, 63], ztab)
+        _compare(batch.trials_of(k), ref, [0, 63])
+    batch.close()
