@@ -6,6 +6,9 @@ the binary64 re-rank of every trial's best state, and the per-instance argmin
 readout.  The instances are staged in device memory before the timed region,
 and the per-step threshold tables are compiled and uploaded by the warm-up
 (the timed steps run the same schedule, so the library reuses them).
+The same timed protocol then runs on e2m1 (FP4) operands ("e2m1" in the
+line): the couplings and spins are exact e2m1 values, so its results must
+equal the int8 run's, which the line records.
 
 Success for TTS99 (Sec. III.A, Eqs. (5)-(6)) is measured against a reference
 energy per instance: the lower of the simulated-annealing reference (the
@@ -55,7 +58,7 @@ def parse():
     ap.add_argument("--sweeps", type=int, default=10000, help="update steps T per trial")
     ap.add_argument("--n", type=int, default=200)
     ap.add_argument("--kernel", default="mfma", choices=["mfma", "plain", "f4"],
-                    help="mfma: int8 operands; f4: e2m1 (FP4) operands where N > 256 (exact for J = +-1)")
+                    help="mfma: int8 operands; f4: e2m1 (FP4) operands (exact for J = +-1, identical results)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-trials", type=int, default=512)
     ap.add_argument("--cpu-steps", type=int, default=2000)
@@ -823,6 +826,33 @@ def main():
     # best energies of the timed run, kept for the plain-kernel comparison
     # (the scan below reruns the batch)
     timed_ebest = [batch.trials_of(q, spins=False)["e_best"] for q in range(min(args.plain_instances, I))]
+    # the same timed protocol on e2m1 (FP4) operands: J = +-1 and the spins are
+    # exact e2m1 values, so every trial must give the int8 run's results
+    e2m1 = None
+    if args.kernel == "mfma" and not args.core_only:
+        timed_res = [(r["e_best"], r["t_best"], r["first_hit"]) for r in res]
+        batch.run(beta, eta, seed=1, kernel="f4", target=target)  # warm-up
+        torch.cuda.synchronize()
+        t4 = time.perf_counter()
+        k4 = []
+        for si in range(args.steps):
+            batch.run(beta, eta, seed=1, kernel="f4", target=target)
+            [batch.best(k) for k in range(I)]
+            k4.append(batch.kernel_ms())
+        torch.cuda.synchronize()
+        dt4 = time.perf_counter() - t4
+        kms4 = float(np.mean(k4))
+        res4 = [batch.trials_of(k, spins=False) for k in range(I)]
+        same4 = all(np.array_equal(a[0], b["e_best"]) and np.array_equal(a[1], b["t_best"]) and
+                    np.array_equal(a[2], b["first_hit"]) for a, b in zip(timed_res, res4))
+        ops4 = 2.0 * n * n * float(I) * R * (T + 1)
+        e2m1 = {"value": updates / (dt4 / args.steps), "unit": "spin-updates/s", "ms_per_step": 1000.0 * dt4 / args.steps,
+                "kernel_ms": kms4, "identical_to_int8": bool(same4),
+                "tts99_s": n99 * T * (kms4 / 1000.0) / (I * R * T) if n99 != math.inf else None,
+                "int8_mfma_frac": ops4 / (kms4 / 1e3) / INT8_MFMA_PEAK,
+                "fp4_mfma_frac": ops4 / (kms4 / 1e3) / FP4_MFMA_PEAK,
+                "note": "couplings +-1 and spins +-2 are exact e2m1 values; binary32 sums of integer products "
+                        "below 2^24 are exact, so trajectories equal the int8 kernel's"}
 
     # TTS99 over the anneal length: the same batch and success threshold, a
     # linear 0.1 -> 3.0 schedule over each T (after the timed region)
@@ -871,7 +901,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "fp4" if (args.kernel == "f4" and n > 256) else "i8",
+        "dtype": "fp4" if args.kernel == "f4" else "i8",
         "data": "synthetic",
         "config": {"workload": f"SK-1 N={n}, {I} instances x {R} trials x {T} steps, kernel {args.kernel}",
                    "instances": I, "trials": R, "steps_per_trial": T, "n": n, "parallelism": "single GPU"},
@@ -896,11 +926,14 @@ def main():
                           "unit": "TOP/s", "frac": mfma_ops / kernel_s / INT8_MFMA_PEAK},
         "roofline_fp4": ({"bound": "mfma", "achieved": mfma_ops / kernel_s / 1e12, "peak": FP4_MFMA_PEAK / 1e12,
                           "unit": "TOP/s", "frac": mfma_ops / kernel_s / FP4_MFMA_PEAK}
-                         if args.kernel == "f4" and n > 256 else None),
+                         if args.kernel == "f4" else None),
         "lds": ({"achieved": lds_bytes / kernel_s / 1e9, "peak": LDS_PEAK / 1e9, "unit": "GB/s",
                  "frac": lds_bytes / kernel_s / LDS_PEAK, "bytes_per_wave_step": lds_per_wave_step}
                 if args.kernel == "mfma" and n <= 256 else None),
     }
+    if e2m1 is not None:
+        e2m1["alu_frac"] = alu_ops / (e2m1["kernel_ms"] / 1e3) / VALU_PEAK
+        line["e2m1"] = e2m1
     if args.plain_instances > 0 and args.kernel == "mfma":
         # the plain FP32 per-instance kernel on the first instances of the same
         # batch (identical trajectories, so equal TTS99): one launch per instance

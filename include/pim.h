@@ -107,13 +107,14 @@ typedef enum {
                                step t changes only spin i = (start_step + t) mod N;
                                integer instances only                               */
   PIM_KERNEL_MFMA_F4 = 3    /* as PIM_KERNEL_MFMA_I8, except that an integer batch
-                               with N > PIM_MAX_N_LDS whose couplings all lie in
-                               {0, +-1, +-2, +-3, +-4, +-6} runs on e2m1 (FP4)
-                               operands with binary32 accumulation: every product
-                               and partial sum is an exact integer (|I| < 2^24), so
-                               results are identical to int8, at twice the matrix
-                               rate; other batches run the int8 kernel.  Integer
-                               instances only; no state recording at N > 256       */
+                               whose couplings all lie in {0, +-1, +-2, +-3, +-4,
+                               +-6} runs on e2m1 (FP4) operands with binary32
+                               accumulation: every product and partial sum is an
+                               exact integer (|2 I| < 2^24), so results are
+                               identical to int8, at twice the matrix rate; other
+                               batches, and runs that record states, run the int8
+                               kernel.  Integer instances only; no state recording
+                               at N > 256                                           */
 } pim_kernel;
 
 /* Operand format of a real-valued instance in the batched MFMA kernel. */

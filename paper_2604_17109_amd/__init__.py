@@ -520,8 +520,8 @@ class Batch:
 
     def run(self, beta, eta, seed, start_step=0, kernel="mfma", target=None, stream=None, record=False):
         """One pim_run: kernel "mfma" (int8 / FP8 / BF16 matrix cores), "f4"
-        (as "mfma", but N > 256 with couplings in {0, +-1, +-2, +-3, +-4, +-6}
-        on e2m1 operands, identical results), "plain" or "seq"."""
+        (as "mfma", but couplings in {0, +-1, +-2, +-3, +-4, +-6} run on e2m1
+        operands, identical results), "plain" or "seq"."""
         beta = np.ascontiguousarray(beta, dtype=np.float64)
         eta = np.ascontiguousarray(eta, dtype=np.float64)
         if beta.shape != eta.shape or beta.ndim != 1:

@@ -188,6 +188,9 @@ struct RerankArgs {
 
 hipError_t launch_rerank_select(const RerankArgs& a, hipStream_t s);
 hipError_t launch_sweep_mfma(const SweepArgs& a, int count, int nt, bool has_h, hipStream_t s);
+// The same on e2m1 (FP4) operands (couplings in {0, +-1, +-2, +-3, +-4, +-6}):
+// a.jfrag holds pack_f4_fragments output; no state recording.
+hipError_t launch_sweep_mfma4(const SweepArgs& a, int count, int nt, bool has_h, hipStream_t s);
 hipError_t launch_sweep_plain(const PlainArgs& a, bool real, hipStream_t s);
 // 256 < N <= 1024: couplings streamed from global memory, spins in LDS.
 hipError_t launch_sweep_big(const SweepArgs& a, int count, int nt, bool has_h, hipStream_t s);
@@ -289,7 +292,7 @@ struct pim_instance {
   bool has_h = false;
   uint8_t* d_arena = nullptr;     // one allocation holding every buffer below
   int8_t* d_jfrag = nullptr;      // int8, FP8 or BF16 MFMA fragments
-  uint8_t* d_jfrag4 = nullptr;    // e2m1 fragments (integer, N > PIM_MAX_N_LDS, e2m1-exact J) or NULL
+  uint8_t* d_jfrag4 = nullptr;    // e2m1 fragments (integer instances with e2m1-exact J) or NULL
   size_t frag4_bytes = 0;
   float* d_jf32 = nullptr;        // [npad][jstride] FP32 J, zero-padded
   int8_t* d_j8 = nullptr;         // row-major int8 J (re-rank; integer instances)

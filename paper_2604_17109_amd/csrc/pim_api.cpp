@@ -417,7 +417,8 @@ pim_status run_prepare(pim_batch* b, const pim_schedule* sc, hipStream_t s, RunC
       return fail(PIM_ERR_UNSUPPORTED, "e2m1 operands take integer instances");
     if (sc->kernel == PIM_KERNEL_SEQ_I8 && b->real)
       return fail(PIM_ERR_UNSUPPORTED, "the sequential kernel takes integer instances");
-    if (sc->record_states && (sc->kernel != PIM_KERNEL_MFMA_I8 || b->real))
+    // recording runs take the int8 kernel (also when e2m1 operands were asked for)
+    if (sc->record_states && ((sc->kernel != PIM_KERNEL_MFMA_I8 && sc->kernel != PIM_KERNEL_MFMA_F4) || b->real))
       return fail(PIM_ERR_UNSUPPORTED, "state recording is implemented for the int8 MFMA kernel");
     if (b->n > PIM_MAX_N_LDS &&
         ((sc->kernel != PIM_KERNEL_MFMA_I8 && sc->kernel != PIM_KERNEL_MFMA_F4) || sc->record_states))
@@ -581,7 +582,7 @@ pim_status run_prepare(pim_batch* b, const pim_schedule* sc, hipStream_t s, RunC
     ctx.real = real;
     ctx.mfma = mfma;
     ctx.seq = seq;
-    ctx.f4 = sc->kernel == PIM_KERNEL_MFMA_F4 && b->d_jfrag4 && b->nt * 32 > PIM_MAX_N_LDS;
+    ctx.f4 = sc->kernel == PIM_KERNEL_MFMA_F4 && b->d_jfrag4 && !sc->record_states;
     ctx.tgt = std::move(tgt);
     ctx.tgtf = std::move(tgtf);
     return PIM_OK;
@@ -657,7 +658,8 @@ hipError_t run_launch(pim_batch* b, const pim_schedule* sc, uint64_t seed, const
       SweepArgs a = int_sweep_args(b, sc, seed, T);
       if (ctx.f4) {
         a.jfrag = reinterpret_cast<const int8_t*>(b->d_jfrag4);
-        e = launch_sweep_big4(a, b->count, b->nt, b->has_h, s);
+        e = b->nt * 32 > PIM_MAX_N_LDS ? launch_sweep_big4(a, b->count, b->nt, b->has_h, s)
+                                       : launch_sweep_mfma4(a, b->count, b->nt, b->has_h, s);
       } else {
         e = b->nt * 32 > PIM_MAX_N_LDS ? launch_sweep_big(a, b->count, b->nt, b->has_h, s)
                                        : launch_sweep_mfma(a, b->count, b->nt, b->has_h, s);
@@ -1002,8 +1004,8 @@ pim_status pim_create(const int8_t* J, const int32_t* h, const pim_params* param
     if (h)
       for (int i = 0; i < n; ++i) inst->has_h |= (h[i] != 0);
     inst->frag_bytes = (size_t)inst->nt * inst->nt * 1024;
-    // the streamed range also gets e2m1 fragments when every coupling is e2m1-exact
-    if (n > PIM_MAX_N_LDS && f4_couplings(J, (size_t)n * n)) inst->frag4_bytes = f4_frag_bytes(inst->nt);
+    // e2m1 fragments as well when every coupling is e2m1-exact
+    if (f4_couplings(J, (size_t)n * n)) inst->frag4_bytes = f4_frag_bytes(inst->nt);
     inst->jstride = (n + 3) & ~3;
     // device arena: fragments, FP32 J, h (built on the host in one block of
     // the same layout and uploaded by one copy), then the int8 J (copied
@@ -1254,7 +1256,7 @@ pim_status pim_run(pim_batch* b, const pim_schedule* sc, uint64_t seed, void* st
     std::vector<char> in_multi(P, 0);
     std::vector<size_t> mp;
     for (size_t p = 0; p < P; ++p)
-      if (ctx[p].f4) mp.push_back(p);
+      if (ctx[p].f4 && b->parts[p]->nt * 32 > PIM_MAX_N_LDS) mp.push_back(p);
     const Big4Part* d_parts = nullptr;
     const int4* d_work = nullptr;
     int nwork = 0, nt_max = 0;

@@ -309,3 +309,91 @@ def test_f4_one_launch_cancel_and_target_toggle(gpu_lib):
         ref = _oracle(J, h, 1 / np.sqrt(len(h)), beta, eta, 4, 60 + k, [0, 63], ztab)
         _compare(batch.trials_of(k), ref, [0, 63])
     batch.close()
+
+
+LDS_CASES = [
+    # n, trials, steps, values, hmax -- the LDS-resident e2m1 kernel (N <= 256)
+    (1, 40, 30, (-1, 1), 0),
+    (5, 64, 40, (-1, 0, 1), 2),
+    (20, 64, 200, (-1, 1), 0),
+    (31, 33, 60, (-2, -1, 1, 2), 0),         # last-tile tail of 12 registers
+    (32, 64, 50, (-1, 1), 0),
+    (33, 100, 40, (-6, -4, -3, -2, -1, 0, 1, 2, 3, 4, 6), 3),  # tail of 4, fields
+    (64, 64, 40, (-1, 0, 1), 0),
+    (100, 128, 40, (-1, 1), 0),
+    (130, 70, 30, (-4, -2, 2, 4), 0),        # odd tile count: a padded half K step
+    (200, 96, 50, (-1, 1), 0),               # tail of 8
+    (224, 64, 30, (-3, 3), 5),
+    (255, 32, 30, (-1, 1), 0),
+    (256, 64, 24, (-1, 1), 1),
+]
+
+
+@pytest.mark.parametrize("case", LDS_CASES, ids=lambda c: f"{c[0]}-{c[1]}-{c[2]}-{len(c[3])}v-h{c[4]}")
+def test_f4_lds_parity(gpu_lib, case):
+    n, trials, steps, values, hmax = case
+    _say(f"f4 LDS kernel n={n} trials={trials} steps={steps} values={values} hmax={hmax}")
+    probs = [_e2m1_instance(n, 41, k, values, hmax) for k in range(2)]
+    batch, beta, eta, targets, ztab = _run(gpu_lib, probs, trials, steps, "f4", seed=15)
+    for k, (J, h) in enumerate(probs):
+        ref = _oracle(J, h, 1 / np.sqrt(n), beta, eta, 15, 3 + k, np.arange(trials), ztab, target=targets[k])
+        _compare(batch.trials_of(k), ref, np.arange(trials))
+    batch.close()
+
+
+def test_f4_lds_tuned_resume_and_recording(gpu_lib):
+    """N = 200 with e2m1: after autotuning waves per workgroup, from caller
+    spins, resumed in two halves; a recording run falls back to int8 and
+    records the same trajectory."""
+    _say("f4 LDS kernel: tuned, caller spins, resume, recording")
+    pim = gpu_lib
+    n, R, T = 200, 200, 120
+    J, h = w.sk1(n, seed=8)
+    ztab = w.gauss_table(8)
+    inst = pim.Instance(J, h, j_scale=1 / np.sqrt(n), xi=0.5, noise_table=ztab, rng_stream=5)
+    beta = w.linear_beta(T)
+    eta = w.eta_sqrt_beta_over_5(beta)
+    init = np.random.default_rng(2).choice([-1, 1], size=(1, R, n)).astype(np.int8)
+    b = pim.Batch([inst], R, init_spins=init)
+    b.tune(steps=50)
+    full = b.run(beta, eta, seed=3, kernel="f4").trials_of(0)
+    ref = _oracle(J, h, 1 / np.sqrt(n), beta, eta, 3, 5, [0, 127, 128, 199], ztab,
+                  init=init[0][[0, 127, 128, 199]].T.astype(np.int64))
+    _compare(full, ref, [0, 127, 128, 199])
+    a1 = pim.Batch([inst], R, init_spins=init).run(beta[:60], eta[:60], seed=3, kernel="f4").trials_of(0)
+    a2 = pim.Batch([inst], R, init_spins=a1["final"][None]).run(beta[60:], eta[60:], seed=3, start_step=60,
+                                                               kernel="f4").trials_of(0)
+    np.testing.assert_array_equal(a2["final"], full["final"])
+    np.testing.assert_array_equal(np.minimum(a1["e_best"], a2["e_best"]), full["e_best"])
+    rec = pim.Batch([inst], 32, init_spins=init[:, :32]).run(beta[:20], eta[:20], seed=3, kernel="f4", record=True)
+    rec8 = pim.Batch([inst], 32, init_spins=init[:, :32]).run(beta[:20], eta[:20], seed=3, kernel="mfma", record=True)
+    np.testing.assert_array_equal(rec.states(0, 7), rec8.states(0, 7))
+
+
+def test_f4_lds_full_size_sk200_equals_int8(gpu_lib):
+    """The headline workload, 128 SK-1 N = 200 instances x 1024 trials x 10^4
+    steps with first-hit targets, on e2m1 operands: every trial equals the
+    int8 kernel's run, and sampled trials equal the oracle."""
+    _say("f4 LDS kernel sk200 128x1024x10000 vs int8, sampled oracle trials")
+    pim = gpu_lib
+    n, R, T, I = 200, 1024, 10000, 128
+    ztab = w.gauss_table(8)
+    probs = [w.sk1(n, seed=1, index=k) for k in range(I)]
+    insts = [pim.Instance(J, h, j_scale=1 / np.sqrt(n), xi=0.5, noise_table=ztab, rng_stream=k)
+             for k, (J, h) in enumerate(probs)]
+    beta = w.linear_beta(T, 0.1, 3.0)
+    eta = w.eta_sqrt_beta_over_5(beta)
+    tgt = [-2000.0] * I
+    batch = pim.Batch(insts, R)
+    batch.run(beta, eta, seed=1, target=tgt, kernel="mfma")
+    i8 = [batch.trials_of(k) for k in range(I)]
+    batch.run(beta, eta, seed=1, target=tgt, kernel="f4")
+    for k in range(I):
+        got = batch.trials_of(k)
+        for key in ("final", "e_best", "t_best", "best_state", "first_hit", "e_final"):
+            np.testing.assert_array_equal(got[key], i8[k][key], err_msg=f"instance {k} {key}")
+    for k, trials in ((0, [0]), (77, [1023])):
+        J, h = probs[k]
+        ref = _oracle(J, h, 1 / np.sqrt(n), beta, eta, 1, k, trials, ztab, target=tgt[k])
+        _compare(batch.trials_of(k), ref, trials)
+    batch.close()
