@@ -12,10 +12,15 @@
 //     C -> B hand-off still never leaves the lane, and the signed 2-bit field
 //     at the top of a nibble is s itself.
 //
-// Every product is an exact integer and |2 I| <= 2 * 32766 < 2^24 (the row
-// bound instances are validated against), so the binary32 accumulator holds
-// 2 I exactly in any accumulation order; it is converted to int32 and compared
-// with doubled thresholds, and the energy is accumulated as s (2 I + 4 h).
+// Every product is an exact integer and |2 I| <= 2 * 32766 < 2^17 (the row
+// bound instances are validated against).  Each row tile's accumulation
+// starts from 1.5 * 2^23 instead of 0, so every partial sum lies in
+// [2^23, 2^24), where binary32 steps by exactly 1: the accumulator holds
+// 1.5 * 2^23 + 2 I exactly in any accumulation order, and its bit pattern is
+// the integer 0x4B400000 + 2 I.  The kernel compares that pattern with
+// thresholds biased the same way (no float-to-int conversion), and
+// accumulates the energy from its low 24 bits, 2^22 + 2 I (+ 4 h), removing
+// the 2^22 s terms afterwards from a count of the negative spins.
 // Trajectories, energies and best states are identical to the int8 kernel's.
 //
 // Spin layout as in the int8 kernel: register r of half hh of row tile mt is
@@ -41,6 +46,9 @@ typedef float v16f __attribute__((ext_vector_type(16)));
 constexpr int kWaves = 4;                      // most waves (32-trial blocks) per workgroup
 constexpr int kTab32Bytes = kTabEntries * 4;   // a step table in LDS: doubled thresholds as int32
 constexpr uint32_t kPlusTwos = 0x44444444u;    // eight e2m1 +2.0
+constexpr float kAccBias = 12582912.0f;        // 1.5 * 2^23: start of every row tile's sum
+constexpr int32_t kAccBiasBits = 0x4B400000;   // its bit pattern; + 2 I is the biased field
+constexpr int32_t kLow24Bias = 0x400000;       // its low 24 bits: 2^22
 
 #define PIM_FENCE(v) asm volatile("" : "+v"(v))
 
@@ -81,25 +89,27 @@ __device__ __forceinline__ v4i b_operand(const uint2 (&S)[NT], int p) {
   return v4i{(int)lo.x, (int)lo.y, (int)hi.x, (int)hi.y};
 }
 
-// 2 I for row tile mt: ceil(NT / 2) chained e2m1 MFMAs over the K steps.
+// 1.5 * 2^23 + 2 I for row tile mt: ceil(NT / 2) chained e2m1 MFMAs over the
+// K steps, the first one adding to the bias registers.
 template <int NT>
-__device__ __forceinline__ v16f row_tile(const v4i* sJl, int mt, const uint2 (&S)[NT]) {
+__device__ __forceinline__ v16f row_tile(const v4i* sJl, int mt, const uint2 (&S)[NT], const v16f& bias) {
   constexpr int NP = (NT + 1) / 2;
-  v16f acc = v16f{};
+  v16f acc = mfma_f4(sJl[(mt * NP) * 64], b_operand<NT>(S, 0), bias);
 #pragma unroll
-  for (int p = 0; p < NP; ++p) acc = mfma_f4(sJl[(mt * NP + p) * 64], b_operand<NT>(S, p), acc);
+  for (int p = 1; p < NP; ++p) acc = mfma_f4(sJl[(mt * NP + p) * 64], b_operand<NT>(S, p), acc);
   return acc;
 }
 
-// Step table into the wave's LDS buffer as doubled thresholds: lane l holds
-// host entries 8l .. 8l + 7 (16-bit) and writes eight int32 2 * theta.
+// Step table into the wave's LDS buffer as biased doubled thresholds: lane l
+// holds host entries 8l .. 8l + 7 (16-bit) and writes eight int32
+// 0x4B400000 + 2 theta.
 __device__ __forceinline__ void stage_table(int32_t* dst, uint4 v, int lane) {
   const uint32_t w[4] = {v.x, v.y, v.z, v.w};
   int32_t o[8];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    o[2 * q] = (int32_t)(w[q] << 16) >> 15;              // 2 * sign-extended low half
-    o[2 * q + 1] = (int32_t)(w[q] & 0xFFFF0000u) >> 15;  // 2 * sign-extended high half
+    o[2 * q] = ((int32_t)(w[q] << 16) >> 15) + kAccBiasBits;              // low half
+    o[2 * q + 1] = ((int32_t)(w[q] & 0xFFFF0000u) >> 15) + kAccBiasBits;  // high half
   }
   reinterpret_cast<int4*>(dst)[2 * lane] = int4{o[0], o[1], o[2], o[3]};
   reinterpret_cast<int4*>(dst)[2 * lane + 1] = int4{o[4], o[5], o[6], o[7]};
@@ -166,6 +176,17 @@ __global__ __launch_bounds__(64 * kWaves, 3) void sweep_mfma4_kernel(SweepArgs a
   Ctr4 x_next = noise_block((uint32_t)half, a.start_step, (uint32_t)trial, stream, k0, k1);
   int done = a.T;
   stage_table(sTab, gTab4[lane], lane);  // table of step 0
+  // the accumulator start, kept in registers (fenced: not rematerialised as
+  // sixteen moves before every row tile)
+  v16f bias;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    float b = kAccBias;
+    PIM_FENCE(b);
+    bias[i] = b;
+  }
+  // the 2^22 s terms of one step's energy sums: 2^22 (decided spins - 2 negatives)
+  constexpr int kDecided = 16 * (NT - 1) + TAIL;
 
   for (int t = 0;; ++t) {
     const int tg = a.start_step + t;
@@ -183,7 +204,8 @@ __global__ __launch_bounds__(64 * kWaves, 3) void sweep_mfma4_kernel(SweepArgs a
     PIM_FENCE(ctr_half);
     PIM_FENCE(ctr_trial);
     const v4i* sJl0 = sJ + lane;
-    v16f acc_next = row_tile<NT>(sJl0, 0, S);
+    v16f acc_next = row_tile<NT>(sJl0, 0, S, bias);
+    int32_t nneg = 0;  // negative spins among this lane's decided registers
 #pragma unroll
     for (int mt = 0; mt < NT; ++mt) {
       const v16f acc = acc_next;
@@ -205,24 +227,28 @@ __global__ __launch_bounds__(64 * kWaves, 3) void sweep_mfma4_kernel(SweepArgs a
         th[r] = tab[(int)((xw[r >> 2] >> (8 * (r & 3))) & 0xFFu) ^ sv[r]];
       }
       // (2) the next tile's MFMA chain and noise block cover the LDS latency
-      if (mt + 1 < NT) acc_next = row_tile<NT>(sJl, mt + 1, S);
+      if (mt + 1 < NT) acc_next = row_tile<NT>(sJl, mt + 1, S, bias);
       if (mt + 1 < NT) x_next = noise_block(2u * (mt + 1) + ctr_half, tg, ctr_trial, stream, k0, k1);
       else x_next = noise_block(ctr_half, tg + 1, ctr_trial, stream, k0, k1);
       // (3) energy of s(t) and the decisions of this tile
       int d[16];
 #pragma unroll
       for (int r = 0; r < kRegs; ++r) {
-        int I = (int)acc[r];  // 2 I, exact
+        int I = __float_as_int(acc[r]);  // 0x4B400000 + 2 I
         int v = I;
         if (HAS_H) {
           const int hv = sH[hoff + r];
           I += hv;
           v = I + hv;
         }
-        ep += __mul24(sv[r], v);  // |v| <= 4 * 32766 < 2^23
+        ep += __mul24(sv[r], v);  // low 24 bits: 2^22 + 2 I (+ 4 h), below 2^23
         PIM_FENCE(ep);            // one multiply-add per term
         d[r] = I - th[r];         // >= 0  <=>  s(t+1) = +1
       }
+      // sign bits of the decided registers' old spins (registers 8q + b in
+      // the low nibbles, 8q + 4 + b in the high ones)
+      nneg += __builtin_popcount(sw[0] & (kRegs >= 8 ? 0x88888888u : 0x08080808u)) +
+              (kRegs > 8 ? __builtin_popcount(sw[1] & (kRegs >= 16 ? 0x88888888u : 0x08080808u)) : 0);
       uint32_t w[2];
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
@@ -249,6 +275,8 @@ __global__ __launch_bounds__(64 * kWaves, 3) void sweep_mfma4_kernel(SweepArgs a
       PIM_FENCE(Sn[mt].y);
       __builtin_amdgcn_sched_barrier(0);
     }
+    // sum over decided spins of s (2^22 + 2 I + 4 h), less 2^22 sum s
+    ep -= kLow24Bias * (kDecided - 2 * nneg);
     const int32_t E = -((ep + __shfl_xor(ep, 32)) / 4);  // sum s (2 I + 4 h) = 4 * (-E)
     if (E < e_best) {
       e_best = E;
