@@ -394,12 +394,13 @@ def uneven_leg(args):
     """Batched SK-1 with uneven N: 128 instances, N_k = [100, 200, 400, 800,
     1000][k mod 5], J = +-1, h = 0, c = 1/sqrt(N_k), xi = 0.5, 1024 replicas
     each, beta linear 0.1 -> 3.0 with eta = sqrt(beta / 5).  All instances run
-    in one batch: one part per N, launched together as one captured graph.
-    Parts with N > 256 run on e2m1 (FP4) operands (J = +-1 is exact in e2m1,
-    results identical to int8); the same graph on int8 operands is timed
-    beside it and must give identical results.  Also each N bucket alone, for
-    per-N rates and MFMA fractions (2 N^2 ops per replica-step, against the
-    int8 peak and, for e2m1 buckets, the FP4 peak)."""
+    in one batch: one part per N, launched together as one captured graph, on
+    e2m1 (FP4) operands (J = +-1 is exact in e2m1, results identical to int8):
+    couplings in LDS for N <= 256, and the parts above as one launch over a
+    longest-first work list.  The same graph on int8 operands is timed beside
+    it and must give identical results.  Also each N bucket alone on both
+    operand types, for per-N rates and MFMA fractions (2 N^2 ops per
+    replica-step, against the int8 and the FP4 peaks)."""
     import paper_2604_17109_amd as pim
     import workloads as w
     sizes = [100, 200, 400, 800, 1000]
@@ -428,7 +429,7 @@ def uneven_leg(args):
     ops = float(sum(2 * n * n for n in ns)) * R * (T + 1)
     hits = [(r["first_hit"] >= 0).mean() for r in res4]
     out = {"workload": f"{count} SK-1 instances, N in {sizes}, {R} replicas x {T} steps, one graph launch",
-           "kernel": "int8 MFMA for N <= 256 (couplings in LDS), e2m1 (FP4) MFMA for N > 256 (streamed)",
+           "kernel": "e2m1 (FP4) MFMA: couplings in LDS for N <= 256, streamed above (one launch over all such parts)",
            "kernel_ms": kms, "spin_updates_per_s": updates / (kms / 1e3),
            "int8_mfma_frac": ops / (kms / 1e3) / INT8_MFMA_PEAK,
            "int8_operands": {"kernel_ms": k8, "spin_updates_per_s": updates / (k8 / 1e3),
@@ -443,11 +444,9 @@ def uneven_leg(args):
         sub = [i for i, m in zip(insts, ns) if m == n]
         sub_tgt = [t for t, m in zip(tgt, ns) if m == n]
         b = pim.Batch(sub, R)
-        big = n > 256
-        if big:
-            b.run(beta, eta, seed=2, kernel="mfma")
-            b.run(beta, eta, seed=2, target=sub_tgt, kernel="mfma")
-            k8n = b.kernel_ms()
+        b.run(beta, eta, seed=2, kernel="mfma")
+        b.run(beta, eta, seed=2, target=sub_tgt, kernel="mfma")
+        k8n = b.kernel_ms()
         b.run(beta, eta, seed=2, kernel="f4")
         b.run(beta, eta, seed=2, target=sub_tgt, kernel="f4")
         k = b.kernel_ms()
@@ -460,12 +459,10 @@ def uneven_leg(args):
         tau = (k / 1e3) / (len(sub) * R * T)
         out["per_n"][str(n)] = {"instances": len(sub), "kernel_ms": k, "spin_updates_per_s": u / (k / 1e3),
                                 "int8_mfma_frac": o / (k / 1e3) / INT8_MFMA_PEAK, "p_bar_relaxed": p,
-                                "n99": n99, "tts99_s": n99 * T * tau if n99 else None,
-                                "operands": "e2m1" if big else "int8"}
-        if big:
-            out["per_n"][str(n)]["fp4_mfma_frac"] = o / (k / 1e3) / FP4_MFMA_PEAK
-            out["per_n"][str(n)]["int8_operands"] = {"kernel_ms": k8n, "spin_updates_per_s": u / (k8n / 1e3),
-                                                     "int8_mfma_frac": o / (k8n / 1e3) / INT8_MFMA_PEAK}
+                                "n99": n99, "tts99_s": n99 * T * tau if n99 else None, "operands": "e2m1",
+                                "fp4_mfma_frac": o / (k / 1e3) / FP4_MFMA_PEAK,
+                                "int8_operands": {"kernel_ms": k8n, "spin_updates_per_s": u / (k8n / 1e3),
+                                                  "int8_mfma_frac": o / (k8n / 1e3) / INT8_MFMA_PEAK}}
         if e_sa:
             out["per_n"][str(n)]["reference"] = reference_summary([g for g, m in zip(gpu, ns) if m == n],
                                                                   [a for a, m in zip(e_sa, ns) if m == n])
