@@ -34,6 +34,7 @@
 
 #include <climits>
 #include <cstdint>
+#include <type_traits>
 
 #include "internal.hpp"
 #include "philox.hpp"
@@ -166,14 +167,32 @@ __device__ __forceinline__ void rows_f4(const v4i* __restrict__ gA, const v4i* s
 
 // Eq. (4) decisions and Eq. (1) energy terms of row tile mt for the four
 // column blocks: s(t+1) of the tile written into the next spin buffer, the
-// partial sums s_r (2 I_r + 4 h_r) added to ep.  The accumulator holds 2 I
-// exactly; sH and tab hold 2 h and the doubled thresholds, indexed as in the
-// int8 kernel by u ^ s (u ^ 1 for s = +1, ~u for s = -1).
+// energy terms added to ep.  The accumulator holds 2 I exactly; tab holds the
+// doubled thresholds, indexed as in the int8 kernel by u ^ s (u ^ 1 for
+// s = +1, ~u for s = -1).
+//   With fields (HAS_H): sH holds 2 h, the field is converted to int32, and
+//   ep (int32) gathers s (2 I + 4 h).
+//   Without: tab holds binary32 2 theta, the decision is one binary32
+//   subtraction of exact integers, and ep (binary32) gathers (2 s)(2 I) with
+//   one fused multiply-add per spin, 2 s being the old spin's e2m1 value
+//   converted two at a time; a lane's step total over at most 64 spins stays
+//   below 2^23, so every partial sum is exact.
+template <bool HAS_H>
+using EpT = typename std::conditional<HAS_H, int32_t, float>::type;
+
+// The two e2m1 spins of byte B of w as binary32 (low nibble, high nibble).
+template <int B>
+__device__ __forceinline__ void spin_pair(uint32_t w, float& lo, float& hi) {
+  const auto p = __builtin_amdgcn_cvt_scalef32_pk_f32_fp4(w, 1.0f, B);
+  lo = p[0];
+  hi = p[1];
+}
+
 template <bool HAS_H>
 __device__ __forceinline__ void decide_f4(const v16f (&acc)[kCB], const uint2* sCur, uint2* sNxt,
                                           const int32_t* sH, const int32_t* tab, int mt, int lane_off, int half,
                                           uint32_t ctr_half, uint32_t ctr_trial, int tg, uint32_t stream,
-                                          uint32_t k0, uint32_t k1, int32_t (&ep)[kCB]) {
+                                          uint32_t k0, uint32_t k1, EpT<HAS_H> (&ep)[kCB]) {
   const int hoff = 32 * mt + 16 * half;
 #pragma unroll
   for (int c = 0; c < kCB; ++c) {
@@ -191,24 +210,39 @@ __device__ __forceinline__ void decide_f4(const v16f (&acc)[kCB], const uint2* s
       sv[r] = (int)__builtin_amdgcn_sbfe(sw[r >> 3], 8 * (r & 3) + 4 * ((r >> 2) & 1) + 2, 2);  // +1 / -1
       th[r] = tab[(int)((xw[r >> 2] >> (8 * (r & 3))) & 0xFFu) ^ sv[r]];
     }
-    int hoff_c = hoff;
-    if (HAS_H) PIM_FENCE(hoff_c);
     int d[16];
-    int32_t e = ep[c];
+    if constexpr (HAS_H) {
+      int hoff_c = hoff;
+      PIM_FENCE(hoff_c);
+      int32_t e = ep[c];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
-      int I = (int)acc[c][r];  // 2 I, exact
-      int v = I;
-      if (HAS_H) {
+      for (int r = 0; r < 16; ++r) {
+        int I = (int)acc[c][r];  // 2 I, exact
         const int hv = sH[hoff_c + r];
         I += hv;
-        v = I + hv;
+        const int v = I + hv;
+        e += __mul24(sv[r], v);  // |v| <= 4 * 32766 < 2^23
+        PIM_FENCE(e);            // one multiply-add per term, not a multiply and an add tree
+        d[r] = I - th[r];        // >= 0  <=>  s(t+1) = +1
       }
-      e += __mul24(sv[r], v);  // |v| <= 4 * 32766 < 2^23
-      PIM_FENCE(e);            // one multiply-add per term, not a multiply and an add tree
-      d[r] = I - th[r];        // >= 0  <=>  s(t+1) = +1
+      ep[c] = e;
+    } else {
+      float s2[16];  // 2 s: the old spins' e2m1 values, registers 8q + b and 8q + 4 + b per byte
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        spin_pair<0>(sw[q], s2[8 * q + 0], s2[8 * q + 4]);
+        spin_pair<1>(sw[q], s2[8 * q + 1], s2[8 * q + 5]);
+        spin_pair<2>(sw[q], s2[8 * q + 2], s2[8 * q + 6]);
+        spin_pair<3>(sw[q], s2[8 * q + 3], s2[8 * q + 7]);
+      }
+      float e = ep[c];
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        e = __builtin_fmaf(s2[r], acc[c][r], e);                       // (2 s)(2 I), exact
+        d[r] = __float_as_int(acc[c][r] - __int_as_float(th[r]));     // 2 (I - theta), exact; sign = decision
+      }
+      ep[c] = e;
     }
-    ep[c] = e;
     uint32_t w[2];
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
@@ -227,7 +261,9 @@ __device__ __forceinline__ void decide_f4(const v16f (&acc)[kCB], const uint2* s
 }
 
 // Step table into LDS as doubled thresholds: lane l holds host entries
-// 8l .. 8l + 7 (16-bit), written as eight int32 2 * theta.
+// 8l .. 8l + 7 (16-bit), written as eight 2 * theta, int32 with fields and
+// binary32 without (|2 theta| <= 2^16: exact either way).
+template <bool HAS_H>
 __device__ __forceinline__ void stage_table(int32_t* dst, uint4 v, int lane) {
   const uint32_t w[4] = {v.x, v.y, v.z, v.w};
   int32_t o[8];
@@ -235,6 +271,10 @@ __device__ __forceinline__ void stage_table(int32_t* dst, uint4 v, int lane) {
   for (int q = 0; q < 4; ++q) {
     o[2 * q] = (int32_t)(w[q] << 16) >> 15;               // 2 * sign-extended low half
     o[2 * q + 1] = (int32_t)(w[q] & 0xFFFF0000u) >> 15;   // 2 * sign-extended high half
+    if (!HAS_H) {
+      o[2 * q] = __float_as_int((float)o[2 * q]);
+      o[2 * q + 1] = __float_as_int((float)o[2 * q + 1]);
+    }
   }
   reinterpret_cast<int4*>(dst)[2 * lane] = int4{o[0], o[1], o[2], o[3]};
   reinterpret_cast<int4*>(dst)[2 * lane + 1] = int4{o[4], o[5], o[6], o[7]};
@@ -311,7 +351,7 @@ __device__ __forceinline__ void big4_body(const SweepArgs& a, int nt, int inst, 
   // table of step 0 into table buffer 0; the next one waits in registers
   uint4 nxt = uint4{0, 0, 0, 0};
   if (wave == 0) {
-    stage_table(sTab, gTab4[lane], lane);
+    stage_table<HAS_H>(sTab, gTab4[lane], lane);
     nxt = gTab4[(size_t)min(1, a.T - 1) * 64 + lane];
   }
   if (threadIdx.x == 0) sFlag[0] = 0;
@@ -336,14 +376,14 @@ __device__ __forceinline__ void big4_body(const SweepArgs& a, int nt, int inst, 
     // the table of step t+1 into the other table buffer (last read in step
     // t-1, before its barrier), then the fetch of the one after
     if (wave == 0) {
-      stage_table(sTab + (cur ^ 1) * kTabEntries, nxt, lane);
+      stage_table<HAS_H>(sTab + (cur ^ 1) * kTabEntries, nxt, lane);
       nxt = gTab4[(size_t)min(t + 2, a.T - 1) * 64 + lane];
     }
     const int32_t* tab = sTab + cur * kTabEntries + kNoiseVals;
     const v4i* sCur = sB + cur * buf;
     const uint2* sCur2 = reinterpret_cast<const uint2*>(sCur);
     uint2* sNxt2 = sB2 + (cur ^ 1) * 2 * buf;
-    int32_t ep[kCB];
+    EpT<HAS_H> ep[kCB];
 #pragma unroll
     for (int c = 0; c < kCB; ++c) ep[c] = 0;
     uint32_t ctr_half = (uint32_t)half, ctr_trial = (uint32_t)trial0;
@@ -374,7 +414,7 @@ __device__ __forceinline__ void big4_body(const SweepArgs& a, int nt, int inst, 
     // per-trial partial energies of s(t) over this wave's rows
 #pragma unroll
     for (int c = 0; c < kCB; ++c) {
-      const int32_t epc = half_sum(ep[c]);
+      const int32_t epc = half_sum((int32_t)ep[c]);  // binary32 totals are exact integers below 2^23
       if (half == 0) sE[((cur * kWaves + wave) * kCB + c) * 32 + col] = epc;
     }
     if (threadIdx.x == 0 && (t & 255) == 0 && t < a.T)
@@ -386,7 +426,8 @@ __device__ __forceinline__ void big4_body(const SweepArgs& a, int nt, int inst, 
       int32_t tot = 0;
 #pragma unroll
       for (int w = 0; w < kWaves; ++w) tot += sE[((cur * kWaves + w) * kCB + c) * 32 + col];
-      const int32_t E = -(tot / 4);  // tot = 2 sum_i s_i (I_i + 2 h_i)
+      // tot = 2 sum_i s_i (I_i + 2 h_i) with fields, 4 sum_i s_i I_i without
+      const int32_t E = HAS_H ? -(tot / 4) : -(tot / 8);
       if (E < e_best[c]) {
         e_best[c] = E;
         if (writer) sStat[(0 * kCB + c) * 32 + col] = tg;
