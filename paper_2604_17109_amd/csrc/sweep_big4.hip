@@ -38,13 +38,12 @@
 
 #include "internal.hpp"
 #include "philox.hpp"
+#include "e2m1.hpp"
 
 namespace pim {
 namespace {
 
-typedef int v4i __attribute__((ext_vector_type(4)));
-typedef int v8i __attribute__((ext_vector_type(8)));
-typedef float v16f __attribute__((ext_vector_type(16)));
+using namespace e2m1;
 
 constexpr int kWaves = 8;            // two waves per SIMD
 constexpr int kCB = 4;               // 32-trial column blocks per workgroup
@@ -52,36 +51,8 @@ constexpr int kTrialsWG = 32 * kCB;  // trials per workgroup
 constexpr int kXcds = 8;
 constexpr int kMinTiles = PIM_MAX_N_LDS / 32 + 1;  // 9
 constexpr int kMaxTiles = PIM_MAX_N / 32;          // 32
-constexpr uint32_t kPlusTwos = 0x44444444u;        // eight e2m1 +2.0 (sign bit 3 of each nibble clear)
-constexpr int kTab32Bytes = kTabEntries * 4;       // a step table in LDS: doubled thresholds as int32
 
 #define PIM_FENCE(v) asm volatile("" : "+v"(v))
-
-// C += A . B on 32x64 / 64x32 e2m1 operands (16 bytes per lane; the upper
-// half of the 8-register operand is unused for this format).  Zero scale
-// operands select the unscaled instruction.
-__device__ __forceinline__ v16f mfma_f4(v4i a, v4i b, v16f c) {
-  const v8i a8 = {a[0], a[1], a[2], a[3], 0, 0, 0, 0};
-  const v8i b8 = {b[0], b[1], b[2], b[3], 0, 0, 0, 0};
-  return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a8, b8, c, 4, 4, 0, 0, 0, 0);
-}
-
-// Spin encodings.  A lane holds the 16 spins r = 0..15 of a row tile (spin
-// 32 mt + 16 half + r).  As e2m1 (s = +1 -> +2.0 = 0x4, s = -1 -> -2.0 = 0xC)
-// they sit in two words q = 0, 1: byte b of word q holds spin 8q + b in its
-// low nibble and spin 8q + 4 + b in its high nibble; the top two bits of a
-// nibble, read as a signed 2-bit field, are s itself.  As int8 (+-1 bytes)
-// they sit in four words k: byte b of word k is spin 4k + b.
-__device__ __forceinline__ uint32_t nib_from_i8(uint32_t lo, uint32_t hi) {
-  return ((lo >> 4) & 0x08080808u) | (hi & 0x80808080u) | kPlusTwos;
-}
-__device__ __forceinline__ uint32_t i8_from_nib(uint32_t w, int hi) {
-  return 0x01010101u + 0xFEu * ((w >> (4 * hi + 3)) & 0x01010101u);
-}
-__device__ __forceinline__ v4i i8_tile(uint2 w) {
-  return v4i{(int)i8_from_nib(w.x, 0), (int)i8_from_nib(w.x, 1), (int)i8_from_nib(w.y, 0),
-             (int)i8_from_nib(w.y, 1)};
-}
 
 __device__ __forceinline__ int32_t half_sum(int32_t v) {
   const auto r = __builtin_amdgcn_permlane32_swap((uint32_t)v, (uint32_t)v, false, false);
@@ -139,7 +110,7 @@ __device__ __forceinline__ void rows_f4(const v4i* __restrict__ gA, const v4i* s
 #pragma unroll
       for (int c = 0; c < kCB; ++c)
 #pragma unroll
-        for (int r = 0; r < MT; ++r) acc[r][c] = mfma_f4(ar[r][i], b[c], acc[r][c]);
+        for (int r = 0; r < MT; ++r) acc[r][c] = mfma(ar[r][i], b[c], acc[r][c]);
       const int kf = min(kt + i + D, np - 1);
 #pragma unroll
       for (int r = 0; r < MT; ++r) ar[r][i] = gA[(fa[r] + kf) * 64 + lane];
@@ -156,7 +127,7 @@ __device__ __forceinline__ void rows_f4(const v4i* __restrict__ gA, const v4i* s
 #pragma unroll
       for (int c = 0; c < kCB; ++c)
 #pragma unroll
-        for (int r = 0; r < MT; ++r) acc[r][c] = mfma_f4(ar[r][i], b[c], acc[r][c]);
+        for (int r = 0; r < MT; ++r) acc[r][c] = mfma(ar[r][i], b[c], acc[r][c]);
       if (kt + i + 1 < np) {
 #pragma unroll
         for (int c = 0; c < kCB; ++c) b[c] = sB[sb_index(kt + i + 1, c, lane)];
@@ -207,7 +178,7 @@ __device__ __forceinline__ void decide_f4(const v16f (&acc)[kCB], const uint2* s
     int sv[16], th[16];
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-      sv[r] = (int)__builtin_amdgcn_sbfe(sw[r >> 3], 8 * (r & 3) + 4 * ((r >> 2) & 1) + 2, 2);  // +1 / -1
+      sv[r] = spin_of(sw, r);
       th[r] = tab[(int)((xw[r >> 2] >> (8 * (r & 3))) & 0xFFu) ^ sv[r]];
     }
     int d[16];
@@ -331,13 +302,10 @@ __device__ __forceinline__ void big4_body(const SweepArgs& a, int nt, int inst, 
       } else {
         const Ctr4 x = philox4x32_10(Ctr4{(uint32_t)(2 * mt + half), 0u, (uint32_t)(trial0 + 32 * c),
                                           (kDomainInit << 24) | stream}, k0, k1);
-        // S2: s = +1 iff u >= 128, i.e. bit 7 of the byte set
-        const uint32_t xs[4] = {x.x, x.y, x.z, x.w};
-#pragma unroll
-        for (int q = 0; q < 4; ++q) v[q] = (int)(0xFFFFFFFFu - 0xFEu * ((xs[q] >> 7) & 0x01010101u));
+        v = v4i{(int)spins_from_bits(x.x), (int)spins_from_bits(x.y), (int)spins_from_bits(x.z),
+                (int)spins_from_bits(x.w)};
       }
-      sB2[sb_half(mt, c, lane)] = uint2{nib_from_i8((uint32_t)v[0], (uint32_t)v[1]),
-                                        nib_from_i8((uint32_t)v[2], (uint32_t)v[3])};
+      sB2[sb_half(mt, c, lane)] = nib_tile(v);
     }
   }
   // odd tile count: the second half of the last K step has no spins (its

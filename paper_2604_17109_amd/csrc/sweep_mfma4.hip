@@ -35,45 +35,19 @@
 
 #include "internal.hpp"
 #include "philox.hpp"
+#include "e2m1.hpp"
 
 namespace pim {
 namespace {
 
-typedef int v4i __attribute__((ext_vector_type(4)));
-typedef int v8i __attribute__((ext_vector_type(8)));
-typedef float v16f __attribute__((ext_vector_type(16)));
+using namespace e2m1;
 
 constexpr int kWaves = 4;                      // most waves (32-trial blocks) per workgroup
-constexpr int kTab32Bytes = kTabEntries * 4;   // a step table in LDS: doubled thresholds as int32
-constexpr uint32_t kPlusTwos = 0x44444444u;    // eight e2m1 +2.0
 constexpr float kAccBias = 12582912.0f;        // 1.5 * 2^23: start of every row tile's sum
 constexpr int32_t kAccBiasBits = 0x4B400000;   // its bit pattern; + 2 I is the biased field
 constexpr int32_t kLow24Bias = 0x400000;       // its low 24 bits: 2^22
 
 #define PIM_FENCE(v) asm volatile("" : "+v"(v))
-
-__device__ __forceinline__ v16f mfma_f4(v4i a, v4i b, v16f c) {
-  const v8i a8 = {a[0], a[1], a[2], a[3], 0, 0, 0, 0};
-  const v8i b8 = {b[0], b[1], b[2], b[3], 0, 0, 0, 0};
-  return __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a8, b8, c, 4, 4, 0, 0, 0, 0);
-}
-
-// int8 spins of rows 8q..8q+3 (lo) and 8q+4..8q+7 (hi) -> one e2m1 word
-__device__ __forceinline__ uint32_t nib_from_i8(uint32_t lo, uint32_t hi) {
-  return ((lo >> 4) & 0x08080808u) | (hi & 0x80808080u) | kPlusTwos;
-}
-// e2m1 word -> int8 spins of rows 8q + 4 hi + b, b = 0..3
-__device__ __forceinline__ uint32_t i8_from_nib(uint32_t w, int hi) {
-  return 0x01010101u + 0xFEu * ((w >> (4 * hi + 3)) & 0x01010101u);
-}
-__device__ __forceinline__ v4i i8_tile(uint2 w) {
-  return v4i{(int)i8_from_nib(w.x, 0), (int)i8_from_nib(w.x, 1), (int)i8_from_nib(w.y, 0),
-             (int)i8_from_nib(w.y, 1)};
-}
-// +1 where the byte's top bit (u >= 128) is set, -1 elsewhere (int8 spins)
-__device__ __forceinline__ uint32_t spins_from_bits(uint32_t w) {
-  return 0xFFFFFFFFu - 0xFEu * ((w >> 7) & 0x01010101u);
-}
 
 __device__ __forceinline__ Ctr4 noise_block(uint32_t block, int tg, uint32_t trial, uint32_t stream,
                                             uint32_t k0, uint32_t k1) {
@@ -94,9 +68,9 @@ __device__ __forceinline__ v4i b_operand(const uint2 (&S)[NT], int p) {
 template <int NT>
 __device__ __forceinline__ v16f row_tile(const v4i* sJl, int mt, const uint2 (&S)[NT], const v16f& bias) {
   constexpr int NP = (NT + 1) / 2;
-  v16f acc = mfma_f4(sJl[(mt * NP) * 64], b_operand<NT>(S, 0), bias);
+  v16f acc = mfma(sJl[(mt * NP) * 64], b_operand<NT>(S, 0), bias);
 #pragma unroll
-  for (int p = 1; p < NP; ++p) acc = mfma_f4(sJl[(mt * NP + p) * 64], b_operand<NT>(S, p), acc);
+  for (int p = 1; p < NP; ++p) acc = mfma(sJl[(mt * NP + p) * 64], b_operand<NT>(S, p), acc);
   return acc;
 }
 
@@ -169,7 +143,7 @@ __global__ __launch_bounds__(64 * kWaves, 3) void sweep_mfma4_kernel(SweepArgs a
       v = v4i{(int)spins_from_bits(x.x), (int)spins_from_bits(x.y), (int)spins_from_bits(x.z),
               (int)spins_from_bits(x.w)};
     }
-    S[mt] = uint2{nib_from_i8((uint32_t)v[0], (uint32_t)v[1]), nib_from_i8((uint32_t)v[2], (uint32_t)v[3])};
+    S[mt] = nib_tile(v);
   }
 
   int32_t e_best = INT_MAX, t_best = -1, first_hit = -1, e_cur = 0;
@@ -223,7 +197,7 @@ __global__ __launch_bounds__(64 * kWaves, 3) void sweep_mfma4_kernel(SweepArgs a
       int sv[16], th[16];
 #pragma unroll
       for (int r = 0; r < kRegs; ++r) {
-        sv[r] = (int)__builtin_amdgcn_sbfe(sw[r >> 3], 8 * (r & 3) + 4 * ((r >> 2) & 1) + 2, 2);  // +1 / -1
+        sv[r] = spin_of(sw, r);
         th[r] = tab[(int)((xw[r >> 2] >> (8 * (r & 3))) & 0xFFu) ^ sv[r]];
       }
       // (2) the next tile's MFMA chain and noise block cover the LDS latency
