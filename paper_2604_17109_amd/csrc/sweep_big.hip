@@ -85,18 +85,17 @@ __device__ __forceinline__ int sb_index(int kt, int c, int lane) { return (kt * 
 // a scheduling barrier per K step keeps the compiler from hoisting more
 // operand loads than these registers.  Fragment indices are wave-uniform
 // (scalar) and the lane offset is a 32-bit register: each load is a scalar
-// base plus one 32-bit vector offset.
+// base plus one 32-bit vector offset.  K step 0 is peeled so its MFMAs take a
+// zero accumulator as an inline constant (inside the loop the accumulators
+// would have to be zeroed by moves, one per register); K step k uses ring
+// slot k % D.
 template <int MT>
 __device__ __forceinline__ void big_rows(const v4i* __restrict__ gA, const v4i* sB, int lane, int mt0, int nt,
                                          v16i (&acc)[MT][kCB]) {
   constexpr int D = MT == 1 ? 4 : 2;
   int fa[MT];
 #pragma unroll
-  for (int r = 0; r < MT; ++r) {
-    fa[r] = (mt0 + kWaves * r) * nt;
-#pragma unroll
-    for (int c = 0; c < kCB; ++c) acc[r][c] = v16i{};
-  }
+  for (int r = 0; r < MT; ++r) fa[r] = (mt0 + kWaves * r) * nt;
   v4i ar[MT][D], b[kCB];
 #pragma unroll
   for (int r = 0; r < MT; ++r)
@@ -104,35 +103,48 @@ __device__ __forceinline__ void big_rows(const v4i* __restrict__ gA, const v4i* 
     for (int i = 0; i < D; ++i) ar[r][i] = gA[(fa[r] + i) * 64 + lane];  // nt >= 9 > D
 #pragma unroll
   for (int c = 0; c < kCB; ++c) b[c] = sB[sb_index(0, c, lane)];
-  const int nfull = nt - nt % D;
-  int kt = 0;
+  // K step 0
+#pragma unroll
+  for (int c = 0; c < kCB; ++c)
+#pragma unroll
+    for (int r = 0; r < MT; ++r) acc[r][c] = __builtin_amdgcn_mfma_i32_32x32x32_i8(ar[r][0], b[c], v16i{}, 0, 0, 0);
+#pragma unroll
+  for (int r = 0; r < MT; ++r) ar[r][0] = gA[(fa[r] + D) * 64 + lane];  // D < nt
+#pragma unroll
+  for (int c = 0; c < kCB; ++c) b[c] = sB[sb_index(1, c, lane)];
+  __builtin_amdgcn_sched_barrier(0);
+  // K steps 1 .. nt - 1: groups of D (K step kt + i, kt = 1 mod D, in slot
+  // (1 + i) % D), then a tail of fewer than D
+  const int nfull = 1 + (nt - 1) - (nt - 1) % D;
+  int kt = 1;
   for (; kt < nfull; kt += D) {
 #pragma unroll
     for (int i = 0; i < D; ++i) {
+      const int slot = (1 + i) % D;
 #pragma unroll
       for (int c = 0; c < kCB; ++c)
 #pragma unroll
         for (int r = 0; r < MT; ++r)
-          acc[r][c] = __builtin_amdgcn_mfma_i32_32x32x32_i8(ar[r][i], b[c], acc[r][c], 0, 0, 0);
-      // refill the slots after their last use, so the loads land in place
+          acc[r][c] = __builtin_amdgcn_mfma_i32_32x32x32_i8(ar[r][slot], b[c], acc[r][c], 0, 0, 0);
+      // refill the slot after its last use, so the load lands in place
       const int kf = min(kt + i + D, nt - 1);
 #pragma unroll
-      for (int r = 0; r < MT; ++r) ar[r][i] = gA[(fa[r] + kf) * 64 + lane];
+      for (int r = 0; r < MT; ++r) ar[r][slot] = gA[(fa[r] + kf) * 64 + lane];
       const int kn = min(kt + i + 1, nt - 1);
 #pragma unroll
       for (int c = 0; c < kCB; ++c) b[c] = sB[sb_index(kn, c, lane)];
       __builtin_amdgcn_sched_barrier(0);
     }
   }
-  // tail: the last nt - nfull (< D) K steps, in ring slots 0 .. D - 2
 #pragma unroll
   for (int i = 0; i < D - 1; ++i) {
     if (kt + i < nt) {  // uniform
+      const int slot = (1 + i) % D;
 #pragma unroll
       for (int c = 0; c < kCB; ++c)
 #pragma unroll
         for (int r = 0; r < MT; ++r)
-          acc[r][c] = __builtin_amdgcn_mfma_i32_32x32x32_i8(ar[r][i], b[c], acc[r][c], 0, 0, 0);
+          acc[r][c] = __builtin_amdgcn_mfma_i32_32x32x32_i8(ar[r][slot], b[c], acc[r][c], 0, 0, 0);
       if (kt + i + 1 < nt) {
 #pragma unroll
         for (int c = 0; c < kCB; ++c) b[c] = sB[sb_index(kt + i + 1, c, lane)];

@@ -80,21 +80,20 @@ __device__ __forceinline__ int sb_half(int mt, int c, int lane) { return 2 * sb_
 // Fields of MT (1 or 2) row tiles mt0, mt0 + kWaves for the four column
 // blocks over np K steps: each K step MT A fragments from global memory, four
 // B fragments from LDS, MT x 4 MFMAs.  The A fragments stream through a ring
-// of D slots per row tile, refilled right after the MFMAs that read them from
-// a clamped, always in-bounds index; the B fragments of the next K step are
-// read right after the current MFMAs are issued; a scheduling barrier per K
-// step keeps the compiler from hoisting more loads than these registers.
+// of D slots per row tile (K step k uses slot k % D), refilled right after
+// the MFMAs that read them from a clamped, always in-bounds index; the B
+// fragments of the next K step are read right after the current MFMAs are
+// issued; a scheduling barrier per K step keeps the compiler from hoisting
+// more loads than these registers.  K step 0 is peeled so its MFMAs take a
+// zero accumulator as an inline constant: inside the loop the accumulators
+// would have to be zeroed by moves, one per register.
 template <int MT>
 __device__ __forceinline__ void rows_f4(const v4i* __restrict__ gA, const v4i* sB, int lane, int mt0, int np,
                                         v16f (&acc)[MT][kCB]) {
   constexpr int D = MT == 1 ? 4 : 2;
   int fa[MT];
 #pragma unroll
-  for (int r = 0; r < MT; ++r) {
-    fa[r] = (mt0 + kWaves * r) * np;
-#pragma unroll
-    for (int c = 0; c < kCB; ++c) acc[r][c] = v16f{};
-  }
+  for (int r = 0; r < MT; ++r) fa[r] = (mt0 + kWaves * r) * np;
   v4i ar[MT][D], b[kCB];
 #pragma unroll
   for (int r = 0; r < MT; ++r)
@@ -102,32 +101,44 @@ __device__ __forceinline__ void rows_f4(const v4i* __restrict__ gA, const v4i* s
     for (int i = 0; i < D; ++i) ar[r][i] = gA[(fa[r] + i) * 64 + lane];  // np >= 5 > D
 #pragma unroll
   for (int c = 0; c < kCB; ++c) b[c] = sB[sb_index(0, c, lane)];
-  const int nfull = np - np % D;
-  int kt = 0;
+  // K step 0
+#pragma unroll
+  for (int c = 0; c < kCB; ++c)
+#pragma unroll
+    for (int r = 0; r < MT; ++r) acc[r][c] = mfma(ar[r][0], b[c], v16f{});
+#pragma unroll
+  for (int r = 0; r < MT; ++r) ar[r][0] = gA[(fa[r] + D) * 64 + lane];  // D < np
+#pragma unroll
+  for (int c = 0; c < kCB; ++c) b[c] = sB[sb_index(1, c, lane)];
+  __builtin_amdgcn_sched_barrier(0);
+  // K steps 1 .. np - 1: groups of D, then a tail of fewer than D
+  const int nfull = 1 + (np - 1) - (np - 1) % D;
+  int kt = 1;
   for (; kt < nfull; kt += D) {
 #pragma unroll
     for (int i = 0; i < D; ++i) {
+      const int slot = (1 + i) % D;  // K step kt + i, kt = 1 mod D
 #pragma unroll
       for (int c = 0; c < kCB; ++c)
 #pragma unroll
-        for (int r = 0; r < MT; ++r) acc[r][c] = mfma(ar[r][i], b[c], acc[r][c]);
+        for (int r = 0; r < MT; ++r) acc[r][c] = mfma(ar[r][slot], b[c], acc[r][c]);
       const int kf = min(kt + i + D, np - 1);
 #pragma unroll
-      for (int r = 0; r < MT; ++r) ar[r][i] = gA[(fa[r] + kf) * 64 + lane];
+      for (int r = 0; r < MT; ++r) ar[r][slot] = gA[(fa[r] + kf) * 64 + lane];
       const int kn = min(kt + i + 1, np - 1);
 #pragma unroll
       for (int c = 0; c < kCB; ++c) b[c] = sB[sb_index(kn, c, lane)];
       __builtin_amdgcn_sched_barrier(0);
     }
   }
-  // tail: the last np - nfull (< D) K steps, in ring slots 0 .. D - 2
 #pragma unroll
   for (int i = 0; i < D - 1; ++i) {
     if (kt + i < np) {  // uniform
+      const int slot = (1 + i) % D;
 #pragma unroll
       for (int c = 0; c < kCB; ++c)
 #pragma unroll
-        for (int r = 0; r < MT; ++r) acc[r][c] = mfma(ar[r][i], b[c], acc[r][c]);
+        for (int r = 0; r < MT; ++r) acc[r][c] = mfma(ar[r][slot], b[c], acc[r][c]);
       if (kt + i + 1 < np) {
 #pragma unroll
         for (int c = 0; c < kCB; ++c) b[c] = sB[sb_index(kt + i + 1, c, lane)];
