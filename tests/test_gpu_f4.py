@@ -397,3 +397,26 @@ def test_f4_lds_full_size_sk200_equals_int8(gpu_lib):
         ref = _oracle(J, h, 1 / np.sqrt(n), beta, eta, 1, k, trials, ztab, target=tgt[k])
         _compare(batch.trials_of(k), ref, trials)
     batch.close()
+
+
+def test_f4_one_launch_caller_initial_spins(gpu_lib):
+    """The one launch over e2m1 parts starting from caller spins (each part's
+    own initial-state buffer travels in the launch's part table)."""
+    _say("f4 one launch from caller spins")
+    pim = gpu_lib
+    ns = [400, 700, 300]
+    trials, steps = 48, 20
+    ztab = w.gauss_table(8)
+    probs = [w.sk1(n, seed=29, index=k) for k, n in enumerate(ns)]
+    insts = [pim.Instance(J, h, j_scale=1 / np.sqrt(len(h)), xi=0.5, noise_table=ztab, rng_stream=80 + k)
+             for k, (J, h) in enumerate(probs)]
+    rng = np.random.default_rng(5)
+    init = [rng.choice([-1, 1], size=(trials, n)).astype(np.int8) for n in ns]
+    beta = w.linear_beta(steps, 0.1, 3.0)
+    eta = w.eta_sqrt_beta_over_5(beta)
+    batch = pim.Batch(insts, trials, init_spins=init).run(beta, eta, seed=6, kernel="f4")
+    for k, (J, h) in enumerate(probs):
+        tr = [0, 17, 47]
+        ref = _oracle(J, h, 1 / np.sqrt(len(h)), beta, eta, 6, 80 + k, tr, ztab, init=init[k][tr].T.astype(np.int64))
+        _compare(batch.trials_of(k), ref, tr)
+    batch.close()
