@@ -728,7 +728,6 @@ hipError_t run_launch(pim_batch* b, const pim_schedule* sc, uint64_t seed, const
   }
 }
 
-// Run-state bookkeeping after a successful launch.
 // Compute units of the current device (cached per device).
 int device_cus() {
   static std::mutex m;
@@ -826,19 +825,15 @@ pim_status stage_multi(pim_batch* b, const std::vector<pim_schedule>& psc, uint6
   return PIM_OK;
 }
 
+// Run-state bookkeeping after a successful launch.
 void run_mark(pim_batch* b, const pim_schedule* sc) {
-  {
-    const int T = sc->steps;
-    b->ran = true;
-    b->recorded = sc->record_states != 0;
-    b->reranked = false;
-    b->cancelled_checked = -1;
-    b->last_T = T;
-    b->last_start = sc->start_step;
-  }
+  b->ran = true;
+  b->recorded = sc->record_states != 0;
+  b->reranked = false;
+  b->cancelled_checked = -1;
+  b->last_T = sc->steps;
+  b->last_start = sc->start_step;
 }
-
-
 
 }  // namespace
 
