@@ -31,6 +31,7 @@
 
 #include "internal.hpp"
 #include "philox.hpp"
+#include "frag_stream.hpp"
 
 namespace pim {
 namespace {
@@ -90,7 +91,7 @@ __device__ __forceinline__ int sb_index(int kt, int c, int lane) { return (kt * 
 // would have to be zeroed by moves, one per register); K step k uses ring
 // slot k % D.
 template <int MT>
-__device__ __forceinline__ void big_rows(const v4i* __restrict__ gA, const v4i* sB, int lane, int mt0, int nt,
+__device__ __forceinline__ void big_rows(const FragStream& gA, const v4i* sB, int lane, int mt0, int nt,
                                          v16i (&acc)[MT][kCB]) {
   constexpr int D = MT == 1 ? 4 : 2;
   int fa[MT];
@@ -100,7 +101,7 @@ __device__ __forceinline__ void big_rows(const v4i* __restrict__ gA, const v4i* 
 #pragma unroll
   for (int r = 0; r < MT; ++r)
 #pragma unroll
-    for (int i = 0; i < D; ++i) ar[r][i] = gA[(fa[r] + i) * 64 + lane];  // nt >= 9 > D
+    for (int i = 0; i < D; ++i) ar[r][i] = gA(fa[r] + i);  // nt >= 9 > D
 #pragma unroll
   for (int c = 0; c < kCB; ++c) b[c] = sB[sb_index(0, c, lane)];
   // K step 0
@@ -109,7 +110,7 @@ __device__ __forceinline__ void big_rows(const v4i* __restrict__ gA, const v4i* 
 #pragma unroll
     for (int r = 0; r < MT; ++r) acc[r][c] = __builtin_amdgcn_mfma_i32_32x32x32_i8(ar[r][0], b[c], v16i{}, 0, 0, 0);
 #pragma unroll
-  for (int r = 0; r < MT; ++r) ar[r][0] = gA[(fa[r] + D) * 64 + lane];  // D < nt
+  for (int r = 0; r < MT; ++r) ar[r][0] = gA(fa[r] + D);  // D < nt
 #pragma unroll
   for (int c = 0; c < kCB; ++c) b[c] = sB[sb_index(1, c, lane)];
   __builtin_amdgcn_sched_barrier(0);
@@ -129,7 +130,7 @@ __device__ __forceinline__ void big_rows(const v4i* __restrict__ gA, const v4i* 
       // refill the slot after its last use, so the load lands in place
       const int kf = min(kt + i + D, nt - 1);
 #pragma unroll
-      for (int r = 0; r < MT; ++r) ar[r][slot] = gA[(fa[r] + kf) * 64 + lane];
+      for (int r = 0; r < MT; ++r) ar[r][slot] = gA(fa[r] + kf);
       const int kn = min(kt + i + 1, nt - 1);
 #pragma unroll
       for (int c = 0; c < kCB; ++c) b[c] = sB[sb_index(kn, c, lane)];
@@ -250,9 +251,8 @@ __global__ __launch_bounds__(64 * kWaves, 2) void sweep_big_kernel(SweepArgs a, 
   const uint4* gTab4 = reinterpret_cast<const uint4*>(a.thtab + (size_t)cls * a.T * kTabEntries);
   const int32_t target = a.target ? a.target[inst] : INT_MIN;
   const uint32_t k0 = a.k0, k1 = a.k1;
-  // the instance's A fragments (fragment f, lane l at gA[f * 64 + l]; at most
-  // 32 * 32 * 64 entries, so 32-bit indices)
-  const v4i* gA = reinterpret_cast<const v4i*>(a.jfrag + (size_t)inst * nt * nt * 1024);
+  // the instance's A fragments (fragment mt * nt + p; at most 32 * 32 of 1 KB)
+  const FragStream gA(a.jfrag + (size_t)inst * nt * nt * 1024, (uint32_t)(nt * nt * 1024), lane);
 
   if (HAS_H)
     for (int i = threadIdx.x; i < npad; i += 64 * kWaves) sH[i] = a.h[(size_t)inst * npad + i];

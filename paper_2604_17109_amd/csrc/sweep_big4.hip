@@ -39,6 +39,7 @@
 #include "internal.hpp"
 #include "philox.hpp"
 #include "e2m1.hpp"
+#include "frag_stream.hpp"
 
 namespace pim {
 namespace {
@@ -88,7 +89,7 @@ __device__ __forceinline__ int sb_half(int mt, int c, int lane) { return 2 * sb_
 // zero accumulator as an inline constant: inside the loop the accumulators
 // would have to be zeroed by moves, one per register.
 template <int MT>
-__device__ __forceinline__ void rows_f4(const v4i* __restrict__ gA, const v4i* sB, int lane, int mt0, int np,
+__device__ __forceinline__ void rows_f4(const FragStream& gA, const v4i* sB, int lane, int mt0, int np,
                                         v16f (&acc)[MT][kCB]) {
   constexpr int D = MT == 1 ? 4 : 2;
   int fa[MT];
@@ -98,7 +99,7 @@ __device__ __forceinline__ void rows_f4(const v4i* __restrict__ gA, const v4i* s
 #pragma unroll
   for (int r = 0; r < MT; ++r)
 #pragma unroll
-    for (int i = 0; i < D; ++i) ar[r][i] = gA[(fa[r] + i) * 64 + lane];  // np >= 5 > D
+    for (int i = 0; i < D; ++i) ar[r][i] = gA(fa[r] + i);  // np >= 5 > D
 #pragma unroll
   for (int c = 0; c < kCB; ++c) b[c] = sB[sb_index(0, c, lane)];
   // K step 0
@@ -107,7 +108,7 @@ __device__ __forceinline__ void rows_f4(const v4i* __restrict__ gA, const v4i* s
 #pragma unroll
     for (int r = 0; r < MT; ++r) acc[r][c] = mfma(ar[r][0], b[c], v16f{});
 #pragma unroll
-  for (int r = 0; r < MT; ++r) ar[r][0] = gA[(fa[r] + D) * 64 + lane];  // D < np
+  for (int r = 0; r < MT; ++r) ar[r][0] = gA(fa[r] + D);  // D < np
 #pragma unroll
   for (int c = 0; c < kCB; ++c) b[c] = sB[sb_index(1, c, lane)];
   __builtin_amdgcn_sched_barrier(0);
@@ -124,7 +125,7 @@ __device__ __forceinline__ void rows_f4(const v4i* __restrict__ gA, const v4i* s
         for (int r = 0; r < MT; ++r) acc[r][c] = mfma(ar[r][slot], b[c], acc[r][c]);
       const int kf = min(kt + i + D, np - 1);
 #pragma unroll
-      for (int r = 0; r < MT; ++r) ar[r][slot] = gA[(fa[r] + kf) * 64 + lane];
+      for (int r = 0; r < MT; ++r) ar[r][slot] = gA(fa[r] + kf);
       const int kn = min(kt + i + 1, np - 1);
 #pragma unroll
       for (int c = 0; c < kCB; ++c) b[c] = sB[sb_index(kn, c, lane)];
@@ -293,8 +294,8 @@ __device__ __forceinline__ void big4_body(const SweepArgs& a, int nt, int inst, 
   const int32_t target = a.target ? a.target[inst] : INT_MIN;
   const uint32_t k0 = a.k0, k1 = a.k1;
   // the instance's A fragments (row tile mt, K step p, lane l at
-  // gA[(mt * np + p) * 64 + l]; at most 32 * 16 * 64 entries)
-  const v4i* gA = reinterpret_cast<const v4i*>(a.jfrag + (size_t)inst * nt * np * 1024);
+  // fragment mt * np + p; at most 32 * 16 fragments of 1 KB)
+  const FragStream gA(a.jfrag + (size_t)inst * nt * np * 1024, (uint32_t)(nt * np * 1024), lane);
 
   if (HAS_H)
     for (int i = threadIdx.x; i < npad; i += 64 * kWaves) sH[i] = 2 * a.h[(size_t)inst * npad + i];
