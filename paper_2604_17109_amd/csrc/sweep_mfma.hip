@@ -37,6 +37,7 @@ typedef int v4i __attribute__((ext_vector_type(4)));
 typedef int v16i __attribute__((ext_vector_type(16)));
 
 constexpr int kWaves = 4;                 // most waves (32-trial blocks) per workgroup
+constexpr int kXcds = 8;                  // XCDs of the device (workgroup placement)
 constexpr int kTabBytes = kTabEntries * 2;  // 1 KB per step table
 static_assert(kTabBytes == 64 * 16, "one 16-byte chunk per lane");
 
@@ -86,12 +87,18 @@ __device__ __forceinline__ void mfma_row_tile(const v4i* sJl, int mt, const v4i 
 // same registers hold spins 32 (NT - 1) + 16 + r, which are padding whenever
 // TAIL < 16.
 template <int NT, int CB, bool HAS_H, bool RECORD, int TAIL>
-__global__ __launch_bounds__(64 * kWaves, 3) void sweep_mfma_kernel(SweepArgs a) {
+__global__ __launch_bounds__(64 * kWaves, 3) void sweep_mfma_kernel(SweepArgs a, int blocks_per_inst) {
   extern __shared__ __align__(16) unsigned char lds[];
   constexpr int kFragBytes = NT * NT * 1024;
   constexpr int kNpad = NT * 32;
   constexpr int kHBytes = HAS_H ? kNpad * 4 : 0;
-  const int inst = blockIdx.y;
+  // workgroup -> (instance, trial block): the blocks of instance k have linear
+  // ids congruent to k modulo the XCD count (consecutive workgroups go to
+  // consecutive XCDs), so they run on one XCD and J is fetched into one L2
+  const int lin = blockIdx.x;
+  const int inst = (lin % kXcds) + kXcds * ((lin / kXcds) / blocks_per_inst);
+  const int tblk = (lin / kXcds) % blocks_per_inst;
+  if (inst >= a.count) return;  // whole workgroup, before any barrier
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   const int col = lane & 31;
@@ -112,7 +119,7 @@ __global__ __launch_bounds__(64 * kWaves, 3) void sweep_mfma_kernel(SweepArgs a)
   uint4* sTab4 = reinterpret_cast<uint4*>(sTab);
   __syncthreads();  // the only workgroup barrier
 
-  const int tbase = (blockIdx.x * (int)(blockDim.x >> 6) + wave) * 32 * CB;
+  const int tbase = (tblk * (int)(blockDim.x >> 6) + wave) * 32 * CB;
   if (tbase >= a.R) return;
   int trial[CB];
   bool live[CB];
@@ -349,8 +356,10 @@ hipError_t launch_tail(const SweepArgs& a, int count, hipStream_t s) {
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   const int per_wg = 32 * kBlocksPerWave * waves;
-  const dim3 grid((a.R + per_wg - 1) / per_wg, count);
-  hipLaunchKernelGGL(kern, grid, dim3(64 * waves), lds, s, a);
+  const int bpi = (a.R + per_wg - 1) / per_wg;
+  const int groups = (count + kXcds - 1) / kXcds;
+  const dim3 grid((unsigned)(bpi * groups * kXcds));
+  hipLaunchKernelGGL(kern, grid, dim3(64 * waves), lds, s, a, bpi);
   return hipGetLastError();
 }
 

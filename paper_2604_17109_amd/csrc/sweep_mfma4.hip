@@ -43,6 +43,7 @@ namespace {
 using namespace e2m1;
 
 constexpr int kWaves = 4;                      // most waves (32-trial blocks) per workgroup
+constexpr int kXcds = 8;                  // XCDs of the device (workgroup placement)
 constexpr float kAccBias = 12582912.0f;        // 1.5 * 2^23: start of every row tile's sum
 constexpr int32_t kAccBiasBits = 0x4B400000;   // its bit pattern; + 2 I is the biased field
 constexpr int32_t kLow24Bias = 0x400000;       // its low 24 bits: 2^22
@@ -93,13 +94,19 @@ __device__ __forceinline__ void stage_table(int32_t* dst, uint4 v, int lane) {
 // below N in the lower lane half, rounded up to 4; the others are padding
 // spins (zero couplings) and keep their initial values.
 template <int NT, bool HAS_H, int TAIL>
-__global__ __launch_bounds__(64 * kWaves, 3) void sweep_mfma4_kernel(SweepArgs a) {
+__global__ __launch_bounds__(64 * kWaves, 3) void sweep_mfma4_kernel(SweepArgs a, int blocks_per_inst) {
   extern __shared__ __align__(16) unsigned char lds[];
   constexpr int NP = (NT + 1) / 2;
   constexpr int kFragBytes = NT * NP * 1024;
   constexpr int kNpad = NT * 32;
   constexpr int kHBytes = HAS_H ? kNpad * 4 : 0;
-  const int inst = blockIdx.y;
+  // workgroup -> (instance, trial block): the blocks of instance k have linear
+  // ids congruent to k modulo the XCD count (consecutive workgroups go to
+  // consecutive XCDs), so they run on one XCD and J is fetched into one L2
+  const int lin = blockIdx.x;
+  const int inst = (lin % kXcds) + kXcds * ((lin / kXcds) / blocks_per_inst);
+  const int tblk = (lin / kXcds) % blocks_per_inst;
+  if (inst >= a.count) return;  // whole workgroup, before any barrier
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
   const int col = lane & 31;
@@ -119,7 +126,7 @@ __global__ __launch_bounds__(64 * kWaves, 3) void sweep_mfma4_kernel(SweepArgs a
   int32_t* sTab = reinterpret_cast<int32_t*>(lds + kFragBytes + kHBytes + wave * kTab32Bytes);
   __syncthreads();  // the only workgroup barrier
 
-  const int trial = (blockIdx.x * (int)(blockDim.x >> 6) + wave) * 32 + col;
+  const int trial = (tblk * (int)(blockDim.x >> 6) + wave) * 32 + col;
   if (trial - col >= a.R) return;  // whole wave
   const bool live = trial < a.R;
   const size_t cell = (size_t)inst * a.R + trial;
@@ -303,8 +310,10 @@ hipError_t launch_tail(const SweepArgs& a, int count, hipStream_t s) {
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   const int per_wg = 32 * waves;
-  const dim3 grid((a.R + per_wg - 1) / per_wg, count);
-  hipLaunchKernelGGL(kern, grid, dim3(64 * waves), lds, s, a);
+  const int bpi = (a.R + per_wg - 1) / per_wg;
+  const int groups = (count + kXcds - 1) / kXcds;
+  const dim3 grid((unsigned)(bpi * groups * kXcds));
+  hipLaunchKernelGGL(kern, grid, dim3(64 * waves), lds, s, a, bpi);
   return hipGetLastError();
 }
 
