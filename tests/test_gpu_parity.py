@@ -84,6 +84,17 @@ def test_sizes_and_ragged_tails(gpu_lib, kernel, n, trials):
     _run_case(gpu_lib, "maxcut" if n > 2 else "sk", n, trials, 120, kernel, seed=n, count=2)
 
 
+@pytest.mark.parametrize("kernel", ["mfma", "f4"])
+def test_instances_not_a_multiple_of_the_xcd_count(gpu_lib, kernel):
+    """Eleven instances of three trial blocks each, the last block ragged: the
+    LDS kernels place an instance's blocks on one XCD (workgroup b runs
+    instance b mod 8 + 8 floor((b / 8) / blocks), the grid padded to whole
+    groups of 8 instances), so every (instance, block) pair must run exactly
+    once.  Every trial of every instance against the oracle."""
+    _say(f"11 instances x 300 trials kernel={kernel}")
+    _run_case(gpu_lib, "sk", 40, 300, 60, kernel, seed=13, count=11)
+
+
 @pytest.mark.parametrize("kernel", KERNELS)
 def test_general_int8_with_fields(gpu_lib, kernel):
     _say(f"int8 couplings with h kernel={kernel}")
