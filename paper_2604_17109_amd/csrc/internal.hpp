@@ -198,24 +198,28 @@ int big_tiles(int n);  // row tiles of the streamed kernel: ceil(n / 32)
 // The same range on e2m1 (FP4) operands, for couplings in {0, +-1, +-2, +-3,
 // +-4, +-6} (exact): a.jfrag holds pack_f4_fragments output.
 hipError_t launch_sweep_big4(const SweepArgs& a, int count, int nt, bool has_h, hipStream_t s);
-// Several e2m1 batches (parts) in one launch: parts[p] holds part p's
-// arguments and row tile count; work[b] = (part, instance, trial block, 0),
-// or part -1 for an empty workgroup.  LDS is sized for the largest tile
+// Several batches (parts) of the streamed kernels in one launch, all on e2m1
+// operands (launch_sweep_big4_multi) or all on int8 (launch_sweep_big_multi):
+// parts[p] holds part p's arguments and row tile count; work[b] = (part,
+// instance, trial block, 0), or part -1 for an empty workgroup.  LDS is sized for the largest tile
 // count.  With has_h every part's a.h is non-null (zeros where a part has no
 // fields).
 // The run's scalars (seed words, steps, first counter step, whether targets
 // are tracked) replace those in the parts' arguments.
-struct Big4Part {
+struct MultiPart {
   SweepArgs a;
   int32_t nt, pad[3];
 };
-struct Big4Run {
+struct MultiRun {
   uint32_t k0, k1;
   int32_t T, start_step, use_target;
 };
-hipError_t launch_sweep_big4_multi(const Big4Part* d_parts, const int4* d_work, int nwork, int nt_max, bool has_h,
-                                   const Big4Run& run, hipStream_t s);
+hipError_t launch_sweep_big4_multi(const MultiPart* d_parts, const int4* d_work, int nwork, int nt_max, bool has_h,
+                                   const MultiRun& run, hipStream_t s);
 double big4_step_cost(int nt);  // relative workgroup time per step, for ordering work
+hipError_t launch_sweep_big_multi(const MultiPart* d_parts, const int4* d_work, int nwork, int nt_max, bool has_h,
+                                  const MultiRun& run, hipStream_t s);
+double big_step_cost(int nt);  // the same for the int8 streamed kernel
 bool f4_couplings(const int8_t* J, size_t count);  // every value e2m1-exact
 size_t f4_frag_bytes(int nt);                      // per instance: nt x ceil(nt/2) fragments of 1 KB
 void pack_f4_fragments(const int8_t* J, int n, int nt, uint8_t* out);

@@ -741,7 +741,8 @@ int device_cus() {
   return cus[dev];
 }
 
-// Parts mp of composite b that run on e2m1 operands, as one launch: each
+// Parts mp of composite b that run the streamed kernel, all on e2m1 operands
+// (f4) or all on int8, as one launch: each
 // instance's trial blocks stay on one XCD (workgroups 8k + x run on XCD x),
 // instances go to the least-loaded XCD longest first, and each XCD takes its
 // workgroups longest first, so short ones fill in behind long ones instead of
@@ -749,10 +750,10 @@ int device_cus() {
 // and the work list are uploaded when they differ from the last upload (after
 // the batch's previous run, which may still read them).
 pim_status stage_multi(pim_batch* b, const std::vector<pim_schedule>& psc, uint64_t seed, int T,
-                       const std::vector<size_t>& mp, hipStream_t s, const Big4Part** d_parts, const int4** d_work,
-                       int* nwork, int* nitems, int* nt_max, bool* has_h) {
+                       const std::vector<size_t>& mp, bool f4, hipStream_t s, const MultiPart** d_parts,
+                       const int4** d_work, int* nwork, int* nitems, int* nt_max, bool* has_h) {
   constexpr int kX = 8;
-  std::vector<Big4Part> parts(mp.size());
+  std::vector<MultiPart> parts(mp.size());
   struct Item {
     int part, inst, bpi;
     double cost;
@@ -763,9 +764,9 @@ pim_status stage_multi(pim_batch* b, const std::vector<pim_schedule>& psc, uint6
   for (size_t i : mp) *has_h |= b->parts[i]->has_h;
   for (size_t i = 0; i < mp.size(); ++i) {
     pim_batch* pb = b->parts[mp[i]];
-    std::memset(&parts[i], 0, sizeof(Big4Part));
+    std::memset(&parts[i], 0, sizeof(MultiPart));
     parts[i].a = int_sweep_args(pb, &psc[mp[i]], seed, T);
-    parts[i].a.jfrag = reinterpret_cast<const int8_t*>(pb->d_jfrag4);
+    if (f4) parts[i].a.jfrag = reinterpret_cast<const int8_t*>(pb->d_jfrag4);  // else the int8 fragments
     parts[i].a.h = *has_h ? pb->d_h : nullptr;  // zeros for instances without fields
     parts[i].a.target = pb->d_target;     // the launch drops it when targets are off
     parts[i].a.k0 = parts[i].a.k1 = 0;    // per run: kernel arguments
@@ -773,7 +774,7 @@ pim_status stage_multi(pim_batch* b, const std::vector<pim_schedule>& psc, uint6
     parts[i].nt = pb->nt;
     *nt_max = std::max(*nt_max, pb->nt);
     const int bpi = (pb->R + 127) / 128;
-    const double c = big4_step_cost(pb->nt);
+    const double c = f4 ? big4_step_cost(pb->nt) : big_step_cost(pb->nt);
     for (int k = 0; k < pb->count; ++k) items.push_back({(int)i, k, bpi, c});
   }
   std::stable_sort(items.begin(), items.end(), [](const Item& x, const Item& y) { return x.cost > y.cost; });
@@ -793,10 +794,10 @@ pim_status stage_multi(pim_batch* b, const std::vector<pim_schedule>& psc, uint6
     for (size_t k = 0; k < lists[x].size(); ++k) work[k * kX + x] = lists[x][k];
   }
   *nitems = (int)items_total;
-  const size_t pbytes = (parts.size() * sizeof(Big4Part) + 255) & ~(size_t)255;
+  const size_t pbytes = (parts.size() * sizeof(MultiPart) + 255) & ~(size_t)255;
   const size_t bytes = pbytes + work.size() * sizeof(int4);
   std::vector<uint8_t> host(bytes, 0);
-  std::memcpy(host.data(), parts.data(), parts.size() * sizeof(Big4Part));
+  std::memcpy(host.data(), parts.data(), parts.size() * sizeof(MultiPart));
   std::memcpy(host.data() + pbytes, work.data(), work.size() * sizeof(int4));
   auto device_fail = [&](hipError_t e, const char* what) {
     b->sticky_error = true;
@@ -819,7 +820,7 @@ pim_status stage_multi(pim_batch* b, const std::vector<pim_schedule>& psc, uint6
     }
     b->h_multi.swap(host);
   }
-  *d_parts = reinterpret_cast<const Big4Part*>(b->d_multi);
+  *d_parts = reinterpret_cast<const MultiPart*>(b->d_multi);
   *d_work = reinterpret_cast<const int4*>(b->d_multi + pbytes);
   *nwork = (int)work.size();
   return PIM_OK;
@@ -1264,22 +1265,26 @@ pim_status pim_run(pim_batch* b, const pim_schedule* sc, uint64_t seed, void* st
       pim_status st = run_prepare(b->parts[p], &psc[p], s, ctx[p]);
       if (st != PIM_OK) return st;
     }
-    // e2m1 parts: one launch over a longest-first work list
+    // streamed parts (N > 256): one launch over a longest-first work list, on
+    // e2m1 operands when at least two parts run on them, else on int8
     std::vector<char> in_multi(P, 0);
-    std::vector<size_t> mp;
+    std::vector<size_t> mp4, mp8;
     for (size_t p = 0; p < P; ++p)
-      if (ctx[p].f4 && b->parts[p]->nt * 32 > PIM_MAX_N_LDS) mp.push_back(p);
-    const Big4Part* d_parts = nullptr;
+      if (b->parts[p]->nt * 32 > PIM_MAX_N_LDS && ctx[p].mfma && !ctx[p].real && !ctx[p].seq)
+        (ctx[p].f4 ? mp4 : mp8).push_back(p);
+    const bool multi_f4 = mp4.size() >= 2;
+    const std::vector<size_t>& mp = multi_f4 ? mp4 : mp8;
+    const MultiPart* d_parts = nullptr;
     const int4* d_work = nullptr;
     int nwork = 0, nitems = 0, nt_max = 0;
     bool multi_h = false;
     if (mp.size() >= 2) {
       pim_status st =
-          stage_multi(b, psc, seed, ctx[0].T, mp, s, &d_parts, &d_work, &nwork, &nitems, &nt_max, &multi_h);
+          stage_multi(b, psc, seed, ctx[0].T, mp, multi_f4, s, &d_parts, &d_work, &nwork, &nitems, &nt_max, &multi_h);
       if (st != PIM_OK) return st;
       for (size_t p : mp) in_multi[p] = 1;
     }
-    const Big4Run run{(uint32_t)seed, (uint32_t)(seed >> 32), ctx[0].T, sc->start_step, sc->use_target ? 1 : 0};
+    const MultiRun run{(uint32_t)seed, (uint32_t)(seed >> 32), ctx[0].T, sc->start_step, sc->use_target ? 1 : 0};
     if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     b->gexec = nullptr;
@@ -1289,7 +1294,7 @@ pim_status pim_run(pim_batch* b, const pim_schedule* sc, uint64_t seed, void* st
     if (e == hipSuccess) e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
       hipError_t ce = hipEventRecord(b->fork_ev, b->cap);
-      // the one launch of the e2m1 parts first: its longest workgroups take
+      // the one launch of the streamed parts first: its longest workgroups take
       // the CUs before the small parts' launches are dispatched.  When it has
       // a workgroup for every CU its longest-first schedule leaves almost no
       // idle tail, and the other parts' workgroups, run beside it, only delay
@@ -1305,8 +1310,9 @@ pim_status pim_run(pim_batch* b, const pim_schedule* sc, uint64_t seed, void* st
         const bool multi_head = nwork > 0 && p == mp[0];
         ce = hipStreamWaitEvent(b->fork[p], (chain && !multi_head) ? b->join[mp[0]] : b->fork_ev, 0);
         if (ce == hipSuccess)
-          ce = multi_head ? launch_sweep_big4_multi(d_parts, d_work, nwork, nt_max, multi_h, run, b->fork[p])
-                          : run_launch(b->parts[p], &psc[p], seed, ctx[p], b->fork[p]);
+          ce = !multi_head ? run_launch(b->parts[p], &psc[p], seed, ctx[p], b->fork[p])
+               : multi_f4  ? launch_sweep_big4_multi(d_parts, d_work, nwork, nt_max, multi_h, run, b->fork[p])
+                           : launch_sweep_big_multi(d_parts, d_work, nwork, nt_max, multi_h, run, b->fork[p]);
         if (ce == hipSuccess) ce = hipEventRecord(b->join[p], b->fork[p]);
         if (ce == hipSuccess) ce = hipStreamWaitEvent(b->cap, b->join[p], 0);
       }

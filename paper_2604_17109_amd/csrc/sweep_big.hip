@@ -215,8 +215,9 @@ __device__ __forceinline__ void big_decide(const v16i (&acc)[kCB], const v4i* sB
   }
 }
 
+// One workgroup's run: trial block tblk (128 trials) of instance inst.
 template <int RPW, bool HAS_H>
-__global__ __launch_bounds__(64 * kWaves, 2) void sweep_big_kernel(SweepArgs a, int nt, int blocks_per_inst) {
+__device__ __forceinline__ void big_body(const SweepArgs& a, int nt, int inst, int tblk) {
   extern __shared__ __align__(16) unsigned char lds[];
   const int npad = nt * 32;
   // LDS: spins [nt][kCB][64] x 16 B | table 1 KB | energy partials
@@ -229,12 +230,6 @@ __global__ __launch_bounds__(64 * kWaves, 2) void sweep_big_kernel(SweepArgs a, 
   int32_t* sFlag = sStat + 3 * kCB * 32;
   int32_t* sH = sFlag + 4;
 
-  // workgroup -> (instance, trial block): the blocks of instance k all have
-  // linear ids congruent to k modulo the XCD count
-  const int lin = blockIdx.x;
-  const int inst = (lin % kXcds) + kXcds * ((lin / kXcds) / blocks_per_inst);
-  const int tblk = (lin / kXcds) % blocks_per_inst;
-  if (inst >= a.count) return;  // whole workgroup: before any barrier
   // wave index made scalar: every row-tile index below is wave-uniform
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
@@ -409,6 +404,38 @@ __global__ __launch_bounds__(64 * kWaves, 2) void sweep_big_kernel(SweepArgs a, 
   }
 }
 
+template <int RPW, bool HAS_H>
+__global__ __launch_bounds__(64 * kWaves, 2) void sweep_big_kernel(SweepArgs a, int nt, int blocks_per_inst) {
+  // workgroup -> (instance, trial block): the blocks of instance k all have
+  // linear ids congruent to k modulo the XCD count (hardware dispatch sends
+  // consecutive workgroups to consecutive XCDs), so they share one L2
+  const int lin = blockIdx.x;
+  const int inst = (lin % kXcds) + kXcds * ((lin / kXcds) / blocks_per_inst);
+  const int tblk = (lin / kXcds) % blocks_per_inst;
+  if (inst >= a.count) return;  // whole workgroup: before any barrier
+  big_body<RPW, HAS_H>(a, nt, inst, tblk);
+}
+
+// Several batches of different N in one launch: workgroup b runs work item
+// work[b] = (part, instance, trial block) with that part's arguments.  The
+// host orders the items so that workgroups 8k + x all run on XCD x, each
+// instance's blocks on one XCD, and each XCD's items longest first.
+template <bool HAS_H>
+__global__ __launch_bounds__(64 * kWaves, 2) void sweep_big_multi_kernel(const MultiPart* parts, const int4* work,
+                                                                         int nwork, MultiRun run) {
+  if ((int)blockIdx.x >= nwork) return;
+  const int4 item = work[blockIdx.x];
+  if (item.x < 0) return;  // padding item: whole workgroup, before any barrier
+  SweepArgs a = parts[item.x].a;
+  const int nt = parts[item.x].nt;
+  a.k0 = run.k0;
+  a.k1 = run.k1;
+  a.T = run.T;
+  a.start_step = run.start_step;
+  if (!run.use_target) a.target = nullptr;
+  big_body<kMaxTiles / kWaves, HAS_H>(a, nt, item.y, item.z);
+}
+
 size_t big_lds_bytes(int nt, bool has_h) {
   return (size_t)nt * kCB * 1024 + kTabBytes + (size_t)(kWaves + 3) * kCB * 32 * 4 + 16 +
          (has_h ? (size_t)nt * 32 * 4 : 0);
@@ -429,6 +456,18 @@ hipError_t launch_rpw(const SweepArgs& a, int count, int nt, hipStream_t s) {
 }
 
 template <bool HAS_H>
+hipError_t launch_multi(const MultiPart* d_parts, const int4* d_work, int nwork, int nt_max, const MultiRun& run,
+                        hipStream_t s) {
+  const size_t lds = big_lds_bytes(nt_max, HAS_H);
+  auto kern = sweep_big_multi_kernel<HAS_H>;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(kern, dim3((unsigned)nwork), dim3(64 * kWaves), lds, s, d_parts, d_work, nwork, run);
+  return hipGetLastError();
+}
+
+template <bool HAS_H>
 hipError_t launch_h(const SweepArgs& a, int count, int nt, hipStream_t s) {
   switch ((nt + kWaves - 1) / kWaves) {  // row tiles per wave
     case 2: return launch_rpw<2, HAS_H>(a, count, nt, s);
@@ -441,6 +480,27 @@ hipError_t launch_h(const SweepArgs& a, int count, int nt, hipStream_t s) {
 }  // namespace
 
 int big_tiles(int n) { return (n + 31) / 32; }
+
+hipError_t launch_sweep_big_multi(const MultiPart* d_parts, const int4* d_work, int nwork, int nt_max, bool has_h,
+                                  const MultiRun& run, hipStream_t s) {
+  if (nwork < 1 || nt_max < kMinTiles || nt_max > kMaxTiles) return hipErrorInvalidValue;
+  return has_h ? launch_multi<true>(d_parts, d_work, nwork, nt_max, run, s)
+               : launch_multi<false>(d_parts, d_work, nwork, nt_max, run, s);
+}
+
+// Relative time of one workgroup-step at nt row tiles, the form of the e2m1
+// kernel's model with int8 K steps of 32 (nt per tile instead of nt / 2):
+// the waves of a SIMD (w and w + 4) run their tiles' contractions and
+// decisions one after the other, and the workgroup waits at every step for
+// its busiest SIMD.
+double big_step_cost(int nt) {
+  int simd_tiles = 0;
+  for (int w = 0; w < kWaves / 2; ++w) {
+    const int t = (nt - w + kWaves - 1) / kWaves + (nt - w - kWaves / 2 + kWaves - 1) / kWaves;
+    simd_tiles = t > simd_tiles ? t : simd_tiles;
+  }
+  return simd_tiles * (128.0 * nt + 2660.0) + 3000.0;
+}
 
 hipError_t launch_sweep_big(const SweepArgs& a, int count, int nt, bool has_h, hipStream_t s) {
   if (a.npad != nt * 32 || nt < kMinTiles || nt > kMaxTiles || a.T < 1 || count < 1 || a.R < 1)

@@ -472,8 +472,8 @@ __global__ __launch_bounds__(64 * kWaves, 2) void sweep_big4_kernel(SweepArgs a,
 // host orders the items so that workgroups 8k + x all run on XCD x, each
 // instance's blocks on one XCD, and each XCD's items longest first.
 template <bool HAS_H>
-__global__ __launch_bounds__(64 * kWaves, 2) void sweep_big4_multi_kernel(const Big4Part* parts, const int4* work,
-                                                                          int nwork, Big4Run run) {
+__global__ __launch_bounds__(64 * kWaves, 2) void sweep_big4_multi_kernel(const MultiPart* parts, const int4* work,
+                                                                          int nwork, MultiRun run) {
   if ((int)blockIdx.x >= nwork) return;
   const int4 item = work[blockIdx.x];
   if (item.x < 0) return;  // padding item: whole workgroup, before any barrier
@@ -569,7 +569,7 @@ void pack_f4_fragments(const int8_t* J, int n, int nt, uint8_t* out) {
 }
 
 template <bool HAS_H>
-hipError_t launch_multi(const Big4Part* d_parts, const int4* d_work, int nwork, int nt_max, const Big4Run& run,
+hipError_t launch_multi(const MultiPart* d_parts, const int4* d_work, int nwork, int nt_max, const MultiRun& run,
                         hipStream_t s) {
   const size_t lds = big4_lds_bytes(nt_max, HAS_H);
   auto kern = sweep_big4_multi_kernel<HAS_H>;
@@ -580,8 +580,8 @@ hipError_t launch_multi(const Big4Part* d_parts, const int4* d_work, int nwork, 
   return hipGetLastError();
 }
 
-hipError_t launch_sweep_big4_multi(const Big4Part* d_parts, const int4* d_work, int nwork, int nt_max, bool has_h,
-                                   const Big4Run& run, hipStream_t s) {
+hipError_t launch_sweep_big4_multi(const MultiPart* d_parts, const int4* d_work, int nwork, int nt_max, bool has_h,
+                                   const MultiRun& run, hipStream_t s) {
   if (nwork < 1 || nt_max < kMinTiles || nt_max > kMaxTiles) return hipErrorInvalidValue;
   return has_h ? launch_multi<true>(d_parts, d_work, nwork, nt_max, run, s)
                : launch_multi<false>(d_parts, d_work, nwork, nt_max, run, s);

@@ -201,13 +201,14 @@ def test_f4_full_size_n1000_sampled(gpu_lib):
     batch.close()
 
 
-def test_f4_one_launch_for_all_parts(gpu_lib):
-    """Several e2m1 parts of an uneven batch run as one launch over a work
-    list: partial trial blocks (200 trials), parts with and without fields,
+@pytest.mark.parametrize("kernel", ["f4", "mfma"])
+def test_f4_one_launch_for_all_parts(gpu_lib, kernel):
+    """Several streamed parts of an uneven batch (e2m1 or int8 operands) run
+    as one launch over a work list: partial trial blocks (200 trials), parts with and without fields,
     odd tile counts, and repeated runs that change the seed (the list is
     uploaded again) or keep it (reused); each result equals the oracle, and
     the third run equals the first."""
-    _say("f4 one launch over parts, 200 trials, fields")
+    _say(f"[{kernel}] f4 one launch over parts, 200 trials, fields")
     pim = gpu_lib
     ns = [300, 520, 300, 1000, 700, 130, 520]
     trials, steps = 200, 24
@@ -222,7 +223,7 @@ def test_f4_one_launch_for_all_parts(gpu_lib):
     batch = pim.Batch(insts, trials)
     first = None
     for run, seed in enumerate((2, 5, 2)):
-        batch.run(beta, eta, seed=seed, kernel="f4")
+        batch.run(beta, eta, seed=seed, kernel=kernel)
         got = [batch.trials_of(k) for k in range(len(ns))]
         if run == 0:
             first = got
@@ -271,13 +272,15 @@ def test_f4_full_size_uneven_batch_sampled(gpu_lib):
     batch.close()
 
 
-def test_f4_one_launch_cancel_and_target_toggle(gpu_lib):
-    """The one launch over e2m1 parts: a run with first-hit targets, then the
+@pytest.mark.parametrize("kernel", ["f4", "mfma"])
+def test_f4_one_launch_cancel_and_target_toggle(gpu_lib, kernel):
+    """The one launch over streamed parts (e2m1 or int8 operands): a run with
+    first-hit targets, then the
     same schedule without them (the uploaded work list is reused, the target
     flag is a kernel argument), then a long run cancelled from the host, then
     a short run that completes; results equal the oracle where they are
     defined."""
-    _say("f4 one launch: targets on/off, cancel")
+    _say(f"[{kernel}] f4 one launch: targets on/off, cancel")
     pim = gpu_lib
     ns = [300, 600, 1000]
     trials, steps = 64, 30
@@ -290,7 +293,7 @@ def test_f4_one_launch_cancel_and_target_toggle(gpu_lib):
     tgt = [float(np.floor(-0.6 * n ** 1.5)) for n in ns]
     batch = pim.Batch(insts, trials)
     for use_target in (True, False):
-        batch.run(beta, eta, seed=4, kernel="f4", target=tgt if use_target else None)
+        batch.run(beta, eta, seed=4, kernel=kernel, target=tgt if use_target else None)
         for k, (J, h) in enumerate(probs):
             got = batch.trials_of(k)
             ref = _oracle(J, h, 1 / np.sqrt(len(h)), beta, eta, 4, 60 + k, np.arange(trials), ztab,
@@ -299,12 +302,12 @@ def test_f4_one_launch_cancel_and_target_toggle(gpu_lib):
             if not use_target:
                 assert np.all(got["first_hit"] == -1)
     T = 60000
-    batch.run(np.full(T, 1.0), np.full(T, 0.4), seed=1, kernel="f4")
+    batch.run(np.full(T, 1.0), np.full(T, 0.4), seed=1, kernel=kernel)
     batch.cancel()
     with pytest.raises(pim.PimError) as ei:
         batch.trials_of(0)
     assert ei.value.status == pim.PIM_ERR_CANCELLED
-    batch.run(beta, eta, seed=4, kernel="f4")
+    batch.run(beta, eta, seed=4, kernel=kernel)
     for k, (J, h) in enumerate(probs):
         ref = _oracle(J, h, 1 / np.sqrt(len(h)), beta, eta, 4, 60 + k, [0, 63], ztab)
         _compare(batch.trials_of(k), ref, [0, 63])
@@ -399,10 +402,12 @@ def test_f4_lds_full_size_sk200_equals_int8(gpu_lib):
     batch.close()
 
 
-def test_f4_one_launch_caller_initial_spins(gpu_lib):
-    """The one launch over e2m1 parts starting from caller spins (each part's
-    own initial-state buffer travels in the launch's part table)."""
-    _say("f4 one launch from caller spins")
+@pytest.mark.parametrize("kernel", ["f4", "mfma"])
+def test_f4_one_launch_caller_initial_spins(gpu_lib, kernel):
+    """The one launch over streamed parts (e2m1 or int8 operands) starting
+    from caller spins (each part's own initial-state buffer travels in the
+    launch's part table)."""
+    _say(f"[{kernel}] f4 one launch from caller spins")
     pim = gpu_lib
     ns = [400, 700, 300]
     trials, steps = 48, 20
@@ -414,9 +419,35 @@ def test_f4_one_launch_caller_initial_spins(gpu_lib):
     init = [rng.choice([-1, 1], size=(trials, n)).astype(np.int8) for n in ns]
     beta = w.linear_beta(steps, 0.1, 3.0)
     eta = w.eta_sqrt_beta_over_5(beta)
-    batch = pim.Batch(insts, trials, init_spins=init).run(beta, eta, seed=6, kernel="f4")
+    batch = pim.Batch(insts, trials, init_spins=init).run(beta, eta, seed=6, kernel=kernel)
     for k, (J, h) in enumerate(probs):
         tr = [0, 17, 47]
         ref = _oracle(J, h, 1 / np.sqrt(len(h)), beta, eta, 6, 80 + k, tr, ztab, init=init[k][tr].T.astype(np.int64))
+        _compare(batch.trials_of(k), ref, tr)
+    batch.close()
+
+
+@pytest.mark.parametrize("exact", [(0, 1), (0,)])
+def test_one_launch_with_parts_on_both_operand_types(gpu_lib, exact):
+    """e2m1 operands asked for, but only the parts listed in `exact` have
+    e2m1-exact couplings; the others (couplings of 5 and 7) fall back to int8.
+    With two exact parts they run as the one e2m1 launch and the int8 parts as
+    their own launches; with one, the int8 parts run as the one launch and the
+    e2m1 part alone.  Sampled trials of every part equal the oracle."""
+    _say(f"one launch, parts on both operand types, exact parts {exact}")
+    pim = gpu_lib
+    ns = [300, 600, 400, 700, 100]
+    trials, steps = 160, 24
+    ztab = w.gauss_table(8)
+    probs = [_e2m1_instance(n, 41, k, (-2, -1, 0, 1, 2) if k in exact or n <= 256 else (-7, -5, -1, 1, 5, 7))
+             for k, n in enumerate(ns)]
+    insts = [pim.Instance(J, h, j_scale=1 / np.sqrt(len(h)), xi=0.5, noise_table=ztab, rng_stream=90 + k)
+             for k, (J, h) in enumerate(probs)]
+    beta = w.linear_beta(steps, 0.1, 3.0)
+    eta = w.eta_sqrt_beta_over_5(beta)
+    batch = pim.Batch(insts, trials).run(beta, eta, seed=8, kernel="f4")
+    for k, (J, h) in enumerate(probs):
+        tr = [0, 127, 128, 159]
+        ref = _oracle(J, h, 1 / np.sqrt(len(h)), beta, eta, 8, 90 + k, tr, ztab)
         _compare(batch.trials_of(k), ref, tr)
     batch.close()
