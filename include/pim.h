@@ -208,10 +208,12 @@ pim_status pim_quantize(const double* J, int32_t n, int32_t prec, double* J_out,
  * pim_prec) with `trials` trials each.  Instances may have different N: the
  * batch then keeps one part per distinct N and pim_run launches the parts'
  * sweeps as one captured HIP graph (one graph launch per run): parallel
- * branches, except that with PIM_KERNEL_MFMA_F4 the e2m1 parts with
- * N > PIM_MAX_N_LDS run as one launch over a longest-first work list, which
- * the other parts follow when it has a workgroup for every CU; init_spins then
- * holds, instance after instance, trials x N_k values.
+ * branches, except that the parts with N > PIM_MAX_N_LDS run as one launch
+ * over a longest-first work list when there are at least two of them on one
+ * operand type (e2m1 when at least two are e2m1 parts of a PIM_KERNEL_MFMA_F4
+ * run, else int8), which the other parts follow when it has a workgroup for
+ * every CU; init_spins then holds, instance after instance, trials x N_k
+ * values.
  * init_spins:
  * host int8 [count][trials][N] of +-1, or NULL for generator-drawn initial
  * spins.  The batch keeps pointers to the instances, which must outlive it.
